@@ -1,0 +1,293 @@
+"""Seeded synthetic inputs for the EDAC-SPH wind-tunnel path.
+
+This module builds particle sets (lattices, inlet/outlet/wall layers, cylinders)
+and the configuration parameters of the five workloads. It holds none of the
+method's arithmetic: no kernel, no neighbour search, no pair term, no boundary
+rule. Both the HIP path and the CPU oracle consume its output, so that they see
+bit-identical FP64 inputs.
+
+Particle-set format (a dict of numpy arrays, one row per particle):
+
+    x, u, ut, uin : float64 (n, 3)   position, momentum velocity, transport
+                                     velocity, prescribed inlet velocity
+    p             : float64 (n,)     gauge pressure
+    ring          : float64 (n, 6, 4) time-average window of (u, v, w, p)
+    head          : int32   (n,)     next ring slot to overwrite
+    avg           : float64 (n, 4)   mean of the ring
+    jprev         : float64 (n, 3)   characteristic variables of the previous step
+    red_prev      : uint8   (n,)     1 if the particle had fluid support last step
+    type          : uint8   (n,)     FLUID/INLET/OUTLET/WALL_SLIP/WALL_NOSLIP/BODY
+    id            : int64   (n,)     stable particle identity
+
+In 2D the third components are zero. Parameters follow the paper's EDAC setup
+(Sec. 2): c_s = 10 U, alpha = 0.5, the 0.01 regulariser of the viscous term, and
+a 6-step averaging window (Sec. 3.4, eq:N). The time step and background
+pressure are chosen by the usual EDAC-TVF rule (acoustic CFL 0.25, viscous
+limit 0.125 h^2/nu, p_b = rho0 c^2) and are passed to both sides as inputs.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+FLUID, INLET, OUTLET, WALL_SLIP, WALL_NOSLIP, BODY, DEAD = 0, 1, 2, 3, 4, 5, 255
+N_AVG = 6
+
+# flag bits shared by both sides' parameter blocks
+FLAG_NO_PAVG = 1   # drop the neighbour-average pressure (conservation tests)
+FLAG_DAMP_NU = 2   # use the physical viscosity in the pressure damping term
+FLAG_NOISE = 4     # add seeded velocity noise to inlet particles at spawn
+
+ID_GENERATION = 1 << 40   # a spawned inlet particle's id is its parent's + this
+
+
+def base_params(*, dim, dx, U=1.0, c_factor=10.0, rho0=1.0, nu=0.01, alpha=0.5,
+                h_over_dx=1.0, name="custom"):
+    h = h_over_dx * dx
+    c = c_factor * U
+    dt = min(0.25 * h / (c + U), 0.125 * h * h / nu) if nu > 0 else 0.25 * h / (c + U)
+    return dict(
+        name=name, dim=dim, dx=dx, h=h, rho0=rho0, c=c, U=U, nu=nu, alpha=alpha,
+        eta=0.01, dt=dt, pb=rho0 * c * c, n_avg=N_AVG, flags=0,
+        lo=[0.0, 0.0, 0.0], hi=[1.0, 1.0, 1.0], periodic=[0, 0, 0],
+        x_inlet=-1e30, x_outlet=1e30, x_outlet_end=1e30, inlet_len=0.0,
+        noise_amp=0.0, noise_seed=0, D=0.0, steps=1,
+    )
+
+
+def _empty(n):
+    return dict(
+        x=np.zeros((n, 3)), u=np.zeros((n, 3)), ut=np.zeros((n, 3)),
+        uin=np.zeros((n, 3)), p=np.zeros(n), ring=np.zeros((n, N_AVG, 4)),
+        head=np.zeros(n, np.int32), avg=np.zeros((n, 4)), jprev=np.zeros((n, 3)),
+        red_prev=np.zeros(n, np.uint8), type=np.zeros(n, np.uint8),
+        id=np.arange(n, dtype=np.int64),
+    )
+
+
+def _finish(parts):
+    """Concatenate blocks, fill rings/averages with the initial (u, v, w, p)."""
+    keys = parts[0].keys()
+    s = {k: np.concatenate([b[k] for b in parts]) for k in keys}
+    n = len(s["p"])
+    s["id"] = np.arange(n, dtype=np.int64)
+    s["ut"] = s["u"].copy()
+    init = np.concatenate([s["u"], s["p"][:, None]], axis=1)
+    s["ring"] = np.repeat(init[:, None, :], N_AVG, axis=1).copy()
+    s["avg"] = init.copy()
+    s["head"] = np.zeros(n, np.int32)
+    s["jprev"] = np.zeros((n, 3))
+    s["red_prev"] = np.zeros(n, np.uint8)
+    return s
+
+
+def _block(xs, ys, zs, typ):
+    g = np.meshgrid(xs, ys, zs, indexing="ij")
+    pts = np.stack([a.ravel() for a in g], axis=1)
+    b = _empty(len(pts))
+    b["x"] = pts
+    b["type"][:] = typ
+    return b
+
+
+def centres(i0, i1, dx, origin=0.0):
+    return origin + (np.arange(i0, i1) + 0.5) * dx
+
+
+def taylor_green_box(n_side=40, L=1.0, U=1.0, nu=0.01):
+    """Periodic unit box, square lattice, Taylor-Green vortex initial state."""
+    dx = L / n_side
+    prm = base_params(dim=2, dx=dx, U=U, nu=nu, name=f"tgv{n_side}")
+    prm.update(lo=[0.0, 0.0, 0.0], hi=[L, L, 0.0], periodic=[1, 1, 0])
+    b = _block(centres(0, n_side, dx), centres(0, n_side, dx), [0.0], FLUID)
+    x, y = b["x"][:, 0], b["x"][:, 1]
+    k = 2.0 * math.pi / L
+    b["u"][:, 0] = -U * np.cos(k * x) * np.sin(k * y)
+    b["u"][:, 1] = U * np.sin(k * x) * np.cos(k * y)
+    b["p"] = -0.25 * prm["rho0"] * U * U * (np.cos(2 * k * x) + np.cos(2 * k * y))
+    return prm, _finish([b])
+
+
+def periodic_lattice(n_side=12, dim=2, dx=0.1, U=0.0):
+    """Perfect periodic lattice with zero fields (used for closed-form checks)."""
+    L = n_side * dx
+    prm = base_params(dim=dim, dx=dx, U=max(U, 1.0), name=f"lattice{dim}d")
+    prm.update(lo=[0.0] * 3, hi=[L, L, L if dim == 3 else 0.0],
+               periodic=[1, 1, 1 if dim == 3 else 0])
+    zs = centres(0, n_side, dx) if dim == 3 else [0.0]
+    b = _block(centres(0, n_side, dx), centres(0, n_side, dx), zs, FLUID)
+    return prm, _finish([b])
+
+
+def channel(Lx=4.0, Ly=1.0, Lz=None, dx=0.01, layers=5, U=1.0, nu=0.01,
+            pulse_amp=None, pulse_x=None, pulse_w=0.1, cyl=None,
+            side_walls=None, wall_layers=3, noise=0.0, noise_seed=1907,
+            name="channel"):
+    """Wind-tunnel channel: inlet layers | fluid | hybrid outlet layers.
+
+    Lz=None gives 2D. side_walls: None (periodic lateral directions),
+    'slip' or 'noslip' (wall_layers layers of wall particles on every lateral
+    face, spanning the whole x range). cyl=(xc, yc, D) adds a no-slip body
+    made of wall_layers concentric rings spaced dx inward from D/2 - dx/2.
+    pulse_amp adds p = A exp(-((x - pulse_x)/pulse_w)^2) to the fluid.
+    """
+    dim = 2 if Lz is None else 3
+    prm = base_params(dim=dim, dx=dx, U=U, nu=nu, name=name)
+    nx, ny = int(round(Lx / dx)), int(round(Ly / dx))
+    nz = int(round(Lz / dx)) if dim == 3 else 0
+    wl = wall_layers if side_walls else 0
+    pad = 2 * dx
+    prm.update(
+        x_inlet=0.0, x_outlet=Lx, x_outlet_end=Lx + layers * dx, inlet_len=layers * dx,
+        lo=[-layers * dx - pad, -wl * dx - (pad if wl else 0.0),
+            (-wl * dx - (pad if wl else 0.0)) if dim == 3 else 0.0],
+        hi=[Lx + layers * dx + pad, Ly + wl * dx + (pad if wl else 0.0),
+            (Lz + wl * dx + (pad if wl else 0.0)) if dim == 3 else 0.0],
+        periodic=[0, 0 if side_walls else 1, (0 if side_walls else 1) if dim == 3 else 0],
+    )
+    ys = centres(0, ny, dx)
+    zs = centres(0, nz, dx) if dim == 3 else [0.0]
+    blocks = []
+    inl = _block(centres(-layers, 0, dx), ys, zs, INLET)
+    inl["uin"][:, 0] = U
+    inl["u"][:, 0] = U
+    blocks.append(inl)
+    fl = _block(centres(0, nx, dx), ys, zs, FLUID)
+    fl["u"][:, 0] = U
+    if pulse_amp is not None:
+        px = Lx / 2 if pulse_x is None else pulse_x
+        fl["p"] = pulse_amp * np.exp(-(((fl["x"][:, 0] - px) / pulse_w) ** 2))
+    if cyl is not None:
+        xc, yc, D = cyl
+        r = np.hypot(fl["x"][:, 0] - xc, fl["x"][:, 1] - yc)
+        keep = r >= 0.5 * D
+        fl = {k: v[keep] for k, v in fl.items()}
+        prm["D"] = D
+    blocks.append(fl)
+    out = _block(centres(nx, nx + layers, dx), ys, zs, OUTLET)
+    out["u"][:, 0] = U
+    blocks.append(out)
+    if side_walls:
+        wt = WALL_SLIP if side_walls == "slip" else WALL_NOSLIP
+        xs_all = centres(-layers, nx + layers, dx)
+        if dim == 2:
+            blocks.append(_block(xs_all, centres(-wl, 0, dx), [0.0], wt))
+            blocks.append(_block(xs_all, centres(ny, ny + wl, dx), [0.0], wt))
+        else:
+            yy = centres(-wl, ny + wl, dx)
+            zz = centres(-wl, nz + wl, dx)
+            g = np.meshgrid(yy, zz, indexing="ij")
+            yz = np.stack([g[0].ravel(), g[1].ravel()], axis=1)
+            inside = ((yz[:, 0] > 0) & (yz[:, 0] < Ly) & (yz[:, 1] > 0) & (yz[:, 1] < Lz))
+            yz = yz[~inside]
+            pts = np.concatenate([
+                np.stack([np.full(len(yz), xv), yz[:, 0], yz[:, 1]], axis=1)
+                for xv in xs_all])
+            wb = _empty(len(pts))
+            wb["x"] = pts
+            wb["type"][:] = wt
+            blocks.append(wb)
+    if cyl is not None:
+        xc, yc, D = cyl
+        pts = []
+        for k in range(wall_layers):
+            rk = 0.5 * D - (k + 0.5) * dx
+            if rk <= 0:
+                break
+            nk = max(1, int(round(2 * math.pi * rk / dx)))
+            th = 2 * math.pi * (np.arange(nk) + 0.5) / nk
+            pts.append(np.stack([xc + rk * np.cos(th), yc + rk * np.sin(th),
+                                 np.zeros(nk)], axis=1))
+        pts = np.concatenate(pts)
+        cb = _empty(len(pts))
+        cb["x"] = pts
+        cb["type"][:] = BODY
+        blocks.append(cb)
+    s = _finish(blocks)
+    if noise:
+        prm["flags"] |= FLAG_NOISE
+        prm["noise_amp"] = noise
+        prm["noise_seed"] = noise_seed
+    return prm, s
+
+
+# ---------------------------------------------------------------- workloads
+
+def config(name, small=False):
+    """The five workloads. small=True gives a reduced-size variant with the
+    same structure (layers, boundary kinds, pulse/cylinder) for parity tests."""
+    if name == "C1":
+        prm, s = taylor_green_box(n_side=40, L=1.0, U=1.0, nu=0.01)
+        prm.update(name="C1 tgv 40x40", steps=100)
+        return prm, s
+    if name == "C2":
+        if small:
+            prm, s = channel(Lx=0.4, Ly=0.1, dx=0.01, pulse_amp=0.1, pulse_x=0.2,
+                             pulse_w=0.02, name="C2-small channel")
+        else:
+            prm, s = channel(Lx=4.0, Ly=1.0, dx=0.01, pulse_amp=0.1, pulse_x=2.0,
+                             pulse_w=0.1, name="C2 channel 4x1 dx0.01 pulse")
+        prm["steps"] = 2000
+        return prm, s
+    if name == "C3":
+        if small:
+            prm, s = channel(Lx=1.2, Ly=0.64, dx=0.04 / 2.5, cyl=(0.3, 0.32, 0.16),
+                             side_walls="slip", nu=0.008, name="C3-small cylinder")
+        else:
+            D = 2.0
+            prm, s = channel(Lx=60.0, Ly=32.0, dx=D / 50, cyl=(5 * D, 16.0, D),
+                             side_walls="slip", nu=1.0 * D / 200.0,
+                             name="C3 cylinder Re200 60x32 dx0.04")
+        prm["steps"] = 5000
+        return prm, s
+    if name == "C4":
+        if small:
+            prm, s = channel(Lx=0.5, Ly=0.2, dx=0.01, cyl=(0.2, 0.1, 0.06),
+                             name="C4-small channel+cylinder")
+        else:
+            prm, s = channel(Lx=4.0, Ly=1.0, dx=0.01, cyl=(1.0, 0.5, 0.2),
+                             nu=1.0 * 0.2 / 20.0, name="C4 channel+cylinder D0.2 Re20")
+        prm["steps"] = 500
+        return prm, s
+    if name == "C5":
+        if small:
+            prm, s = channel(Lx=0.16, Ly=0.08, Lz=0.08, dx=0.01, side_walls="noslip",
+                             noise=0.01, name="C5-small duct")
+        else:
+            prm, s = channel(Lx=4.0, Ly=1.0, Lz=1.0, dx=0.01, side_walls="noslip",
+                             noise=0.01, name="C5 duct 4x1x1 dx0.01")
+        prm["steps"] = 500
+        return prm, s
+    raise KeyError(name)
+
+
+def jitter(prm, s, amp, seed, types=(FLUID,)):
+    """Seeded uniform jitter of +-amp*dx on positions of the given types."""
+    rng = np.random.default_rng(seed)
+    s = {k: v.copy() for k, v in s.items()}
+    m = np.isin(s["type"], types)
+    d = prm["dim"]
+    s["x"][m, :d] += amp * prm["dx"] * rng.uniform(-1, 1, size=(m.sum(), d))
+    return s
+
+
+def random_fields(prm, s, seed, p_range=(-0.5, 0.5), u_range=(0.0, 1.5), ut_dev=0.05):
+    """Seeded random p, u and transport-velocity perturbation on fluid particles,
+    and random averages/previous characteristic values on every particle."""
+    rng = np.random.default_rng(seed)
+    s = {k: v.copy() for k, v in s.items()}
+    n, d = len(s["p"]), prm["dim"]
+    fl = s["type"] == FLUID
+    s["p"][fl] = rng.uniform(*p_range, size=fl.sum())
+    s["u"][fl, :d] = rng.uniform(*u_range, size=(fl.sum(), d))
+    s["ut"][fl, :d] = s["u"][fl, :d] + rng.uniform(-ut_dev, ut_dev, size=(fl.sum(), d))
+    s["avg"][:, :d] = rng.uniform(*u_range, size=(n, d))
+    s["avg"][:, 3] = rng.uniform(*p_range, size=n)
+    s["jprev"][:] = rng.uniform(-0.5, 0.5, size=(n, 3))
+    s["red_prev"][:] = (rng.uniform(size=n) < 0.5).astype(np.uint8)
+    return s
+
+
+def snapshot_copy(s):
+    return {k: np.array(v, copy=True) for k, v in s.items()}
