@@ -1,0 +1,223 @@
+#!/usr/bin/env python3
+"""Benchmark of the EDAC-SPH wind-tunnel hot path on one MI355X.
+
+A step is one explicit-midpoint RK2 step of the whole path (bin + Morton
+sort, neighbour table, density, boundary values, force pass, stage updates,
+time-average/transfer/re-spawn bookkeeping, drag) on the 2D channel workload
+(4 x 1, dx = 0.01, 40,000 fluid particles, 5-layer inlet and hybrid outlet,
+Gaussian pressure pulse of amplitude 0.01 rho0 c0 U at x = 2, width 0.1).
+
+Metric: pair-interactions/s = (fluid-neighbour pairs per right-hand side) x 2
+right-hand sides per step x steps / time, with the state resident in HBM.
+Prints one JSON line. The roofline object reports the force kernel (the
+dominant kernel) timed alone with HIP events on the library's stream; the
+cpu_baseline object times the FP64 CPU oracle on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "pair-interactions/s of EDAC RHS (FP64 vs FP32 vs adjoint) + HBM roofline %"
+WORKLOADS = {
+    "C2": "2D channel 4x1 dx=0.01, 40k fluid + 5-layer inlet + 5-layer hybrid outlet, "
+          "Gaussian pulse A=0.01 rho0 c0 U at x=2 w=0.1, Wendland C2 h=dx",
+    "C1": "2D periodic box 1x1, 40x40 Taylor-Green, Wendland C2 h=dx",
+    "C3": "2D cylinder D=2 Re=200 in 60x32, dx=D/50, 3-layer slip walls",
+    "C4": "2D channel 4x1 dx=0.01 with D=0.2 cylinder, Re=20",
+    "C5": "3D duct 4x1x1 dx=0.01, no-slip walls, inlet noise 1%",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def force_bytes(sim, counts, types, prec_bytes):
+    """Algorithmic HBM bytes of one force-pass launch: every array the kernel
+    needs read once and every output written once (neighbour gathers that hit
+    cache are not counted)."""
+    import numpy as np
+    D = sim.dim
+    n = len(types)
+    fb = (types == 0) | (types == 5)
+    nfb = int(fb.sum())
+    nnz = int(counts[fb].sum())
+    rd = n * 1 + nfb * (8 * D + 2 * prec_bytes * D + 3 * prec_bytes + 4) + 4 * nnz
+    wr = n * (2 * prec_bytes * D + 2 * prec_bytes) + int((types == 5).sum()) * 8 * D
+    return rd + wr, dict(read=rd, write=wr, n=n, n_fluid_or_body=nfb, nnz=nnz)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("pairs.hip", "sph_dev.h"):
+        with open(os.path.join(ROOT, "paper_1907_04034_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(workload, prec):
+    """HBM bytes per force launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"k_force_{workload}_{prec}_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    h = re.search(r"source_sha:\s*([0-9a-f]+)", txt)
+    if not m or not h or h.group(1) != source_hash():
+        return None
+    return float(m.group(1))
+
+
+def cpu_baseline(prm, s, budget_s):
+    """The FP64 oracle as it stands, on the host's cores, over the first steps
+    of the same workload until about budget_s seconds of stepping."""
+    import numpy as np
+    from oracle import oracle as O
+    O.build(force=False)
+    o = O.Oracle(prm, s)
+    steps, pairs, elapsed = 0, 0, 0.0
+    while elapsed < budget_s and steps < prm.get("steps", 2000):
+        row, _ = o.neighbors()
+        fl = o.state()["type"] == 0
+        p_rhs = int((np.diff(row)[fl] - 1).sum())
+        t1 = time.perf_counter()
+        o.step(10)
+        elapsed += time.perf_counter() - t1
+        steps += 10
+        pairs += 2 * 10 * p_rhs
+    return dict(value=pairs / elapsed, unit="pair-interactions/s", cores=O.num_threads(),
+                kind="oracle",
+                sample=f"FP64 oracle, first {steps} RK2 steps ({2 * steps} RHS) of the same "
+                       f"workload, {elapsed:.1f} s of stepping")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--force-reps", type=int, default=100)
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (for counter scaling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1"}))
+        log("bench.py: multi-GPU runs are not part of this build (one GPU only)")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1907_04034_amd import binding as B
+    from paper_1907_04034_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    prm, s = I.config(args.config)
+    log(f"bench: {prm['name']} n={len(s['p'])} prec={args.precision}")
+    sim = B.Simulation(prm, s, prec=args.precision)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"bench: copy calibration {nb} bytes x3 done")
+
+    sim.step(args.warmup)
+    bits = sim.poll_error()
+    if bits:
+        raise SystemExit(f"device error bits after warmup: {bits}")
+    torch.cuda.synchronize()
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    gpu_ms = e0.elapsed_time(e1)
+    bits = sim.poll_error()
+    if bits:
+        raise SystemExit(f"device error bits in timed region: {bits}")
+    log(f"bench: {args.steps} steps in {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms wall")
+
+    # pairs per right-hand side, from the neighbour table of the last stage
+    cnt, _ = sim.neighbor_table()
+    st = sim.state()
+    types = st["type"]
+    fl = types == 0
+    p_rhs = int((cnt[fl] - 1).sum())
+    t_step = max(gpu_ms, wall * 1e3) / args.steps
+    value = 2 * p_rhs / (t_step * 1e-3)
+
+    # dominant kernel alone: fresh bin/neighbours/rhs, then force launches
+    sim.bin()
+    sim.neighbors()
+    sim.rhs()
+    cnt, _ = sim.neighbor_table()
+    types = sim.state()["type"]
+    torch.cuda.synchronize()
+    reps = args.force_reps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    for a_, b_ in evs:
+        a_.record(stream)
+        sim.force(reduce_drag=False)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    f_us = 1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs]))
+    prec_bytes = 8 if args.precision == "fp64" else 4
+    fbytes, fdetail = force_bytes(sim, cnt, types, prec_bytes)
+    achieved = fbytes / (f_us * 1e-6) / 1e9
+    traffic = traffic_from_profile(args.config, args.precision)
+    log(f"bench: k_force {f_us:.2f} us/launch, {fbytes / 1e6:.2f} MB algorithmic, "
+        f"{achieved:.1f} GB/s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 pairs / f64 positions",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config], "config": args.config,
+                   "particles": int(len(s["p"])), "pairs_per_rhs": p_rhs,
+                   "rhs_per_step": 2, "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": "k_force", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic, "algorithmic_bytes_per_launch": fbytes,
+                     "launch_us": f_us, "source_sha": source_hash()},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the CPU oracle sample")
+        out["cpu_baseline"] = cpu_baseline(prm, s, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,208 @@
+/*
+ * sph.h -- C ABI of the MI355X (gfx950) EDAC-SPH wind-tunnel hot path.
+ *
+ * Method: Negi, Ramachandran & Haftu, "An improved non-reflecting outlet
+ * boundary condition for weakly-compressible SPH" (arXiv 1907.04034).
+ * Sec. 2 gives the EDAC-TVF scheme (summation density, number-density
+ * momentum equation with the neighbour-average pressure, EDAC pressure rate,
+ * transport velocity); Sec. 3.3 the characteristic variables and their
+ * Shepard extrapolation with the red/blue fallback; Sec. 3.4 the hybrid
+ * outlet (time-averaged references, acoustic-intensity gate, composition
+ * f_o = f_ac + f_avg, x-only advection, particle transfer); Sec. 4.6 the
+ * force on a solid body.
+ *
+ * Conventions for every entry point:
+ *  - All array pointers in sph_state, sph_nlist and sph_derived are DEVICE
+ *    pointers owned by the caller; the library never allocates or frees them.
+ *    Per-particle arrays are component-major: component k of particle i is
+ *    at [k * cap + i]. The workspace is caller-owned device memory of at
+ *    least sph_workspace_size() bytes, zero-filled before first use.
+ *  - `stream` is a hipStream_t (0 = the null stream). Every call only
+ *    enqueues work on it and returns; nothing synchronises except
+ *    sph_poll_error() and sph_live_count().
+ *  - Argument errors are detected on the host before any launch and return a
+ *    negative sph_status; sph_last_error() then gives a message. Conditions
+ *    found on the device (capacity, non-finite values, skin violation) set
+ *    bits of the device error word, read with sph_poll_error().
+ *  - The first *st->n rows of every state array are the live particles. After
+ *    sph_bin / sph_step they are sorted by Morton cell key, ties by id.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_EINVAL = -1,       /* bad argument, detected on the host */
+    SPH_ECAPACITY = -2,    /* a size exceeds a capacity, detected on the host */
+    SPH_EHIP = -5,         /* a HIP runtime call failed */
+    SPH_EUNSUPPORTED = -6  /* valid but not provided (e.g. dim 1) */
+} sph_status;
+
+typedef enum { SPH_FP64 = 0, SPH_FP32 = 1 } sph_precision;
+
+/* particle kinds (byte per particle) */
+enum {
+    SPH_FLUID = 0, SPH_INLET = 1, SPH_OUTLET = 2,
+    SPH_WALL_SLIP = 3, SPH_WALL_NOSLIP = 4, SPH_BODY = 5, /* BODY: no-slip, drag */
+    SPH_DEAD = 255
+};
+
+/* sph_params.flags */
+enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4 };
+
+/* device error-word bits */
+enum {
+    SPH_ERR_NBR_OVERFLOW = 1u,  /* a particle has more than maxnb neighbours */
+    SPH_ERR_CAPACITY = 2u,      /* a re-spawn found no free row below cap */
+    SPH_ERR_NONFINITE = 4u,     /* a non-finite value after a stage update */
+    SPH_ERR_SKIN = 8u,          /* a particle moved more than the cell skin in a step */
+    SPH_ERR_ESCAPE = 16u,       /* a particle left the box along a closed axis */
+    SPH_ERR_CELL_RANGE = 32u    /* corrupt cell/neighbour index found (input misuse) */
+};
+
+/* Host parameter block (copied by value). Symbols follow Sec. 2 of the paper:
+ * h smoothing length (support 2h of the Wendland C2 kernel), c the artificial
+ * speed of sound c_s, nu the kinematic viscosity, alpha the EDAC damping
+ * coefficient (nu_edac = alpha h c / 8), eta the 0.01 regulariser, pb the
+ * background pressure of the transport velocity, U the inlet reference speed
+ * (also sets the acoustic-intensity gate |p| > rho0 U^2 / 2). */
+typedef struct sph_params {
+    int32_t dim;          /* 2 or 3 */
+    int32_t n_avg;        /* time-average window, must be 6 */
+    int32_t flags;        /* SPH_FLAG_* */
+    int32_t periodic[3];  /* 1 = periodic axis */
+    double h, dx, rho0, c, U, nu, alpha, eta, dt, pb;
+    double lo[3], hi[3];  /* box; periodic axes have length hi - lo */
+    double x_inlet;       /* inlet | fluid interface */
+    double x_outlet;      /* fluid | outlet interface */
+    double x_outlet_end;  /* outlet particles beyond are deleted */
+    double inlet_len;     /* re-spawn offset of inlet particles */
+    double noise_amp;     /* relative inlet velocity noise (SPH_FLAG_NOISE) */
+    uint64_t noise_seed;
+} sph_params;
+
+/* Particle state. Element type of u, ut, p is double for SPH_FP64 and float
+ * for SPH_FP32; every other array has the type given. ring holds the last
+ * n_avg accepted (u_1..u_dim, p) samples as [n_avg][dim+1][cap]; avg their
+ * mean as [dim+1][cap]; head the next slot to overwrite. */
+typedef struct sph_state {
+    int64_t cap;          /* rows in every array */
+    int32_t prec;         /* sph_precision */
+    int32_t dim;          /* must equal sph_params.dim */
+    int64_t *n;           /* device scalar: live particle count */
+    double *x;            /* [3][cap] positions (always FP64) */
+    void *u, *ut;         /* [3][cap] momentum and transport velocity */
+    void *p;              /* [cap] pressure */
+    double *uin;          /* [3][cap] prescribed inlet velocity */
+    double *ring;         /* [n_avg][dim+1][cap] */
+    uint8_t *head;        /* [cap] */
+    double *avg;          /* [dim+1][cap] */
+    double *jprev;        /* [3][cap] characteristic variables of the last step */
+    uint8_t *red_prev;    /* [cap] fluid support at the last step */
+    uint8_t *type;        /* [cap] SPH_FLUID ... */
+    int64_t *id;          /* [cap] */
+} sph_state;
+
+/* Neighbour table: neighbours of particle i (itself included) are
+ * nbr[k * cap + i] for k < count[i], in stencil-then-cell order. */
+typedef struct sph_nlist {
+    int32_t maxnb;        /* rows of nbr */
+    int32_t *count;       /* [cap] */
+    int32_t *nbr;         /* [maxnb][cap] */
+} sph_nlist;
+
+/* Results of one right-hand-side evaluation. rho, vol, pavg, a, b, pdot have
+ * the state's element type. a, b, pdot are written for fluid particles (zero
+ * elsewhere); force only for body particles (other rows are left as they
+ * are); drag is the body total. */
+typedef struct sph_derived {
+    void *rho, *vol, *pavg;   /* [cap] */
+    void *a, *b;              /* [3][cap] momentum rate and background term */
+    void *pdot;               /* [cap] */
+    double *jcur;             /* [3][cap] characteristic variables this stage */
+    uint8_t *red;             /* [cap] */
+    double *force;            /* [3][cap] per body particle */
+    double *drag;             /* [3] */
+} sph_derived;
+
+/* Bytes of workspace needed for capacity `cap` (cell grid, sort buffers,
+ * start-of-step copy, scan scratch, error word). */
+int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
+
+/* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D). */
+int32_t sph_default_maxnb(const sph_params *prm);
+
+/* Cell-linked list (no paper passage; the neighbour structure is the
+ * implementation's): cell = floor((x - lo) / cs) with cells at least 2.2h
+ * wide, Morton key, counting sort with ties ordered by id, then gathers
+ * every state array into *alt and exchanges the buffers of *st and *alt.
+ * Dead particles are dropped and *st->n updated. */
+int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws,
+            size_t ws_bytes, void *stream);
+
+/* Neighbour table at the current positions from the cells of the last
+ * sph_bin on this workspace: j is a neighbour of i iff |r_i - r_j|^2 < (2h)^2
+ * in FP64 without fused multiply-add, minimum image on periodic axes. */
+int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* Summation density, Sec. 2 eq:summation-density, and the number-density
+ * volume V_i = 1 / sum_j W_ij, for every particle. */
+int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+                sph_derived *out, void *ws, size_t ws_bytes, void *stream);
+
+/* Boundary values from the fluid (needs sph_density first): wall ghost
+ * pressure/velocity by Shepard averaging; outlet particles by the hybrid rule
+ * of Sec. 3.4 (J1, J2 of eq:characteristic-vars with time-average references,
+ * Shepard eq:shepard, J3 = 0, previous-step red average eq:average_old,
+ * f_o = f_ac + f_avg eq:acou); inlet particles keep their prescribed velocity
+ * and take p from the Shepard-extrapolated J3. Computed in FP64 for both
+ * precisions. Writes u, ut, p of non-fluid particles and jcur, red. */
+int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist *nl,
+                           sph_derived *out, void *ws, size_t ws_bytes, void *stream);
+
+/* One right-hand side: sph_density, sph_outlet_extrapolate, then the force
+ * pass of Sec. 2 (eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum, eq:p-edac and
+ * the background term of eq:transport-vel) for fluid particles and the body
+ * force of Sec. 4.6 eq:tvf-momentum_solid, reduced into out->drag. */
+int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_derived *out,
+            void *ws, size_t ws_bytes, void *stream);
+
+/* The force pass alone (needs sph_density and sph_outlet_extrapolate on the
+ * same neighbour table first): eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
+ * eq:p-edac and the background term of eq:transport-vel for fluid particles;
+ * eq:tvf-momentum_solid for body particles, reduced into out->drag (skipped
+ * when out->drag is NULL, so that the call is exactly one kernel launch). */
+int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+              sph_derived *out, void *ws, size_t ws_bytes, void *stream);
+
+/* nsteps explicit-midpoint RK2 steps: bin, stage 1, half update, stage 2,
+ * full update, then the end-of-step bookkeeping of Sec. 3.4 (gated
+ * time-average push, fluid->outlet, outlet deletion, inlet->fluid with
+ * re-spawn). drag_hist (device, [nsteps][3], may be NULL) receives the body
+ * force of stage 1 of every step. */
+int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+             sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
+             size_t ws_bytes, void *stream);
+
+/* Synchronises `stream`, returns the accumulated device error bits in *bits
+ * and clears them. */
+int sph_poll_error(void *ws, size_t ws_bytes, uint32_t *bits, void *stream);
+
+/* Synchronises `stream` and returns *st->n. */
+int sph_live_count(const sph_state *st, int64_t *n, void *stream);
+
+/* Thread-local message of the last non-OK return. */
+const char *sph_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SPH_H */

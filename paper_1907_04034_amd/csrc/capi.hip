@@ -1,0 +1,473 @@
+// capi.hip -- the extern "C" boundary of libsph: host-side validation,
+// workspace carving and the launch sequences of every entry point.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "sph_launch.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int check_hip(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(SPH_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return SPH_OK;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+int ceil_log2(int v)
+{
+    int b = 0;
+    while ((1 << b) < v) ++b;
+    return b;
+}
+
+}  // namespace
+
+namespace sph {
+
+// Validates the parameter block and derives the kernel constants.
+static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *k)
+{
+    if (!p) return fail(SPH_EINVAL, "params is NULL");
+    if (p->dim == 1) return fail(SPH_EUNSUPPORTED, "dim 1 is not provided");
+    if (p->dim != 2 && p->dim != 3) return fail(SPH_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
+    if (p->n_avg != kNavg) return fail(SPH_EINVAL, "n_avg must be %d (got %d)", kNavg, p->n_avg);
+    if (!(p->h > 0) || !(p->dx > 0) || !(p->rho0 > 0) || !(p->c > 0) || !(p->dt > 0) ||
+        !(p->eta > 0) || !(p->nu >= 0) || !(p->pb >= 0) || !(p->alpha >= 0) || !(p->U >= 0))
+        return fail(SPH_EINVAL, "h, dx, rho0, c, dt, eta must be > 0 and nu, pb, alpha, U >= 0");
+    if (p->dt * (p->c + p->U) > 0.5 * p->h)
+        return fail(SPH_EINVAL, "dt = %g exceeds the acoustic bound 0.5 h / (c + U) = %g", p->dt,
+                    0.5 * p->h / (p->c + p->U));
+    if (cap < 1 || cap > INT32_MAX) return fail(SPH_EINVAL, "cap must be in [1, 2^31)");
+    if (prec != SPH_FP64 && prec != SPH_FP32) return fail(SPH_EINVAL, "bad precision %d", prec);
+    std::memset(k, 0, sizeof *k);
+    k->dim = p->dim;
+    k->flags = p->flags;
+    k->prec = prec;
+    k->maxnb = maxnb;
+    k->cap = cap;
+    k->h = p->h;
+    const double cell_min = 2.0 * p->h * (1.0 + kSkin);
+    int total_bits = 0;
+    double min_slack = 1e300;
+    for (int d = 0; d < 3; ++d) {
+        k->periodic[d] = d < p->dim ? (p->periodic[d] != 0) : 0;
+        if (d >= p->dim) {
+            k->nc[d] = 1;
+            k->L[d] = 1.0;
+            k->cs[d] = 1.0;
+            k->inv_cs[d] = 1.0;
+            k->halfL[d] = 0.5;
+            continue;
+        }
+        double L = p->hi[d] - p->lo[d];
+        if (!(L > 0)) return fail(SPH_EINVAL, "box axis %d has length %g", d, L);
+        int nc = int(std::floor(L / cell_min));
+        if (nc < 1) nc = 1;
+        if (k->periodic[d] && nc < 3)
+            return fail(SPH_EINVAL, "periodic axis %d needs at least 3 cells of 2.2h", d);
+        const int max_nc = p->dim == 2 ? 65535 : 1023;
+        if (nc > max_nc) return fail(SPH_EINVAL, "axis %d has %d cells (max %d)", d, nc, max_nc);
+        k->nc[d] = nc;
+        k->bits[d] = ceil_log2(nc);
+        total_bits += k->bits[d];
+        k->lo[d] = p->lo[d];
+        k->L[d] = L;
+        k->halfL[d] = 0.5 * L;
+        k->cs[d] = L / nc;
+        k->inv_cs[d] = nc / L;
+        min_slack = std::fmin(min_slack, k->cs[d] - 2.0 * p->h);
+    }
+    if (total_bits > 30) return fail(SPH_EINVAL, "cell grid too large (%d key bits)", total_bits);
+    k->nkeys = uint32_t(1) << total_bits;
+    {
+        double s = 2.0 * p->h;
+        k->sup2 = s * s;
+    }
+    const double pi = 3.14159265358979323846;
+    k->wnorm = p->dim == 2 ? 7.0 / (4.0 * pi * p->h * p->h)
+                           : 21.0 / (16.0 * pi * p->h * p->h * p->h);
+    k->gnorm = -5.0 * k->wnorm / (p->h * p->h);
+    k->mass = p->dim == 2 ? p->rho0 * p->dx * p->dx : p->rho0 * p->dx * p->dx * p->dx;
+    k->rho0 = p->rho0;
+    k->c = p->c;
+    k->c2 = p->c * p->c;
+    k->nu = p->nu;
+    const double nu_edac = p->alpha * p->h * p->c / 8.0;  // Sec. 2 eq:edac-nu
+    k->nu_damp = (p->flags & SPH_FLAG_DAMP_NU) ? p->nu : nu_edac;
+    k->eta_h2 = p->eta * p->h * p->h;
+    k->pb = p->pb;
+    k->dt = p->dt;
+    k->hdt = 0.5 * p->dt;
+    k->disp_max = 0.999 * 0.5 * min_slack;
+    k->x_inlet = p->x_inlet;
+    k->x_outlet = p->x_outlet;
+    k->x_outlet_end = p->x_outlet_end;
+    k->inlet_len = p->inlet_len;
+    k->pgate = 0.5 * p->rho0 * p->U * p->U;
+    k->U = p->U;
+    k->noise_amp = p->noise_amp;
+    k->noise_seed = p->noise_seed;
+    k->hf = float(p->h);
+    k->inv_hf = float(1.0 / p->h);
+    k->sup2f = float(k->sup2);
+    k->wnormf = float(k->wnorm);
+    k->gnormf = float(k->gnorm);
+    k->massf = float(k->mass);
+    k->c2f = float(k->c2);
+    k->nuf = float(k->nu);
+    k->nu_dampf = float(k->nu_damp);
+    k->eta_h2f = float(k->eta_h2);
+    k->pbf = float(k->pb);
+    return SPH_OK;
+}
+
+static WsLayout layout(const Dev &k)
+{
+    WsLayout w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    const size_t C = size_t(k.cap);
+    w.err = take(sizeof(uint32_t));
+    w.nspawn = take(sizeof(int32_t));
+    w.spread = take(sizeof(uint32_t) * 3 * kSpreadStride);
+    w.cell_start = take(sizeof(int32_t) * (size_t(k.nkeys) + 2));
+    w.cursor = take(sizeof(int32_t) * (size_t(k.nkeys) + 1));
+    w.keys = take(sizeof(uint32_t) * C);
+    w.tmp = take(sizeof(int32_t) * C);
+    w.cpos = take(sizeof(uint32_t) * C);
+    w.cpos_s = take(sizeof(uint32_t) * C);
+    w.x0 = take(sizeof(double) * 3 * C);
+    w.u0 = take(sizeof(double) * 3 * C);
+    w.p0 = take(sizeof(double) * C);
+    w.blocksum = take(sizeof(int32_t) * size_t(scan_blocksum_len(int64_t(k.nkeys) + 2)));
+    w.dragpart = take(sizeof(double) * 3 * size_t(nblocks(k.cap)));
+    w.total = off;
+    return w;
+}
+
+template <typename P>
+static P *at(void *ws, size_t off)
+{
+    return reinterpret_cast<P *>(static_cast<char *>(ws) + off);
+}
+
+static int check_state(const sph_state *s, const sph_params *p, const char *name)
+{
+    if (!s) return fail(SPH_EINVAL, "%s is NULL", name);
+    if (s->dim != p->dim) return fail(SPH_EINVAL, "%s->dim %d != params dim %d", name, s->dim, p->dim);
+    if (s->prec != SPH_FP64 && s->prec != SPH_FP32)
+        return fail(SPH_EINVAL, "%s->prec must be SPH_FP64 or SPH_FP32", name);
+    if (s->cap < 1 || s->cap > INT32_MAX) return fail(SPH_EINVAL, "%s->cap out of range", name);
+    if (!s->n || !s->x || !s->u || !s->ut || !s->p || !s->uin || !s->ring || !s->head ||
+        !s->avg || !s->jprev || !s->red_prev || !s->type || !s->id)
+        return fail(SPH_EINVAL, "%s has a NULL array", name);
+    return SPH_OK;
+}
+
+static int check_nlist(const sph_nlist *nl)
+{
+    if (!nl || !nl->count || !nl->nbr) return fail(SPH_EINVAL, "neighbour table has NULL arrays");
+    if (nl->maxnb < 1 || nl->maxnb > 1024) return fail(SPH_EINVAL, "maxnb out of [1, 1024]");
+    return SPH_OK;
+}
+
+static int check_derived(const sph_derived *o, bool need_drag = true)
+{
+    if (!o || !o->rho || !o->vol || !o->pavg || !o->a || !o->b || !o->pdot || !o->jcur ||
+        !o->red || !o->force || (need_drag && !o->drag))
+        return fail(SPH_EINVAL, "derived output has a NULL array");
+    return SPH_OK;
+}
+
+static DevState dev_state(const sph_state *s)
+{
+    DevState d;
+    d.n = s->n;
+    d.x = s->x;
+    d.u = s->u;
+    d.ut = s->ut;
+    d.p = s->p;
+    d.uin = s->uin;
+    d.ring = s->ring;
+    d.avg = s->avg;
+    d.jprev = s->jprev;
+    d.head = s->head;
+    d.red_prev = s->red_prev;
+    d.type = s->type;
+    d.id = s->id;
+    return d;
+}
+
+static DevDerived dev_derived(const sph_derived *o)
+{
+    DevDerived d;
+    d.rho = o->rho;
+    d.vol = o->vol;
+    d.pavg = o->pavg;
+    d.a = o->a;
+    d.b = o->b;
+    d.pdot = o->pdot;
+    d.jcur = o->jcur;
+    d.force = o->force;
+    d.drag = o->drag;
+    d.red = o->red;
+    return d;
+}
+
+static DevNlist dev_nlist(const sph_nlist *nl)
+{
+    DevNlist d;
+    d.maxnb = nl->maxnb;
+    d.count = nl->count;
+    d.nbr = nl->nbr;
+    return d;
+}
+
+struct Ctx {
+    Dev k;
+    WsLayout w;
+    void *ws;
+    hipStream_t s;
+    uint32_t *err() const { return at<uint32_t>(ws, w.err); }
+};
+
+static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws,
+                   size_t ws_bytes, void *stream, Ctx *c)
+{
+    int rc = check_state(st, p, "state");
+    if (rc) return rc;
+    rc = make_dev(p, st->cap, st->prec, maxnb, &c->k);
+    if (rc) return rc;
+    c->w = layout(c->k);
+    if (!ws) return fail(SPH_EINVAL, "workspace is NULL");
+    if (ws_bytes < c->w.total)
+        return fail(SPH_ECAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, c->w.total);
+    c->ws = ws;
+    c->s = static_cast<hipStream_t>(stream);
+    return SPH_OK;
+}
+
+static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
+{
+    const Dev &k = c.k;
+    int32_t *cell_start = at<int32_t>(c.ws, c.w.cell_start);
+    int32_t *cursor = at<int32_t>(c.ws, c.w.cursor);
+    launch_fill_i32(cell_start, int64_t(k.nkeys) + 2, 0, c.s);
+    launch_fill_i32(cursor, int64_t(k.nkeys) + 1, 0, c.s);
+    DevState a = dev_state(st), b = dev_state(alt);
+    b.n = a.n;
+    launch_keys(k, a, at<uint32_t>(c.ws, c.w.spread), at<uint32_t>(c.ws, c.w.keys),
+                at<uint32_t>(c.ws, c.w.cpos), cell_start, c.err(), c.s);
+    launch_scan(cell_start, int64_t(k.nkeys) + 2, at<int32_t>(c.ws, c.w.blocksum), c.s);
+    launch_scatter(k, a, at<uint32_t>(c.ws, c.w.keys), cell_start, cursor,
+                   at<int32_t>(c.ws, c.w.tmp), c.s);
+    launch_cellsort(k, a, cell_start, at<int32_t>(c.ws, c.w.tmp), c.s);
+    launch_gather(k, a, b, at<int32_t>(c.ws, c.w.tmp), cell_start, at<uint32_t>(c.ws, c.w.cpos),
+                  at<uint32_t>(c.ws, c.w.cpos_s), at<double>(c.ws, c.w.x0),
+                  at<void>(c.ws, c.w.u0), at<void>(c.ws, c.w.p0), c.s);
+    launch_set_count(k, a, cell_start, c.s);
+    if (alt->n != st->n) launch_set_count(k, dev_state(alt), cell_start, c.s);
+    // exchange the buffers: *st now describes the sorted particles
+    sph_state tmp = *st;
+    int64_t *n_st = st->n, *n_alt = alt->n;
+    *st = *alt;
+    *alt = tmp;
+    st->n = n_st;
+    alt->n = n_alt;
+}
+
+static void do_neighbors(Ctx &c, const sph_state *st, const sph_nlist *nl)
+{
+    launch_neighbors(c.k, dev_state(st), dev_nlist(nl), at<uint32_t>(c.ws, c.w.spread),
+                     at<int32_t>(c.ws, c.w.cell_start), at<uint32_t>(c.ws, c.w.cpos_s), c.err(),
+                     c.s);
+}
+
+static void do_rhs(Ctx &c, const sph_state *st, const sph_nlist *nl, const sph_derived *o,
+                   double *hist)
+{
+    DevState s = dev_state(st);
+    DevNlist n = dev_nlist(nl);
+    DevDerived d = dev_derived(o);
+    launch_density(c.k, s, n, d, c.err(), c.s);
+    launch_boundary(c.k, s, n, d, c.err(), c.s);
+    double *part = at<double>(c.ws, c.w.dragpart);
+    launch_force(c.k, s, n, d, part, c.err(), c.s);
+    launch_drag_final(c.k, part, o->drag, hist, c.s);
+}
+
+}  // namespace sph
+
+using namespace sph;
+
+extern "C" {
+
+const char *sph_last_error(void) { return g_err.c_str(); }
+
+int32_t sph_default_maxnb(const sph_params *prm)
+{
+    return prm && prm->dim == 3 ? 80 : 32;
+}
+
+int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes)
+{
+    if (!bytes) return fail(SPH_EINVAL, "bytes is NULL");
+    Dev k;
+    int rc = make_dev(prm, cap, SPH_FP64, 1, &k);
+    if (rc) return rc;
+    *bytes = layout(k).total;
+    return SPH_OK;
+}
+
+int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws, size_t ws_bytes,
+            void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, 1, ws, ws_bytes, stream, &c);
+    if (rc) return rc;
+    rc = check_state(alt, prm, "alt");
+    if (rc) return rc;
+    if (alt->cap != st->cap || alt->prec != st->prec)
+        return fail(SPH_EINVAL, "alt must match state in cap and precision");
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    do_bin(c, st, alt);
+    return check_hip("sph_bin");
+}
+
+int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc) return rc;
+    rc = check_nlist(nl);
+    if (rc) return rc;
+    do_neighbors(c, st, nl);
+    return check_hip("sph_neighbors");
+}
+
+int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+                sph_derived *out, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
+    launch_density(c.k, dev_state(st), dev_nlist(nl), dev_derived(out), c.err(), c.s);
+    return check_hip("sph_density");
+}
+
+int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist *nl,
+                           sph_derived *out, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
+    launch_boundary(c.k, dev_state(st), dev_nlist(nl), dev_derived(out), c.err(), c.s);
+    return check_hip("sph_outlet_extrapolate");
+}
+
+int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_derived *out,
+            void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
+    do_rhs(c, st, nl, out, nullptr);
+    return check_hip("sph_rhs");
+}
+
+int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+              sph_derived *out, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
+    const bool reduce = out->drag != nullptr;
+    double *part = at<double>(c.ws, c.w.dragpart);
+    launch_force(c.k, dev_state(st), dev_nlist(nl), dev_derived(out), part, c.err(), c.s);
+    if (reduce) launch_drag_final(c.k, part, out->drag, nullptr, c.s);
+    return check_hip("sph_force");
+}
+
+int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+             sph_derived *out, int32_t nsteps, double *drag_hist, void *ws, size_t ws_bytes,
+             void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
+    rc = check_state(alt, prm, "alt");
+    if (rc) return rc;
+    if (alt->cap != st->cap || alt->prec != st->prec)
+        return fail(SPH_EINVAL, "alt must match state in cap and precision");
+    if (nsteps < 0) return fail(SPH_EINVAL, "nsteps < 0");
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    const Dev &k = c.k;
+    double *x0 = at<double>(ws, c.w.x0);
+    void *u0 = at<void>(ws, c.w.u0), *p0 = at<void>(ws, c.w.p0);
+    int32_t *nspawn = at<int32_t>(ws, c.w.nspawn);
+    for (int32_t s = 0; s < nsteps; ++s) {
+        do_bin(c, st, alt);  // also records x0, u0, p0
+        do_neighbors(c, st, nl);
+        do_rhs(c, st, nl, out, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr);
+        launch_stage(k, dev_state(st), dev_derived(out), x0, u0, p0, 0, c.err(), c.s);
+        do_neighbors(c, st, nl);
+        do_rhs(c, st, nl, out, nullptr);
+        launch_stage(k, dev_state(st), dev_derived(out), x0, u0, p0, 1, c.err(), c.s);
+        launch_end_of_step(k, dev_state(st), dev_derived(out), nspawn, c.err(), c.s);
+        launch_finish_spawn(k, dev_state(st), nspawn, c.s);
+    }
+    return check_hip("sph_step");
+}
+
+int sph_poll_error(void *ws, size_t ws_bytes, uint32_t *bits, void *stream)
+{
+    if (!ws || !bits) return fail(SPH_EINVAL, "NULL argument");
+    if (ws_bytes < 256) return fail(SPH_EINVAL, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    uint32_t *err = at<uint32_t>(ws, 0);
+    if (hipStreamSynchronize(s) != hipSuccess) return check_hip("sph_poll_error sync");
+    uint32_t h = 0;
+    if (hipMemcpy(&h, err, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
+        return check_hip("sph_poll_error copy");
+    launch_fill_i32(reinterpret_cast<int32_t *>(err), 1, 0, s);
+    if (hipStreamSynchronize(s) != hipSuccess) return check_hip("sph_poll_error clear");
+    *bits = h;
+    return check_hip("sph_poll_error");
+}
+
+int sph_live_count(const sph_state *st, int64_t *n, void *stream)
+{
+    if (!st || !st->n || !n) return fail(SPH_EINVAL, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(s) != hipSuccess) return check_hip("sph_live_count sync");
+    if (hipMemcpy(n, st->n, sizeof *n, hipMemcpyDeviceToHost) != hipSuccess)
+        return check_hip("sph_live_count copy");
+    return SPH_OK;
+}
+
+}  // extern "C"

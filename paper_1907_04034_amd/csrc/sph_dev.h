@@ -1,0 +1,162 @@
+// sph_dev.h -- device-side helpers shared by the gfx950 kernels of libsph.
+//
+// Everything here is wave64 / CDNA4 code. Per-particle arrays are
+// component-major ([comp][cap]) so that one wave reads 64 consecutive
+// elements of a component in one coalesced transaction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kBlock = 256;        // 4 waves of 64
+constexpr int kNavg = 6;           // time-average window (Sec. 3.4, eq:N)
+constexpr double kSkin = 0.1;      // cells are at least 2h (1 + kSkin) wide
+constexpr int64_t kIdGeneration = int64_t(1) << 40;
+
+// Constants derived once per call on the host and passed by value.
+struct Dev {
+    int dim, flags, maxnb, prec;
+    int periodic[3];
+    int nc[3];          // cells per axis
+    int bits[3];        // Morton bits per axis
+    uint32_t nkeys;     // 2^(sum bits); key nkeys marks a dead particle
+    int64_t cap;
+    double lo[3], L[3], halfL[3], cs[3], inv_cs[3];
+    double h, sup2, wnorm, gnorm, mass, rho0, c, c2, nu, nu_damp, eta_h2, pb;
+    double dt, hdt, disp_max;
+    double x_inlet, x_outlet, x_outlet_end, inlet_len, pgate, U, noise_amp;
+    uint64_t noise_seed;
+    float hf, inv_hf, sup2f, wnormf, gnormf, massf, c2f, nuf, nu_dampf, eta_h2f, pbf;
+};
+
+// Device pointers of one state (element type of the real fields depends on
+// the precision).
+struct DevState {
+    int64_t *n;
+    double *x;
+    void *u, *ut, *p;
+    double *uin, *ring, *avg, *jprev;
+    uint8_t *head, *red_prev, *type;
+    int64_t *id;
+};
+
+struct DevDerived {
+    void *rho, *vol, *pavg, *a, *b, *pdot;
+    double *jcur, *force, *drag;
+    uint8_t *red;
+};
+
+struct DevNlist {
+    int32_t maxnb;
+    int32_t *count, *nbr;
+};
+
+// Workspace carving (byte offsets from the workspace base).
+struct WsLayout {
+    size_t err, nspawn, spread, cell_start, cursor, keys, tmp, cpos, cpos_s, x0, u0, p0,
+        blocksum, dragpart, total;
+};
+
+__host__ __device__ inline bool is_wall(int t)
+{
+    return t == SPH_WALL_SLIP || t == SPH_WALL_NOSLIP || t == SPH_BODY;
+}
+
+// ------------------------------------------------------------------ kernel
+// Wendland C2 quintic with support 2h: W = a (1 - q/2)^4 (2q + 1),
+// grad_i W_ij = F (r_i - r_j) with F = -5 a (1 - q/2)^3 / h^2.
+template <typename T>
+__device__ inline T wendland_w(T q, T wnorm)
+{
+    T t = T(1) - T(0.5) * q;
+    T t2 = t * t;
+    return q < T(2) ? wnorm * t2 * t2 * (T(2) * q + T(1)) : T(0);
+}
+
+template <typename T>
+__device__ inline T wendland_f(T q, T gnorm)  // gnorm = -5 a / h^2
+{
+    T t = T(1) - T(0.5) * q;
+    return q < T(2) ? gnorm * t * t * t : T(0);
+}
+
+// ------------------------------------------------------------------ geometry
+// Minimum-image difference and its square, FP64, summed left to right with
+// contraction disabled: the neighbour predicate must be bitwise reproducible.
+__device__ inline double min_image(double v, int per, double L, double half)
+{
+    if (per) {
+        if (v > half) v -= L;
+        else if (v < -half) v += L;
+    }
+    return v;
+}
+
+template <int DIM>
+__device__ inline double dist2_exact(const Dev &k, const double *xi, const double *xj,
+                                     double r[3])
+{
+#pragma clang fp contract(off)
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        r[d] = min_image(xi[d] - xj[d], k.periodic[d], k.L[d], k.halfL[d]);
+    }
+    s = r[0] * r[0];
+    s = s + r[1] * r[1];
+    if (DIM == 3) s = s + r[2] * r[2];
+    return s;
+}
+
+// Packed integer cell coordinates: 2D 16 bits per axis, 3D 10 bits per axis.
+template <int DIM>
+__host__ __device__ inline uint32_t pack_cell(const int c[3])
+{
+    if (DIM == 2) return uint32_t(c[0]) | (uint32_t(c[1]) << 16);
+    return uint32_t(c[0]) | (uint32_t(c[1]) << 10) | (uint32_t(c[2]) << 20);
+}
+
+template <int DIM>
+__host__ __device__ inline void unpack_cell(uint32_t p, int c[3])
+{
+    if (DIM == 2) {
+        c[0] = int(p & 0xFFFFu);
+        c[1] = int(p >> 16);
+        c[2] = 0;
+    } else {
+        c[0] = int(p & 0x3FFu);
+        c[1] = int((p >> 10) & 0x3FFu);
+        c[2] = int(p >> 20);
+    }
+}
+
+// Morton key from per-axis "spread" tables: spread[d * kSpreadStride + c] is
+// the coordinate c with its bits moved to the key positions of axis d.
+constexpr int kSpreadStride = 1 << 16;  // entries per axis table (2D axes up to 65536)
+
+template <int DIM>
+__device__ inline uint32_t morton_key(const uint32_t *spread, const int c[3])
+{
+    uint32_t k = spread[c[0]] | spread[kSpreadStride + c[1]];
+    if (DIM == 3) k |= spread[2 * kSpreadStride + c[2]];
+    return k;
+}
+
+__device__ inline void raise_error(uint32_t *err, uint32_t bit) { atomicOr(err, bit); }
+
+template <typename T>
+__device__ inline T ld(const void *p, int64_t i)
+{
+    return static_cast<const T *>(p)[i];
+}
+template <typename T>
+__device__ inline void st(void *p, int64_t i, T v)
+{
+    static_cast<T *>(p)[i] = v;
+}
+
+}  // namespace sph

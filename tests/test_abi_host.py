@@ -1,0 +1,72 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point declared in include/sph.h, and rejects bad arguments on the
+host before any launch."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1907_04034_amd import binding as B
+from paper_1907_04034_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "sph.h")).read()
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(sph_\w+)\s*\(", src, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = B.lib()
+    names = _declared()
+    assert len(names) >= 11
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(B.EXPORTED)
+
+
+def test_struct_sizes_match_header_layout():
+    assert C.sizeof(B.SphParams) == 4 * 6 + 8 * 10 + 8 * 6 + 8 * 5 + 8
+    assert C.sizeof(B.SphState) == 8 + 4 + 4 + 8 * 13
+    assert C.sizeof(B.SphNlist) == 8 + 8 * 2
+    assert C.sizeof(B.SphDerived) == 8 * 10
+
+
+@pytest.mark.parametrize("cfg", ["C1", "C2", "C3", "C5"])
+def test_workspace_size_for_workloads(cfg):
+    prm, s = I.config(cfg, small=True)
+    nbytes = B.workspace_size(prm, len(s["p"]) * 2)
+    assert nbytes > 0
+
+
+def _bad(prm, **kw):
+    p = dict(prm)
+    p.update(kw)
+    with pytest.raises(B.SphError):
+        B.workspace_size(p, 1000)
+
+
+def test_host_validation_rejects_bad_parameters():
+    prm, _ = I.config("C1")
+    _bad(prm, dim=4)
+    _bad(prm, h=0.0)
+    _bad(prm, n_avg=5)
+    _bad(prm, dt=1.0)  # above the acoustic bound
+    _bad(prm, hi=[0.05, 1.0, 0.0])  # periodic axis with fewer than 3 cells
+    with pytest.raises(B.SphError):
+        B.workspace_size(prm, 0)
+    q = B.make_params(dict(prm, dim=1))
+    out = C.c_size_t(0)
+    assert B.lib().sph_workspace_size(C.byref(q), 10, C.byref(out)) == -6
+
+
+def test_null_state_rejected_before_launch():
+    prm, _ = I.config("C1")
+    q = B.make_params(prm)
+    st = B.SphState()
+    st.cap, st.dim, st.prec = 100, 2, 0
+    rc = B.lib().sph_bin(C.byref(q), C.byref(st), C.byref(st), None, 0, None)
+    assert rc == -1
+    assert b"NULL" in B.lib().sph_last_error()
