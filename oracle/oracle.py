@@ -72,6 +72,7 @@ def lib():
         L.orc_count.argtypes = [P]
         L.orc_get.argtypes = [P] * 13
         L.orc_get_derived.argtypes = [P] * 10
+        L.orc_get_abs.argtypes = [P] * 4
         L.orc_rhs.argtypes = [P, C.c_int, P]
         L.orc_step.argtypes = [P, C.c_int32, C.c_int, P]
         L.orc_neighbors.restype = C.c_int64
@@ -153,6 +154,8 @@ class Oracle:
         lib().orc_get_derived(self.h, *[_ptr(d[k]) for k in
                                         ("rho", "vol", "pavg", "a", "b", "pdot", "jcur",
                                          "red", "force")])
+        d["abs_a"], d["abs_b"], d["abs_pdot"] = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
+        lib().orc_get_abs(self.h, _ptr(d["abs_a"]), _ptr(d["abs_b"]), _ptr(d["abs_pdot"]))
         return d
 
     def rhs(self, brute=False):

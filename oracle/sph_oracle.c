@@ -79,6 +79,7 @@ typedef struct {
     int32_t red_prev, red;
     double rho, vol, pavg;
     double a[3], b[3], pdot;
+    double abs_a[3], abs_b[3], abs_pdot; /* sums of |pair contribution| (error scale) */
     double force[3];       /* per-body-particle drag contribution */
     double x0[3], u0[3], p0; /* state at the start of the step */
     int32_t type;
@@ -466,7 +467,8 @@ static void boundary_values(sim *S)
  * enter the divergence term with their (zero) wall velocity and the viscous
  * term with their ghost velocity; eta_i = rho_i nu. */
 static void pair_terms(const orc_params *q, const part *pi, const part *pj,
-                       double pavg_i, double acc[3], double bacc[3], double *pdot)
+                       double pavg_i, double acc[3], double bacc[3], double *pdot,
+                       double abs_acc[3], double abs_bacc[3], double *abs_pdot)
 {
     const int dim = q->dim;
     const double m = particle_mass(q);
@@ -506,6 +508,8 @@ static void pair_terms(const orc_params *q, const part *pi, const part *pj,
         if (visc) term += eta_ij * dfac * uij;
         acc[d] += vsq / m * term;
         bacc[d] += -q->pb / m * vsq * gw[d];
+        abs_acc[d] += fabs(vsq / m * term);
+        abs_bacc[d] += fabs(q->pb / m * vsq * gw[d]);
     }
     /* divergence part: walls move with their wall velocity, which is zero */
     double udiv = 0.0;
@@ -513,8 +517,9 @@ static void pair_terms(const orc_params *q, const part *pi, const part *pj,
         double uj = is_wall(pj->type) ? 0.0 : pj->u[d];
         udiv += (pi->u[d] - uj) * gw[d];
     }
-    *pdot += m * ri / rj * q->c * q->c * udiv
-             + vsq / m * eta_edac * dfac * (pi->p - pj->p);
+    double dp = m * ri / rj * q->c * q->c * udiv + vsq / m * eta_edac * dfac * (pi->p - pj->p);
+    *pdot += dp;
+    *abs_pdot += fabs(dp);
 }
 
 /* Sec. 2 eq:pavg: mean pressure over all neighbours (fluid and boundary),
@@ -535,8 +540,9 @@ static void forces(sim *S)
     #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < S->n; ++i) {
         part *pi = &S->P[i];
-        for (int d = 0; d < 3; ++d) pi->a[d] = pi->b[d] = pi->force[d] = 0.0;
-        pi->pdot = 0.0;
+        for (int d = 0; d < 3; ++d)
+            pi->a[d] = pi->b[d] = pi->force[d] = pi->abs_a[d] = pi->abs_b[d] = 0.0;
+        pi->pdot = pi->abs_pdot = 0.0;
         pi->pavg = 0.0;
         if (pi->type != T_FLUID && pi->type != T_BODY) continue;
         double pavg = neighbour_pavg(S, i);
@@ -546,7 +552,8 @@ static void forces(sim *S)
             if (j == i) continue;
             const part *pj = &S->P[j];
             if (pi->type == T_FLUID) {
-                pair_terms(q, pi, pj, pavg, pi->a, pi->b, &pi->pdot);
+                pair_terms(q, pi, pj, pavg, pi->a, pi->b, &pi->pdot, pi->abs_a, pi->abs_b,
+                           &pi->abs_pdot);
             } else if (pj->type == T_FLUID) {
                 /* Sec. 4.6 eq:tvf-momentum_solid: force on the body from
                  * fluid j, with u_ij = u_g,i - u_j */
@@ -841,6 +848,21 @@ void orc_get_derived(void *h, double *rho, double *vol, double *pavg, double *a,
             b[3 * i + d] = pi->b[d];
             jcur[3 * i + d] = pi->jcur[d];
             force[3 * i + d] = pi->force[d];
+        }
+    }
+}
+
+/* Sums over j of |pair contribution| to a, b, pdot of the last evaluation:
+ * the scale against which rounding in those sums is judged. */
+void orc_get_abs(void *h, double *abs_a, double *abs_b, double *abs_pdot)
+{
+    sim *S = (sim *)h;
+    for (int64_t i = 0; i < S->n; ++i) {
+        part *pi = &S->P[i];
+        abs_pdot[i] = pi->abs_pdot;
+        for (int d = 0; d < 3; ++d) {
+            abs_a[3 * i + d] = pi->abs_a[d];
+            abs_b[3 * i + d] = pi->abs_b[d];
         }
     }
 }

@@ -1,9 +1,11 @@
 """GPU (libsph, FP64) against the CPU oracle on identical seeded inputs.
 
 Neighbour sets must be bitwise equal (matched by particle id). FP64 fields
-must agree to 1e-12 of the field's scale: max|reference|, floored by a
-physical pair-term scale so that fields that cancel to rounding level on a
-perfect lattice (the background term) are not judged relative to noise.
+must agree to 1e-12 of the field's scale: for pair sums (a, b, pdot) the
+largest sum of absolute pair contributions max_i sum_j |t_ij| that the oracle
+reports (rounding in a sum is bounded relative to that, and fields that cancel
+to rounding level on a perfect lattice are not judged against their own
+noise); for every other field max|reference|.
 """
 import numpy as np
 import pytest
@@ -27,11 +29,10 @@ def _match(gs, os_):
     return np.array([idx[int(v)] for v in gs["id"]])
 
 
-def _floors(prm):
-    rho0, h = prm["rho0"], prm["h"]
-    return dict(a=1e-3 * (1.0 + rho0 * prm["U"] ** 2) / (rho0 * h),
-                b=1e-3 * prm["pb"] / (rho0 * h),
-                pdot=1e-3 * rho0 * prm["c"] ** 2 * max(prm["U"], 1.0) / h)
+def _floors(od, sel):
+    """Per-field scale max_i sum_j |t_ij| over the selected rows."""
+    return dict(a=np.abs(od["abs_a"][sel]).max(), b=np.abs(od["abs_b"][sel]).max(),
+                pdot=np.abs(od["abs_pdot"][sel]).max())
 
 
 def _nerr(got, ref, floor=0.0):
@@ -96,7 +97,7 @@ def test_rhs_parity_fp64(name):
     fl = t == I.FLUID
     D = prm["dim"]
     fl_or_body = fl | (t == I.BODY)
-    floors = _floors(prm)
+    floors = _floors(od, perm[fl])
     assert _nerr(gd["rho"], od["rho"][perm]) < TOL
     assert _nerr(gd["vol"], od["vol"][perm]) < TOL
     assert _nerr(gd["pavg"][fl_or_body], od["pavg"][perm][fl_or_body]) < TOL
@@ -233,7 +234,7 @@ def test_full_size_rhs_parity(cfg):
     os_, od, F = O.rhs_once(prm, s)
     perm = _match(gs, os_)
     fl = gs["type"] == I.FLUID
-    floors = _floors(prm)
+    floors = _floors(od, perm[fl])
     D = prm["dim"]
     assert _nerr(gd["rho"], od["rho"][perm]) < TOL
     for key in ("a", "b"):
