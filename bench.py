@@ -52,7 +52,8 @@ def force_bytes(sim, counts, types, prec_bytes):
     fb = (types == 0) | (types == 5)
     nfb = int(fb.sum())
     nnz = int(counts[fb].sum())
-    rd = n * 1 + nfb * (8 * D + 2 * prec_bytes * D + 3 * prec_bytes + 4) + 4 * nnz
+    pos = 8 * D if prec_bytes == 8 else 4 * D + 4  # FP32: cell offsets + packed cell
+    rd = n * 1 + nfb * (pos + 2 * prec_bytes * D + 3 * prec_bytes + 4) + 4 * nnz
     wr = n * (2 * prec_bytes * D + 2 * prec_bytes) + int((types == 5).sum()) * 8 * D
     return rd + wr, dict(read=rd, write=wr, n=n, n_fluid_or_body=nfb, nnz=nnz)
 
@@ -86,16 +87,17 @@ def cpu_baseline(prm, s, budget_s):
     from oracle import oracle as O
     O.build(force=False)
     o = O.Oracle(prm, s)
+    chunk = max(1, min(10, 400_000 // len(s["p"])))
     steps, pairs, elapsed = 0, 0, 0.0
     while elapsed < budget_s and steps < prm.get("steps", 2000):
         row, _ = o.neighbors()
         fl = o.state()["type"] == 0
         p_rhs = int((np.diff(row)[fl] - 1).sum())
         t1 = time.perf_counter()
-        o.step(10)
+        o.step(chunk)
         elapsed += time.perf_counter() - t1
-        steps += 10
-        pairs += 2 * 10 * p_rhs
+        steps += chunk
+        pairs += 2 * chunk * p_rhs
     return dict(value=pairs / elapsed, unit="pair-interactions/s", cores=O.num_threads(),
                 kind="oracle",
                 sample=f"FP64 oracle, first {steps} RK2 steps ({2 * steps} RHS) of the same "

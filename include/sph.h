@@ -86,6 +86,8 @@ typedef struct sph_params {
     double inlet_len;     /* re-spawn offset of inlet particles */
     double noise_amp;     /* relative inlet velocity noise (SPH_FLAG_NOISE) */
     uint64_t noise_seed;
+    int32_t group_force;  /* lanes per target in the force pass: 0 = automatic, or 1..32 (power of 2) */
+    int32_t group_nbr;    /* lanes per target in the neighbour search: same convention */
 } sph_params;
 
 /* Particle state. Element type of u, ut, p is double for SPH_FP64 and float
@@ -110,12 +112,12 @@ typedef struct sph_state {
     int64_t *id;          /* [cap] */
 } sph_state;
 
-/* Neighbour table: neighbours of particle i (itself included) are
- * nbr[k * cap + i] for k < count[i], in stencil-then-cell order. */
+/* Neighbour table, row-major: the neighbours of particle i (itself included)
+ * are nbr[i * maxnb + k] for k < count[i], in stencil-then-cell order. */
 typedef struct sph_nlist {
     int32_t maxnb;        /* rows of nbr */
     int32_t *count;       /* [cap] */
-    int32_t *nbr;         /* [maxnb][cap] */
+    int32_t *nbr;         /* [cap][maxnb] */
 } sph_nlist;
 
 /* Results of one right-hand-side evaluation. rho, vol, pavg, a, b, pdot have
@@ -149,12 +151,15 @@ int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws,
 
 /* Neighbour table at the current positions from the cells of the last
  * sph_bin on this workspace: j is a neighbour of i iff |r_i - r_j|^2 < (2h)^2
- * in FP64 without fused multiply-add, minimum image on periodic axes. */
-int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, void *ws,
-                  size_t ws_bytes, void *stream);
+ * in FP64 without fused multiply-add, minimum image on periodic axes. If out
+ * is not NULL the summation density of sph_density is written from the same
+ * pairs. Particles must not have moved more than the cell skin since the bin
+ * (sph_step checks this on the device). */
+int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph_derived *out,
+                  void *ws, size_t ws_bytes, void *stream);
 
 /* Summation density, Sec. 2 eq:summation-density, and the number-density
- * volume V_i = 1 / sum_j W_ij, for every particle. */
+ * volume V_i = 1 / sum_j W_ij, for every particle, from the neighbour table. */
 int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
                 sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
@@ -183,11 +188,14 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
 int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
               sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
-/* nsteps explicit-midpoint RK2 steps: bin, stage 1, half update, stage 2,
- * full update, then the end-of-step bookkeeping of Sec. 3.4 (gated
- * time-average push, fluid->outlet, outlet deletion, inlet->fluid with
- * re-spawn). drag_hist (device, [nsteps][3], may be NULL) receives the body
- * force of stage 1 of every step. */
+/* nsteps explicit-midpoint RK2 steps: bin, stage 1 (neighbours + density,
+ * boundary values, force pass fused with the half update into an internal
+ * half state), stage 2 (the same at the half state, fused with the full
+ * update), then the end-of-step bookkeeping of Sec. 3.4 (gated time-average
+ * push, fluid->outlet, outlet deletion, inlet->fluid with re-spawn).
+ * drag_hist (device, [nsteps][3], may be NULL) receives the body force of
+ * stage 1 of every step. out receives the density and boundary data of the
+ * last stage (a, b, pdot are not written). */
 int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
              sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
              size_t ws_bytes, void *stream);

@@ -35,6 +35,7 @@ class SphParams(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("x_inlet", C.c_double), ("x_outlet", C.c_double), ("x_outlet_end", C.c_double),
         ("inlet_len", C.c_double), ("noise_amp", C.c_double), ("noise_seed", C.c_uint64),
+        ("group_force", C.c_int32), ("group_nbr", C.c_int32),
     ]
 
 
@@ -74,7 +75,7 @@ def lib():
         L.sph_default_maxnb.argtypes = [SP]
         L.sph_default_maxnb.restype = C.c_int32
         L.sph_bin.argtypes = [SP, ST, ST, _P, sz, _P]
-        L.sph_neighbors.argtypes = [SP, ST, NL, _P, sz, _P]
+        L.sph_neighbors.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_density.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_outlet_extrapolate.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_rhs.argtypes = [SP, ST, NL, DE, _P, sz, _P]
@@ -110,6 +111,8 @@ def make_params(prm):
               "x_outlet", "x_outlet_end", "inlet_len", "noise_amp"):
         setattr(q, k, float(prm[k]))
     q.noise_seed = int(prm["noise_seed"])
+    q.group_force = int(prm.get("group_force", 0))
+    q.group_nbr = int(prm.get("group_nbr", 0))
     return q
 
 
@@ -245,8 +248,8 @@ class Simulation:
         if not self.binned:
             self.bin()
         ws, nb = self._ws()
-        _check(lib().sph_neighbors(C.byref(self.q), C.byref(self.st), C.byref(self.nl), ws, nb,
-                                   self.stream), "sph_neighbors")
+        _check(lib().sph_neighbors(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
+                                   C.byref(self.out), ws, nb, self.stream), "sph_neighbors")
 
     def density(self):
         ws, nb = self._ws()
@@ -335,7 +338,7 @@ class Simulation:
     def neighbor_table(self):
         n = self.live_count()
         cnt = self.nl_count[:n].cpu().numpy()
-        nbr = self.nl_nbr.view(self.maxnb, self.cap)[:, :n].cpu().numpy().T
+        nbr = self.nl_nbr.view(self.cap, self.maxnb)[:n].cpu().numpy()
         return cnt, nbr
 
 

@@ -1,12 +1,13 @@
-// bin.hip -- cell binning of libsph: Morton keys, integer histogram, exclusive
-// scan, scatter, per-cell ordering by particle id, and the gather that moves
-// every per-particle array into sorted order.
+// bin.hip -- cell binning of libsph: Morton keys with an integer histogram,
+// one-launch exclusive scan, scatter, per-cell ordering by particle id, and
+// the gather that moves every per-particle array into sorted order.
 //
-// The sort is deterministic and stable without a radix sort: the histogram
-// and the scan are integer (exact), the scatter writes each cell's members in
+// The sort is deterministic and stable without a radix sort: histogram and
+// scan are integer (exact), the scatter writes each cell's members in
 // arbitrary order, and one thread per cell then orders its few members by
-// their unique id. The result depends only on (cell, id), never on the order
-// in which atomics land.
+// their unique id, so the result depends only on (cell, id), never on the
+// order in which atomics land. No launch is spent on clearing: every counter
+// is zeroed by the kernel that consumes it (the workspace starts zeroed).
 #include "sph_launch.h"
 
 namespace sph {
@@ -36,136 +37,172 @@ __global__ void k_spread(Dev k, uint32_t *spread)
     spread[t] = v;
 }
 
-__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+constexpr int kTileSlots = 8;  // sub-counters per tile total (spreads the atomics)
+
+int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
+int64_t tilesum_len(int64_t n) { return scan_tiles(n) * kTileSlots; }
+
+// live rows this bin sees: the last count plus rows re-spawned since
+__device__ inline int64_t rows_to_bin(const Dev &k, const DevState &s, const int32_t *nspawn)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+    int64_t n = *s.n + *nspawn;
+    return n < k.cap ? n : k.cap;
 }
 
 template <int DIM>
-__global__ void k_keys(Dev k, DevState s, const uint32_t *spread, uint32_t *keys,
-                       uint32_t *cpos, int32_t *counts, uint32_t *err)
+__global__ void __launch_bounds__(kBlock) k_keys(Dev k, DevState s, const int32_t *nspawn,
+                                                 const uint32_t *spread, uint32_t *keys,
+                                                 uint32_t *cpos, int32_t *counts,
+                                                 int32_t *tilesum, int32_t *bcount, uint32_t *err)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = *s.n;
-    if (i >= n) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    if (i == 0) *bcount = 0;
+    const int64_t n = rows_to_bin(k, s, nspawn);
     uint32_t key = k.nkeys;
-    if (s.type[i] != SPH_DEAD) {
-        int c[3] = {0, 0, 0};
-        bool escaped = false;
+    if (i < n) {
+        if (s.type[i] != SPH_DEAD) {
+            int c[3] = {0, 0, 0};
+            bool escaped = false;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            double f = floor((s.x[d * k.cap + i] - k.lo[d]) * k.inv_cs[d]);
-            int v;  // NaN and out-of-box values are clamped and flagged below
-            if (!(f >= 0.0)) v = -1;
-            else if (f >= double(k.nc[d])) v = k.nc[d];
-            else v = int(f);
-            if (v < 0 || v >= k.nc[d]) {
-                if (!k.periodic[d]) escaped = true;
-                v = v < 0 ? 0 : k.nc[d] - 1;
+            for (int d = 0; d < DIM; ++d) {
+                const double f = floor((s.x[d * k.cap + i] - k.lo[d]) * k.inv_cs[d]);
+                int v;  // NaN and out-of-box values are clamped and flagged
+                if (!(f >= 0.0)) v = -1;
+                else if (f >= double(k.nc[d])) v = k.nc[d];
+                else v = int(f);
+                if (v < 0 || v >= k.nc[d]) {
+                    if (!k.periodic[d]) escaped = true;
+                    v = v < 0 ? 0 : k.nc[d] - 1;
+                }
+                c[d] = v;
             }
-            c[d] = v;
+            if (escaped) raise_error(err, SPH_ERR_ESCAPE);
+            key = morton_key<DIM>(spread, c);
+            cpos[i] = pack_cell<DIM>(c);
         }
-        if (escaped) raise_error(err, SPH_ERR_ESCAPE);
-        key = morton_key<DIM>(spread, c);
-        cpos[i] = pack_cell<DIM>(c);
+        keys[i] = key;
+        atomicAdd(&counts[key], 1);
     }
-    keys[i] = key;
-    atomicAdd(&counts[key], 1);
+    // Tile totals for the scan. Rows arrive almost sorted, so lanes of a wave
+    // mostly share a tile: only the first lane of each run of equal tiles
+    // adds the run length (about one atomic per wave instead of per row).
+    const uint32_t tile = i < n ? key / kScanTile : 0xFFFFFFFFu;
+    const uint32_t prev = __shfl_up(tile, 1);
+    const bool leader = i < n && (lane == 0 || prev != tile);
+    const uint64_t lead = __ballot(leader);
+    if (leader) {
+        const uint64_t above = lane == 63 ? 0ull : (lead & ~((2ull << lane) - 1));
+        const int64_t wave_end = (i - lane) + 64 < n ? 64 : n - (i - lane);
+        const int next = above ? __ffsll((long long)above) - 1 : int(wave_end);
+        atomicAdd(&tilesum[int64_t(tile) * kTileSlots + (blockIdx.x % kTileSlots)], next - lane);
+    }
 }
-
-// ------------------------------------------------------------------- scan
-// Exclusive scan of int32 in place, three launches: per-tile sums, a scan of
-// the tile sums in one block, then per-tile scans with the tile offset.
-constexpr int kScanItems = 8;
-constexpr int kScanTile = kBlock * kScanItems;
-
-int64_t scan_blocksum_len(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 
 __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total)
 {
-    int t = threadIdx.x;
+    const int t = threadIdx.x;
     lds[t] = v;
     __syncthreads();
     for (int off = 1; off < kBlock; off <<= 1) {
-        int32_t add = t >= off ? lds[t - off] : 0;
+        const int32_t add = t >= off ? lds[t - off] : 0;
         __syncthreads();
         lds[t] += add;
         __syncthreads();
     }
-    int32_t incl = lds[t];
+    const int32_t incl = lds[t];
     *total = lds[kBlock - 1];
     __syncthreads();
     return incl - v;
 }
 
-__global__ void __launch_bounds__(kBlock) k_scan_reduce(const int32_t *data, int64_t n,
-                                                        int32_t *blocksum)
+// cell_start = exclusive scan of counts (n entries); every tile adds the sum
+// of the tile totals before it, so one launch suffices. Consumed counts are
+// zeroed for the next bin.
+__global__ void __launch_bounds__(kBlock) k_scan(int32_t *counts, int32_t *cell_start, int64_t n,
+                                                 const int32_t *tilesum)
 {
     __shared__ int32_t lds[kBlock];
-    int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
-    int32_t s = 0;
-    for (int q = 0; q < kScanItems; ++q)
-        if (base + q < n) s += data[base + q];
+    int32_t pre = 0;
+    for (int64_t t = threadIdx.x; t < int64_t(blockIdx.x) * kTileSlots; t += kBlock) pre += tilesum[t];
     int32_t total;
-    block_exclusive_scan(s, lds, &total);
-    if (threadIdx.x == 0) blocksum[blockIdx.x] = total;
-}
-
-__global__ void __launch_bounds__(kBlock) k_scan_blocks(int32_t *blocksum, int64_t nb)
-{
-    __shared__ int32_t lds[kBlock];
-    int32_t carry = 0;
-    for (int64_t base = 0; base < nb; base += kBlock) {
-        int64_t i = base + threadIdx.x;
-        int32_t v = i < nb ? blocksum[i] : 0;
-        int32_t total;
-        int32_t ex = block_exclusive_scan(v, lds, &total);
-        if (i < nb) blocksum[i] = ex + carry;
-        carry += total;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_scan_apply(int32_t *data, int64_t n,
-                                                       const int32_t *blocksum)
-{
-    __shared__ int32_t lds[kBlock];
-    int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
+    block_exclusive_scan(pre, lds, &total);
+    const int32_t tile_off = total;
+    const int64_t base = int64_t(blockIdx.x) * kScanTile + int64_t(threadIdx.x) * kScanItems;
     int32_t v[kScanItems];
     int32_t s = 0;
     for (int q = 0; q < kScanItems; ++q) {
-        v[q] = base + q < n ? data[base + q] : 0;
+        v[q] = base + q < n ? counts[base + q] : 0;
         s += v[q];
     }
-    int32_t total;
-    int32_t run = block_exclusive_scan(s, lds, &total) + blocksum[blockIdx.x];
+    int32_t run = block_exclusive_scan(s, lds, &total) + tile_off;
     for (int q = 0; q < kScanItems; ++q) {
-        if (base + q < n) data[base + q] = run;
+        if (base + q < n) {
+            cell_start[base + q] = run;
+            counts[base + q] = 0;
+        }
         run += v[q];
     }
 }
 
-// ------------------------------------------------------------ scatter, sort
-__global__ void k_scatter(Dev k, DevState s, const uint32_t *keys, const int32_t *cell_start,
-                          int32_t *cursor, int32_t *tmp)
+__global__ void k_scatter(Dev k, DevState s, const int32_t *nspawn, const uint32_t *keys,
+                          const int32_t *cell_start, int32_t *cursor, int32_t *tmp)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = *s.n;
-    if (i >= n) return;
-    uint32_t key = keys[i];
-    int32_t slot = cell_start[key] + atomicAdd(&cursor[key], 1);
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= rows_to_bin(k, s, nspawn)) return;
+    const uint32_t key = keys[i];
+    const int32_t slot = cell_start[key] + atomicAdd(&cursor[key], 1);
     tmp[slot] = int32_t(i);
 }
 
-// One thread per cell: insertion sort of the members by id (ids are unique).
-__global__ void k_cellsort(Dev k, DevState s, const int32_t *cell_start, int32_t *tmp)
+// One thread per cell orders its members by id (ids are unique), then
+// clears the scatter cursor and the tile sums for the next bin. Cells of up to
+// 16 members are sorted in registers by an odd-even transposition network
+// (static indices only); larger cells fall back to insertion sort in memory.
+__device__ inline void cswap(int64_t &ka, int32_t &va, int64_t &kb, int32_t &vb)
 {
-    int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= int64_t(k.nkeys)) return;
-    int32_t b = cell_start[c], e = cell_start[c + 1];
+    const bool sw = ka > kb;
+    const int64_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
+    const int32_t v0 = sw ? vb : va, v1 = sw ? va : vb;
+    ka = k0;
+    kb = k1;
+    va = v0;
+    vb = v1;
+}
+
+__global__ void k_cellsort(Dev k, DevState s, const int32_t *cell_start, int32_t *tmp,
+                           int32_t *cursor, int32_t *tilesum, int64_t ntiles)
+{
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c < ntiles * kTileSlots) tilesum[c] = 0;
+    if (c > int64_t(k.nkeys)) return;
+    cursor[c] = 0;
+    if (c == int64_t(k.nkeys)) return;  // dead particles need no order
+    const int32_t b = cell_start[c], e = cell_start[c + 1];
+    const int m = e - b;
+    if (m <= 1) return;
+    constexpr int R = 16;
+    if (m <= R) {
+        int32_t v[R];
+        int64_t key[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) v[q] = q < m ? tmp[b + q] : 0;
+#pragma unroll
+        for (int q = 0; q < R; ++q) key[q] = q < m ? s.id[v[q]] : INT64_MAX;
+#pragma unroll
+        for (int pass = 0; pass < R; ++pass)
+#pragma unroll
+            for (int q = pass & 1; q + 1 < R; q += 2) cswap(key[q], v[q], key[q + 1], v[q + 1]);
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+            if (q < m) tmp[b + q] = v[q];
+        return;
+    }
     for (int32_t q = b + 1; q < e; ++q) {
-        int32_t v = tmp[q];
-        int64_t key = s.id[v];
+        const int32_t v = tmp[q];
+        const int64_t key = s.id[v];
         int32_t r = q - 1;
         while (r >= b && s.id[tmp[r]] > key) {
             tmp[r + 1] = tmp[r];
@@ -175,48 +212,58 @@ __global__ void k_cellsort(Dev k, DevState s, const int32_t *cell_start, int32_t
     }
 }
 
-// Row k of the sorted state is row tmp[k] of the old one. Also records the
-// start-of-step copies of x, u, p used by the two-stage update.
+// Row r of the sorted state is row tmp[r] of the old one. Non-fluid rows are
+// listed for the boundary pass; the live count is published and the re-spawn
+// counter cleared.
 template <int DIM, typename T>
 __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
-                         const int32_t *cell_start, const uint32_t *cpos_in,
-                         uint32_t *cpos_out, double *x0, T *u0, T *p0)
+                         const int32_t *cell_start, const uint32_t *cpos_in, uint32_t *cpos_out,
+                         int32_t *blist, int32_t *bcount, int32_t *nspawn)
 {
-    int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = cell_start[k.nkeys];
-    if (r >= n) return;
-    int64_t i = tmp[r];
-    const int64_t C = k.cap;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double xv = a.x[d * C + i];
-        T uv = ld<T>(a.u, d * C + i);
-        b.x[d * C + r] = xv;
-        x0[d * C + r] = xv;
-        st<T>(b.u, d * C + r, uv);
-        u0[d * C + r] = uv;
-        st<T>(b.ut, d * C + r, ld<T>(a.ut, d * C + i));
-        b.uin[d * C + r] = a.uin[d * C + i];
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = cell_start[k.nkeys];
+    if (r == 0 && blockIdx.y == 0) {
+        *a.n = n;
+        *nspawn = 0;
     }
-    T pv = ld<T>(a.p, i);
-    st<T>(b.p, r, pv);
-    p0[r] = pv;
+    if (r >= n) return;
+    const int64_t i = tmp[r];
+    const int64_t C = k.cap;
+    constexpr int NR = kNavg * (DIM + 1);  // ring words, split over slices 1 and 2
+    switch (blockIdx.y) {
+    case 0: {
 #pragma unroll
-    for (int q = 0; q < kNavg * (DIM + 1); ++q) b.ring[q * C + r] = a.ring[q * C + i];
+        for (int d = 0; d < DIM; ++d) {
+            b.x[d * C + r] = a.x[d * C + i];
+            st<T>(b.u, d * C + r, ld<T>(a.u, d * C + i));
+            st<T>(b.ut, d * C + r, ld<T>(a.ut, d * C + i));
+            b.uin[d * C + r] = a.uin[d * C + i];
+        }
+        st<T>(b.p, r, ld<T>(a.p, i));
+        b.head[r] = a.head[i];
+        b.red_prev[r] = a.red_prev[i];
+        const uint8_t t = a.type[i];
+        b.type[r] = t;
+        b.id[r] = a.id[i];
+        cpos_out[r] = cpos_in[i];
+        if (t != SPH_FLUID) blist[atomicAdd(bcount, 1)] = int32_t(r);
+        break;
+    }
+    case 1:
 #pragma unroll
-    for (int q = 0; q < DIM + 1; ++q) b.avg[q * C + r] = a.avg[q * C + i];
+        for (int q = 0; q < NR / 2; ++q) b.ring[q * C + r] = a.ring[q * C + i];
+        break;
+    case 2:
 #pragma unroll
-    for (int q = 0; q < 3; ++q) b.jprev[q * C + r] = a.jprev[q * C + i];
-    b.head[r] = a.head[i];
-    b.red_prev[r] = a.red_prev[i];
-    b.type[r] = a.type[i];
-    b.id[r] = a.id[i];
-    cpos_out[r] = cpos_in[i];
-}
-
-__global__ void k_set_count(Dev k, DevState s, const int32_t *cell_start)
-{
-    if (blockIdx.x == 0 && threadIdx.x == 0) *s.n = cell_start[k.nkeys];
+        for (int q = NR / 2; q < NR; ++q) b.ring[q * C + r] = a.ring[q * C + i];
+        break;
+    default:
+#pragma unroll
+        for (int q = 0; q < DIM + 1; ++q) b.avg[q * C + r] = a.avg[q * C + i];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b.jprev[q * C + r] = a.jprev[q * C + i];
+        break;
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -226,68 +273,39 @@ void launch_spread(const Dev &k, uint32_t *spread, hipStream_t s)
                        k, spread);
 }
 
-void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s)
+void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBufs &w,
+                uint32_t *err, hipStream_t s)
 {
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(n)), dim3(kBlock), 0, s, p, n, v);
-}
-
-void launch_keys(const Dev &k, const DevState &st, const uint32_t *spread, uint32_t *keys,
-                 uint32_t *cpos, int32_t *counts, uint32_t *err, hipStream_t s)
-{
+    const dim3 g(nblocks(k.cap)), blk(kBlock);
+    const int64_t nscan = int64_t(k.nkeys) + 2;
+    const int64_t ntiles = scan_tiles(nscan);
     if (k.dim == 2)
-        hipLaunchKernelGGL(k_keys<2>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, st, spread,
-                           keys, cpos, counts, err);
+        hipLaunchKernelGGL(k_keys<2>, g, blk, 0, s, k, a, w.nspawn, w.spread, w.keys, w.cpos,
+                           w.counts, w.tilesum, w.bcount, err);
     else
-        hipLaunchKernelGGL(k_keys<3>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, st, spread,
-                           keys, cpos, counts, err);
-}
-
-void launch_scan(int32_t *data, int64_t n, int32_t *blocksum, hipStream_t s)
-{
-    int64_t nb = scan_blocksum_len(n);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(kBlock), 0, s, data, n, blocksum);
-    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(kBlock), 0, s, blocksum, nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nb), dim3(kBlock), 0, s, data, n, blocksum);
-}
-
-void launch_scatter(const Dev &k, const DevState &st, const uint32_t *keys,
-                    const int32_t *cell_start, int32_t *cursor, int32_t *tmp, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scatter, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, st, keys,
-                       cell_start, cursor, tmp);
-}
-
-void launch_cellsort(const Dev &k, const DevState &st, const int32_t *cell_start, int32_t *tmp,
-                     hipStream_t s)
-{
-    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(k.nkeys)), dim3(kBlock), 0, s, k, st,
-                       cell_start, tmp);
-}
-
-void launch_gather(const Dev &k, const DevState &src, const DevState &dst, const int32_t *tmp,
-                   const int32_t *cell_start, const uint32_t *cpos_in, uint32_t *cpos_out,
-                   double *x0, void *u0, void *p0, hipStream_t s)
-{
-    dim3 g(nblocks(k.cap)), b(kBlock);
+        hipLaunchKernelGGL(k_keys<3>, g, blk, 0, s, k, a, w.nspawn, w.spread, w.keys, w.cpos,
+                           w.counts, w.tilesum, w.bcount, err);
+    hipLaunchKernelGGL(k_scan, dim3(ntiles), blk, 0, s, w.counts, w.cell_start, nscan,
+                       w.tilesum);
+    hipLaunchKernelGGL(k_scatter, g, blk, 0, s, k, a, w.nspawn, w.keys, w.cell_start, w.cursor,
+                       w.tmp);
+    const int64_t ncs = (int64_t(k.nkeys) + 1) > ntiles * kTileSlots ? int64_t(k.nkeys) + 1
+                                                                     : ntiles * kTileSlots;
+    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(ncs)), blk, 0, s, k, a, w.cell_start, w.tmp,
+                       w.cursor, w.tilesum, ntiles);
+    const dim3 gg(nblocks(k.cap), 4);
     if (k.dim == 2 && k.prec == SPH_FP64)
-        hipLaunchKernelGGL((k_gather<2, double>), g, b, 0, s, k, src, dst, tmp, cell_start,
-                           cpos_in, cpos_out, x0, (double *)u0, (double *)p0);
+        hipLaunchKernelGGL((k_gather<2, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
     else if (k.dim == 3 && k.prec == SPH_FP64)
-        hipLaunchKernelGGL((k_gather<3, double>), g, b, 0, s, k, src, dst, tmp, cell_start,
-                           cpos_in, cpos_out, x0, (double *)u0, (double *)p0);
+        hipLaunchKernelGGL((k_gather<3, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
     else if (k.dim == 2)
-        hipLaunchKernelGGL((k_gather<2, float>), g, b, 0, s, k, src, dst, tmp, cell_start,
-                           cpos_in, cpos_out, x0, (float *)u0, (float *)p0);
+        hipLaunchKernelGGL((k_gather<2, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
     else
-        hipLaunchKernelGGL((k_gather<3, float>), g, b, 0, s, k, src, dst, tmp, cell_start,
-                           cpos_in, cpos_out, x0, (float *)u0, (float *)p0);
-}
-
-void launch_set_count(const Dev &k, const DevState &st, const int32_t *cell_start,
-                      hipStream_t s)
-{
-    hipLaunchKernelGGL(k_set_count, dim3(1), dim3(64), 0, s, k, st, cell_start);
+        hipLaunchKernelGGL((k_gather<3, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
 }
 
 }  // namespace sph

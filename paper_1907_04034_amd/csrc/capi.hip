@@ -62,6 +62,8 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     std::memset(k, 0, sizeof *k);
     k->dim = p->dim;
     k->flags = p->flags;
+    k->g_force = p->group_force;
+    k->g_nbr = p->group_nbr;
     k->prec = prec;
     k->maxnb = maxnb;
     k->cap = cap;
@@ -94,6 +96,7 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         k->L[d] = L;
         k->halfL[d] = 0.5 * L;
         k->cs[d] = L / nc;
+        k->csf[d] = float(k->cs[d]);
         k->inv_cs[d] = nc / L;
         min_slack = std::fmin(min_slack, k->cs[d] - 2.0 * p->h);
     }
@@ -107,7 +110,9 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     k->wnorm = p->dim == 2 ? 7.0 / (4.0 * pi * p->h * p->h)
                            : 21.0 / (16.0 * pi * p->h * p->h * p->h);
     k->gnorm = -5.0 * k->wnorm / (p->h * p->h);
+    k->inv_h = 1.0 / p->h;
     k->mass = p->dim == 2 ? p->rho0 * p->dx * p->dx : p->rho0 * p->dx * p->dx * p->dx;
+    k->inv_mass = 1.0 / k->mass;
     k->rho0 = p->rho0;
     k->c = p->c;
     k->c2 = p->c * p->c;
@@ -151,20 +156,26 @@ static WsLayout layout(const Dev &k)
         return o;
     };
     const size_t C = size_t(k.cap);
+    const size_t nscan = size_t(k.nkeys) + 2;
     w.err = take(sizeof(uint32_t));
     w.nspawn = take(sizeof(int32_t));
+    w.bcount = take(sizeof(int32_t));
     w.spread = take(sizeof(uint32_t) * 3 * kSpreadStride);
-    w.cell_start = take(sizeof(int32_t) * (size_t(k.nkeys) + 2));
+    w.counts = take(sizeof(int32_t) * nscan);
+    w.cell_start = take(sizeof(int32_t) * nscan);
     w.cursor = take(sizeof(int32_t) * (size_t(k.nkeys) + 1));
+    w.tilesum = take(sizeof(int32_t) * size_t(tilesum_len(int64_t(nscan))));
     w.keys = take(sizeof(uint32_t) * C);
     w.tmp = take(sizeof(int32_t) * C);
     w.cpos = take(sizeof(uint32_t) * C);
     w.cpos_s = take(sizeof(uint32_t) * C);
-    w.x0 = take(sizeof(double) * 3 * C);
-    w.u0 = take(sizeof(double) * 3 * C);
-    w.p0 = take(sizeof(double) * C);
-    w.blocksum = take(sizeof(int32_t) * size_t(scan_blocksum_len(int64_t(k.nkeys) + 2)));
-    w.dragpart = take(sizeof(double) * 3 * size_t(nblocks(k.cap)));
+    w.blist = take(sizeof(int32_t) * C);
+    w.hx = take(sizeof(double) * 3 * C);  // half state (element size of FP64)
+    w.hu = take(sizeof(double) * 3 * C);
+    w.hut = take(sizeof(double) * 3 * C);
+    w.hp = take(sizeof(double) * C);
+    w.off = take(sizeof(float) * 3 * C);
+    w.dragpart = take(sizeof(double) * 3 * size_t(force_grid_max(k)));
     w.total = off;
     return w;
 }
@@ -253,7 +264,45 @@ struct Ctx {
     void *ws;
     hipStream_t s;
     uint32_t *err() const { return at<uint32_t>(ws, w.err); }
+    BinBufs bins() const
+    {
+        BinBufs b;
+        b.nspawn = at<int32_t>(ws, w.nspawn);
+        b.bcount = at<int32_t>(ws, w.bcount);
+        b.counts = at<int32_t>(ws, w.counts);
+        b.cell_start = at<int32_t>(ws, w.cell_start);
+        b.cursor = at<int32_t>(ws, w.cursor);
+        b.tilesum = at<int32_t>(ws, w.tilesum);
+        b.tmp = at<int32_t>(ws, w.tmp);
+        b.blist = at<int32_t>(ws, w.blist);
+        b.spread = at<uint32_t>(ws, w.spread);
+        b.keys = at<uint32_t>(ws, w.keys);
+        b.cpos = at<uint32_t>(ws, w.cpos);
+        b.cpos_s = at<uint32_t>(ws, w.cpos_s);
+        return b;
+    }
+    Fields half() const
+    {
+        Fields f;
+        f.x = at<double>(ws, w.hx);
+        f.u = at<void>(ws, w.hu);
+        f.ut = at<void>(ws, w.hut);
+        f.p = at<void>(ws, w.hp);
+        return f;
+    }
+    float *off() const { return at<float>(ws, w.off); }
+    double *dragpart() const { return at<double>(ws, w.dragpart); }
 };
+
+static Fields fields_of(const sph_state *s)
+{
+    Fields f;
+    f.x = s->x;
+    f.u = s->u;
+    f.ut = s->ut;
+    f.p = s->p;
+    return f;
+}
 
 static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws,
                    size_t ws_bytes, void *stream, Ctx *c)
@@ -263,6 +312,8 @@ static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws
     rc = make_dev(p, st->cap, st->prec, maxnb, &c->k);
     if (rc) return rc;
     c->w = layout(c->k);
+    if (force_grid(c->k) > force_grid_max(c->k))  // the drag partials are sized for the latter
+        return fail(SPH_EINVAL, "internal: force grid exceeds the drag-partial buffer");
     if (!ws) return fail(SPH_EINVAL, "workspace is NULL");
     if (ws_bytes < c->w.total)
         return fail(SPH_ECAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, c->w.total);
@@ -271,27 +322,15 @@ static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws
     return SPH_OK;
 }
 
+// Sorts *st into *alt and exchanges their buffers (the live-count pointer of
+// each struct stays with it).
 static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
 {
-    const Dev &k = c.k;
-    int32_t *cell_start = at<int32_t>(c.ws, c.w.cell_start);
-    int32_t *cursor = at<int32_t>(c.ws, c.w.cursor);
-    launch_fill_i32(cell_start, int64_t(k.nkeys) + 2, 0, c.s);
-    launch_fill_i32(cursor, int64_t(k.nkeys) + 1, 0, c.s);
     DevState a = dev_state(st), b = dev_state(alt);
     b.n = a.n;
-    launch_keys(k, a, at<uint32_t>(c.ws, c.w.spread), at<uint32_t>(c.ws, c.w.keys),
-                at<uint32_t>(c.ws, c.w.cpos), cell_start, c.err(), c.s);
-    launch_scan(cell_start, int64_t(k.nkeys) + 2, at<int32_t>(c.ws, c.w.blocksum), c.s);
-    launch_scatter(k, a, at<uint32_t>(c.ws, c.w.keys), cell_start, cursor,
-                   at<int32_t>(c.ws, c.w.tmp), c.s);
-    launch_cellsort(k, a, cell_start, at<int32_t>(c.ws, c.w.tmp), c.s);
-    launch_gather(k, a, b, at<int32_t>(c.ws, c.w.tmp), cell_start, at<uint32_t>(c.ws, c.w.cpos),
-                  at<uint32_t>(c.ws, c.w.cpos_s), at<double>(c.ws, c.w.x0),
-                  at<void>(c.ws, c.w.u0), at<void>(c.ws, c.w.p0), c.s);
-    launch_set_count(k, a, cell_start, c.s);
-    if (alt->n != st->n) launch_set_count(k, dev_state(alt), cell_start, c.s);
-    // exchange the buffers: *st now describes the sorted particles
+    launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
+    if (alt->n != st->n)
+        (void)hipMemcpyAsync(alt->n, st->n, sizeof(int64_t), hipMemcpyDeviceToDevice, c.s);
     sph_state tmp = *st;
     int64_t *n_st = st->n, *n_alt = alt->n;
     *st = *alt;
@@ -300,24 +339,29 @@ static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
     alt->n = n_alt;
 }
 
-static void do_neighbors(Ctx &c, const sph_state *st, const sph_nlist *nl)
+static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
+                       const sph_derived *o, int dens)
 {
-    launch_neighbors(c.k, dev_state(st), dev_nlist(nl), at<uint32_t>(c.ws, c.w.spread),
-                     at<int32_t>(c.ws, c.w.cell_start), at<uint32_t>(c.ws, c.w.cpos_s), c.err(),
-                     c.s);
+    launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? dev_derived(o) : DevDerived{},
+                   dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
+                   at<uint32_t>(c.ws, c.w.cpos_s), c.off(), c.err(), c.s);
 }
 
-static void do_rhs(Ctx &c, const sph_state *st, const sph_nlist *nl, const sph_derived *o,
-                   double *hist)
+static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
+                        const sph_derived *o)
 {
-    DevState s = dev_state(st);
-    DevNlist n = dev_nlist(nl);
-    DevDerived d = dev_derived(o);
-    launch_density(c.k, s, n, d, c.err(), c.s);
-    launch_boundary(c.k, s, n, d, c.err(), c.s);
-    double *part = at<double>(c.ws, c.w.dragpart);
-    launch_force(c.k, s, n, d, part, c.err(), c.s);
-    launch_drag_final(c.k, part, o->drag, hist, c.s);
+    launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), dev_derived(o),
+                    at<int32_t>(c.ws, c.w.blist), at<int32_t>(c.ws, c.w.bcount), c.err(), c.s);
+}
+
+static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields &W,
+                     const sph_nlist *nl, const sph_derived *o, int mode, double *drag,
+                     double *hist)
+{
+    const int want = drag || hist;
+    launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), dev_derived(o), c.off(),
+                 at<uint32_t>(c.ws, c.w.cpos_s), mode, want, c.dragpart(), c.err(), c.s);
+    if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
 }
 
 }  // namespace sph
@@ -358,15 +402,14 @@ int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws, size
     return check_hip("sph_bin");
 }
 
-int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, void *ws,
-                  size_t ws_bytes, void *stream)
+int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph_derived *out,
+                  void *ws, size_t ws_bytes, void *stream)
 {
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
-    if (rc) return rc;
-    rc = check_nlist(nl);
-    if (rc) return rc;
-    do_neighbors(c, st, nl);
+    if (rc || (rc = check_nlist(nl))) return rc;
+    if (out && (rc = check_derived(out, false))) return rc;
+    do_nbrdens(c, st, fields_of(st), nl, out, out != nullptr);
     return check_hip("sph_neighbors");
 }
 
@@ -375,8 +418,9 @@ int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
 {
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
-    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
-    launch_density(c.k, dev_state(st), dev_nlist(nl), dev_derived(out), c.err(), c.s);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
+    launch_density(c.k, dev_state(st), fields_of(st), dev_nlist(nl), dev_derived(out), c.err(),
+                   c.s);
     return check_hip("sph_density");
 }
 
@@ -385,8 +429,8 @@ int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist
 {
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
-    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
-    launch_boundary(c.k, dev_state(st), dev_nlist(nl), dev_derived(out), c.err(), c.s);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
+    do_boundary(c, st, fields_of(st), nl, out);
     return check_hip("sph_outlet_extrapolate");
 }
 
@@ -396,7 +440,10 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
-    do_rhs(c, st, nl, out, nullptr);
+    const Fields F = fields_of(st);
+    launch_density(c.k, dev_state(st), F, dev_nlist(nl), dev_derived(out), c.err(), c.s);
+    do_boundary(c, st, F, nl, out);
+    do_force(c, st, F, F, nl, out, 0, out->drag, nullptr);
     return check_hip("sph_rhs");
 }
 
@@ -406,10 +453,8 @@ int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
-    const bool reduce = out->drag != nullptr;
-    double *part = at<double>(c.ws, c.w.dragpart);
-    launch_force(c.k, dev_state(st), dev_nlist(nl), dev_derived(out), part, c.err(), c.s);
-    if (reduce) launch_drag_final(c.k, part, out->drag, nullptr, c.s);
+    const Fields F = fields_of(st);
+    do_force(c, st, F, F, nl, out, 0, out->drag, nullptr);
     return check_hip("sph_force");
 }
 
@@ -419,28 +464,29 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
 {
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
-    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
     rc = check_state(alt, prm, "alt");
     if (rc) return rc;
     if (alt->cap != st->cap || alt->prec != st->prec)
         return fail(SPH_EINVAL, "alt must match state in cap and precision");
     if (nsteps < 0) return fail(SPH_EINVAL, "nsteps < 0");
     launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
-    const Dev &k = c.k;
-    double *x0 = at<double>(ws, c.w.x0);
-    void *u0 = at<void>(ws, c.w.u0), *p0 = at<void>(ws, c.w.p0);
+    const Fields H = c.half();
     int32_t *nspawn = at<int32_t>(ws, c.w.nspawn);
     for (int32_t s = 0; s < nsteps; ++s) {
-        do_bin(c, st, alt);  // also records x0, u0, p0
-        do_neighbors(c, st, nl);
-        do_rhs(c, st, nl, out, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr);
-        launch_stage(k, dev_state(st), dev_derived(out), x0, u0, p0, 0, c.err(), c.s);
-        do_neighbors(c, st, nl);
-        do_rhs(c, st, nl, out, nullptr);
-        launch_stage(k, dev_state(st), dev_derived(out), x0, u0, p0, 1, c.err(), c.s);
-        launch_end_of_step(k, dev_state(st), dev_derived(out), nspawn, c.err(), c.s);
-        launch_finish_spawn(k, dev_state(st), nspawn, c.s);
+        do_bin(c, st, alt);
+        const Fields M = fields_of(st);
+        // stage 1 at the start state, written to the half state
+        do_nbrdens(c, st, M, nl, out, 1);
+        do_boundary(c, st, M, nl, out);
+        do_force(c, st, M, H, nl, out, 1, nullptr, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr);
+        // stage 2 at the half state, written back over the start state
+        do_nbrdens(c, st, H, nl, out, 1);
+        do_boundary(c, st, H, nl, out);
+        do_force(c, st, H, M, nl, out, 2, nullptr, nullptr);
+        launch_end_of_step(c.k, dev_state(st), dev_derived(out), nspawn, c.err(), c.s);
     }
+    if (nsteps > 0) launch_finish_spawn(c.k, dev_state(st), nspawn, c.s);
     return check_hip("sph_step");
 }
 
@@ -454,8 +500,9 @@ int sph_poll_error(void *ws, size_t ws_bytes, uint32_t *bits, void *stream)
     uint32_t h = 0;
     if (hipMemcpy(&h, err, sizeof h, hipMemcpyDeviceToHost) != hipSuccess)
         return check_hip("sph_poll_error copy");
-    launch_fill_i32(reinterpret_cast<int32_t *>(err), 1, 0, s);
-    if (hipStreamSynchronize(s) != hipSuccess) return check_hip("sph_poll_error clear");
+    const uint32_t zero = 0;
+    if (hipMemcpy(err, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess)
+        return check_hip("sph_poll_error clear");
     *bits = h;
     return check_hip("sph_poll_error");
 }

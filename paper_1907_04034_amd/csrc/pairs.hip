@@ -1,33 +1,194 @@
-// pairs.hip -- neighbour-pair passes of libsph for gfx950: neighbour table,
-// summation density, boundary values (walls, hybrid outlet, MOC inlet) and the
-// EDAC-TVF force pass with the body force.
+// pairs.hip -- neighbour-pair passes of libsph for gfx950: fused neighbour
+// table + summation density, boundary values (walls, hybrid outlet, MOC
+// inlet) and the EDAC-TVF force pass (optionally fused with the RK2 stage
+// update) with the body force.
 //
-// One work-item per target particle; particles are Morton-sorted so the
-// neighbours of a wave's 64 targets lie in a handful of cells and their
-// gathers are served from L2. The neighbour table is column-major
-// (nbr[k * cap + i]) so the k-th neighbour of 64 consecutive targets is one
-// coalesced 256-byte load.
+// Work decomposition: a group of G lanes (G = 16 in 2D, 32 in 3D; 4 or 2
+// groups per wave64) owns one target particle and each lane one neighbour, so
+// every neighbour gather of a target is in flight at once and small particle
+// counts still put thousands of waves on the 256 CUs. Per-target sums are
+// reduced across the group with lane shuffles; in FP32 the reduction carries
+// the rounding error of every addition (TwoSum), i.e. compensated FP32
+// accumulation. Particles are Morton-sorted, the neighbour table is row-major
+// (the neighbours of one target are contiguous, one coalesced load per group)
+// and the block -> particle-range mapping is XCD-aware so that each of the 8
+// XCDs works on a contiguous slab and its L2 serves the neighbour re-reads.
 #include "sph_launch.h"
 
 namespace sph {
 
-// ---------------------------------------------------------- neighbour table
+// ----------------------------------------------------------------- helpers
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_neighbors(Dev k, DevState s, DevNlist nl,
-                                                      const uint32_t *spread,
-                                                      const int32_t *cell_start,
-                                                      const uint32_t *cpos, uint32_t *err)
+struct Grp {
+    static constexpr int G = DIM == 2 ? 16 : 32;   // lanes per target
+    static constexpr int NS = DIM == 2 ? 9 : 27;   // stencil cells
+    static constexpr int LOGNS = DIM == 2 ? 4 : 5; // binary-search steps
+    static constexpr int PER_BLOCK = kBlock / G;   // targets per block
+};
+
+// Lanes per target of the neighbour search and the force pass are template
+// parameters: many lanes per target keep small systems busy (every gather of
+// a target in flight at once), few lanes (down to one) spend no issue slots on
+// idle lanes and cross-lane reductions when the particle count alone fills
+// the chip. The host picks them from the capacity (override in sph_params).
+
+// Logical block for hardware block blockIdx.x when nb_logical blocks are
+// needed: the 8 XCDs (which receive consecutive hardware blocks round-robin)
+// each get one contiguous range of logical blocks. Returns -1 for hardware
+// blocks beyond the need.
+__device__ inline int64_t xcd_block(int64_t nb_logical)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = *s.n;
-    if (i >= n) return;
+    const int64_t per = (nb_logical + 7) / 8;
+    const int64_t b = blockIdx.x;
+    if (b / 8 >= per) return -1;
+    const int64_t lb = (b % 8) * per + b / 8;
+    return lb < nb_logical ? lb : -1;
+}
+
+inline int xcd_grid(int64_t nb_logical) { return int(((nb_logical + 7) / 8) * 8); }
+
+template <int G, typename V>
+__device__ inline V gsum(V v)
+{
+#pragma unroll
+    for (int m = G / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, G);
+    return v;
+}
+
+// Error-free addition (Knuth TwoSum): s + e == a + b exactly.
+__device__ inline void two_sum(float a, float b, float &s, float &e)
+{
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Per-lane accumulator and its group reduction: plain sums in FP64; in FP32
+// a value plus its running rounding error, carried through the reduction.
+template <typename T>
+struct Acc {
+    T s = T(0);
+    __device__ inline void add(T v) { s += v; }
+    template <int G>
+    __device__ inline T reduce() { return gsum<G>(s); }
+};
+
+template <>
+struct Acc<float> {
+    float s = 0.f, e = 0.f;
+    __device__ inline void add(float v)
+    {
+        float t;
+        two_sum(s, v, s, t);
+        e += t;
+    }
+    template <int G>
+    __device__ inline float reduce()
+    {
+#pragma unroll
+        for (int m = G / 2; m > 0; m >>= 1) {
+            float os = __shfl_xor(s, m, G), oe = __shfl_xor(e, m, G), t;
+            two_sum(s, os, s, t);
+            e = e + oe + t;
+        }
+        return s + e;
+    }
+};
+
+__device__ inline bool bad_index(int32_t j, int64_t n) { return uint64_t(j) >= uint64_t(n); }
+
+// Pair separation r_i - r_j in the arithmetic type. FP64: minimum image of
+// the absolute positions. FP32: cell-relative offsets plus the (wrapped)
+// cell difference times the cell size, so no large coordinate is rounded to
+// FP32.
+template <int DIM, typename T>
+struct Sep;
+
+template <int DIM>
+struct Sep<DIM, double> {
+    double xi[3];
+    __device__ inline void load_i(const Dev &k, const Fields &R, const float *, const uint32_t *,
+                                  int64_t i)
+    {
+        xi[2] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * k.cap + i];
+    }
+    __device__ inline double get(const Dev &k, const Fields &R, const float *, const uint32_t *,
+                                 int64_t j, double r[3]) const
+    {
+        double xj[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * k.cap + j];
+        return dist2_exact<DIM>(k, xi, xj, r);
+    }
+};
+
+template <int DIM>
+struct Sep<DIM, float> {
+    float oi[3];
+    int ci[3];
+    __device__ inline void load_i(const Dev &k, const Fields &, const float *off,
+                                  const uint32_t *cpos, int64_t i)
+    {
+        oi[2] = 0.f;
+        unpack_cell<DIM>(cpos[i], ci);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) oi[d] = off[d * k.cap + i];
+    }
+    __device__ inline float get(const Dev &k, const Fields &, const float *off,
+                                const uint32_t *cpos, int64_t j, float r[3]) const
+    {
+        int cj[3];
+        unpack_cell<DIM>(cpos[j], cj);
+        float s = 0.f;
+        r[2] = 0.f;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            int dc = ci[d] - cj[d];
+            if (k.periodic[d]) {
+                if (dc > 1) dc -= k.nc[d];
+                else if (dc < -1) dc += k.nc[d];
+            }
+            r[d] = (oi[d] - off[d * k.cap + j]) + float(dc) * k.csf[d];
+            s += r[d] * r[d];
+        }
+        return s;
+    }
+};
+
+// ---------------------------------------------- neighbour table + density
+// The group walks the 3^d stencil cells in (dz, dy, dx) order; for each cell
+// its lanes test members b + lane, b + lane + G, ... with the FMA-free FP64
+// predicate |r|^2 < (2h)^2 and hits are compacted with a ballot, so the table
+// keeps the stencil-then-cell order. The density (Sec. 2
+// eq:summation-density, V = 1/sum W) is summed from the same pairs when `dens`
+// is set. FP32 mode records the cell-relative offsets the force pass uses.
+template <int DIM, typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R, DevNlist nl,
+                                                    DevDerived o, int dens,
+                                                    const uint32_t *spread,
+                                                    const int32_t *cell_start,
+                                                    const uint32_t *cpos, float *off,
+                                                    uint32_t *err)
+{
+    constexpr int PB = kBlock / G;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t n = *m.n;
+    const int64_t lb = xcd_block((n + PB - 1) / PB);
+    const int64_t i = lb * PB + threadIdx.x / G;
+    if (lb < 0 || i >= n) return;  // uniform across the group
     const int64_t C = k.cap;
     double xi[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xi[d] = s.x[d * C + i];
+    for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
     int c[3];
     unpack_cell<DIM>(cpos[i], c);
+    const int gshift = (threadIdx.x & 63) & ~(G - 1);
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
+    const uint64_t below = (1ull << lane) - 1;
     int cnt = 0;
+    Acc<T> sw;
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz)
         for (int dy = -1; dy <= 1; ++dy)
@@ -42,178 +203,381 @@ __global__ void __launch_bounds__(kBlock) k_neighbors(Dev k, DevState s, DevNlis
                     }
                 }
                 if (!ok) continue;
-                uint32_t key = morton_key<DIM>(spread, cc);
-                int32_t b = cell_start[key], e = cell_start[key + 1];
+                const uint32_t key = morton_key<DIM>(spread, cc);
+                const int32_t b = cell_start[key], e = cell_start[key + 1];
                 if (b < 0 || e > n || b > e) {
                     raise_error(err, SPH_ERR_CELL_RANGE);
                     continue;
                 }
-                for (int32_t j = b; j < e; ++j) {
-                    double xj[3] = {0, 0, 0};
+                for (int32_t j0 = b; j0 < e; j0 += G) {
+                    const int32_t j = j0 + lane;
+                    bool hit = false;
+                    double r2 = 0.0;
+                    if (j < e) {
+                        double xj[3] = {0, 0, 0};
 #pragma unroll
-                    for (int d = 0; d < DIM; ++d) xj[d] = s.x[d * C + j];
-                    double r[3];
-                    double r2 = dist2_exact<DIM>(k, xi, xj, r);
-                    if (r2 < k.sup2) {
-                        if (cnt < nl.maxnb) nl.nbr[int64_t(cnt) * C + i] = j;
-                        ++cnt;
+                        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
+                        double r[3];
+                        r2 = dist2_exact<DIM>(k, xi, xj, r);
+                        hit = r2 < k.sup2;
                     }
+                    int pos = cnt, nhit = hit ? 1 : 0;
+                    if (G > 1) {
+                        const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
+                        pos = cnt + __popcll(bal & below);
+                        nhit = __popcll(bal);
+                    }
+                    if (hit) {
+                        if (pos < nl.maxnb) nl.nbr[i * nl.maxnb + pos] = j;
+                        if (dens) sw.add(wendland_w<T>(T(sqrt(r2) * k.inv_h), T(k.wnorm)));
+                    }
+                    cnt += nhit;
                 }
             }
-    if (cnt > nl.maxnb) {
-        raise_error(err, SPH_ERR_NBR_OVERFLOW);
-        cnt = nl.maxnb;
+    const T S = sw.template reduce<G>();
+    if (lane == 0) {
+        if (cnt > nl.maxnb) {
+            raise_error(err, SPH_ERR_NBR_OVERFLOW);
+            cnt = nl.maxnb;
+        }
+        nl.count[i] = cnt;
+        if (dens) {
+            st<T>(o.rho, i, T(k.mass) * S);
+            st<T>(o.vol, i, T(1) / S);
+        }
     }
-    nl.count[i] = cnt;
+    if (sizeof(T) == 4) {
+        // offsets from the bin cell's corner, for the FP32 pair arithmetic
+        for (int d = lane; d < DIM; d += G)
+            off[d * C + i] = float(xi[d] - (k.lo[d] + double(c[d]) * k.cs[d]));
+    }
 }
 
-// Neighbour index check: a table from the wrong workspace or a stale count
-// must not send a gather out of bounds.
-__device__ inline bool bad_index(int32_t j, int64_t n) { return uint64_t(j) >= uint64_t(n); }
-
-// ------------------------------------------------------------------ density
-// Sec. 2 eq:summation-density with m_j = m, and V_i = 1 / sum_j W_ij.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState s, DevNlist nl,
+// Summation density from an existing neighbour table (the API path; the step
+// path sums it while building the table).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R, DevNlist nl,
                                                     DevDerived o, uint32_t *err)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = *s.n;
-    if (i >= n) return;
+    using P = Grp<DIM>;
+    constexpr int G = P::G;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t n = *m.n;
+    const int64_t lb = xcd_block((n + P::PER_BLOCK - 1) / P::PER_BLOCK);
+    const int64_t i = lb * P::PER_BLOCK + threadIdx.x / G;
+    if (lb < 0 || i >= n) return;
     const int64_t C = k.cap;
     double xi[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xi[d] = s.x[d * C + i];
-    int cnt = nl.count[i];
-    double sw = 0.0;
-    for (int q = 0; q < cnt; ++q) {
-        int32_t j = nl.nbr[int64_t(q) * C + i];
+    for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
+    const int cnt = nl.count[i];
+    Acc<T> sw;
+    for (int q = lane; q < cnt; q += G) {
+        const int32_t j = nl.nbr[i * nl.maxnb + q];
         if (bad_index(j, n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
             continue;
         }
         double xj[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) xj[d] = s.x[d * C + j];
+        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
         double r[3];
-        double r2 = dist2_exact<DIM>(k, xi, xj, r);
-        sw += wendland_w(sqrt(r2) / k.h, k.wnorm);
+        sw.add(wendland_w<T>(T(sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h), T(k.wnorm)));
     }
-    st<double>(o.rho, i, k.mass * sw);
-    st<double>(o.vol, i, 1.0 / sw);
+    const T S = sw.template reduce<G>();
+    if (lane == 0) {
+        st<T>(o.rho, i, T(k.mass) * S);
+        st<T>(o.vol, i, T(1) / S);
+    }
 }
 
 // ---------------------------------------------------------- boundary values
-// Walls: Shepard-averaged fluid pressure and ghost velocity u_g = -<u_f>
-// (static walls, no body force). Outlet: characteristic variables of the
-// fluid with the fluid's own time averages as references (Sec. 3.3
-// eq:characteristic-vars, Sec. 3.4), Shepard-interpolated (eq:shepard), J3 = 0;
-// particles with no fluid in support take the mean previous-step value of
-// same-kind neighbours that had support (eq:average_old), else their own;
-// then u, p = time average + acoustic part (eq:acou) with rho_ref = rho0.
-// Inlet: prescribed velocity, p = Shepard J3 with reference (u_in, 0).
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState s, DevNlist nl,
-                                                     DevDerived o, uint32_t *err)
+// Over the non-fluid rows listed at bin time. Walls: Shepard-averaged fluid
+// pressure and ghost velocity u_g = -<u_f> (static walls, no body force).
+// Outlet: characteristic variables of the fluid with the fluid's own time
+// averages as references (Sec. 3.3 eq:characteristic-vars, Sec. 3.4),
+// Shepard-interpolated (eq:shepard), J3 = 0; without fluid support the mean
+// previous-step value of same-kind neighbours that had support
+// (eq:average_old), else the particle's own; then u, p = time average +
+// acoustic part (eq:acou) with rho_ref = rho0. Inlet: prescribed velocity,
+// p = Shepard J3 with reference (u_in, 0). Always FP64 arithmetic.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R, DevNlist nl,
+                                                     DevDerived o, const int32_t *blist,
+                                                     const int32_t *bcount, uint32_t *err)
 {
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = *s.n;
-    if (i >= n) return;
-    const int t = s.type[i];
-    if (t == SPH_FLUID) return;
+    using P = Grp<DIM>;
+    constexpr int G = P::G;
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t n = *m.n;
+    const int64_t nbnd = *bcount;
     const int64_t C = k.cap;
-    double xi[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) xi[d] = s.x[d * C + i];
-    const double uin0 = s.uin[i];
-    double sw = 0.0, sp = 0.0, su[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
-    int cnt = nl.count[i];
-    for (int q = 0; q < cnt; ++q) {
-        int32_t j = nl.nbr[int64_t(q) * C + i];
-        if (bad_index(j, n)) {
+    const int64_t stride = int64_t(gridDim.x) * P::PER_BLOCK;
+    for (int64_t g = int64_t(blockIdx.x) * P::PER_BLOCK + threadIdx.x / G; g < nbnd;
+         g += stride) {
+        const int64_t i = blist[g];
+        if (bad_index(int32_t(i), n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
             continue;
         }
-        if (s.type[j] != SPH_FLUID) continue;
-        double xj[3] = {0, 0, 0};
+        const int t = m.type[i];
+        if (t == SPH_FLUID) continue;
+        double xi[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) xj[d] = s.x[d * C + j];
-        double r[3];
-        double w = wendland_w(sqrt(dist2_exact<DIM>(k, xi, xj, r)) / k.h, k.wnorm);
-        double pj = ld<double>(s.p, j);
-        double rhoj = ld<double>(o.rho, j);
-        double uj0 = ld<double>(s.u, j);
-        sw += w;
-        sp += pj * w;
+        for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
+        const double uin0 = m.uin[i];
+        const int cnt = nl.count[i];
+        double sw = 0.0, sp = 0.0, su[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
+        for (int q = lane; q < cnt; q += G) {
+            const int32_t j = nl.nbr[i * nl.maxnb + q];
+            if (bad_index(j, n)) {
+                raise_error(err, SPH_ERR_CELL_RANGE);
+                continue;
+            }
+            if (m.type[j] != SPH_FLUID) continue;
+            double xj[3] = {0, 0, 0};
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) su[d] += ld<double>(s.u, d * C + j) * w;
-        if (t == SPH_INLET) {
-            sJ[2] += (-rhoj * k.c * (uj0 - uin0) + pj) * w;
-        } else if (t == SPH_OUTLET) {
-            double dp = pj - s.avg[DIM * C + j];
-            double du = uj0 - s.avg[j];
-            sJ[0] += (-k.c2 * (rhoj - k.rho0) + dp) * w;
-            sJ[1] += (rhoj * k.c * du + dp) * w;
-            sJ[2] += (-rhoj * k.c * du + dp) * w;
-        }
-    }
-    if (is_wall(t)) {
-        double pw = 0.0, ug[3] = {0, 0, 0};
-        if (sw > 0.0) {
-            pw = sp / sw;
+            for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
+            double r[3];
+            const double w = wendland_w(sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h, k.wnorm);
+            const double pj = double(ld<T>(R.p, j));
+            const double rhoj = double(ld<T>(o.rho, j));
+            const double uj0 = double(ld<T>(R.u, j));
+            sw += w;
+            sp += pj * w;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) ug[d] = -(su[d] / sw);
-        }
-        st<double>(s.p, i, pw);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) st<double>(s.u, d * C + i, ug[d]);
-        return;
-    }
-    double J[3];
-    uint8_t red;
-    if (sw > 0.0) {
-        red = 1;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) J[a] = sJ[a] / sw;
-        if (t == SPH_OUTLET) J[2] = 0.0;
-    } else {
-        red = 0;
-        double acc[3] = {0, 0, 0};
-        int M = 0;
-        for (int q = 0; q < cnt; ++q) {
-            int32_t j = nl.nbr[int64_t(q) * C + i];
-            if (bad_index(j, n)) continue;
-            if (s.type[j] == t && s.red_prev[j]) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) acc[a] += s.jprev[a * C + j];
-                ++M;
+            for (int d = 0; d < DIM; ++d) su[d] += double(ld<T>(R.u, d * C + j)) * w;
+            if (t == SPH_INLET) {
+                sJ[2] += (-rhoj * k.c * (uj0 - uin0) + pj) * w;
+            } else if (t == SPH_OUTLET) {
+                const double dp = pj - m.avg[DIM * C + j];
+                const double du = uj0 - m.avg[j];
+                sJ[0] += (-k.c2 * (rhoj - k.rho0) + dp) * w;
+                sJ[1] += (rhoj * k.c * du + dp) * w;
+                sJ[2] += (-rhoj * k.c * du + dp) * w;
             }
         }
+        sw = gsum<G>(sw);
+        sp = gsum<G>(sp);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) J[a] = M ? acc[a] / double(M) : s.jprev[a * C + i];
-    }
+        for (int d = 0; d < DIM; ++d) su[d] = gsum<G>(su[d]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) o.jcur[a * C + i] = J[a];
-    o.red[i] = red;
-    if (t == SPH_OUTLET) {
-        double p_ac = 0.5 * (J[1] + J[2]);
-        double u_ac = (J[1] - J[2]) / (2.0 * k.rho0 * k.c);
-        st<double>(s.p, i, s.avg[DIM * C + i] + p_ac);
-        double u0v = s.avg[i] + u_ac;
-        st<double>(s.u, i, u0v);
-        st<double>(s.ut, i, u0v);
+        for (int a = 0; a < 3; ++a) sJ[a] = gsum<G>(sJ[a]);
+        if (is_wall(t)) {
+            if (lane == 0) {
+                double pw = 0.0;
+                double ug[3] = {0, 0, 0};
+                if (sw > 0.0) {
+                    pw = sp / sw;
 #pragma unroll
-        for (int d = 1; d < DIM; ++d) {
-            st<double>(s.u, d * C + i, s.avg[d * C + i]);
-            st<double>(s.ut, d * C + i, s.avg[d * C + i]);
+                    for (int d = 0; d < DIM; ++d) ug[d] = -(su[d] / sw);
+                }
+                st<T>(R.p, i, T(pw));
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, T(ug[d]));
+            }
+            continue;
         }
-    } else {  // inlet
-        st<double>(s.p, i, J[2]);
+        double J[3];
+        uint8_t red;
+        if (sw > 0.0) {
+            red = 1;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) J[a] = sJ[a] / sw;
+            if (t == SPH_OUTLET) J[2] = 0.0;
+        } else {
+            red = 0;
+            double acc[3] = {0, 0, 0}, M = 0.0;
+            for (int q = lane; q < cnt; q += G) {
+                const int32_t j = nl.nbr[i * nl.maxnb + q];
+                if (bad_index(j, n)) continue;
+                if (m.type[j] == t && m.red_prev[j]) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) acc[a] += m.jprev[a * C + j];
+                    M += 1.0;
+                }
+            }
+            M = gsum<G>(M);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                acc[a] = gsum<G>(acc[a]);
+                J[a] = M > 0.0 ? acc[a] / M : m.jprev[a * C + i];
+            }
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) o.jcur[a * C + i] = J[a];
+            o.red[i] = red;
+            if (t == SPH_OUTLET) {
+                const double p_ac = 0.5 * (J[1] + J[2]);
+                const double u_ac = (J[1] - J[2]) / (2.0 * k.rho0 * k.c);
+                st<T>(R.p, i, T(m.avg[DIM * C + i] + p_ac));
+                const double u0v = m.avg[i] + u_ac;
+                st<T>(R.u, i, T(u0v));
+                st<T>(R.ut, i, T(u0v));
+#pragma unroll
+                for (int d = 1; d < DIM; ++d) {
+                    st<T>(R.u, d * C + i, T(m.avg[d * C + i]));
+                    st<T>(R.ut, d * C + i, T(m.avg[d * C + i]));
+                }
+            } else {  // inlet: prescribed velocity, p = J3
+                st<T>(R.p, i, T(J[2]));
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    st<T>(R.u, d * C + i, T(m.uin[d * C + i]));
+                    st<T>(R.ut, d * C + i, T(m.uin[d * C + i]));
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ stage updates
+// Explicit-midpoint RK2 (the integrator is the implementation's reading; the
+// paper defers time stepping to the EDAC paper) with eq:transport-vel applied
+// per stage and eq:advection for positions. Contraction is off so that the
+// update evaluates the formula as written.
+template <int DIM, typename T>
+__device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &W, int64_t i,
+                                   int mode, const T ui[3], T pi, const T a[3], const T b[3],
+                                   T pd, uint32_t *err)
+{
+#pragma clang fp contract(off)
+    const int64_t C = k.cap;
+    const double dt = mode == 2 ? k.dt : k.hdt;
+    bool fin = true;
+    double xn[3] = {0, 0, 0}, un[3] = {0, 0, 0}, utn[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double x0 = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
+        const double u0 = mode == 2 ? double(ld<T>(W.u, d * C + i)) : double(ui[d]);
+        un[d] = u0 + dt * double(a[d]);
+        utn[d] = un[d] + dt * double(b[d]);
+        const double adv = mode == 2 ? double(ld<T>(R.ut, d * C + i)) : utn[d];
+        xn[d] = x0 + dt * adv;
+        fin = fin && isfinite(un[d]) && isfinite(utn[d]);
+    }
+    const double p0 = mode == 2 ? double(ld<T>(W.p, i)) : double(pi);
+    const double pn = p0 + dt * double(pd);
+    fin = fin && isfinite(pn);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double v = xn[d];
+        if (k.periodic[d]) {
+            const double hi = k.lo[d] + k.L[d];
+            if (v >= hi) v -= k.L[d];
+            else if (v < k.lo[d]) v += k.L[d];
+        }
+        if (mode == 1) {
+            const double disp = min_image(v - R.x[d * C + i], k.periodic[d], k.L[d], k.halfL[d]);
+            if (!(fabs(disp) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
+        }
+        fin = fin && isfinite(v);
+        W.x[d * C + i] = v;
+        st<T>(W.u, d * C + i, T(un[d]));
+        st<T>(W.ut, d * C + i, T(utn[d]));
+    }
+    st<T>(W.p, i, T(pn));
+    if (!fin) raise_error(err, SPH_ERR_NONFINITE);
+}
+
+// Inlet rows move with their prescribed velocity and outlet rows along x with
+// their composed velocity (Sec. 3.4: no transverse motion); walls are fixed.
+// The full update also makes the half state's boundary values the step's.
+template <int DIM, typename T>
+__device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fields &R,
+                                      const Fields &W, int64_t i, int t, int mode,
+                                      uint32_t *err)
+{
+#pragma clang fp contract(off)
+    const int64_t C = k.cap;
+    const double dt = mode == 2 ? k.dt : k.hdt;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double x0 = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
+        double v = x0;
+        if (d == 0 && (t == SPH_INLET || t == SPH_OUTLET)) {
+            const double vx = t == SPH_INLET ? m.uin[i] : double(ld<T>(R.u, i));
+            v = x0 + dt * vx;
+            if (mode == 1 && !(fabs(v - x0) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
+            if (!isfinite(v)) raise_error(err, SPH_ERR_NONFINITE);
+        }
+        W.x[d * C + i] = v;
+        if (mode == 2) {
+            st<T>(W.u, d * C + i, ld<T>(R.u, d * C + i));
+            st<T>(W.ut, d * C + i, ld<T>(R.ut, d * C + i));
+        }
+    }
+    if (mode == 2) st<T>(W.p, i, ld<T>(R.p, i));
+}
+
+// One neighbour's data as a lane of the force pass needs it.
+template <int DIM, typename T>
+struct Nbr {
+    int32_t j;
+    int tj;
+    T r[3], r2, u[3], w[3], p, rho, vol;  // w = ut - u
+};
+
+template <int DIM, typename T>
+__device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R,
+                                const DevDerived &o, const float *off, const uint32_t *cpos,
+                                const Sep<DIM, T> &sep, int32_t j, Nbr<DIM, T> &nb)
+{
+    const int64_t C = k.cap;
+    nb.j = j;
+    nb.tj = m.type[j];
+    nb.r2 = sep.get(k, R, off, cpos, j, nb.r);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        nb.u[d] = ld<T>(R.u, d * C + j);
+        nb.w[d] = ld<T>(R.ut, d * C + j) - nb.u[d];
+    }
+    nb.p = ld<T>(R.p, j);
+    nb.rho = ld<T>(o.rho, j);
+    nb.vol = ld<T>(o.vol, j);
+}
+
+// Contribution of neighbour nb to target i (see the force-pass comment).
+template <int DIM, typename T>
+__device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3], T pi, T rhoi,
+                                T vi2, T pavg, const Nbr<DIM, T> &nb, Acc<T> acc[3],
+                                Acc<T> bacc[3], Acc<T> &pdot, double fb[3])
+{
+    const T F = wendland_f<T>(T(sqrt(nb.r2)) * T(k.inv_h), T(k.gnorm));
+    T gw[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) gw[d] = F * nb.r[d];
+    const T vsq = vi2 + nb.vol * nb.vol;
+    const T inv_rs = T(1) / (rhoi + nb.rho);
+    const T ptil = (nb.rho * (pi - pavg) + rhoi * (nb.p - pavg)) * inv_rs;
+    const T hm = T(2) * rhoi * nb.rho * inv_rs;  // eta~ / nu
+    const T dfac = F * nb.r2 / (nb.r2 + T(k.eta_h2));
+    const T nu = T(k.nu);
+    if (t == SPH_FLUID) {
+        T si = T(0), sj = T(0);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) si += wi[d] * gw[d];
+        if (nb.tj == SPH_FLUID)
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sj += nb.w[d] * gw[d];
+        const T visc = nb.tj == SPH_WALL_SLIP ? T(0) : hm * nu * dfac;
+        const T f = vsq * T(k.inv_mass);
+        const bool wall = is_wall(nb.tj);
+        T udiv = T(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            st<double>(s.u, d * C + i, s.uin[d * C + i]);
-            st<double>(s.ut, d * C + i, s.uin[d * C + i]);
+            const T aterm = T(0.5) * (rhoi * ui[d] * si + nb.rho * nb.u[d] * sj);
+            acc[d].add(f * (-ptil * gw[d] + aterm + visc * (ui[d] - nb.u[d])));
+            bacc[d].add(-T(k.pb) * T(k.inv_mass) * vsq * gw[d]);
+            udiv += (ui[d] - (wall ? T(0) : nb.u[d])) * gw[d];
         }
+        pdot.add(T(k.mass) * rhoi / nb.rho * T(k.c2) * udiv +
+                 f * (hm * T(k.nu_damp)) * dfac * (pi - nb.p));
+    } else {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d)
+            fb[d] += double(vsq * (-ptil * gw[d] + hm * nu * dfac * (ui[d] - nb.u[d])));
     }
 }
 
@@ -224,121 +588,124 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState s, DevNlist
 // for fluid, 0 otherwise; slip walls take no viscous part; walls enter the
 // divergence with zero wall velocity and the viscous term with u_g.
 // Body i: force of eq:tvf-momentum_solid from fluid neighbours.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState s, DevNlist nl, DevDerived o,
+//
+// mode 0 writes a, b, pdot, pavg (and force for body rows). Modes 1 (half)
+// and 2 (full) instead apply the explicit-midpoint stage update from the
+// start-of-step values,
+//     u = u0 + dt a,  p = p0 + dt pdot,  ut = u + dt b,  x = x0 + dt ut_half,
+// reading the stage state R and writing W. Half: R is the start state and W
+// the half state. Full: R is the half state and W the start state, whose own
+// row each target reads before overwriting it (no other lane reads W).
+// Inlet particles move with their prescribed velocity, outlet particles along
+// x with their composed velocity, walls are fixed; in the full update the
+// boundary values of the half state become those of the step.
+template <int DIM, typename T, int G>
+__global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, Fields W,
+                                                  DevNlist nl, DevDerived o, const float *off,
+                                                  const uint32_t *cpos, int mode, int want_drag,
                                                   double *dragpart, uint32_t *err)
 {
-    __shared__ double red_lds[3][kBlock];
-    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    int64_t n = *s.n;
+    constexpr int PB = kBlock / G;
+    __shared__ double red_lds[3][PB];
+    const int lane = threadIdx.x & (G - 1);
+    const int64_t n = *m.n;
+    const int64_t lb = xcd_block((n + PB - 1) / PB);
+    const int64_t i = lb * PB + threadIdx.x / G;
     const int64_t C = k.cap;
     double fb[3] = {0, 0, 0};
-    if (i < n) {
-        const int t = s.type[i];
-        double acc[3] = {0, 0, 0}, bacc[3] = {0, 0, 0}, pdot = 0.0, pavg = 0.0;
+    if (lb >= 0 && i < n) {
+        const int t = m.type[i];
         if (t == SPH_FLUID || t == SPH_BODY) {
             const int cnt = nl.count[i];
-            if (!(k.flags & SPH_FLAG_NO_PAVG)) {
-                double sp = 0.0;
-                for (int q = 0; q < cnt; ++q) {
-                    int32_t j = nl.nbr[int64_t(q) * C + i];
-                    if (bad_index(j, n)) continue;
-                    sp += ld<double>(s.p, j);
-                }
-                pavg = sp / double(cnt);
-            }
-            double xi[3] = {0, 0, 0}, ui[3] = {0, 0, 0}, wi[3] = {0, 0, 0};
+            Sep<DIM, T> sep;
+            sep.load_i(k, R, off, cpos, i);
+            T ui[3] = {0, 0, 0}, wi[3] = {0, 0, 0};
 #pragma unroll
             for (int d = 0; d < DIM; ++d) {
-                xi[d] = s.x[d * C + i];
-                ui[d] = ld<double>(s.u, d * C + i);
-                wi[d] = ld<double>(s.ut, d * C + i) - ui[d];
+                ui[d] = ld<T>(R.u, d * C + i);
+                wi[d] = ld<T>(R.ut, d * C + i) - ui[d];
             }
-            const double pi = ld<double>(s.p, i);
-            const double rhoi = ld<double>(o.rho, i);
-            const double vi = ld<double>(o.vol, i);
-            const double vi2 = vi * vi;
-            const double inv_m = 1.0 / k.mass;
-            for (int q = 0; q < cnt; ++q) {
-                int32_t j = nl.nbr[int64_t(q) * C + i];
+            const T pi = ld<T>(R.p, i);
+            const T rhoi = ld<T>(o.rho, i);
+            const T vi = ld<T>(o.vol, i);
+            const T vi2 = vi * vi;
+            // the lane's first neighbour is loaded before the pbar reduction so
+            // that with at most G neighbours all gathers form one round trip
+            const bool have0 = lane < cnt;
+            const int32_t j0 = have0 ? nl.nbr[i * nl.maxnb + lane] : -1;
+            const bool ok0 = have0 && !bad_index(j0, n);
+            if (have0 && !ok0) raise_error(err, SPH_ERR_CELL_RANGE);
+            Nbr<DIM, T> nb0;
+            if (ok0) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j0, nb0);
+            T pavg = T(0);
+            if (!(k.flags & SPH_FLAG_NO_PAVG)) {
+                Acc<T> sp;
+                if (ok0) sp.add(nb0.p);
+                for (int q = lane + G; q < cnt; q += G) {
+                    const int32_t j = nl.nbr[i * nl.maxnb + q];
+                    if (!bad_index(j, n)) sp.add(ld<T>(R.p, j));
+                }
+                pavg = sp.template reduce<G>() / T(cnt);
+            }
+            Acc<T> acc[3], bacc[3], pdot;
+            if (ok0 && j0 != i && !(t == SPH_BODY && nb0.tj != SPH_FLUID))
+                pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb0, acc, bacc, pdot, fb);
+            for (int q = lane + G; q < cnt; q += G) {
+                const int32_t j = nl.nbr[i * nl.maxnb + q];
                 if (bad_index(j, n)) {
                     raise_error(err, SPH_ERR_CELL_RANGE);
                     continue;
                 }
                 if (j == i) continue;
-                const int tj = s.type[j];
-                if (t == SPH_BODY && tj != SPH_FLUID) continue;
-                double xj[3] = {0, 0, 0};
+                Nbr<DIM, T> nb;
+                load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j, nb);
+                if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
+                pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
+            }
+            T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) xj[d] = s.x[d * C + j];
-                double r[3];
-                const double r2 = dist2_exact<DIM>(k, xi, xj, r);
-                const double F = wendland_f(sqrt(r2) / k.h, k.gnorm);
-                double gw[3] = {0, 0, 0}, uj[3] = {0, 0, 0};
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    gw[d] = F * r[d];
-                    uj[d] = ld<double>(s.u, d * C + j);
-                }
-                const double vj = ld<double>(o.vol, j);
-                const double vsq = vi2 + vj * vj;
-                const double rhoj = ld<double>(o.rho, j);
-                const double pj = ld<double>(s.p, j);
-                const double inv_rs = 1.0 / (rhoi + rhoj);
-                const double ptil = (rhoj * (pi - pavg) + rhoi * (pj - pavg)) * inv_rs;
-                const double hm = 2.0 * rhoi * rhoj * inv_rs;  // eta~ / nu
-                const double dfac = F * r2 / (r2 + k.eta_h2);
-                if (t == SPH_FLUID) {
-                    double si = 0.0, sj = 0.0;
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) si += wi[d] * gw[d];
-                    if (tj == SPH_FLUID) {
-#pragma unroll
-                        for (int d = 0; d < DIM; ++d)
-                            sj += (ld<double>(s.ut, d * C + j) - uj[d]) * gw[d];
-                    }
-                    const double visc = tj == SPH_WALL_SLIP ? 0.0 : hm * k.nu * dfac;
-                    const double f = vsq * inv_m;
-                    double udiv = 0.0;
-                    const bool wall = is_wall(tj);
+            for (int d = 0; d < DIM; ++d) {
+                a[d] = acc[d].template reduce<G>();
+                b[d] = bacc[d].template reduce<G>();
+                fb[d] = gsum<G>(fb[d]);
+            }
+            const T pd = pdot.template reduce<G>();
+            if (lane == 0) {
+                if (mode == 0) {
 #pragma unroll
                     for (int d = 0; d < DIM; ++d) {
-                        const double aterm = 0.5 * (rhoi * ui[d] * si + rhoj * uj[d] * sj);
-                        acc[d] += f * (-ptil * gw[d] + aterm + visc * (ui[d] - uj[d]));
-                        bacc[d] += -k.pb * inv_m * vsq * gw[d];
-                        udiv += (ui[d] - (wall ? 0.0 : uj[d])) * gw[d];
+                        st<T>(o.a, d * C + i, a[d]);
+                        st<T>(o.b, d * C + i, b[d]);
                     }
-                    pdot += k.mass * rhoi / rhoj * k.c2 * udiv +
-                            f * (hm * k.nu_damp) * dfac * (pi - pj);
-                } else {
+                    st<T>(o.pdot, i, pd);
+                    st<T>(o.pavg, i, pavg);
+                    if (t == SPH_BODY)
 #pragma unroll
-                    for (int d = 0; d < DIM; ++d)
-                        fb[d] += vsq * (-ptil * gw[d] + hm * k.nu * dfac * (ui[d] - uj[d]));
+                        for (int d = 0; d < DIM; ++d) o.force[d * C + i] = fb[d];
+                } else if (t == SPH_FLUID) {
+                    stage_fluid<DIM, T>(k, R, W, i, mode, ui, pi, a, b, pd, err);
                 }
             }
         }
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            st<double>(o.a, d * C + i, acc[d]);
-            st<double>(o.b, d * C + i, bacc[d]);
-            if (t == SPH_BODY) o.force[d * C + i] = fb[d];
-        }
-        st<double>(o.pdot, i, pdot);
-        st<double>(o.pavg, i, pavg);
+        // every non-fluid row (walls, bodies, inlet, outlet) takes its stage
+        // position and, in the full update, its half-state boundary values
+        if (mode != 0 && t != SPH_FLUID && lane == 0) stage_boundary<DIM, T>(k, m, R, W, i, t, mode, err);
     }
-    // deterministic per-block partial of the body force (fixed tree order)
+    if (!want_drag) return;
+    // deterministic per-block partial of the body force (fixed order)
+    const int gid = threadIdx.x / G;
+    if (lane == 0)
 #pragma unroll
-    for (int d = 0; d < 3; ++d) red_lds[d][threadIdx.x] = fb[d];
+        for (int d = 0; d < 3; ++d) red_lds[d][gid] = fb[d];
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (int(threadIdx.x) < off)
+    if (threadIdx.x == 0) {
+        double s[3] = {0, 0, 0};
+        for (int q = 0; q < PB; ++q)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) red_lds[d][threadIdx.x] += red_lds[d][threadIdx.x + off];
-        __syncthreads();
+            for (int d = 0; d < 3; ++d) s[d] += red_lds[d][q];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) dragpart[d * gridDim.x + blockIdx.x] = s[d];
     }
-    if (threadIdx.x == 0)
-#pragma unroll
-        for (int d = 0; d < 3; ++d) dragpart[d * gridDim.x + blockIdx.x] = red_lds[d][0];
 }
 
 __global__ void __launch_bounds__(kBlock) k_drag_final(int nb, const double *dragpart,
@@ -352,10 +719,10 @@ __global__ void __launch_bounds__(kBlock) k_drag_final(int nb, const double *dra
 #pragma unroll
     for (int d = 0; d < 3; ++d) lds[d][threadIdx.x] = acc[d];
     __syncthreads();
-    for (int off = kBlock / 2; off > 0; off >>= 1) {
-        if (int(threadIdx.x) < off)
+    for (int offs = kBlock / 2; offs > 0; offs >>= 1) {
+        if (int(threadIdx.x) < offs)
 #pragma unroll
-            for (int d = 0; d < 3; ++d) lds[d][threadIdx.x] += lds[d][threadIdx.x + off];
+            for (int d = 0; d < 3; ++d) lds[d][threadIdx.x] += lds[d][threadIdx.x + offs];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
@@ -368,46 +735,152 @@ __global__ void __launch_bounds__(kBlock) k_drag_final(int nb, const double *dra
 }
 
 // ------------------------------------------------------------------ launchers
-#define SPH_DIM_DISPATCH(KERNEL, ...)                                                         \
+static int grid_for(const Dev &k, int G) { return xcd_grid((k.cap + (kBlock / G) - 1) / (kBlock / G)); }
+
+// Lanes per target from the capacity (measured on MI355X): a few lanes per
+// target keep gathers in flight without idling many lanes; below ~300k
+// particles a few more lanes help fill the chip. Powers of two only.
+static int pick(int override, int64_t cap, int small, int large)
+{
+    if (override == 1 || override == 2 || override == 4 || override == 8 || override == 16 ||
+        override == 32)
+        return override;
+    return cap < 300000 ? small : large;
+}
+
+int force_group(const Dev &k) { return pick(k.g_force, k.cap, k.dim == 2 ? 4 : 8, k.dim == 2 ? 2 : 4); }
+int nbr_group(const Dev &k) { return pick(k.g_nbr, k.cap, k.dim == 2 ? 4 : 8, 2); }
+int force_grid(const Dev &k) { return grid_for(k, force_group(k)); }
+// the most blocks any variant launches (fewest targets per block): sizes the
+// per-block drag partials
+int force_grid_max(const Dev &k) { return grid_for(k, 32); }
+
+template <int DIM>
+static int bnd_grid(const Dev &k)
+{
+    // grid-stride over the device-side count of boundary rows
+    const int64_t want = (k.cap + Grp<DIM>::PER_BLOCK - 1) / Grp<DIM>::PER_BLOCK;
+    return int(want < 1024 ? want : 1024);
+}
+
+#define SPH_PREC_DIM(KERNEL, GRID, ...)                                                       \
     do {                                                                                      \
-        if (k.dim == 2)                                                                       \
-            hipLaunchKernelGGL(KERNEL<2>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s,           \
+        if (k.dim == 2 && k.prec == SPH_FP64)                                                 \
+            hipLaunchKernelGGL((KERNEL<2, double>), dim3(GRID), dim3(kBlock), 0, s,           \
+                               __VA_ARGS__);                                                  \
+        else if (k.dim == 3 && k.prec == SPH_FP64)                                            \
+            hipLaunchKernelGGL((KERNEL<3, double>), dim3(GRID), dim3(kBlock), 0, s,           \
+                               __VA_ARGS__);                                                  \
+        else if (k.dim == 2)                                                                  \
+            hipLaunchKernelGGL((KERNEL<2, float>), dim3(GRID), dim3(kBlock), 0, s,            \
                                __VA_ARGS__);                                                  \
         else                                                                                  \
-            hipLaunchKernelGGL(KERNEL<3>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s,           \
+            hipLaunchKernelGGL((KERNEL<3, float>), dim3(GRID), dim3(kBlock), 0, s,            \
                                __VA_ARGS__);                                                  \
     } while (0)
 
-void launch_neighbors(const Dev &k, const DevState &st, const DevNlist &nl,
-                      const uint32_t *spread, const int32_t *cell_start, const uint32_t *cpos,
-                      uint32_t *err, hipStream_t s)
+template <int DIM, typename T, int G>
+static void nbrdens_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                      const DevDerived &o, int dens, const uint32_t *spread,
+                      const int32_t *cell_start, const uint32_t *cpos, float *off, uint32_t *err,
+                      hipStream_t s)
 {
-    SPH_DIM_DISPATCH(k_neighbors, k, st, nl, spread, cell_start, cpos, err);
+    hipLaunchKernelGGL((k_nbrdens<DIM, T, G>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m, R,
+                       nl, o, dens, spread, cell_start, cpos, off, err);
 }
 
-void launch_density(const Dev &k, const DevState &st, const DevNlist &nl, const DevDerived &o,
-                    uint32_t *err, hipStream_t s)
+template <int DIM, typename T>
+static void nbrdens_dt(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                       const DevDerived &o, int dens, const uint32_t *spread,
+                       const int32_t *cell_start, const uint32_t *cpos, float *off,
+                       uint32_t *err, hipStream_t s)
 {
-    SPH_DIM_DISPATCH(k_density, k, st, nl, o, err);
+    switch (nbr_group(k)) {
+    case 1: nbrdens_g<DIM, T, 1>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    case 2: nbrdens_g<DIM, T, 2>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    case 4: nbrdens_g<DIM, T, 4>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    case 8: nbrdens_g<DIM, T, 8>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    case 16: nbrdens_g<DIM, T, 16>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    default: nbrdens_g<DIM, T, 32>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    }
 }
 
-void launch_boundary(const Dev &k, const DevState &st, const DevNlist &nl, const DevDerived &o,
+void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                    const DevDerived &o, int dens, const uint32_t *spread,
+                    const int32_t *cell_start, const uint32_t *cpos, float *off, uint32_t *err,
+                    hipStream_t s)
+{
+    if (k.dim == 2 && k.prec == SPH_FP64)
+        nbrdens_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+    else if (k.dim == 3 && k.prec == SPH_FP64)
+        nbrdens_dt<3, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+    else if (k.dim == 2)
+        nbrdens_dt<2, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+    else
+        nbrdens_dt<3, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+}
+
+void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                    const DevDerived &o, uint32_t *err, hipStream_t s)
+{
+    SPH_PREC_DIM(k_density, (k.dim == 2 ? grid_for(k, Grp<2>::G) : grid_for(k, Grp<3>::G)), k, m,
+                 R, nl, o, err);
+}
+
+void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                     const DevDerived &o, const int32_t *blist, const int32_t *bcount,
                      uint32_t *err, hipStream_t s)
 {
-    SPH_DIM_DISPATCH(k_boundary, k, st, nl, o, err);
+    SPH_PREC_DIM(k_boundary, (k.dim == 2 ? bnd_grid<2>(k) : bnd_grid<3>(k)), k, m, R, nl, o,
+                 blist, bcount, err);
 }
 
-void launch_force(const Dev &k, const DevState &st, const DevNlist &nl, const DevDerived &o,
-                  double *dragpart, uint32_t *err, hipStream_t s)
+template <int DIM, typename T, int G>
+static void force_g(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
+                    const DevNlist &nl, const DevDerived &o, const float *off,
+                    const uint32_t *cpos, int mode, int want_drag, double *dragpart,
+                    uint32_t *err, hipStream_t s)
 {
-    SPH_DIM_DISPATCH(k_force, k, st, nl, o, dragpart, err);
+    hipLaunchKernelGGL((k_force<DIM, T, G>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m, R, W,
+                       nl, o, off, cpos, mode, want_drag, dragpart, err);
+}
+
+template <int DIM, typename T>
+static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
+                     const DevNlist &nl, const DevDerived &o, const float *off,
+                     const uint32_t *cpos, int mode, int want_drag, double *dragpart,
+                     uint32_t *err, hipStream_t s)
+{
+    switch (force_group(k)) {
+    case 1: force_g<DIM, T, 1>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    case 2: force_g<DIM, T, 2>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    case 4: force_g<DIM, T, 4>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    case 8: force_g<DIM, T, 8>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    case 16: force_g<DIM, T, 16>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    default: force_g<DIM, T, 32>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    }
+}
+
+void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
+                  const DevNlist &nl, const DevDerived &o, const float *off,
+                  const uint32_t *cpos, int mode, int want_drag, double *dragpart,
+                  uint32_t *err, hipStream_t s)
+{
+    if (k.dim == 2 && k.prec == SPH_FP64)
+        force_dt<2, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+    else if (k.dim == 3 && k.prec == SPH_FP64)
+        force_dt<3, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+    else if (k.dim == 2)
+        force_dt<2, float>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+    else
+        force_dt<3, float>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
 }
 
 void launch_drag_final(const Dev &k, const double *dragpart, double *drag, double *hist,
                        hipStream_t s)
 {
-    hipLaunchKernelGGL(k_drag_final, dim3(1), dim3(kBlock), 0, s, nblocks(k.cap), dragpart,
-                       drag, hist);
+    hipLaunchKernelGGL(k_drag_final, dim3(1), dim3(kBlock), 0, s, force_grid(k), dragpart, drag,
+                       hist);
 }
 
 }  // namespace sph

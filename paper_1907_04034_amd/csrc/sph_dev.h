@@ -20,13 +20,15 @@ constexpr int64_t kIdGeneration = int64_t(1) << 40;
 // Constants derived once per call on the host and passed by value.
 struct Dev {
     int dim, flags, maxnb, prec;
+    int g_force, g_nbr;  // lanes per target requested (0 = automatic)
     int periodic[3];
     int nc[3];          // cells per axis
     int bits[3];        // Morton bits per axis
     uint32_t nkeys;     // 2^(sum bits); key nkeys marks a dead particle
     int64_t cap;
     double lo[3], L[3], halfL[3], cs[3], inv_cs[3];
-    double h, sup2, wnorm, gnorm, mass, rho0, c, c2, nu, nu_damp, eta_h2, pb;
+    float csf[3];
+    double h, inv_h, sup2, wnorm, gnorm, mass, inv_mass, rho0, c, c2, nu, nu_damp, eta_h2, pb;
     double dt, hdt, disp_max;
     double x_inlet, x_outlet, x_outlet_end, inlet_len, pgate, U, noise_amp;
     uint64_t noise_seed;
@@ -44,6 +46,14 @@ struct DevState {
     int64_t *id;
 };
 
+// The four fields a right-hand side reads at its stage (x, u, ut, p) and the
+// fields a stage update writes; the start-of-step state and the half state
+// each provide one.
+struct Fields {
+    double *x;
+    void *u, *ut, *p;
+};
+
 struct DevDerived {
     void *rho, *vol, *pavg, *a, *b, *pdot;
     double *jcur, *force, *drag;
@@ -57,8 +67,8 @@ struct DevNlist {
 
 // Workspace carving (byte offsets from the workspace base).
 struct WsLayout {
-    size_t err, nspawn, spread, cell_start, cursor, keys, tmp, cpos, cpos_s, x0, u0, p0,
-        blocksum, dragpart, total;
+    size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, tmp, cpos,
+        cpos_s, blist, hx, hu, hut, hp, off, dragpart, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

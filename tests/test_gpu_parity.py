@@ -240,3 +240,29 @@ def test_full_size_rhs_parity(cfg):
     for key in ("a", "b"):
         assert _nerr(gd[key][fl, :D], od[key][perm][fl, :D], floors[key]) < TOL
     assert _nerr(gd["pdot"][fl], od["pdot"][perm][fl], floors["pdot"]) < TOL
+
+
+@pytest.mark.parametrize("g", [1, 2, 4, 8, 16, 32])
+@pytest.mark.parametrize("name", ["C2-small", "C5-small"])
+def test_lane_group_variants(name, g):
+    """Every lanes-per-target variant of the neighbour search and the force
+    pass gives the same neighbour sets and FP64 forces (to rounding)."""
+    _print_case(f"lane groups {name} g={g}")
+    prm, s = _case(name)
+    prm = dict(prm, group_force=g, group_nbr=g)
+    gs, gd, sim = B().rhs_once(prm, s)
+    assert sim.poll_error() == 0
+    os_, od, F = O.rhs_once(prm, s)
+    perm = _match(gs, os_)
+    fl = gs["type"] == I.FLUID
+    floors = _floors(od, perm[fl])
+    D = prm["dim"]
+    for key in ("a", "b"):
+        assert _nerr(gd[key][fl, :D], od[key][perm][fl, :D], floors[key]) < TOL
+    assert _nerr(gd["pdot"][fl], od["pdot"][perm][fl], floors["pdot"]) < TOL
+    cnt, nbr = sim.neighbor_table()
+    row, col = O.Oracle(prm, s).neighbors(brute=True)
+    ids = s["id"]
+    ref = {int(ids[i]): set(ids[col[row[i]:row[i + 1]]].tolist()) for i in range(len(row) - 1)}
+    for r in range(len(cnt)):
+        assert set(gs["id"][nbr[r, :cnt[r]]].tolist()) == ref[int(gs["id"][r])]
