@@ -132,6 +132,7 @@ typedef struct sph_derived {
     uint8_t *red;             /* [cap] */
     double *force;            /* [3][cap] per body particle */
     double *drag;             /* [3] */
+    double *sfl;              /* [cap] sum of W over fluid neighbours (non-fluid rows) */
 } sph_derived;
 
 /* Bytes of workspace needed for capacity `cap` (cell grid, sort buffers,
@@ -199,6 +200,35 @@ int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
 int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
              sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
              size_t ws_bytes, void *stream);
+
+/* Reverse pass (vector-Jacobian product) of one right-hand side, written by
+ * hand from the forward formulas (no automatic differentiation): the
+ * gradient of
+ *     L = sum over fluid rows (abar . a + bbar . b + pdbar pdot) + fbar . drag
+ * with respect to the fluid's x, u, ut, p, the inlet rows' prescribed velocity
+ * and the outlet rows' time averages, through the force pass, the neighbour
+ * average pressure (eq:pavg), the boundary values (walls, hybrid outlet
+ * eq:characteristic-vars / eq:shepard / eq:acou, inlet J3) and the summation
+ * density. Preconditions: sph_neighbors and sph_rhs have run on the same
+ * state, table, derived buffers and workspace (the reverse reads the stored
+ * rho, V, pbar, boundary values, J and Shepard sums). Boundary values taken
+ * from the previous step (particles without fluid support) reach no fluid
+ * force, so their inputs get no gradient. Gather-only, deterministic. */
+typedef struct sph_adjoint {
+    const void *abar, *bbar;  /* [3][cap] weights, state element type (may be NULL) */
+    const void *pdbar;        /* [cap] (may be NULL) */
+    double fbar[3];           /* weight of the body force */
+    double *xbar;             /* out [3][cap] dL/dx (every row) */
+    double *ubar, *utbar;     /* out [3][cap] dL/du, dL/dut (fluid rows) */
+    double *pbar;             /* out [cap] dL/dp (fluid rows) */
+    double *uinbar;           /* out [3][cap] dL/du_in (inlet rows) */
+    double *avgbar;           /* out [dim+1][cap] dL/d<u,p> (fluid and outlet rows) */
+    double *scratch;          /* [8][cap] work space */
+} sph_adjoint;
+
+int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+                    const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
+                    void *stream);
 
 /* Synchronises `stream`, returns the accumulated device error bits in *bits
  * and clears them. */

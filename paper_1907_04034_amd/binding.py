@@ -22,7 +22,7 @@ ERR_BITS = {1: "NBR_OVERFLOW", 2: "CAPACITY", 4: "NONFINITE", 8: "SKIN", 16: "ES
 
 EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors",
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
-            "sph_poll_error", "sph_live_count", "sph_last_error"]
+            "sph_rhs_adjoint", "sph_poll_error", "sph_live_count", "sph_last_error"]
 
 
 class SphParams(C.Structure):
@@ -53,9 +53,15 @@ class SphNlist(C.Structure):
     _fields_ = [("maxnb", C.c_int32), ("count", _P), ("nbr", _P)]
 
 
+class SphAdjoint(C.Structure):
+    _fields_ = [("abar", _P), ("bbar", _P), ("pdbar", _P), ("fbar", C.c_double * 3),
+                ("xbar", _P), ("ubar", _P), ("utbar", _P), ("pbar", _P), ("uinbar", _P),
+                ("avgbar", _P), ("scratch", _P)]
+
+
 class SphDerived(C.Structure):
     _fields_ = [("rho", _P), ("vol", _P), ("pavg", _P), ("a", _P), ("b", _P), ("pdot", _P),
-                ("jcur", _P), ("red", _P), ("force", _P), ("drag", _P)]
+                ("jcur", _P), ("red", _P), ("force", _P), ("drag", _P), ("sfl", _P)]
 
 
 _lib = None
@@ -81,6 +87,7 @@ def lib():
         L.sph_rhs.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_force.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_step.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, sz, _P]
+        L.sph_rhs_adjoint.argtypes = [SP, ST, NL, DE, C.POINTER(SphAdjoint), _P, sz, _P]
         L.sph_poll_error.argtypes = [_P, sz, C.POINTER(C.c_uint32), _P]
         L.sph_live_count.argtypes = [ST, C.POINTER(C.c_int64), _P]
         L.sph_last_error.restype = C.c_char_p
@@ -161,6 +168,7 @@ class Simulation:
             red=torch.zeros(cap, dtype=torch.uint8, device=self.dev),
             force=torch.zeros(3 * cap, dtype=torch.float64, device=self.dev),
             drag=torch.zeros(3, dtype=torch.float64, device=self.dev),
+            sfl=torch.zeros(cap, dtype=torch.float64, device=self.dev),
         )
         self.ws_bytes = workspace_size(prm, cap)
         self.ws = torch.zeros(self.ws_bytes, dtype=torch.uint8, device=self.dev)
@@ -171,7 +179,7 @@ class Simulation:
         d = self.der
         self.out = SphDerived(*[d[k].data_ptr() for k in
                                 ("rho", "vol", "pavg", "a", "b", "pdot", "jcur", "red", "force",
-                                 "drag")])
+                                 "drag", "sfl")])
         self.binned = False
 
     # ------------------------------------------------------------ memory
@@ -295,6 +303,49 @@ class Simulation:
         n = C.c_int64(0)
         _check(lib().sph_live_count(C.byref(self.st), C.byref(n), self.stream), "sph_live_count")
         return n.value
+
+    def rhs_adjoint(self, abar=None, bbar=None, pdbar=None, fbar=(0.0, 0.0, 0.0)):
+        """Gradient of L = sum_fluid(abar.a + bbar.b + pdbar*pdot) + fbar.drag for the
+        current stage (sph_neighbors and sph_rhs must have run). Weights are host
+        arrays in the current device row order ((n, 3) or (n,)); returns host
+        gradients in the same order (xbar, ubar, utbar, uinbar: (n, 3); pbar: (n,);
+        avgbar: (n, 4) with the pressure in the last column)."""
+        t, cap, D = self.torch, self.cap, self.dim
+        n = self.live_count()
+        if not hasattr(self, "adj"):
+            z = lambda k: t.zeros(k * cap, dtype=t.float64, device=self.dev)  # noqa: E731
+            self.adj = dict(xbar=z(3), ubar=z(3), utbar=z(3), pbar=z(1), uinbar=z(3),
+                            avgbar=z(D + 1), scratch=z(8),
+                            abar=t.zeros(3 * cap, dtype=self.rdt, device=self.dev),
+                            bbar=t.zeros(3 * cap, dtype=self.rdt, device=self.dev),
+                            pdbar=t.zeros(cap, dtype=self.rdt, device=self.dev))
+        A = self.adj
+        for name, w, comps in (("abar", abar, 3), ("bbar", bbar, 3), ("pdbar", pdbar, 1)):
+            A[name].zero_()
+            if w is not None:
+                w = np.asarray(w, np.float64)
+                view = A[name].view(comps, cap) if comps > 1 else A[name]
+                host = np.ascontiguousarray(w.T if comps > 1 else w)
+                view[..., :n].copy_(t.from_numpy(host).to(view.dtype))
+        st = SphAdjoint()
+        st.abar, st.bbar, st.pdbar = A["abar"].data_ptr(), A["bbar"].data_ptr(), A["pdbar"].data_ptr()
+        for d in range(3):
+            st.fbar[d] = float(fbar[d])
+        for k in ("xbar", "ubar", "utbar", "pbar", "uinbar", "avgbar", "scratch"):
+            setattr(st, k, A[k].data_ptr())
+        ws, nb = self._ws()
+        _check(lib().sph_rhs_adjoint(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
+                                     C.byref(self.out), C.byref(st), ws, nb, self.stream),
+               "sph_rhs_adjoint")
+        out = {}
+        for k in ("xbar", "ubar", "utbar", "uinbar"):
+            out[k] = A[k].view(3, cap)[:, :n].cpu().numpy().T.copy()
+        out["pbar"] = A["pbar"][:n].cpu().numpy().copy()
+        av = A["avgbar"].view(D + 1, cap)[:, :n].cpu().numpy().T
+        out["avgbar"] = np.zeros((n, 4))
+        out["avgbar"][:, :D] = av[:, :D]
+        out["avgbar"][:, 3] = av[:, D]
+        return out
 
     # ------------------------------------------------------------ results
     def state(self):

@@ -1,0 +1,566 @@
+// adjoint.hip -- hand-written reverse (vector-Jacobian product) of one
+// right-hand side for gfx950: force pass, neighbour-average pressure,
+// boundary values (walls, hybrid outlet, inlet) and summation density.
+//
+// Given weights (abar, bbar, pdbar) on the fluid outputs (a, b, pdot) and a
+// weight fbar on the body force, the kernels return the gradient of
+//     L = sum_fluid (abar . a + bbar . b + pdbar pdot) + fbar . F_body
+// with respect to positions x, velocities u, transport velocities ut,
+// pressures p of the fluid, the prescribed inlet velocities and the outlet
+// time averages. Everything is gather-only (each particle sums what every
+// pair contributes to it; no float atomics), so results are deterministic:
+//   R1  pairs:     each particle k reverses every pair term twice, once as the
+//                  target (its own weights) and once as the neighbour of a
+//                  fluid/body target j (j's weights);
+//   R2a pbar:      the adjoint of the neighbour average pbar_i = sum_j p_j / N_i
+//                  is spread to the p_j of its neighbours;
+//   R2b boundary:  the adjoints of the boundary values flow back through the
+//                  Shepard averages to the fluid (p, u, rho, x), to the inlet
+//                  velocity and the outlet averages; then Sbar = m rhobar - V^2 Vbar;
+//   R3  density:   xbar_k += sum_j (Sbar_k + Sbar_j) F_kj r_kj.
+// Values of boundary particles without fluid support come from the previous
+// step's characteristic values; by the symmetry of the neighbour predicate no
+// fluid particle has such a particle in its support, so those values reach no
+// fluid force and no drag, and their adjoint is not propagated.
+#include "sph_launch.h"
+
+namespace sph {
+
+template <typename T>
+struct Ep {  // endpoint of a pair as the force pass sees it
+    T u[3], w[3], p, rho, vol;
+    int t;
+};
+
+template <typename T>
+struct EpBar {  // adjoint accumulators of an endpoint
+    T u[3] = {0, 0, 0}, w[3] = {0, 0, 0}, p = 0, rho = 0, vol = 0;
+};
+
+template <int DIM, typename T>
+__device__ inline void load_ep(const Dev &k, const DevState &m, const Fields &R,
+                               const DevDerived &o, int64_t i, Ep<T> &e)
+{
+    const int64_t C = k.cap;
+    e.t = m.type[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) e.u[d] = e.w[d] = T(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        e.u[d] = ld<T>(R.u, d * C + i);
+        e.w[d] = ld<T>(R.ut, d * C + i) - e.u[d];
+    }
+    e.p = ld<T>(R.p, i);
+    e.rho = ld<T>(o.rho, i);
+    e.vol = ld<T>(o.vol, i);
+}
+
+// Quantities of the forward pair term shared by the fluid and body reverses.
+template <int DIM, typename T>
+struct PairFwd {
+    T F, G, gw[3], V2, inv, pt, hm, E, D;
+    __device__ inline PairFwd(const Dev &k, const T r[3], T r2, const Ep<T> &I, const Ep<T> &J,
+                              T P)
+    {
+        const T q = T(sqrt(r2)) * T(k.inv_h);
+        const T t = T(1) - T(0.5) * q;
+        const T gn = T(k.gnorm);
+        F = gn * t * t * t;
+        // (dF/dr)/|r| with dF/dr = -1.5 gnorm t^2 / h
+        G = T(-1.5) * gn * t * t * T(k.inv_h) * T(k.inv_h) / q;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) gw[d] = F * r[d];
+        V2 = I.vol * I.vol + J.vol * J.vol;
+        inv = T(1) / (I.rho + J.rho);
+        pt = (J.rho * (I.p - P) + I.rho * (J.p - P)) * inv;
+        hm = T(2) * I.rho * J.rho * inv;
+        E = r2 + T(k.eta_h2);
+        D = F * r2 / E;
+    }
+};
+
+// From the adjoints of V2, pt, hm, D, F and gw to the endpoints and r.
+template <int DIM, typename T>
+__device__ inline void pair_tail(const Dev &k, const T r[3], T r2, const Ep<T> &I,
+                                 const Ep<T> &J, T P, const PairFwd<DIM, T> &f, T V2b, T ptb,
+                                 T hmb, T Db, T Fb, const T gwb[3], EpBar<T> &Ib, EpBar<T> &Jb,
+                                 T &Pb, T rb[3])
+{
+    Ib.vol += T(2) * I.vol * V2b;
+    Jb.vol += T(2) * J.vol * V2b;
+    Ib.p += ptb * J.rho * f.inv;
+    Jb.p += ptb * I.rho * f.inv;
+    Pb -= ptb;  // d pt / d P = -(rho_i + rho_j) / (rho_i + rho_j)
+    Ib.rho += ptb * ((J.p - P) - f.pt) * f.inv + hmb * (T(2) * J.rho - f.hm) * f.inv;
+    Jb.rho += ptb * ((I.p - P) - f.pt) * f.inv + hmb * (T(2) * I.rho - f.hm) * f.inv;
+    Fb += Db * r2 / f.E;
+    const T r2b = Db * f.F * T(k.eta_h2) / (f.E * f.E);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) Fb += gwb[d] * r[d];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) rb[d] += f.F * gwb[d] + Fb * f.G * r[d] + T(2) * r2b * r[d];
+}
+
+// Reverse of the fluid-target pair term (target I, neighbour J, r = x_I - x_J)
+// for output weights ab (on a), bb (on b), pdb (on pdot).
+template <int DIM, typename T>
+__device__ inline void pair_adj_fluid(const Dev &k, const T r[3], T r2, const Ep<T> &I,
+                                      const Ep<T> &J, T P, const T ab[3], const T bb[3], T pdb,
+                                      EpBar<T> &Ib, EpBar<T> &Jb, T &Pb, T rb[3])
+{
+    const PairFwd<DIM, T> f(k, r, r2, I, J, P);
+    const T nu = T(k.nu), nud = T(k.nu_damp), im = T(k.inv_mass), pbg = T(k.pb);
+    T si = T(0), sj = T(0);
+    const bool jfl = J.t == SPH_FLUID;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        si += I.w[d] * f.gw[d];
+        if (jfl) sj += J.w[d] * f.gw[d];
+    }
+    const bool cv = J.t != SPH_WALL_SLIP;
+    const T visc = cv ? f.hm * nu * f.D : T(0);
+    const T ff = f.V2 * im;
+    const bool wall = is_wall(J.t);
+    T udiv = T(0), ujd[3] = {0, 0, 0}, A[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        ujd[d] = wall ? T(0) : J.u[d];
+        udiv += (I.u[d] - ujd[d]) * f.gw[d];
+        A[d] = -f.pt * f.gw[d] + T(0.5) * (I.rho * I.u[d] * si + J.rho * J.u[d] * sj) +
+               visc * (I.u[d] - J.u[d]);
+    }
+    // a_I += ff * A
+    T ffb = T(0), Av[3] = {0, 0, 0}, ptb = T(0), gwb[3] = {0, 0, 0}, uiAv = T(0), ujAv = T(0),
+      viscb = T(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        ffb += ab[d] * A[d];
+        Av[d] = ff * ab[d];
+        ptb -= Av[d] * f.gw[d];
+        gwb[d] = -f.pt * Av[d];
+        uiAv += I.u[d] * Av[d];
+        ujAv += J.u[d] * Av[d];
+        viscb += Av[d] * (I.u[d] - J.u[d]);
+    }
+    const T sib = T(0.5) * I.rho * uiAv, sjb = T(0.5) * J.rho * ujAv;
+    Ib.rho += T(0.5) * si * uiAv;
+    Jb.rho += T(0.5) * sj * ujAv;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        Ib.u[d] += T(0.5) * I.rho * si * Av[d] + visc * Av[d];
+        Jb.u[d] += T(0.5) * J.rho * sj * Av[d] - visc * Av[d];
+    }
+    // b_I += -(pb/m) V2 gw
+    T V2b = T(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        V2b -= pbg * im * bb[d] * f.gw[d];
+        gwb[d] -= pbg * im * f.V2 * bb[d];
+    }
+    // pdot_I += m (rho_I / rho_J) c^2 udiv + ff hm nu_d D (p_I - p_J)
+    const T c1 = T(k.mass) * T(k.c2) / J.rho;
+    Ib.rho += pdb * c1 * udiv;
+    Jb.rho -= pdb * c1 * I.rho * udiv / J.rho;
+    const T udivb = pdb * c1 * I.rho;
+    const T dp = I.p - J.p;
+    ffb += pdb * f.hm * nud * f.D * dp;
+    T hmb = pdb * ff * nud * f.D * dp;
+    T Db = pdb * ff * f.hm * nud * dp;
+    Ib.p += pdb * ff * f.hm * nud * f.D;
+    Jb.p -= pdb * ff * f.hm * nud * f.D;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        Ib.u[d] += udivb * f.gw[d];
+        if (!wall) Jb.u[d] -= udivb * f.gw[d];
+        gwb[d] += udivb * (I.u[d] - ujd[d]) + sib * I.w[d] + (jfl ? sjb * J.w[d] : T(0));
+        Ib.w[d] += sib * f.gw[d];
+        if (jfl) Jb.w[d] += sjb * f.gw[d];
+    }
+    if (cv) {
+        hmb += viscb * nu * f.D;
+        Db += viscb * f.hm * nu;
+    }
+    V2b += ffb * im;
+    T Fb = T(0);
+    pair_tail<DIM, T>(k, r, r2, I, J, P, f, V2b, ptb, hmb, Db, Fb, gwb, Ib, Jb, Pb, rb);
+}
+
+// Reverse of the body-force pair term (body I, fluid J) for the weight fb.
+template <int DIM, typename T>
+__device__ inline void pair_adj_body(const Dev &k, const T r[3], T r2, const Ep<T> &I,
+                                     const Ep<T> &J, T P, const T fb[3], EpBar<T> &Ib,
+                                     EpBar<T> &Jb, T &Pb, T rb[3])
+{
+    const PairFwd<DIM, T> f(k, r, r2, I, J, P);
+    const T nu = T(k.nu);
+    T V2b = T(0), ptb = T(0), gwb[3] = {0, 0, 0}, du_av = T(0);
+    T Av[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const T du = I.u[d] - J.u[d];
+        V2b += fb[d] * (-f.pt * f.gw[d] + f.hm * nu * f.D * du);
+        Av[d] = f.V2 * fb[d];
+        ptb -= Av[d] * f.gw[d];
+        gwb[d] = -f.pt * Av[d];
+        du_av += Av[d] * du;
+        Ib.u[d] += f.hm * nu * f.D * Av[d];
+        Jb.u[d] -= f.hm * nu * f.D * Av[d];
+    }
+    const T hmb = nu * f.D * du_av, Db = f.hm * nu * du_av;
+    T Fb = T(0);
+    pair_tail<DIM, T>(k, r, r2, I, J, P, f, V2b, ptb, hmb, Db, Fb, gwb, Ib, Jb, Pb, rb);
+}
+
+template <typename T>
+__device__ inline T ldw(const void *p, int64_t i)
+{
+    return p ? ld<T>(p, i) : T(0);
+}
+
+// R1: pair reverses, gathered per particle.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields R, DevNlist nl,
+                                                      DevDerived o, DevAdj A, const float *off,
+                                                      const uint32_t *cpos, uint32_t *err)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = *m.n;
+    if (i >= n) return;
+    const int64_t C = k.cap;
+    Ep<T> K;
+    load_ep<DIM, T>(k, m, R, o, i, K);
+    const T PK = ld<T>(o.pavg, i);
+    T abK[3] = {0, 0, 0}, bbK[3] = {0, 0, 0}, pdbK = T(0), fbar[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) fbar[d] = T(A.fbar[d]);
+    if (K.t == SPH_FLUID) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            abK[d] = ldw<T>(A.abar, d * C + i);
+            bbK[d] = ldw<T>(A.bbar, d * C + i);
+        }
+        pdbK = ldw<T>(A.pdbar, i);
+    }
+    Sep<DIM, T> sep;
+    sep.load_i(k, R, off, cpos, i);
+    EpBar<T> Kb;
+    T Pb = T(0), xb[3] = {0, 0, 0};
+    const int cnt = nl.count[i];
+    for (int q = 0; q < cnt; ++q) {
+        const int32_t j = nl.nbr[i * nl.maxnb + q];
+        if (bad_index(j, n)) {
+            raise_error(err, SPH_ERR_CELL_RANGE);
+            continue;
+        }
+        if (j == i) continue;
+        Ep<T> J;
+        load_ep<DIM, T>(k, m, R, o, j, J);
+        T r[3], rn[3];
+        const T r2 = sep.get(k, R, off, cpos, j, r);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) rn[d] = -r[d];
+        EpBar<T> dummy;
+        T Pdummy = T(0);
+        // k as the target
+        if (K.t == SPH_FLUID || (K.t == SPH_BODY && J.t == SPH_FLUID)) {
+            T rb[3] = {0, 0, 0};
+            if (K.t == SPH_FLUID)
+                pair_adj_fluid<DIM, T>(k, r, r2, K, J, PK, abK, bbK, pdbK, Kb, dummy, Pb, rb);
+            else
+                pair_adj_body<DIM, T>(k, r, r2, K, J, PK, fbar, Kb, dummy, Pb, rb);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xb[d] += rb[d];
+        }
+        // k as the neighbour of target j
+        if (J.t == SPH_FLUID || (J.t == SPH_BODY && K.t == SPH_FLUID)) {
+            const T PJ = ld<T>(o.pavg, j);
+            T rb[3] = {0, 0, 0};
+            if (J.t == SPH_FLUID) {
+                T abJ[3] = {0, 0, 0}, bbJ[3] = {0, 0, 0};
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) {
+                    abJ[d] = ldw<T>(A.abar, d * C + j);
+                    bbJ[d] = ldw<T>(A.bbar, d * C + j);
+                }
+                pair_adj_fluid<DIM, T>(k, rn, r2, J, K, PJ, abJ, bbJ, ldw<T>(A.pdbar, j), dummy, Kb,
+                                       Pdummy, rb);
+            } else {
+                pair_adj_body<DIM, T>(k, rn, r2, J, K, PJ, fbar, dummy, Kb, Pdummy, rb);
+            }
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xb[d] -= rb[d];
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        A.xbar[d * C + i] = double(xb[d]);
+        A.ubar[d * C + i] = double(Kb.u[d]);
+        A.wbar[d * C + i] = double(Kb.w[d]);
+    }
+    A.pbar[i] = double(Kb.p);
+    A.rhobar[i] = double(Kb.rho);
+    A.volbar[i] = double(Kb.vol);
+    A.Pbar[i] = double(Pb);
+}
+
+// R2a: pbar_i = (1/N_i) sum_{j in N(i)} p_j  ->  pbar_j += Pbar_i / N_i.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist nl, DevAdj A,
+                                                     uint32_t *err)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = *m.n;
+    if (i >= n) return;
+    if (k.flags & SPH_FLAG_NO_PAVG) return;
+    double acc = 0.0;
+    const int cnt = nl.count[i];
+    for (int q = 0; q < cnt; ++q) {
+        const int32_t j = nl.nbr[i * nl.maxnb + q];
+        if (bad_index(j, n)) {
+            raise_error(err, SPH_ERR_CELL_RANGE);
+            continue;
+        }
+        const int tj = m.type[j];
+        if (tj == SPH_FLUID || tj == SPH_BODY) acc += A.Pbar[j] / double(nl.count[j]);
+    }
+    A.pbar[i] += acc;
+}
+
+// Reverse of the Shepard weight W_bf of boundary particle b and fluid f
+// given the adjoints of b's values: returns Wbar and adds the fluid-side
+// adjoints (p, u_x, rho, averages) when `to_fluid`; adds the inlet velocity
+// adjoint of b when `to_inlet`.
+struct BndIn {
+    int t;
+    double S, pbar, ubar[3], p, u[3], J2, J3, uin0;
+};
+
+template <int DIM>
+__device__ inline double bnd_weight_adj(const Dev &k, const BndIn &b, double w, double pf,
+                                        const double uf[3], double rhof, const double avgf[4],
+                                        double &pfb, double ufb[3], double &rhofb,
+                                        double avgfb[4], double &uinb0)
+{
+    if (is_wall(b.t)) {
+        pfb += b.pbar * w / b.S;
+        double Wb = b.pbar * (pf - b.p);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            ufb[d] -= b.ubar[d] * w / b.S;
+            Wb -= b.ubar[d] * (uf[d] + b.u[d]);
+        }
+        return Wb / b.S;
+    }
+    if (b.t == SPH_OUTLET) {
+        const double J2hb = 0.5 * b.pbar + b.ubar[0] / (2.0 * k.rho0 * k.c);
+        const double du = uf[0] - avgf[0], dp = pf - avgf[DIM];
+        const double J2f = rhof * k.c * du + dp;
+        const double J2fb = J2hb * w / b.S;
+        rhofb += J2fb * k.c * du;
+        ufb[0] += J2fb * rhof * k.c;
+        pfb += J2fb;
+        avgfb[0] -= J2fb * rhof * k.c;
+        avgfb[DIM] -= J2fb;
+        return J2hb * (J2f - b.J2) / b.S;
+    }
+    // inlet: p_b = Shepard J3, J3_f = -rho_f c (u_f - u_in,b) + p_f
+    const double J3f = -rhof * k.c * (uf[0] - b.uin0) + pf;
+    const double J3fb = b.pbar * w / b.S;
+    rhofb -= J3fb * k.c * (uf[0] - b.uin0);
+    ufb[0] -= J3fb * rhof * k.c;
+    pfb += J3fb;
+    uinb0 += J3fb * rhof * k.c;
+    return b.pbar * (J3f - b.J3) / b.S;
+}
+
+template <int DIM, typename T>
+__device__ inline void load_bnd(const Dev &k, const DevState &m, const Fields &R,
+                                const DevDerived &o, const DevAdj &A, int64_t b, BndIn &B)
+{
+    const int64_t C = k.cap;
+    B.t = m.type[b];
+    B.S = o.sfl[b];
+    B.pbar = A.pbar[b];
+    B.p = double(ld<T>(R.p, b));
+#pragma unroll
+    for (int d = 0; d < 3; ++d) B.ubar[d] = B.u[d] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        B.ubar[d] = A.ubar[d * C + b];
+        B.u[d] = double(ld<T>(R.u, d * C + b));
+    }
+    B.J2 = o.jcur[C + b];
+    B.J3 = o.jcur[2 * C + b];
+    B.uin0 = m.uin[b];
+}
+
+// R2b: boundary reverses, then Sbar = m rhobar - V^2 Vbar.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R, DevNlist nl,
+                                                    DevDerived o, DevAdj A, uint32_t *err)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = *m.n;
+    if (i >= n) return;
+    const int64_t C = k.cap;
+    const int t = m.type[i];
+    const int cnt = nl.count[i];
+    double xi[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, avgb[4] = {0, 0, 0, 0};
+    double uinb[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        xi[d] = R.x[d * C + i];
+        xb[d] = A.xbar[d * C + i];
+        ub[d] = A.ubar[d * C + i];
+    }
+    double pb = A.pbar[i], rhob = A.rhobar[i];
+    if (t == SPH_FLUID) {
+        const double pf = double(ld<T>(R.p, i)), rhof = double(ld<T>(o.rho, i));
+        double uf[3] = {0, 0, 0}, avgf[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) uf[d] = double(ld<T>(R.u, d * C + i));
+#pragma unroll
+        for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + i];
+        for (int q = 0; q < cnt; ++q) {
+            const int32_t b = nl.nbr[i * nl.maxnb + q];
+            if (bad_index(b, n)) {
+                raise_error(err, SPH_ERR_CELL_RANGE);
+                continue;
+            }
+            const int tb = m.type[b];
+            if (tb == SPH_FLUID || !(o.sfl[b] > 0.0)) continue;
+            BndIn B;
+            load_bnd<DIM, T>(k, m, R, o, A, b, B);
+            double xj[3] = {0, 0, 0}, r[3];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + b];
+            const double r2 = dist2_exact<DIM>(k, xj, xi, r);  // r = x_b - x_f
+            const double q2 = sqrt(r2) * k.inv_h;
+            const double w = wendland_w(q2, k.wnorm), F = wendland_f(q2, k.gnorm);
+            double dummy_uin = 0.0;
+            const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, pb, ub, rhob, avgb,
+                                                  dummy_uin);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xb[d] -= Wb * F * r[d];
+        }
+    } else if (o.sfl[i] > 0.0) {
+        BndIn B;
+        load_bnd<DIM, T>(k, m, R, o, A, i, B);
+        for (int q = 0; q < cnt; ++q) {
+            const int32_t f = nl.nbr[i * nl.maxnb + q];
+            if (bad_index(f, n)) continue;
+            if (m.type[f] != SPH_FLUID) continue;
+            double xf[3] = {0, 0, 0}, r[3];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xf[d] = R.x[d * C + f];
+            const double r2 = dist2_exact<DIM>(k, xi, xf, r);  // r = x_b - x_f
+            const double q2 = sqrt(r2) * k.inv_h;
+            const double w = wendland_w(q2, k.wnorm), F = wendland_f(q2, k.gnorm);
+            const double pf = double(ld<T>(R.p, f)), rhof = double(ld<T>(o.rho, f));
+            double uf[3] = {0, 0, 0}, avgf[4] = {0, 0, 0, 0}, sink_u[3] = {0, 0, 0},
+                   sink_avg[4] = {0, 0, 0, 0}, sink_p = 0.0, sink_rho = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) uf[d] = double(ld<T>(R.u, d * C + f));
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + f];
+            const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, sink_p, sink_u,
+                                                  sink_rho, sink_avg, uinb[0]);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xb[d] += Wb * F * r[d];
+        }
+    }
+    if (t == SPH_INLET) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) uinb[d] += ub[d];  // u = u_in
+    } else if (t == SPH_OUTLET) {
+        // u_o = <u> + u_ac, v_o = <v>, p_o = <p> + p_ac
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) avgb[d] += ub[d];
+        avgb[DIM] += pb;
+    }
+    const double vol = double(ld<T>(o.vol, i));
+    const double Sb = k.mass * rhob - vol * vol * A.volbar[i];
+    // boundary rows' pbar and ubar are read by their fluid neighbours in this
+    // launch, so only fluid rows write theirs back
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        A.xbar[d * C + i] = xb[d];
+        if (t == SPH_FLUID) A.ubar[d * C + i] = ub[d];
+        A.uinbar[d * C + i] = uinb[d];
+    }
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) A.avgbar[c * C + i] = avgb[c];
+    if (t == SPH_FLUID) A.pbar[i] = pb;
+    A.rhobar[i] = rhob;
+    A.Sbar[i] = Sb;
+}
+
+// R3: density reverse, xbar_k += sum_j (Sbar_k + Sbar_j) F_kj r_kj; final
+// velocity adjoints (u enters directly and through w = ut - u).
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R, DevNlist nl,
+                                                     DevAdj A, uint32_t *err)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = *m.n;
+    if (i >= n) return;
+    const int64_t C = k.cap;
+    double xi[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        xi[d] = R.x[d * C + i];
+        xb[d] = A.xbar[d * C + i];
+    }
+    const double Si = A.Sbar[i];
+    const int cnt = nl.count[i];
+    for (int q = 0; q < cnt; ++q) {
+        const int32_t j = nl.nbr[i * nl.maxnb + q];
+        if (bad_index(j, n)) {
+            raise_error(err, SPH_ERR_CELL_RANGE);
+            continue;
+        }
+        if (j == i) continue;
+        double xj[3] = {0, 0, 0}, r[3];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
+        const double r2 = dist2_exact<DIM>(k, xi, xj, r);
+        const double F = wendland_f(sqrt(r2) * k.inv_h, k.gnorm);
+        const double s = (Si + A.Sbar[j]) * F;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xb[d] += s * r[d];
+    }
+    const bool fl = m.type[i] == SPH_FLUID;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        A.xbar[d * C + i] = xb[d];
+        const double w = A.wbar[d * C + i];
+        A.utbar[d * C + i] = fl ? w : 0.0;
+        if (fl) A.ubar[d * C + i] -= w;
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+#define SPH_ADJ_DISPATCH(KERNEL, ...)                                                         \
+    do {                                                                                      \
+        const dim3 g(nblocks(k.cap)), b(kBlock);                                              \
+        if (k.dim == 2 && k.prec == SPH_FP64)                                                 \
+            hipLaunchKernelGGL((KERNEL<2, double>), g, b, 0, s, __VA_ARGS__);                 \
+        else if (k.dim == 3 && k.prec == SPH_FP64)                                            \
+            hipLaunchKernelGGL((KERNEL<3, double>), g, b, 0, s, __VA_ARGS__);                 \
+        else if (k.dim == 2)                                                                  \
+            hipLaunchKernelGGL((KERNEL<2, float>), g, b, 0, s, __VA_ARGS__);                  \
+        else                                                                                  \
+            hipLaunchKernelGGL((KERNEL<3, float>), g, b, 0, s, __VA_ARGS__);                  \
+    } while (0)
+
+void launch_rhs_adjoint(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                        const DevDerived &o, const DevAdj &A, const float *off,
+                        const uint32_t *cpos, uint32_t *err, hipStream_t s)
+{
+    SPH_ADJ_DISPATCH(k_adj_pairs, k, m, R, nl, o, A, off, cpos, err);
+    SPH_ADJ_DISPATCH(k_adj_pavg, k, m, nl, A, err);
+    SPH_ADJ_DISPATCH(k_adj_bnd, k, m, R, nl, o, A, err);
+    SPH_ADJ_DISPATCH(k_adj_dens, k, m, R, nl, A, err);
+}
+
+}  // namespace sph

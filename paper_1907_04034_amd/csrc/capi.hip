@@ -209,7 +209,7 @@ static int check_nlist(const sph_nlist *nl)
 static int check_derived(const sph_derived *o, bool need_drag = true)
 {
     if (!o || !o->rho || !o->vol || !o->pavg || !o->a || !o->b || !o->pdot || !o->jcur ||
-        !o->red || !o->force || (need_drag && !o->drag))
+        !o->red || !o->force || !o->sfl || (need_drag && !o->drag))
         return fail(SPH_EINVAL, "derived output has a NULL array");
     return SPH_OK;
 }
@@ -245,6 +245,7 @@ static DevDerived dev_derived(const sph_derived *o)
     d.jcur = o->jcur;
     d.force = o->force;
     d.drag = o->drag;
+    d.sfl = o->sfl;
     d.red = o->red;
     return d;
 }
@@ -488,6 +489,38 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
     }
     if (nsteps > 0) launch_finish_spawn(c.k, dev_state(st), nspawn, c.s);
     return check_hip("sph_step");
+}
+
+int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+                    const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
+                    void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(fwd, false))) return rc;
+    if (!adj || !adj->xbar || !adj->ubar || !adj->utbar || !adj->pbar || !adj->uinbar ||
+        !adj->avgbar || !adj->scratch)
+        return fail(SPH_EINVAL, "adjoint buffers have a NULL array");
+    DevAdj A;
+    A.abar = adj->abar;
+    A.bbar = adj->bbar;
+    A.pdbar = adj->pdbar;
+    for (int d = 0; d < 3; ++d) A.fbar[d] = adj->fbar[d];
+    A.xbar = adj->xbar;
+    A.ubar = adj->ubar;
+    A.utbar = adj->utbar;
+    A.pbar = adj->pbar;
+    A.uinbar = adj->uinbar;
+    A.avgbar = adj->avgbar;
+    const int64_t C = st->cap;
+    A.wbar = adj->scratch;             // [3][cap]
+    A.rhobar = adj->scratch + 3 * C;
+    A.volbar = adj->scratch + 4 * C;
+    A.Pbar = adj->scratch + 5 * C;
+    A.Sbar = adj->scratch + 6 * C;
+    launch_rhs_adjoint(c.k, dev_state(st), fields_of(st), dev_nlist(nl), dev_derived(fwd), A,
+                       c.off(), at<uint32_t>(c.ws, c.w.cpos_s), c.err(), c.s);
+    return check_hip("sph_rhs_adjoint");
 }
 
 int sph_poll_error(void *ws, size_t ws_bytes, uint32_t *bits, void *stream)

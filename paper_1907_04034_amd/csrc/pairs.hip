@@ -95,68 +95,6 @@ struct Acc<float> {
     }
 };
 
-__device__ inline bool bad_index(int32_t j, int64_t n) { return uint64_t(j) >= uint64_t(n); }
-
-// Pair separation r_i - r_j in the arithmetic type. FP64: minimum image of
-// the absolute positions. FP32: cell-relative offsets plus the (wrapped)
-// cell difference times the cell size, so no large coordinate is rounded to
-// FP32.
-template <int DIM, typename T>
-struct Sep;
-
-template <int DIM>
-struct Sep<DIM, double> {
-    double xi[3];
-    __device__ inline void load_i(const Dev &k, const Fields &R, const float *, const uint32_t *,
-                                  int64_t i)
-    {
-        xi[2] = 0.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * k.cap + i];
-    }
-    __device__ inline double get(const Dev &k, const Fields &R, const float *, const uint32_t *,
-                                 int64_t j, double r[3]) const
-    {
-        double xj[3] = {0, 0, 0};
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * k.cap + j];
-        return dist2_exact<DIM>(k, xi, xj, r);
-    }
-};
-
-template <int DIM>
-struct Sep<DIM, float> {
-    float oi[3];
-    int ci[3];
-    __device__ inline void load_i(const Dev &k, const Fields &, const float *off,
-                                  const uint32_t *cpos, int64_t i)
-    {
-        oi[2] = 0.f;
-        unpack_cell<DIM>(cpos[i], ci);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) oi[d] = off[d * k.cap + i];
-    }
-    __device__ inline float get(const Dev &k, const Fields &, const float *off,
-                                const uint32_t *cpos, int64_t j, float r[3]) const
-    {
-        int cj[3];
-        unpack_cell<DIM>(cpos[j], cj);
-        float s = 0.f;
-        r[2] = 0.f;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            int dc = ci[d] - cj[d];
-            if (k.periodic[d]) {
-                if (dc > 1) dc -= k.nc[d];
-                else if (dc < -1) dc += k.nc[d];
-            }
-            r[d] = (oi[d] - off[d * k.cap + j]) + float(dc) * k.csf[d];
-            s += r[d] * r[d];
-        }
-        return s;
-    }
-};
-
 // ---------------------------------------------- neighbour table + density
 // The group walks the 3^d stencil cells in (dz, dy, dx) order; for each cell
 // its lanes test members b + lane, b + lane + G, ... with the FMA-free FP64
@@ -363,6 +301,7 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
         for (int d = 0; d < DIM; ++d) su[d] = gsum<G>(su[d]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) sJ[a] = gsum<G>(sJ[a]);
+        if (lane == 0) o.sfl[i] = sw;
         if (is_wall(t)) {
             if (lane == 0) {
                 double pw = 0.0;

@@ -56,8 +56,17 @@ struct Fields {
 
 struct DevDerived {
     void *rho, *vol, *pavg, *a, *b, *pdot;
-    double *jcur, *force, *drag;
+    double *jcur, *force, *drag, *sfl;
     uint8_t *red;
+};
+
+// Objective weights and gradient buffers of the reverse pass (all FP64
+// storage; arithmetic in the state's precision).
+struct DevAdj {
+    const void *abar, *bbar, *pdbar;
+    double fbar[3];
+    double *xbar, *ubar, *utbar, *pbar, *uinbar, *avgbar;
+    double *wbar, *rhobar, *volbar, *Pbar, *Sbar;
 };
 
 struct DevNlist {
@@ -168,5 +177,67 @@ __device__ inline void st(void *p, int64_t i, T v)
 {
     static_cast<T *>(p)[i] = v;
 }
+
+__device__ inline bool bad_index(int32_t j, int64_t n) { return uint64_t(j) >= uint64_t(n); }
+
+// Pair separation r_i - r_j in the arithmetic type. FP64: minimum image of
+// the absolute positions. FP32: cell-relative offsets plus the (wrapped)
+// cell difference times the cell size, so no large coordinate is rounded to
+// FP32.
+template <int DIM, typename T>
+struct Sep;
+
+template <int DIM>
+struct Sep<DIM, double> {
+    double xi[3];
+    __device__ inline void load_i(const Dev &k, const Fields &R, const float *, const uint32_t *,
+                                  int64_t i)
+    {
+        xi[2] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * k.cap + i];
+    }
+    __device__ inline double get(const Dev &k, const Fields &R, const float *, const uint32_t *,
+                                 int64_t j, double r[3]) const
+    {
+        double xj[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * k.cap + j];
+        return dist2_exact<DIM>(k, xi, xj, r);
+    }
+};
+
+template <int DIM>
+struct Sep<DIM, float> {
+    float oi[3];
+    int ci[3];
+    __device__ inline void load_i(const Dev &k, const Fields &, const float *off,
+                                  const uint32_t *cpos, int64_t i)
+    {
+        oi[2] = 0.f;
+        unpack_cell<DIM>(cpos[i], ci);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) oi[d] = off[d * k.cap + i];
+    }
+    __device__ inline float get(const Dev &k, const Fields &, const float *off,
+                                const uint32_t *cpos, int64_t j, float r[3]) const
+    {
+        int cj[3];
+        unpack_cell<DIM>(cpos[j], cj);
+        float s = 0.f;
+        r[2] = 0.f;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            int dc = ci[d] - cj[d];
+            if (k.periodic[d]) {
+                if (dc > 1) dc -= k.nc[d];
+                else if (dc < -1) dc += k.nc[d];
+            }
+            r[d] = (oi[d] - off[d * k.cap + j]) + float(dc) * k.csf[d];
+            s += r[d] * r[d];
+        }
+        return s;
+    }
+};
 
 }  // namespace sph

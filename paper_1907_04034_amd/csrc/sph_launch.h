@@ -39,6 +39,11 @@ void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields
 void launch_drag_final(const Dev &k, const double *dragpart, double *drag, double *hist,
                        hipStream_t s);
 
+// reverse pass of one right-hand side
+void launch_rhs_adjoint(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                        const DevDerived &o, const DevAdj &A, const float *off,
+                        const uint32_t *cpos, uint32_t *err, hipStream_t s);
+
 // bookkeeping
 void launch_end_of_step(const Dev &k, const DevState &st, const DevDerived &o,
                         int32_t *nspawn, uint32_t *err, hipStream_t s);

@@ -1,0 +1,142 @@
+"""Hand-written reverse pass of one right-hand side (sph_rhs_adjoint) against
+finite differences of the FP64 oracle.
+
+Dot-product test: for random output weights w and a random input direction d,
+    <d, J^T w>  (adjoint, GPU)  ==  d/de L(s + e d)  (4th-order central FD, oracle)
+with L = sum_fluid (abar.a + bbar.b + pdbar pdot) + fbar.drag. Inputs are
+seeded jittered states with random fields, so no pair sits at the support edge
+and the neighbour sets do not change under the perturbation.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_04034_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def B():
+    from paper_1907_04034_amd import binding
+    return binding
+
+
+def _case(name, seed):
+    if name == "C1-jit":
+        prm, s = I.config("C1")
+    else:
+        prm, s = I.config(name.split("-")[0], small=True)
+    s = I.random_fields(prm, I.jitter(prm, s, 0.2, seed), seed + 100)
+    return prm, s
+
+
+def _objective_weights(prm, s, od, rng):
+    """Random weights on the fluid outputs, each field scaled by its magnitude."""
+    n, D = len(s["p"]), prm["dim"]
+    fl = s["type"] == I.FLUID
+    w = {}
+    for key in ("a", "b"):
+        sc = np.abs(od["abs_" + key][fl]).max()
+        v = np.zeros((n, 3))
+        v[fl, :D] = rng.standard_normal((fl.sum(), D)) / sc
+        w[key] = v
+    sc = np.abs(od["abs_pdot"][fl]).max()
+    v = np.zeros(n)
+    v[fl] = rng.standard_normal(fl.sum()) / sc
+    w["pdot"] = v
+    w["fbar"] = rng.standard_normal(3) if (s["type"] == I.BODY).any() else np.zeros(3)
+    if D == 2:
+        w["fbar"][2] = 0.0
+    return w
+
+
+def _L(prm, s, w):
+    _, d, F = O.rhs_once(prm, s)
+    return ((w["a"] * d["a"]).sum() + (w["b"] * d["b"]).sum() + (w["pdot"] * d["pdot"]).sum()
+            + (w["fbar"] * F).sum())
+
+
+def _direction(prm, s, rng):
+    n, D = len(s["p"]), prm["dim"]
+    t = s["type"]
+    fl = t == I.FLUID
+    movable = np.isin(t, [I.FLUID, I.INLET, I.OUTLET])
+    d = {k: np.zeros_like(v, dtype=np.float64) for k, v in s.items()
+         if k in ("x", "u", "ut", "p", "uin", "avg")}
+    d["x"][movable, :D] = prm["dx"] * rng.standard_normal((movable.sum(), D))
+    d["u"][fl, :D] = rng.standard_normal((fl.sum(), D))
+    d["ut"][fl, :D] = rng.standard_normal((fl.sum(), D))
+    d["p"][fl] = rng.standard_normal(fl.sum())
+    inl = t == I.INLET
+    d["uin"][inl, :D] = rng.standard_normal((inl.sum(), D))
+    av = (fl | (t == I.OUTLET))
+    d["avg"][av, :D] = rng.standard_normal((av.sum(), D))
+    d["avg"][av, 3] = rng.standard_normal(av.sum())
+    return d
+
+
+def _perturbed(s, d, e):
+    s2 = I.snapshot_copy(s)
+    for k, v in d.items():
+        s2[k] = s[k] + e * v
+    return s2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 2e-7), ("fp32", 2e-4)])
+@pytest.mark.parametrize("name", ["C1-jit", "C2-small", "C3-small", "C4-small", "C5-small"])
+def test_rhs_adjoint_dot_product(name, prec, tol):
+    print(f"adjoint {name} {prec}", flush=True)
+    rng = np.random.default_rng(7)
+    prm, s = _case(name, 3)
+    _, od, _ = O.rhs_once(prm, s)
+    w = _objective_weights(prm, s, od, rng)
+    d = _direction(prm, s, rng)
+    # GPU forward + reverse
+    gs, gd, sim = B().rhs_once(prm, s, prec=prec)
+    idx = {int(v): k for k, v in enumerate(s["id"])}
+    perm = np.array([idx[int(v)] for v in gs["id"]])  # device row -> input row
+    g = sim.rhs_adjoint(abar=w["a"][perm], bbar=w["b"][perm], pdbar=w["pdot"][perm],
+                        fbar=w["fbar"])
+    assert sim.poll_error() == 0
+    D = prm["dim"]
+    adj = 0.0
+    for key, gk in (("x", "xbar"), ("u", "ubar"), ("ut", "utbar"), ("uin", "uinbar")):
+        adj += (d[key][perm][:, :D] * g[gk][:, :D]).sum()
+    adj += (d["p"][perm] * g["pbar"]).sum()
+    adj += (d["avg"][perm][:, :D] * g["avgbar"][:, :D]).sum() + (d["avg"][perm][:, 3] * g["avgbar"][:, 3]).sum()
+    # 4th-order central difference on the oracle
+    e = 1e-6
+    Lp1, Lm1 = _L(prm, _perturbed(s, d, e), w), _L(prm, _perturbed(s, d, -e), w)
+    Lp2, Lm2 = _L(prm, _perturbed(s, d, 2 * e), w), _L(prm, _perturbed(s, d, -2 * e), w)
+    fd = (8 * (Lp1 - Lm1) - (Lp2 - Lm2)) / (12 * e)
+    rel = abs(adj - fd) / max(abs(fd), 1e-300)
+    print(f"  fd={fd:.12e} adjoint={adj:.12e} rel={rel:.2e}", flush=True)
+    assert rel < tol, (fd, adj, rel)
+
+
+def test_rhs_adjoint_parts_isolated():
+    """Each input block separately (C3-small, FP64): positions, velocities,
+    transport velocities, pressures; catches errors that cancel in a sum."""
+    rng = np.random.default_rng(11)
+    prm, s = _case("C3-small", 5)
+    _, od, _ = O.rhs_once(prm, s)
+    w = _objective_weights(prm, s, od, rng)
+    dall = _direction(prm, s, rng)
+    gs, gd, sim = B().rhs_once(prm, s)
+    idx = {int(v): k for k, v in enumerate(s["id"])}
+    perm = np.array([idx[int(v)] for v in gs["id"]])
+    g = sim.rhs_adjoint(abar=w["a"][perm], bbar=w["b"][perm], pdbar=w["pdot"][perm],
+                        fbar=w["fbar"])
+    D = prm["dim"]
+    for key, gk in (("x", "xbar"), ("u", "ubar"), ("ut", "utbar"), ("p", "pbar")):
+        d = {k: np.zeros_like(v) for k, v in dall.items()}
+        d[key] = dall[key]
+        gv = g[gk]
+        adj = (d[key][perm][:, :D] * gv[:, :D]).sum() if gv.ndim == 2 else (d[key][perm] * gv).sum()
+        e = 1e-6
+        fd = (8 * (_L(prm, _perturbed(s, d, e), w) - _L(prm, _perturbed(s, d, -e), w))
+              - (_L(prm, _perturbed(s, d, 2 * e), w) - _L(prm, _perturbed(s, d, -2 * e), w))) / (12 * e)
+        rel = abs(adj - fd) / max(abs(fd), 1e-300)
+        print(f"  {key}: fd={fd:.10e} adjoint={adj:.10e} rel={rel:.2e}", flush=True)
+        assert rel < 2e-7, (key, fd, adj)
