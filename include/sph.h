@@ -67,6 +67,14 @@ enum {
     SPH_ERR_CELL_RANGE = 32u    /* corrupt cell/neighbour index found (input misuse) */
 };
 
+/* per-row events of one step, recorded by sph_step_record for the reverse */
+enum {
+    SPH_EV_PUSH = 1,       /* the time-average ring took this step's sample */
+    SPH_EV_TO_OUTLET = 2,  /* fluid particle crossed into the outlet */
+    SPH_EV_DELETE = 4,     /* outlet particle passed the outlet end */
+    SPH_EV_SPAWN = 8       /* inlet particle entered the fluid and left a child */
+};
+
 /* Host parameter block (copied by value). Symbols follow Sec. 2 of the paper:
  * h smoothing length (support 2h of the Wendland C2 kernel), c the artificial
  * speed of sound c_s, nu the kinematic viscosity, alpha the EDAC damping
@@ -211,24 +219,90 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
  * eq:characteristic-vars / eq:shepard / eq:acou, inlet J3) and the summation
  * density. Preconditions: sph_neighbors and sph_rhs have run on the same
  * state, table, derived buffers and workspace (the reverse reads the stored
- * rho, V, pbar, boundary values, J and Shepard sums). Boundary values taken
- * from the previous step (particles without fluid support) reach no fluid
- * force, so their inputs get no gradient. Gather-only, deterministic. */
+ * rho, V, pbar, boundary values, J and Shepard sums). Optional seeds add
+ *     + sum over non-fluid rows (pseed p + useed . u) + sum over inlet/outlet
+ *       rows jseed . J
+ * to L, where p, u are the boundary values and J the characteristic values
+ * (jcur) this right-hand side computed; inlet/outlet rows without fluid
+ * support took J from the previous-step values (eq:average_old), whose
+ * gradient goes to jprevbar. Gather-only, deterministic. */
 typedef struct sph_adjoint {
     const void *abar, *bbar;  /* [3][cap] weights, state element type (may be NULL) */
     const void *pdbar;        /* [cap] (may be NULL) */
+    const double *pseed;      /* [cap] adjoint added to non-fluid rows' p (may be NULL) */
+    const double *useed;      /* [3][cap] adjoint added to non-fluid rows' u (may be NULL) */
+    const double *jseed;      /* [3][cap] weight of inlet/outlet rows' J (may be NULL) */
     double fbar[3];           /* weight of the body force */
     double *xbar;             /* out [3][cap] dL/dx (every row) */
     double *ubar, *utbar;     /* out [3][cap] dL/du, dL/dut (fluid rows) */
     double *pbar;             /* out [cap] dL/dp (fluid rows) */
     double *uinbar;           /* out [3][cap] dL/du_in (inlet rows) */
     double *avgbar;           /* out [dim+1][cap] dL/d<u,p> (fluid and outlet rows) */
-    double *scratch;          /* [8][cap] work space */
+    double *jprevbar;         /* out [3][cap] dL/d jprev (inlet/outlet rows; may be NULL,
+                                 then the previous-step values are not differentiated) */
+    double *scratch;          /* [10][cap] work space */
 } sph_adjoint;
 
 int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
                     const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
                     void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Reverse of time steps (discrete adjoint of the explicit-midpoint step).
+ *
+ * Adjoint of a particle state: one FP64 device array per continuous state
+ * field, in the state's layout ([3][cap] for x, u, ut, uin, jprev; [cap] for
+ * p; [n_avg][dim+1][cap] ring; [dim+1][cap] avg), rows in the state's order.
+ */
+typedef struct sph_state_adjoint {
+    int64_t cap;
+    double *x, *u, *ut, *p, *uin, *ring, *avg, *jprev;
+} sph_state_adjoint;
+
+/* One step exactly as sph_step (bit-identical result), recording for the
+ * reverse: child[r] = row of the inlet particle that sorted row r left behind
+ * (-1 if none) and events[r] = SPH_EV_* bits, for r < the live count after
+ * the step's bin (device arrays of cap entries). drag (device [3], may be
+ * NULL) receives the stage-1 body force. */
+int sph_step_record(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+                    sph_derived *out, double *drag, int32_t *child, uint8_t *events,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Bytes of the scratch buffer sph_step_adjoint needs for capacity cap. */
+int sph_step_adjoint_scratch_size(const sph_params *prm, int64_t cap, size_t *bytes);
+
+/* Reverse of one step. st is the state the step started from (unchanged;
+ * typically a stored copy), child / events what sph_step_record wrote for
+ * that step. Given lam_next, the adjoint of the state after the step (rows in
+ * that state's order: the step's sorted rows, then its children), and fbar,
+ * the weight of the stage-1 body force, writes lam, the adjoint of st (rows
+ * in st's order; rows the bin dropped get zero), with the discrete events of
+ * the recorded step held fixed. The stage values are recomputed from st:
+ * work is a scratch state (own live-count pointer), nl1/nl2 and d1/d2 scratch
+ * neighbour tables and derived buffers of the two stages; scratch holds
+ * sph_step_adjoint_scratch_size() bytes. lam and lam_next must not share
+ * arrays. The reverse runs back through the stage updates (explicit midpoint
+ * with eq:transport-vel and eq:advection), the right-hand side
+ * (eq:summation-density, eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
+ * eq:p-edac, eq:tvf-momentum_solid), the boundary values
+ * (eq:characteristic-vars, eq:shepard, eq:average_old, eq:acou, inlet J3) and
+ * the bookkeeping of Sec. 3.4 (gated average eq:acouinten, transfers,
+ * re-spawn). Gather-only, deterministic. */
+int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work,
+                     const int32_t *child, const uint8_t *events, sph_nlist *nl1,
+                     sph_nlist *nl2, sph_derived *d1, sph_derived *d2, const double fbar[3],
+                     const sph_state_adjoint *lam_next, sph_state_adjoint *lam, void *scratch,
+                     size_t scratch_bytes, void *ws, size_t ws_bytes, void *stream);
+
+/* Gradient with respect to an inlet velocity profile theta[ntheta] that set,
+ * for every row q of st with index[q] = k >= 0, the x components of u_in, u,
+ * ut, every ring slot and the mean to theta[k]:
+ *     grad[k] = sum over those rows of the corresponding entries of lam.
+ * index: device int32 [cap] (-1 = not a profile row); grad: device [ntheta].
+ * One block per entry, fixed summation order. */
+int sph_inlet_profile_grad(const sph_params *prm, const sph_state *st,
+                           const sph_state_adjoint *lam, const int32_t *index, int32_t ntheta,
+                           double *grad, void *stream);
 
 /* Synchronises `stream`, returns the accumulated device error bits in *bits
  * and clears them. */

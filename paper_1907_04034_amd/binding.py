@@ -22,7 +22,10 @@ ERR_BITS = {1: "NBR_OVERFLOW", 2: "CAPACITY", 4: "NONFINITE", 8: "SKIN", 16: "ES
 
 EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors",
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
-            "sph_rhs_adjoint", "sph_poll_error", "sph_live_count", "sph_last_error"]
+            "sph_rhs_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
+            "sph_step_adjoint", "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count",
+            "sph_last_error"]
+EV_PUSH, EV_TO_OUTLET, EV_DELETE, EV_SPAWN = 1, 2, 4, 8
 
 
 class SphParams(C.Structure):
@@ -54,9 +57,15 @@ class SphNlist(C.Structure):
 
 
 class SphAdjoint(C.Structure):
-    _fields_ = [("abar", _P), ("bbar", _P), ("pdbar", _P), ("fbar", C.c_double * 3),
+    _fields_ = [("abar", _P), ("bbar", _P), ("pdbar", _P), ("pseed", _P), ("useed", _P),
+                ("jseed", _P), ("fbar", C.c_double * 3),
                 ("xbar", _P), ("ubar", _P), ("utbar", _P), ("pbar", _P), ("uinbar", _P),
-                ("avgbar", _P), ("scratch", _P)]
+                ("avgbar", _P), ("jprevbar", _P), ("scratch", _P)]
+
+
+class SphStateAdjoint(C.Structure):
+    _fields_ = [("cap", C.c_int64), ("x", _P), ("u", _P), ("ut", _P), ("p", _P), ("uin", _P),
+                ("ring", _P), ("avg", _P), ("jprev", _P)]
 
 
 class SphDerived(C.Structure):
@@ -88,6 +97,12 @@ def lib():
         L.sph_force.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_step.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, sz, _P]
         L.sph_rhs_adjoint.argtypes = [SP, ST, NL, DE, C.POINTER(SphAdjoint), _P, sz, _P]
+        LA = C.POINTER(SphStateAdjoint)
+        L.sph_step_record.argtypes = [SP, ST, ST, NL, DE, _P, _P, _P, _P, sz, _P]
+        L.sph_step_adjoint_scratch_size.argtypes = [SP, C.c_int64, C.POINTER(C.c_size_t)]
+        L.sph_step_adjoint.argtypes = [SP, ST, ST, _P, _P, NL, NL, DE, DE,
+                                       C.POINTER(C.c_double * 3), LA, LA, _P, sz, _P, sz, _P]
+        L.sph_inlet_profile_grad.argtypes = [SP, ST, LA, _P, C.c_int32, _P, _P]
         L.sph_poll_error.argtypes = [_P, sz, C.POINTER(C.c_uint32), _P]
         L.sph_live_count.argtypes = [ST, C.POINTER(C.c_int64), _P]
         L.sph_last_error.restype = C.c_char_p
@@ -304,23 +319,27 @@ class Simulation:
         _check(lib().sph_live_count(C.byref(self.st), C.byref(n), self.stream), "sph_live_count")
         return n.value
 
-    def rhs_adjoint(self, abar=None, bbar=None, pdbar=None, fbar=(0.0, 0.0, 0.0)):
-        """Gradient of L = sum_fluid(abar.a + bbar.b + pdbar*pdot) + fbar.drag for the
-        current stage (sph_neighbors and sph_rhs must have run). Weights are host
-        arrays in the current device row order ((n, 3) or (n,)); returns host
-        gradients in the same order (xbar, ubar, utbar, uinbar: (n, 3); pbar: (n,);
-        avgbar: (n, 4) with the pressure in the last column)."""
+    def rhs_adjoint(self, abar=None, bbar=None, pdbar=None, fbar=(0.0, 0.0, 0.0), pseed=None,
+                    useed=None, jseed=None):
+        """Gradient of L = sum_fluid(abar.a + bbar.b + pdbar*pdot) + fbar.drag
+        + sum_nonfluid(pseed*p + useed.u) + sum_inlet/outlet(jseed.J) for the current
+        stage (sph_neighbors and sph_rhs must have run). Weights are host arrays in
+        the current device row order ((n, 3) or (n,)); returns host gradients in the
+        same order (xbar, ubar, utbar, uinbar, jprevbar: (n, 3); pbar: (n,); avgbar:
+        (n, 4) with the pressure in the last column)."""
         t, cap, D = self.torch, self.cap, self.dim
         n = self.live_count()
         if not hasattr(self, "adj"):
             z = lambda k: t.zeros(k * cap, dtype=t.float64, device=self.dev)  # noqa: E731
             self.adj = dict(xbar=z(3), ubar=z(3), utbar=z(3), pbar=z(1), uinbar=z(3),
-                            avgbar=z(D + 1), scratch=z(8),
+                            avgbar=z(D + 1), jprevbar=z(3), scratch=z(10), pseed=z(1),
+                            useed=z(3), jseed=z(3),
                             abar=t.zeros(3 * cap, dtype=self.rdt, device=self.dev),
                             bbar=t.zeros(3 * cap, dtype=self.rdt, device=self.dev),
                             pdbar=t.zeros(cap, dtype=self.rdt, device=self.dev))
         A = self.adj
-        for name, w, comps in (("abar", abar, 3), ("bbar", bbar, 3), ("pdbar", pdbar, 1)):
+        for name, w, comps in (("abar", abar, 3), ("bbar", bbar, 3), ("pdbar", pdbar, 1),
+                               ("pseed", pseed, 1), ("useed", useed, 3), ("jseed", jseed, 3)):
             A[name].zero_()
             if w is not None:
                 w = np.asarray(w, np.float64)
@@ -331,14 +350,15 @@ class Simulation:
         st.abar, st.bbar, st.pdbar = A["abar"].data_ptr(), A["bbar"].data_ptr(), A["pdbar"].data_ptr()
         for d in range(3):
             st.fbar[d] = float(fbar[d])
-        for k in ("xbar", "ubar", "utbar", "pbar", "uinbar", "avgbar", "scratch"):
+        for k in ("pseed", "useed", "jseed", "xbar", "ubar", "utbar", "pbar", "uinbar", "avgbar",
+                  "jprevbar", "scratch"):
             setattr(st, k, A[k].data_ptr())
         ws, nb = self._ws()
         _check(lib().sph_rhs_adjoint(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
                                      C.byref(self.out), C.byref(st), ws, nb, self.stream),
                "sph_rhs_adjoint")
         out = {}
-        for k in ("xbar", "ubar", "utbar", "uinbar"):
+        for k in ("xbar", "ubar", "utbar", "uinbar", "jprevbar"):
             out[k] = A[k].view(3, cap)[:, :n].cpu().numpy().T.copy()
         out["pbar"] = A["pbar"][:n].cpu().numpy().copy()
         av = A["avgbar"].view(D + 1, cap)[:, :n].cpu().numpy().T

@@ -18,10 +18,12 @@
 //                  Shepard averages to the fluid (p, u, rho, x), to the inlet
 //                  velocity and the outlet averages; then Sbar = m rhobar - V^2 Vbar;
 //   R3  density:   xbar_k += sum_j (Sbar_k + Sbar_j) F_kj r_kj.
-// Values of boundary particles without fluid support come from the previous
-// step's characteristic values; by the symmetry of the neighbour predicate no
-// fluid particle has such a particle in its support, so those values reach no
-// fluid force and no drag, and their adjoint is not propagated.
+// Boundary values may also carry seeds (pseed, useed on p and u of non-fluid
+// rows, jseed on J of inlet/outlet rows) from a stage update or the next
+// step that reads them. Inlet/outlet particles without fluid support take J
+// from the previous step's values; by the symmetry of the neighbour predicate
+// no fluid particle has such a particle in its support, so only seeds reach
+// them, and their adjoint goes to the previous-step values (jprevbar).
 #include "sph_launch.h"
 
 namespace sph {
@@ -291,13 +293,16 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
             for (int d = 0; d < DIM; ++d) xb[d] -= rb[d];
         }
     }
+    // boundary values may carry adjoints from outside this right-hand side
+    // (a stage update that reads them)
+    const bool seeded = K.t != SPH_FLUID;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         A.xbar[d * C + i] = double(xb[d]);
-        A.ubar[d * C + i] = double(Kb.u[d]);
+        A.ubar[d * C + i] = double(Kb.u[d]) + (seeded && A.useed ? A.useed[d * C + i] : 0.0);
         A.wbar[d * C + i] = double(Kb.w[d]);
     }
-    A.pbar[i] = double(Kb.p);
+    A.pbar[i] = double(Kb.p) + (seeded && A.pseed ? A.pseed[i] : 0.0);
     A.rhobar[i] = double(Kb.rho);
     A.volbar[i] = double(Kb.vol);
     A.Pbar[i] = double(Pb);
@@ -326,15 +331,19 @@ __global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist
     A.pbar[i] += acc;
 }
 
-// Reverse of the Shepard weight W_bf of boundary particle b and fluid f
-// given the adjoints of b's values: returns Wbar and adds the fluid-side
-// adjoints (p, u_x, rho, averages) when `to_fluid`; adds the inlet velocity
-// adjoint of b when `to_inlet`.
+// Adjoint of boundary particle b's characteristic values J = (J1, J2, J3)
+// (stored as jcur[0..2]) from the adjoints of its pressure and velocity and a
+// seed on J itself (J becomes the next step's previous-step value). Outlet:
+// p = <p> + (J2 + J3)/2, u = <u> + (J2 - J3)/(2 rho0 c) (eq:acou) with J3
+// forced to zero when J comes from the Shepard sums; inlet: p = J3.
 struct BndIn {
     int t;
-    double S, pbar, ubar[3], p, u[3], J2, J3, uin0;
+    double S, pbar, ubar[3], p, u[3], J[3], Jb[3], uin0;
 };
 
+// Reverse of the Shepard weight W_bf of boundary particle b and fluid f
+// given the adjoints of b's values: returns Wbar and adds the fluid-side
+// adjoints (p, u_x, rho, averages) and the inlet velocity adjoint of b.
 template <int DIM>
 __device__ inline double bnd_weight_adj(const Dev &k, const BndIn &b, double w, double pf,
                                         const double uf[3], double rhof, const double avgf[4],
@@ -352,25 +361,26 @@ __device__ inline double bnd_weight_adj(const Dev &k, const BndIn &b, double w, 
         return Wb / b.S;
     }
     if (b.t == SPH_OUTLET) {
-        const double J2hb = 0.5 * b.pbar + b.ubar[0] / (2.0 * k.rho0 * k.c);
+        // J1_f = -c^2 (rho_f - rho0) + dp, J2_f = rho_f c du + dp (eq:characteristic-vars)
         const double du = uf[0] - avgf[0], dp = pf - avgf[DIM];
+        const double J1f = -k.c2 * (rhof - k.rho0) + dp;
         const double J2f = rhof * k.c * du + dp;
-        const double J2fb = J2hb * w / b.S;
-        rhofb += J2fb * k.c * du;
+        const double J1fb = b.Jb[0] * w / b.S, J2fb = b.Jb[1] * w / b.S;
+        rhofb += J2fb * k.c * du - J1fb * k.c2;
         ufb[0] += J2fb * rhof * k.c;
-        pfb += J2fb;
+        pfb += J1fb + J2fb;
         avgfb[0] -= J2fb * rhof * k.c;
-        avgfb[DIM] -= J2fb;
-        return J2hb * (J2f - b.J2) / b.S;
+        avgfb[DIM] -= J1fb + J2fb;
+        return (b.Jb[0] * (J1f - b.J[0]) + b.Jb[1] * (J2f - b.J[1])) / b.S;
     }
-    // inlet: p_b = Shepard J3, J3_f = -rho_f c (u_f - u_in,b) + p_f
+    // inlet: J3_f = -rho_f c (u_f - u_in,b) + p_f
     const double J3f = -rhof * k.c * (uf[0] - b.uin0) + pf;
-    const double J3fb = b.pbar * w / b.S;
+    const double J3fb = b.Jb[2] * w / b.S;
     rhofb -= J3fb * k.c * (uf[0] - b.uin0);
     ufb[0] -= J3fb * rhof * k.c;
     pfb += J3fb;
     uinb0 += J3fb * rhof * k.c;
-    return b.pbar * (J3f - b.J3) / b.S;
+    return b.Jb[2] * (J3f - b.J[2]) / b.S;
 }
 
 template <int DIM, typename T>
@@ -389,12 +399,26 @@ __device__ inline void load_bnd(const Dev &k, const DevState &m, const Fields &R
         B.ubar[d] = A.ubar[d * C + b];
         B.u[d] = double(ld<T>(R.u, d * C + b));
     }
-    B.J2 = o.jcur[C + b];
-    B.J3 = o.jcur[2 * C + b];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        B.J[a] = o.jcur[a * C + b];
+        B.Jb[a] = A.jseed ? A.jseed[a * C + b] : 0.0;
+    }
+    if (B.t == SPH_OUTLET) {
+        const double ub = B.ubar[0] / (2.0 * k.rho0 * k.c);
+        B.Jb[1] += 0.5 * B.pbar + ub;
+        B.Jb[2] = B.S > 0.0 ? 0.0 : B.Jb[2] + 0.5 * B.pbar - ub;
+    } else if (B.t == SPH_INLET) {
+        B.Jb[2] += B.pbar;
+    }
     B.uin0 = m.uin[b];
 }
 
-// R2b: boundary reverses, then Sbar = m rhobar - V^2 Vbar.
+// R2b: boundary reverses, then Sbar = m rhobar - V^2 Vbar. A boundary row
+// without fluid support took J from the previous-step values of same-kind
+// neighbours (or its own): its J adjoint is split over those, here as
+// jg = Jbar / M for the neighbours to gather in R3 (or straight into its own
+// jprevbar when M = 0).
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R, DevNlist nl,
                                                     DevDerived o, DevAdj A, uint32_t *err)
@@ -406,7 +430,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
     const int t = m.type[i];
     const int cnt = nl.count[i];
     double xi[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, avgb[4] = {0, 0, 0, 0};
-    double uinb[3] = {0, 0, 0};
+    double uinb[3] = {0, 0, 0}, jg[3] = {0, 0, 0}, jown[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         xi[d] = R.x[d * C + i];
@@ -468,6 +492,22 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
 #pragma unroll
             for (int d = 0; d < DIM; ++d) xb[d] += Wb * F * r[d];
         }
+    } else if ((t == SPH_INLET || t == SPH_OUTLET) && A.jprevbar) {
+        // no fluid support: J = mean of the previous-step values of same-kind
+        // neighbours that had support (eq:average_old), else the own value
+        BndIn B;
+        load_bnd<DIM, T>(k, m, R, o, A, i, B);
+        double M = 0.0;
+        for (int q = 0; q < cnt; ++q) {
+            const int32_t j = nl.nbr[i * nl.maxnb + q];
+            if (bad_index(j, n)) continue;
+            if (m.type[j] == t && m.red_prev[j]) M += 1.0;
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (M > 0.0) jg[a] = B.Jb[a] / M;
+            else jown[a] = B.Jb[a];
+        }
     }
     if (t == SPH_INLET) {
 #pragma unroll
@@ -490,6 +530,13 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
     }
 #pragma unroll
     for (int c = 0; c <= DIM; ++c) A.avgbar[c * C + i] = avgb[c];
+    if (A.jprevbar) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            A.jg[a * C + i] = jg[a];
+            A.jprevbar[a * C + i] = jown[a];
+        }
+    }
     if (t == SPH_FLUID) A.pbar[i] = pb;
     A.rhobar[i] = rhob;
     A.Sbar[i] = Sb;
@@ -529,13 +576,27 @@ __global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R
 #pragma unroll
         for (int d = 0; d < DIM; ++d) xb[d] += s * r[d];
     }
-    const bool fl = m.type[i] == SPH_FLUID;
+    const int t = m.type[i];
+    const bool fl = t == SPH_FLUID;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         A.xbar[d * C + i] = xb[d];
         const double w = A.wbar[d * C + i];
         A.utbar[d * C + i] = fl ? w : 0.0;
         if (fl) A.ubar[d * C + i] -= w;
+    }
+    // previous-step values of i read by unsupported same-kind neighbours
+    // (i itself included), reverse of the mean taken in R2b
+    if (A.jprevbar && (t == SPH_INLET || t == SPH_OUTLET) && m.red_prev[i]) {
+        double g[3] = {0, 0, 0};
+        for (int q = 0; q < cnt; ++q) {
+            const int32_t j = nl.nbr[i * nl.maxnb + q];
+            if (bad_index(j, n) || m.type[j] != t) continue;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[a] += A.jg[a * C + j];
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) A.jprevbar[a * C + i] += g[a];
     }
 }
 

@@ -101,23 +101,6 @@ __global__ void __launch_bounds__(kBlock) k_keys(Dev k, DevState s, const int32_
     }
 }
 
-__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total)
-{
-    const int t = threadIdx.x;
-    lds[t] = v;
-    __syncthreads();
-    for (int off = 1; off < kBlock; off <<= 1) {
-        const int32_t add = t >= off ? lds[t - off] : 0;
-        __syncthreads();
-        lds[t] += add;
-        __syncthreads();
-    }
-    const int32_t incl = lds[t];
-    *total = lds[kBlock - 1];
-    __syncthreads();
-    return incl - v;
-}
-
 // cell_start = exclusive scan of counts (n entries); every tile adds the sum
 // of the tile totals before it, so one launch suffices. Consumed counts are
 // zeroed for the next bin.

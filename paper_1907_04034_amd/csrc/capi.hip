@@ -176,6 +176,8 @@ static WsLayout layout(const Dev &k)
     w.hp = take(sizeof(double) * C);
     w.off = take(sizeof(float) * 3 * C);
     w.dragpart = take(sizeof(double) * 3 * size_t(force_grid_max(k)));
+    w.sflag = take(C);
+    w.stile = take(sizeof(int32_t) * size_t(nblocks(k.cap)));
     w.total = off;
     return w;
 }
@@ -365,6 +367,108 @@ static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields 
     if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
 }
 
+// One explicit-midpoint step (bin, two stages, end-of-step bookkeeping);
+// spawned rows stay counted in the workspace until the next bin or
+// launch_finish_spawn. child / events (may be NULL) record the step.
+static void one_step(Ctx &c, sph_state *st, sph_state *alt, sph_nlist *nl, sph_derived *out,
+                     double *hist, int32_t *child, uint8_t *events)
+{
+    const Fields H = c.half();
+    do_bin(c, st, alt);
+    const Fields M = fields_of(st);
+    // stage 1 at the start state, written to the half state
+    do_nbrdens(c, st, M, nl, out, 1);
+    do_boundary(c, st, M, nl, out);
+    do_force(c, st, M, H, nl, out, 1, nullptr, hist);
+    // stage 2 at the half state, written back over the start state
+    do_nbrdens(c, st, H, nl, out, 1);
+    do_boundary(c, st, H, nl, out);
+    do_force(c, st, H, M, nl, out, 2, nullptr, nullptr);
+    launch_end_of_step(c.k, dev_state(st), dev_derived(out), at<int32_t>(c.ws, c.w.nspawn),
+                       at<uint8_t>(c.ws, c.w.sflag), at<int32_t>(c.ws, c.w.stile), child, events,
+                       c.err(), c.s);
+}
+
+// Carving of the step-adjoint scratch buffer, in units of cap doubles.
+struct AdjLayout {
+    size_t acc_x, acc_u, acc_ut, acc_p, acc_uin, acc_ring, acc_avg, acc_jprev;
+    size_t Lx, Lu, Lut, Lp, hut, jseed;
+    size_t abar, bbar, pdbar, pseed, useed;
+    size_t xbar, ubar, utbar, pbar, uinbar, avgbar, jprevbar;
+    size_t wbar, rhobar, volbar, Pbar, Sbar, jg, inv;
+    size_t total;
+};
+
+static AdjLayout adj_layout()
+{
+    AdjLayout L;
+    size_t o = 0;
+    auto take = [&](size_t k) {
+        size_t r = o;
+        o += k;
+        return r;
+    };
+    L.acc_x = take(3);
+    L.acc_u = take(3);
+    L.acc_ut = take(3);
+    L.acc_p = take(1);
+    L.acc_uin = take(3);
+    L.acc_ring = take(kNavg * 4);
+    L.acc_avg = take(4);
+    L.acc_jprev = take(3);
+    L.Lx = take(3);
+    L.Lu = take(3);
+    L.Lut = take(3);
+    L.Lp = take(1);
+    L.hut = take(3);
+    L.jseed = take(3);
+    L.abar = take(3);
+    L.bbar = take(3);
+    L.pdbar = take(1);
+    L.pseed = take(1);
+    L.useed = take(3);
+    L.xbar = take(3);
+    L.ubar = take(3);
+    L.utbar = take(3);
+    L.pbar = take(1);
+    L.uinbar = take(3);
+    L.avgbar = take(4);
+    L.jprevbar = take(3);
+    L.wbar = take(3);
+    L.rhobar = take(1);
+    L.volbar = take(1);
+    L.Pbar = take(1);
+    L.Sbar = take(1);
+    L.jg = take(3);
+    L.inv = take(1);  // int32 entries
+    L.total = o;
+    return L;
+}
+
+static DevLam dev_lam(const sph_state_adjoint *l)
+{
+    DevLam d;
+    d.x = l->x;
+    d.u = l->u;
+    d.ut = l->ut;
+    d.p = l->p;
+    d.uin = l->uin;
+    d.ring = l->ring;
+    d.avg = l->avg;
+    d.jprev = l->jprev;
+    return d;
+}
+
+static int check_lam(const sph_state_adjoint *l, int64_t cap, const char *name)
+{
+    if (!l) return fail(SPH_EINVAL, "%s is NULL", name);
+    if (l->cap != cap) return fail(SPH_EINVAL, "%s->cap %lld != state cap %lld", name,
+                                   (long long)l->cap, (long long)cap);
+    if (!l->x || !l->u || !l->ut || !l->p || !l->uin || !l->ring || !l->avg || !l->jprev)
+        return fail(SPH_EINVAL, "%s has a NULL array", name);
+    return SPH_OK;
+}
+
 }  // namespace sph
 
 using namespace sph;
@@ -472,23 +576,173 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
         return fail(SPH_EINVAL, "alt must match state in cap and precision");
     if (nsteps < 0) return fail(SPH_EINVAL, "nsteps < 0");
     launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
-    const Fields H = c.half();
-    int32_t *nspawn = at<int32_t>(ws, c.w.nspawn);
-    for (int32_t s = 0; s < nsteps; ++s) {
-        do_bin(c, st, alt);
-        const Fields M = fields_of(st);
-        // stage 1 at the start state, written to the half state
-        do_nbrdens(c, st, M, nl, out, 1);
-        do_boundary(c, st, M, nl, out);
-        do_force(c, st, M, H, nl, out, 1, nullptr, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr);
-        // stage 2 at the half state, written back over the start state
-        do_nbrdens(c, st, H, nl, out, 1);
-        do_boundary(c, st, H, nl, out);
-        do_force(c, st, H, M, nl, out, 2, nullptr, nullptr);
-        launch_end_of_step(c.k, dev_state(st), dev_derived(out), nspawn, c.err(), c.s);
-    }
-    if (nsteps > 0) launch_finish_spawn(c.k, dev_state(st), nspawn, c.s);
+    for (int32_t s = 0; s < nsteps; ++s)
+        one_step(c, st, alt, nl, out, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr, nullptr,
+                 nullptr);
+    if (nsteps > 0) launch_finish_spawn(c.k, dev_state(st), at<int32_t>(ws, c.w.nspawn), c.s);
     return check_hip("sph_step");
+}
+
+int sph_step_record(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+                    sph_derived *out, double *drag, int32_t *child, uint8_t *events, void *ws,
+                    size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
+    rc = check_state(alt, prm, "alt");
+    if (rc) return rc;
+    if (alt->cap != st->cap || alt->prec != st->prec)
+        return fail(SPH_EINVAL, "alt must match state in cap and precision");
+    if (!child || !events) return fail(SPH_EINVAL, "child and events must not be NULL");
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    one_step(c, st, alt, nl, out, drag, child, events);
+    launch_finish_spawn(c.k, dev_state(st), at<int32_t>(ws, c.w.nspawn), c.s);
+    return check_hip("sph_step_record");
+}
+
+int sph_step_adjoint_scratch_size(const sph_params *prm, int64_t cap, size_t *bytes)
+{
+    if (!bytes) return fail(SPH_EINVAL, "bytes is NULL");
+    Dev k;
+    int rc = make_dev(prm, cap, SPH_FP64, 1, &k);
+    if (rc) return rc;
+    *bytes = adj_layout().total * sizeof(double) * size_t(cap);
+    return SPH_OK;
+}
+
+int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work,
+                     const int32_t *child, const uint8_t *events, sph_nlist *nl1,
+                     sph_nlist *nl2, sph_derived *d1, sph_derived *d2, const double fbar[3],
+                     const sph_state_adjoint *lam_next, sph_state_adjoint *lam, void *scratch,
+                     size_t scratch_bytes, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl1 ? nl1->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl1)) || (rc = check_nlist(nl2)) ||
+        (rc = check_derived(d1, false)) || (rc = check_derived(d2, false)))
+        return rc;
+    if (nl1->maxnb != nl2->maxnb) return fail(SPH_EINVAL, "nl1 and nl2 differ in maxnb");
+    rc = check_state(work, prm, "work");
+    if (rc) return rc;
+    if (work->cap != st->cap || work->prec != st->prec)
+        return fail(SPH_EINVAL, "work must match state in cap and precision");
+    if (work->n == st->n) return fail(SPH_EINVAL, "work needs its own live-count pointer");
+    if (!child || !events || !fbar) return fail(SPH_EINVAL, "child, events, fbar must not be NULL");
+    if ((rc = check_lam(lam_next, st->cap, "lam_next")) || (rc = check_lam(lam, st->cap, "lam")))
+        return rc;
+    {
+        const double *a[8] = {lam->x, lam->u, lam->ut, lam->p, lam->uin, lam->ring, lam->avg,
+                              lam->jprev};
+        const double *b[8] = {lam_next->x, lam_next->u,   lam_next->ut,  lam_next->p,
+                              lam_next->uin, lam_next->ring, lam_next->avg, lam_next->jprev};
+        for (int i = 0; i < 8; ++i)
+            for (int j = 0; j < 8; ++j)
+                if (a[i] == b[j]) return fail(SPH_EINVAL, "lam and lam_next share an array");
+    }
+    const AdjLayout L = adj_layout();
+    const size_t C = size_t(st->cap);
+    if (!scratch) return fail(SPH_EINVAL, "scratch is NULL");
+    if (scratch_bytes < L.total * sizeof(double) * C)
+        return fail(SPH_ECAPACITY, "scratch has %zu bytes, needs %zu", scratch_bytes,
+                    L.total * sizeof(double) * C);
+    double *sc = static_cast<double *>(scratch);
+    auto P = [&](size_t off) { return sc + off * C; };
+
+    // recompute the step from st: bin into work (st stays untouched; the
+    // live count goes to work's own pointer), then both stages
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    launch_adj_prep(st->n, work->n, at<int32_t>(ws, c.w.nspawn), c.s);
+    DevState a = dev_state(st), b = dev_state(work);
+    a.n = work->n;
+    launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
+    int32_t *inv = reinterpret_cast<int32_t *>(P(L.inv));
+    launch_inverse_perm(c.k, work->n, at<int32_t>(ws, c.w.tmp), inv, c.s);
+    const Fields M = fields_of(work), H = c.half();
+    do_nbrdens(c, work, M, nl1, d1, 1);
+    do_boundary(c, work, M, nl1, d1);
+    do_force(c, work, M, H, nl1, d1, 1, nullptr, nullptr);
+    do_nbrdens(c, work, H, nl2, d2, 1);
+    do_boundary(c, work, H, nl2, d2);
+    do_force(c, work, H, H, nl2, d2, 0, nullptr, nullptr);
+
+    StepAdj S;
+    S.next = dev_lam(lam_next);
+    S.out = dev_lam(lam);
+    S.acc.x = P(L.acc_x);
+    S.acc.u = P(L.acc_u);
+    S.acc.ut = P(L.acc_ut);
+    S.acc.p = P(L.acc_p);
+    S.acc.uin = P(L.acc_uin);
+    S.acc.ring = P(L.acc_ring);
+    S.acc.avg = P(L.acc_avg);
+    S.acc.jprev = P(L.acc_jprev);
+    S.Lx = P(L.Lx);
+    S.Lu = P(L.Lu);
+    S.Lut = P(L.Lut);
+    S.Lp = P(L.Lp);
+    S.hut = P(L.hut);
+    S.jseed = P(L.jseed);
+    S.inv = inv;
+    S.child = child;
+    S.events = events;
+    S.n_pre = st->n;
+    DevAdj A;
+    A.abar = P(L.abar);
+    A.bbar = P(L.bbar);
+    A.pdbar = P(L.pdbar);
+    A.pseed = P(L.pseed);
+    A.useed = P(L.useed);
+    A.jseed = S.jseed;
+    for (int d = 0; d < 3; ++d) A.fbar[d] = 0.0;
+    A.xbar = P(L.xbar);
+    A.ubar = P(L.ubar);
+    A.utbar = P(L.utbar);
+    A.pbar = P(L.pbar);
+    A.uinbar = P(L.uinbar);
+    A.avgbar = P(L.avgbar);
+    A.jprevbar = P(L.jprevbar);
+    A.wbar = P(L.wbar);
+    A.rhobar = P(L.rhobar);
+    A.volbar = P(L.volbar);
+    A.Pbar = P(L.Pbar);
+    A.Sbar = P(L.Sbar);
+    A.jg = P(L.jg);
+
+    const DevState m = dev_state(work);
+    const uint32_t *cpos_s = at<uint32_t>(ws, c.w.cpos_s);
+    launch_adj_eos(c.k, m, S, c.s);
+    launch_adj_full(c.k, m, S, A, c.s);
+    launch_rhs_adjoint(c.k, m, H, dev_nlist(nl2), dev_derived(d2), A, c.off(), cpos_s, c.err(),
+                       c.s);
+    launch_adj_half(c.k, m, S, A, c.s);
+    // the FP32 pair arithmetic reads cell-relative offsets of the stage's
+    // positions: rebuild those of the start state (same table, same values)
+    if (c.k.prec == SPH_FP32) do_nbrdens(c, work, M, nl1, d1, 1);
+    DevAdj A1 = A;
+    A1.jseed = nullptr;
+    for (int d = 0; d < 3; ++d) A1.fbar[d] = fbar[d];
+    launch_rhs_adjoint(c.k, m, M, dev_nlist(nl1), dev_derived(d1), A1, c.off(), cpos_s, c.err(),
+                       c.s);
+    launch_adj_start(c.k, m, S, A1, c.s);
+    launch_adj_unbin(c.k, S, c.s);
+    return check_hip("sph_step_adjoint");
+}
+
+int sph_inlet_profile_grad(const sph_params *prm, const sph_state *st,
+                           const sph_state_adjoint *lam, const int32_t *index, int32_t ntheta,
+                           double *grad, void *stream)
+{
+    int rc = check_state(st, prm, "state");
+    if (rc) return rc;
+    Dev k;
+    if ((rc = make_dev(prm, st->cap, st->prec, 1, &k))) return rc;
+    if ((rc = check_lam(lam, st->cap, "lam"))) return rc;
+    if (!index || !grad) return fail(SPH_EINVAL, "index and grad must not be NULL");
+    if (ntheta < 1 || ntheta > 65535) return fail(SPH_EINVAL, "ntheta must be in [1, 65535]");
+    launch_profile_grad(k, st->n, dev_lam(lam), index, ntheta, grad,
+                        static_cast<hipStream_t>(stream));
+    return check_hip("sph_inlet_profile_grad");
 }
 
 int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
@@ -505,6 +759,10 @@ int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist 
     A.abar = adj->abar;
     A.bbar = adj->bbar;
     A.pdbar = adj->pdbar;
+    A.pseed = adj->pseed;
+    A.useed = adj->useed;
+    A.jseed = adj->jseed;
+    A.jprevbar = adj->jprevbar;
     for (int d = 0; d < 3; ++d) A.fbar[d] = adj->fbar[d];
     A.xbar = adj->xbar;
     A.ubar = adj->ubar;
@@ -518,6 +776,7 @@ int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist 
     A.volbar = adj->scratch + 4 * C;
     A.Pbar = adj->scratch + 5 * C;
     A.Sbar = adj->scratch + 6 * C;
+    A.jg = adj->scratch + 7 * C;       // [3][cap]
     launch_rhs_adjoint(c.k, dev_state(st), fields_of(st), dev_nlist(nl), dev_derived(fwd), A,
                        c.off(), at<uint32_t>(c.ws, c.w.cpos_s), c.err(), c.s);
     return check_hip("sph_rhs_adjoint");

@@ -621,8 +621,9 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                     if (t == SPH_BODY)
 #pragma unroll
                         for (int d = 0; d < DIM; ++d) o.force[d * C + i] = fb[d];
-                } else if (t == SPH_FLUID) {
-                    stage_fluid<DIM, T>(k, R, W, i, mode, ui, pi, a, b, pd, err);
+                } else {
+                    st<T>(o.pavg, i, pavg);  // kept for a reverse pass
+                    if (t == SPH_FLUID) stage_fluid<DIM, T>(k, R, W, i, mode, ui, pi, a, b, pd, err);
                 }
             }
         }

@@ -64,9 +64,53 @@ struct DevDerived {
 // storage; arithmetic in the state's precision).
 struct DevAdj {
     const void *abar, *bbar, *pdbar;
+    const double *pseed, *useed;  // adjoints seeded on boundary values (non-fluid rows)
+    const double *jseed;          // adjoint seeded on the characteristic values J
     double fbar[3];
-    double *xbar, *ubar, *utbar, *pbar, *uinbar, *avgbar;
-    double *wbar, *rhobar, *volbar, *Pbar, *Sbar;
+    double *xbar, *ubar, *utbar, *pbar, *uinbar, *avgbar, *jprevbar;
+    double *wbar, *rhobar, *volbar, *Pbar, *Sbar, *jg;
+};
+
+// Exclusive prefix sum of one value per thread over a block of kBlock
+// threads (lds: kBlock entries); *total receives the block sum.
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total)
+{
+    const int t = threadIdx.x;
+    lds[t] = v;
+    __syncthreads();
+    for (int off = 1; off < kBlock; off <<= 1) {
+        const int32_t add = t >= off ? lds[t - off] : 0;
+        __syncthreads();
+        lds[t] += add;
+        __syncthreads();
+    }
+    const int32_t incl = lds[t];
+    *total = lds[kBlock - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+// events of one row at the end of a step, recorded for the reverse pass
+constexpr uint8_t kEvPush = SPH_EV_PUSH, kEvToOutlet = SPH_EV_TO_OUTLET,
+                  kEvDelete = SPH_EV_DELETE, kEvSpawn = SPH_EV_SPAWN;
+
+// adjoint of a particle state, laid out like the state ([comp][cap])
+struct DevLam {
+    double *x, *u, *ut, *p, *uin, *ring, *avg, *jprev;
+};
+
+// buffers of the reverse of one step
+struct StepAdj {
+    DevLam next;  // adjoint of the state after the step (its row order)
+    DevLam acc;   // accumulators of the sorted start state
+    DevLam out;   // adjoint of the state before the step (its row order)
+    double *Lx, *Lu, *Lut, *Lp;  // adjoint of the values after the full update
+    double *hut;                 // direct adjoint of the half-state ut
+    double *jseed;               // adjoint of the stage-2 characteristic values
+    int32_t *inv;                // start-state row -> sorted row (-1: dropped)
+    const int32_t *child;
+    const uint8_t *events;
+    const int64_t *n_pre;  // rows of the state before the step
 };
 
 struct DevNlist {
@@ -77,7 +121,7 @@ struct DevNlist {
 // Workspace carving (byte offsets from the workspace base).
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, tmp, cpos,
-        cpos_s, blist, hx, hu, hut, hp, off, dragpart, total;
+        cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

@@ -46,7 +46,23 @@ void launch_rhs_adjoint(const Dev &k, const DevState &m, const Fields &R, const 
 
 // bookkeeping
 void launch_end_of_step(const Dev &k, const DevState &st, const DevDerived &o,
-                        int32_t *nspawn, uint32_t *err, hipStream_t s);
+                        int32_t *nspawn, uint8_t *sflag, int32_t *stile, int32_t *child,
+                        uint8_t *events, uint32_t *err, hipStream_t s);
 void launch_finish_spawn(const Dev &k, const DevState &st, int32_t *nspawn, hipStream_t s);
+
+// reverse of one step
+void launch_adj_prep(const int64_t *n_src, int64_t *n_dst, int32_t *nspawn, hipStream_t s);
+void launch_inverse_perm(const Dev &k, const int64_t *n_post, const int32_t *perm,
+                         int32_t *inv, hipStream_t s);
+void launch_adj_eos(const Dev &k, const DevState &m, const StepAdj &S, hipStream_t s);
+void launch_adj_full(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                     hipStream_t s);
+void launch_adj_half(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                     hipStream_t s);
+void launch_adj_start(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                      hipStream_t s);
+void launch_adj_unbin(const Dev &k, const StepAdj &S, hipStream_t s);
+void launch_profile_grad(const Dev &k, const int64_t *n, const DevLam &L, const int32_t *index,
+                         int32_t ntheta, double *grad, hipStream_t s);
 
 }  // namespace sph

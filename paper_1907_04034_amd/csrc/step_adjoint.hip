@@ -1,0 +1,403 @@
+// step_adjoint.hip -- hand-written reverse of one explicit-midpoint step for
+// gfx950, built on the reverse of the right-hand side (adjoint.hip).
+//
+// A step maps the state S_n (rows in the order the previous step left them)
+// to S_{n+1}:
+//   bin        S'_n = S_n gathered in cell order (dead rows dropped);
+//   stage 1    boundary values of S'_n, force pass, half update -> H;
+//   stage 2    boundary values of H, force pass, full update -> S_{n+1};
+//   end        characteristic values become previous-step values, gated ring
+//              push with its mean, transfers, inlet re-spawn (children are
+//              appended after the live rows).
+// Given the adjoint of S_{n+1} (lam_next) and the weight of the stage-1 body
+// force, the reverse returns the adjoint of S_n, for fixed discrete events
+// (neighbour sets, supported / unsupported boundary particles, gates,
+// transfers), which the forward recorded. The reverse recomputes the stage
+// values from S_n and runs, per row, gather-only kernels:
+//   eos    reverse of the end-of-step bookkeeping (children -> parents, ring
+//          push and mean, J -> previous-step values);
+//   full   reverse of the full update: weights on stage-2 rates, seeds on the
+//          stage-2 boundary values, direct position/velocity/pressure parts;
+//   (reverse of the stage-2 right-hand side)
+//   half   reverse of the half update: weights on stage-1 rates and seeds;
+//   (reverse of the stage-1 right-hand side, with the drag weight)
+//   start  sum of the start-state parts;
+//   unbin  back to the row order of S_n.
+#include "sph_launch.h"
+
+namespace sph {
+
+// ------------------------------------------------------------ bookkeeping
+__global__ void k_adj_prep(const int64_t *n_src, int64_t *n_dst, int32_t *nspawn)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *n_dst = *n_src;
+        *nspawn = 0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_inv_fill(int64_t cap, int32_t *inv)
+{
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q < cap) inv[q] = -1;
+}
+
+// inv[perm[r]] = r: the bin's permutation is injective, so no two rows write
+// the same entry
+__global__ void __launch_bounds__(kBlock) k_inv_scatter(int64_t cap, const int64_t *n_post,
+                                                        const int32_t *perm, int32_t *inv)
+{
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= *n_post) return;
+    const int32_t q = perm[r];
+    if (q >= 0 && q < cap) inv[q] = int32_t(r);
+}
+
+// ------------------------------------------------------------ eos reverse
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_eos(Dev k, DevState m, StepAdj S)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= *m.n) return;
+    constexpr int NC = DIM + 1, NR = kNavg * NC;
+    const int64_t C = k.cap;
+    const int t = m.type[i];
+    const uint8_t ev = S.events[i];
+    const int32_t r = S.child[i];
+    const DevLam &N = S.next;
+    double Lx[3] = {0, 0, 0}, Lu[3] = {0, 0, 0}, Lut[3] = {0, 0, 0}, uin[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        Lx[d] = N.x[d * C + i];
+        Lu[d] = N.u[d * C + i];
+        Lut[d] = N.ut[d * C + i];
+        uin[d] = N.uin[d * C + i];
+    }
+    double Lp = N.p[i];
+    double ring[NR], avg[NC], jp[3];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) ring[q] = N.ring[q * C + i];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) avg[c] = N.avg[c * C + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jp[a] = N.jprev[a * C + i];
+    if ((ev & kEvSpawn) && r >= 0 && r < C) {
+        // the re-spawned inlet particle: x = parent x - inlet_len (x only),
+        // u = ut = ring = mean = u_in of the parent, p and the p-slots = parent p
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) Lx[d] += N.x[d * C + r];
+        double cp = N.p[r] + N.avg[DIM * C + r];
+#pragma unroll
+        for (int q = 0; q < kNavg; ++q) cp += N.ring[(q * NC + DIM) * C + r];
+        Lp += cp;
+        if (!(k.flags & SPH_FLAG_NOISE)) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                double cu = N.uin[d * C + r] + N.u[d * C + r] + N.ut[d * C + r] + N.avg[d * C + r];
+#pragma unroll
+                for (int q = 0; q < kNavg; ++q) cu += N.ring[(q * NC + d) * C + r];
+                uin[d] += cu;
+            }
+        }
+    }
+    if (ev & kEvPush) {
+        // ring[h] = (u, p) after the step; mean = sum of the ring / N
+        const int h = m.head[i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double share = avg[c] / double(kNavg);
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < kNavg; ++q) {
+                const double tot = ring[q * NC + c] + share;
+                if (q == h) v = tot;
+                ring[q * NC + c] = q == h ? 0.0 : tot;
+            }
+            avg[c] = 0.0;
+            if (c < DIM) Lu[c] += v;
+            else Lp += v;
+        }
+    }
+    double js[3] = {0, 0, 0};
+    if (t == SPH_INLET || t == SPH_OUTLET) {
+        // previous-step values of the next step = this step's stage-2 J
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            js[a] = jp[a];
+            jp[a] = 0.0;
+        }
+    } else if (ev & kEvToOutlet) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) jp[a] = 0.0;
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        S.Lx[d * C + i] = Lx[d];
+        S.Lu[d * C + i] = Lu[d];
+        S.Lut[d * C + i] = Lut[d];
+        S.acc.uin[d * C + i] = uin[d];
+        S.jseed[d * C + i] = js[d];
+        S.acc.jprev[d * C + i] = jp[d];
+    }
+    S.Lp[i] = Lp;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) S.acc.ring[q * C + i] = ring[q];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] = avg[c];
+}
+
+// ------------------------------------------------------------ full update
+// fluid:   u' = u + dt a2, ut' = u' + dt b2, x' = x + dt ut_H, p' = p + dt pdot2
+// inlet:   x' = x + dt u_in (x only); u', ut', p' = stage-2 boundary values
+// outlet:  x' = x + dt u_H (x only, u_H its stage-2 boundary value); same
+// walls:   x' = x; u', p' = stage-2 boundary values
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_full(Dev k, DevState m, StepAdj S, DevAdj A)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= *m.n) return;
+    const int64_t C = k.cap;
+    const int t = m.type[i];
+    const double dt = k.dt;
+    double *useed = const_cast<double *>(A.useed), *pseed = const_cast<double *>(A.pseed);
+    double us[3] = {0, 0, 0}, ps = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const bool on = d < DIM;
+        const double Lx = on ? S.Lx[d * C + i] : 0.0;
+        const double Lu = on ? S.Lu[d * C + i] : 0.0;
+        const double Lut = on ? S.Lut[d * C + i] : 0.0;
+        S.acc.x[d * C + i] = Lx;
+        S.acc.ut[d * C + i] = 0.0;
+        double au = 0.0, ab = 0.0, hut = 0.0, uacc = 0.0;
+        if (t == SPH_FLUID) {
+            uacc = Lu + Lut;
+            au = dt * uacc;
+            ab = dt * Lut;
+            hut = dt * Lx;
+        } else if (t == SPH_INLET || t == SPH_OUTLET) {
+            us[d] = Lu + Lut;  // the boundary value is written to u and ut
+            if (d == 0 && t == SPH_INLET) S.acc.uin[i] += dt * Lx;
+            if (d == 0 && t == SPH_OUTLET) us[0] += dt * Lx;
+        } else {
+            us[d] = Lu;
+        }
+        S.acc.u[d * C + i] = uacc;
+        S.hut[d * C + i] = hut;
+        if (on) {
+            st<T>(const_cast<void *>(A.abar), d * C + i, T(au));
+            st<T>(const_cast<void *>(A.bbar), d * C + i, T(ab));
+        }
+        useed[d * C + i] = us[d];
+    }
+    const double Lp = S.Lp[i];
+    double pd = 0.0, pacc = 0.0;
+    if (t == SPH_FLUID) {
+        pd = dt * Lp;
+        pacc = Lp;
+    } else {
+        ps = Lp;
+    }
+    st<T>(const_cast<void *>(A.pdbar), i, T(pd));
+    pseed[i] = ps;
+    S.acc.p[i] = pacc;
+}
+
+// ------------------------------------------------------------ half update
+// fluid:   u_H = u + hdt a1, ut_H = u_H + hdt b1, x_H = x + hdt ut_H,
+//          p_H = p + hdt pdot1
+// inlet:   x_H = x + hdt u_in (x only); outlet: x_H = x + hdt u_1 (x only,
+//          u_1 its stage-1 boundary value); walls: x_H = x
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_half(Dev k, DevState m, StepAdj S, DevAdj A)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= *m.n) return;
+    constexpr int NC = DIM + 1;
+    const int64_t C = k.cap;
+    const int t = m.type[i];
+    const double hdt = k.hdt;
+    double *useed = const_cast<double *>(A.useed), *pseed = const_cast<double *>(A.pseed);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] += A.avgbar[c * C + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) S.acc.jprev[a * C + i] += A.jprevbar[a * C + i];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double xH = A.xbar[d * C + i];
+        S.acc.x[d * C + i] += xH;
+        S.acc.uin[d * C + i] += A.uinbar[d * C + i];
+        double au = 0.0, ab = 0.0, us = 0.0;
+        if (t == SPH_FLUID) {
+            const double utot = A.utbar[d * C + i] + S.hut[d * C + i] + hdt * xH;
+            const double uu = A.ubar[d * C + i] + utot;
+            au = hdt * uu;
+            ab = hdt * utot;
+            S.acc.u[d * C + i] += uu;
+        } else if (d == 0 && t == SPH_INLET) {
+            S.acc.uin[i] += hdt * xH;
+        } else if (d == 0 && t == SPH_OUTLET) {
+            us = hdt * xH;
+        }
+        st<T>(const_cast<void *>(A.abar), d * C + i, T(au));
+        st<T>(const_cast<void *>(A.bbar), d * C + i, T(ab));
+        useed[d * C + i] = us;
+    }
+    double pd = 0.0;
+    if (t == SPH_FLUID) {
+        const double pH = A.pbar[i];
+        pd = hdt * pH;
+        S.acc.p[i] += pH;
+    }
+    st<T>(const_cast<void *>(A.pdbar), i, T(pd));
+    pseed[i] = 0.0;
+}
+
+// ------------------------------------------------------------ start state
+// Boundary rows' u, ut, p of the start state are overwritten by the stage-1
+// boundary values before any use, so only fluid rows take those parts.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_start(Dev k, DevState m, StepAdj S, DevAdj A)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= *m.n) return;
+    constexpr int NC = DIM + 1;
+    const int64_t C = k.cap;
+    const bool fl = m.type[i] == SPH_FLUID;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        S.acc.x[d * C + i] += A.xbar[d * C + i];
+        S.acc.uin[d * C + i] += A.uinbar[d * C + i];
+        if (fl) {
+            S.acc.u[d * C + i] += A.ubar[d * C + i];
+            S.acc.ut[d * C + i] += A.utbar[d * C + i];
+        }
+    }
+    if (fl) S.acc.p[i] += A.pbar[i];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] += A.avgbar[c * C + i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) S.acc.jprev[a * C + i] += A.jprevbar[a * C + i];
+}
+
+// ------------------------------------------------------------ unbin
+// Adjoint of S_n: row q takes the accumulators of its sorted row, or zero if
+// the bin dropped it (a deleted particle has no influence).
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_adj_unbin(Dev k, StepAdj S)
+{
+    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (q >= *S.n_pre) return;
+    constexpr int NC = DIM + 1, NR = kNavg * NC;
+    const int64_t C = k.cap;
+    const int32_t r = S.inv[q];
+    const bool live = r >= 0 && r < C;
+    const DevLam &A = S.acc;
+    const DevLam &O = S.out;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const bool on = live && d < DIM;
+        O.x[d * C + q] = on ? A.x[d * C + r] : 0.0;
+        O.u[d * C + q] = on ? A.u[d * C + r] : 0.0;
+        O.ut[d * C + q] = on ? A.ut[d * C + r] : 0.0;
+        O.uin[d * C + q] = on ? A.uin[d * C + r] : 0.0;
+        O.jprev[d * C + q] = live ? A.jprev[d * C + r] : 0.0;
+    }
+    O.p[q] = live ? A.p[r] : 0.0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) O.ring[s * C + q] = live ? A.ring[s * C + r] : 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) O.avg[c * C + q] = live ? A.avg[c * C + r] : 0.0;
+}
+
+// ------------------------------------------------------------ inlet profile
+// grad[k] = sum over rows q with index[q] = k of the adjoint of the x
+// components the initial state takes from the profile value (u_in, u, ut,
+// every ring slot and the mean). One block per profile entry; fixed order.
+__global__ void __launch_bounds__(kBlock) k_profile_grad(Dev k, const int64_t *n, DevLam L,
+                                                         const int32_t *index, double *grad)
+{
+    __shared__ double lds[kBlock];
+    const int32_t e = blockIdx.x;
+    const int64_t C = k.cap, rows = *n;
+    const int NC = k.dim + 1;
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < rows; q += blockDim.x) {
+        if (index[q] != e) continue;
+        double v = L.uin[q] + L.u[q] + L.ut[q] + L.avg[q];
+        for (int s = 0; s < kNavg; ++s) v += L.ring[int64_t(s) * NC * C + q];
+        acc += v;
+    }
+    lds[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) lds[threadIdx.x] += lds[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[e] = lds[0];
+}
+
+// ------------------------------------------------------------ launchers
+#define SPH_STEP_DISPATCH(KERNEL, ...)                                                        \
+    do {                                                                                      \
+        const dim3 g(nblocks(k.cap)), b(kBlock);                                              \
+        if (k.dim == 2 && k.prec == SPH_FP64)                                                 \
+            hipLaunchKernelGGL((KERNEL<2, double>), g, b, 0, s, __VA_ARGS__);                 \
+        else if (k.dim == 3 && k.prec == SPH_FP64)                                            \
+            hipLaunchKernelGGL((KERNEL<3, double>), g, b, 0, s, __VA_ARGS__);                 \
+        else if (k.dim == 2)                                                                  \
+            hipLaunchKernelGGL((KERNEL<2, float>), g, b, 0, s, __VA_ARGS__);                  \
+        else                                                                                  \
+            hipLaunchKernelGGL((KERNEL<3, float>), g, b, 0, s, __VA_ARGS__);                  \
+    } while (0)
+
+void launch_adj_prep(const int64_t *n_src, int64_t *n_dst, int32_t *nspawn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adj_prep, dim3(1), dim3(64), 0, s, n_src, n_dst, nspawn);
+}
+
+void launch_inverse_perm(const Dev &k, const int64_t *n_post, const int32_t *perm,
+                         int32_t *inv, hipStream_t s)
+{
+    const dim3 g(nblocks(k.cap)), b(kBlock);
+    hipLaunchKernelGGL(k_inv_fill, g, b, 0, s, k.cap, inv);
+    hipLaunchKernelGGL(k_inv_scatter, g, b, 0, s, k.cap, n_post, perm, inv);
+}
+
+void launch_adj_eos(const Dev &k, const DevState &m, const StepAdj &S, hipStream_t s)
+{
+    SPH_STEP_DISPATCH(k_adj_eos, k, m, S);
+}
+
+void launch_adj_full(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                     hipStream_t s)
+{
+    SPH_STEP_DISPATCH(k_adj_full, k, m, S, A);
+}
+
+void launch_adj_half(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                     hipStream_t s)
+{
+    SPH_STEP_DISPATCH(k_adj_half, k, m, S, A);
+}
+
+void launch_adj_start(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                      hipStream_t s)
+{
+    SPH_STEP_DISPATCH(k_adj_start, k, m, S, A);
+}
+
+void launch_adj_unbin(const Dev &k, const StepAdj &S, hipStream_t s)
+{
+    const dim3 g(nblocks(k.cap)), b(kBlock);
+    if (k.dim == 2) hipLaunchKernelGGL(k_adj_unbin<2>, g, b, 0, s, k, S);
+    else hipLaunchKernelGGL(k_adj_unbin<3>, g, b, 0, s, k, S);
+}
+
+void launch_profile_grad(const Dev &k, const int64_t *n, const DevLam &L, const int32_t *index,
+                         int32_t ntheta, double *grad, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_profile_grad, dim3(ntheta), dim3(kBlock), 0, s, k, n, L, index, grad);
+}
+
+}  // namespace sph

@@ -291,3 +291,45 @@ def random_fields(prm, s, seed, p_range=(-0.5, 0.5), u_range=(0.0, 1.5), ut_dev=
 
 def snapshot_copy(s):
     return {k: np.array(v, copy=True) for k, v in s.items()}
+
+
+# ------------------------------------------------------- inlet profile
+
+def inlet_rows(prm, s):
+    """Lattice row of every inlet particle (-1 for other kinds): rows are
+    numbered by the transverse lattice position ((j + 1/2) dx in y, and z in
+    3D, row = jy * nz + jz)."""
+    n, dx = len(s["p"]), prm["dx"]
+    rows = np.full(n, -1, np.int64)
+    m = s["type"] == INLET
+    if not m.any():
+        return rows
+    jy = np.rint(s["x"][m, 1] / dx - 0.5).astype(np.int64)
+    if prm["dim"] == 3:
+        jz = np.rint(s["x"][m, 2] / dx - 0.5).astype(np.int64)
+        jy = jy - jy.min()
+        jz = jz - jz.min()
+        rows[m] = jy * (jz.max() + 1) + jz
+    else:
+        rows[m] = jy - jy.min()
+    return rows
+
+
+def inlet_profile(prm, s, rows):
+    """The streamwise inlet velocity of every row (first particle found)."""
+    theta = np.zeros(int(rows.max()) + 1)
+    for k in range(len(theta)):
+        theta[k] = s["uin"][np.flatnonzero(rows == k)[0], 0]
+    return theta
+
+
+def set_inlet_profile(prm, s, rows, theta):
+    """Copy of s whose inlet row k has streamwise u_in = u = ut = ring = mean
+    = theta[k]."""
+    s = snapshot_copy(s)
+    m = rows >= 0
+    v = np.asarray(theta, np.float64)[rows[m]]
+    for key in ("uin", "u", "ut", "avg"):
+        s[key][m, 0] = v
+    s["ring"][m, :, 0] = v[:, None]
+    return s

@@ -32,6 +32,29 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(B.SphState) == 8 + 4 + 4 + 8 * 13
     assert C.sizeof(B.SphNlist) == 8 + 8 * 2
     assert C.sizeof(B.SphDerived) == 8 * 11
+    assert C.sizeof(B.SphAdjoint) == 8 * 6 + 8 * 3 + 8 * 8
+    assert C.sizeof(B.SphStateAdjoint) == 8 + 8 * 8
+
+
+def test_step_adjoint_scratch_size_and_validation():
+    prm, s = I.config("C4", small=True)
+    q = B.make_params(prm)
+    out = C.c_size_t(0)
+    assert B.lib().sph_step_adjoint_scratch_size(C.byref(q), 1000, C.byref(out)) == 0
+    assert out.value == 102 * 8 * 1000
+    st = B.SphState()
+    st.cap, st.dim, st.prec = 100, 2, 0
+    lam = B.SphStateAdjoint()
+    fb = (C.c_double * 3)(0.0, 0.0, 0.0)
+    nl = B.SphNlist()
+    de = B.SphDerived()
+    rc = B.lib().sph_step_adjoint(C.byref(q), C.byref(st), C.byref(st), None, None,
+                                  C.byref(nl), C.byref(nl), C.byref(de), C.byref(de),
+                                  C.byref(fb), C.byref(lam), C.byref(lam), None, 0, None, 0, None)
+    assert rc == -1
+    rc = B.lib().sph_inlet_profile_grad(C.byref(q), C.byref(st), C.byref(lam), None, 10, None,
+                                        None)
+    assert rc == -1
 
 
 @pytest.mark.parametrize("cfg", ["C1", "C2", "C3", "C5"])

@@ -22,12 +22,12 @@ def B():
     return binding
 
 
-def _case(name, seed):
+def _case(name, seed, types=(I.FLUID,)):
     if name == "C1-jit":
         prm, s = I.config("C1")
     else:
         prm, s = I.config(name.split("-")[0], small=True)
-    s = I.random_fields(prm, I.jitter(prm, s, 0.2, seed), seed + 100)
+    s = I.random_fields(prm, I.jitter(prm, s, 0.2, seed, types=types), seed + 100)
     return prm, s
 
 
@@ -140,3 +140,69 @@ def test_rhs_adjoint_parts_isolated():
         rel = abs(adj - fd) / max(abs(fd), 1e-300)
         print(f"  {key}: fd={fd:.10e} adjoint={adj:.10e} rel={rel:.2e}", flush=True)
         assert rel < 2e-7, (key, fd, adj)
+
+
+def _seeded_L(prm, s, w):
+    """Objective plus seeds on the boundary values (p, u of non-fluid rows) and
+    on the characteristic values J of inlet/outlet rows."""
+    os_, d, F = O.rhs_once(prm, s)
+    L = ((w["a"] * d["a"]).sum() + (w["b"] * d["b"]).sum() + (w["pdot"] * d["pdot"]).sum()
+         + (w["fbar"] * F).sum())
+    return L + (w["pseed"] * os_["p"]).sum() + (w["useed"] * os_["u"]).sum() + \
+        (w["jseed"] * d["jcur"]).sum()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 2e-7), ("fp32", 2e-4)])
+@pytest.mark.parametrize("name", ["C2-small", "C3-small", "C4-small", "C5-small"])
+def test_rhs_adjoint_seeded(name, prec, tol):
+    """Seeds on boundary values and J (as a stage update and the next step read
+    them) and the previous-step values J_prev of unsupported inlet/outlet rows
+    (eq:average_old) as an input direction."""
+    print(f"seeded adjoint {name} {prec}", flush=True)
+    rng = np.random.default_rng(17)
+    # inlet/outlet rows are jittered too: on the lattice their same-kind
+    # neighbours sit exactly at 2h, where the fallback mean of eq:average_old
+    # switches
+    prm, s = _case(name, 4, types=(I.FLUID, I.INLET, I.OUTLET))
+    _, od, _ = O.rhs_once(prm, s)
+    w = _objective_weights(prm, s, od, rng)
+    n, D = len(s["p"]), prm["dim"]
+    t = s["type"]
+    nf = t != I.FLUID
+    io = (t == I.INLET) | (t == I.OUTLET)
+    w["pseed"] = np.where(nf, rng.standard_normal(n), 0.0)
+    w["useed"] = np.zeros((n, 3))
+    w["useed"][nf, :D] = rng.standard_normal((nf.sum(), D))
+    w["jseed"] = np.zeros((n, 3))
+    w["jseed"][io] = rng.standard_normal((io.sum(), 3)) * 0.1
+    d = _direction(prm, s, rng)
+    d["jprev"] = np.zeros((n, 3))
+    d["jprev"][io] = rng.standard_normal((io.sum(), 3))
+    gs, gd, sim = B().rhs_once(prm, s, prec=prec)
+    idx = {int(v): k for k, v in enumerate(s["id"])}
+    perm = np.array([idx[int(v)] for v in gs["id"]])
+    assert (gd["red"][io[perm]] == 0).any(), "case has no unsupported inlet/outlet rows"
+    g = sim.rhs_adjoint(abar=w["a"][perm], bbar=w["b"][perm], pdbar=w["pdot"][perm],
+                        fbar=w["fbar"], pseed=w["pseed"][perm], useed=w["useed"][perm],
+                        jseed=w["jseed"][perm])
+    assert sim.poll_error() == 0
+    adj = 0.0
+    for key, gk in (("x", "xbar"), ("u", "ubar"), ("ut", "utbar"), ("uin", "uinbar")):
+        adj += (d[key][perm][:, :D] * g[gk][:, :D]).sum()
+    adj += (d["p"][perm] * g["pbar"]).sum() + (d["jprev"][perm] * g["jprevbar"]).sum()
+    adj += (d["avg"][perm][:, :D] * g["avgbar"][:, :D]).sum() + (d["avg"][perm][:, 3] * g["avgbar"][:, 3]).sum()
+    e = 1e-6
+    Ls = {k: _seeded_L(prm, _perturbed(s, d, k * e), w) for k in (-2, -1, 1, 2)}
+    fd = (8 * (Ls[1] - Ls[-1]) - (Ls[2] - Ls[-2])) / (12 * e)
+    rel = abs(adj - fd) / max(abs(fd), 1e-300)
+    print(f"  fd={fd:.12e} adjoint={adj:.12e} rel={rel:.2e}", flush=True)
+    assert rel < tol, (fd, adj, rel)
+    # the J_prev part alone
+    dj = {k: np.zeros_like(v) for k, v in d.items()}
+    dj["jprev"] = d["jprev"]
+    adj_j = (dj["jprev"][perm] * g["jprevbar"]).sum()
+    Ls = {k: _seeded_L(prm, _perturbed(s, dj, k * e), w) for k in (-1, 1)}
+    fd_j = (Ls[1] - Ls[-1]) / (2 * e)
+    print(f"  jprev part: fd={fd_j:.12e} adjoint={adj_j:.12e}", flush=True)
+    assert abs(fd_j) > 0.0, "J_prev direction reaches no output"
+    assert abs(adj_j - fd_j) <= tol * max(abs(fd_j), 1e-3 * abs(fd)), (fd_j, adj_j)

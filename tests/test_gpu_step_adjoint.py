@@ -1,0 +1,331 @@
+"""Reverse of time steps (sph_step_record + sph_step_adjoint) and the
+inlet-profile drag gradient.
+
+1. Multi-step dot-product test against the FP64 oracle: for random weights on
+   the per-step body force and on the final state (keyed by particle id) and a
+   random direction v on the initial state,
+       <v, lambda_0>  (GPU reverse)  ==  d/de L(s + e v)  (4th-order central FD
+                                                           over oracle runs),
+   L = sum_n fbar_n . F^n + sum_i lambda_N(i) . S_N(i). Inputs are the small
+   workloads jittered by 0.1 dx with small seeded field perturbations; the long
+   runs contain every end-of-step event (ring pushes, fluid->outlet transfers,
+   outlet deletions, inlet re-spawns); the checkpoint segment is shorter than
+   the run, so the replay across segments is exercised too.
+2. The time-averaged drag J(theta) of the channel-with-cylinder workload
+   (4 x 1 channel, D = 0.2 cylinder, Re = 20, 500 steps) against central
+   finite differences of the FP64 GPU path, per profile entry and along a
+   random direction: the difference is taken at the largest step size
+   (1e-6, 1e-7, 1e-8) whose +e and -e runs have the same end-of-step events and
+   supported boundary rows at every step, and must agree with the next clean
+   one. Gate: max |g_adj - g_FD| / max |g_FD| <= 1e-4.
+3. A directional finite difference of J on the small channel-with-cylinder
+   case with the oracle against the GPU adjoint.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_04034_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MOVING = (I.FLUID, I.INLET, I.OUTLET)
+
+
+def B():
+    from paper_1907_04034_amd import binding
+    return binding
+
+
+def A():
+    from paper_1907_04034_amd import adjoint
+    return adjoint
+
+
+def _case(name, seed, jit=0.1):
+    """The small workload near its natural state: positions jittered by jit dx,
+    small seeded velocity and pressure perturbations on the fluid, seeded
+    averages and previous-step characteristic values (so that the outlet and
+    the fallback paths carry sensitivity), inlet rows moved 0.45 dx downstream
+    so that re-spawns start within the first steps. The flow stays calm, so no
+    discrete event (neighbour count, support, gate) sits within the finite-
+    difference perturbation of its threshold."""
+    prm, s = I.config(name.split("-")[0], small=True)
+    s = I.jitter(prm, s, jit, seed, types=MOVING)
+    rng = np.random.default_rng(seed + 100)
+    n, D = len(s["p"]), prm["dim"]
+    t = s["type"]
+    fl, inl = t == I.FLUID, t == I.INLET
+    s["x"][inl, 0] += 0.45 * prm["dx"]
+    s["u"][fl, :D] += 0.02 * rng.standard_normal((fl.sum(), D))
+    s["ut"][fl] = s["u"][fl]
+    s["p"][fl] += 0.05 * rng.standard_normal(fl.sum())
+    s["avg"][:, :D] += 0.05 * rng.standard_normal((n, D))
+    s["avg"][:, 3] += 0.05 * rng.standard_normal(n)
+    io = inl | (t == I.OUTLET)
+    s["jprev"][io] = 0.1 * rng.standard_normal((io.sum(), 3))
+    s["red_prev"][io] = (rng.uniform(size=io.sum()) < 0.5).astype(np.uint8)
+    return prm, s
+
+
+def _final_weights(prm, ids, types, seed):
+    """Random adjoint of the final state for the particles `ids`, a function of
+    the id only (so that any row order gets the same weights)."""
+    D = prm["dim"]
+    n = len(ids)
+    out = dict(x=np.zeros((n, 3)), u=np.zeros((n, 3)), ut=np.zeros((n, 3)), p=np.zeros(n),
+               uin=np.zeros((n, 3)), ring=np.zeros((n, 6, D + 1)), avg=np.zeros((n, D + 1)),
+               jprev=np.zeros((n, 3)))
+    for r, (i, t) in enumerate(zip(ids, types)):
+        if t == I.DEAD:
+            continue
+        g = np.random.default_rng([seed, int(i) & 0xFFFFFFFF, int(i) >> 32])
+        mv, io = t in MOVING, t in (I.INLET, I.OUTLET)
+        if mv:
+            out["x"][r, :D] = g.standard_normal(D) * 10.0
+            out["ut"][r, :D] = g.standard_normal(D)
+            out["ring"][r] = 0.1 * g.standard_normal((6, D + 1))
+            out["avg"][r] = g.standard_normal(D + 1)
+        out["u"][r, :D] = g.standard_normal(D)
+        out["p"][r] = g.standard_normal()
+        if t == I.INLET:
+            out["uin"][r, :D] = g.standard_normal(D)
+        if io:
+            out["jprev"][r] = 0.1 * g.standard_normal(3)
+    return out
+
+
+def _direction(prm, s, rng):
+    n, D = len(s["p"]), prm["dim"]
+    t = s["type"]
+    fl, inl = t == I.FLUID, t == I.INLET
+    io = inl | (t == I.OUTLET)
+    mv = np.isin(t, MOVING)
+    v = {k: np.zeros_like(s[k], dtype=np.float64) for k in
+         ("x", "u", "ut", "p", "uin", "ring", "avg", "jprev")}
+    v["x"][mv, :D] = prm["dx"] * rng.standard_normal((mv.sum(), D))
+    v["u"][fl, :D] = rng.standard_normal((fl.sum(), D))
+    v["ut"][fl, :D] = rng.standard_normal((fl.sum(), D))
+    v["p"][fl] = rng.standard_normal(fl.sum())
+    v["uin"][inl, :D] = rng.standard_normal((inl.sum(), D))
+    cols = list(range(D)) + [3]
+    for c in cols:
+        v["ring"][fl | inl, :, c] = rng.standard_normal(((fl | inl).sum(), 6))
+        v["avg"][mv, c] = rng.standard_normal(mv.sum())
+    v["jprev"][io] = rng.standard_normal((io.sum(), 3))
+    return v
+
+
+def _dot(prm, lam, v):
+    D = prm["dim"]
+    cols = list(range(D)) + [3]
+    tot = 0.0
+    for k in ("x", "u", "ut", "uin", "jprev"):
+        w = 3 if k == "jprev" else D
+        tot += (lam[k][:, :w] * v[k][:, :w]).sum()
+    tot += (lam["p"] * v["p"]).sum()
+    tot += (lam["ring"] * v["ring"][:, :, cols]).sum() + (lam["avg"] * v["avg"][:, cols]).sum()
+    return tot
+
+
+def _oracle_L(prm, s, nsteps, fbar, seed, ref_ids):
+    o = O.Oracle(prm, s)
+    drag = o.step(nsteps)
+    st = o.state()
+    live = st["type"] != I.DEAD
+    assert set(st["id"][live].tolist()) == ref_ids, "events differ from the GPU run"
+    W = _final_weights(prm, st["id"], st["type"], seed)
+    D = prm["dim"]
+    cols = list(range(D)) + [3]
+    L = (fbar * drag).sum()
+    for k in ("x", "u", "ut", "uin", "jprev"):
+        L += (W[k] * st[k]).sum()
+    L += (W["p"] * st["p"]).sum()
+    L += (W["ring"] * st["ring"][:, :, cols]).sum() + (W["avg"] * st["avg"][:, cols]).sum()
+    return L
+
+
+@pytest.mark.parametrize("name,nsteps,pavg", [
+    ("C4-small", 30, False), ("C2-small", 30, False), ("C3-small", 26, False),
+    ("C5-small", 30, False), ("C4-small", 4, True), ("C2-small", 4, True),
+    ("C3-small", 3, True), ("C5-small", 4, True)])
+def test_step_adjoint_dot_product(name, nsteps, pavg):
+    """Long runs (every end-of-step event) with the neighbour average of
+    eq:pavg off, short runs with it on: its neighbour count N_i jumps when a
+    pair crosses r = 2h, which happens ever more often as a run gets longer, and
+    a finite difference across such a jump is meaningless. The finite
+    difference is taken at two step sizes that must agree (no event inside
+    either window)."""
+    print(f"step adjoint {name} {nsteps} steps pavg={pavg}", flush=True)
+    rng = np.random.default_rng(23)
+    prm, s = _case(name, 9)
+    if not pavg:
+        prm = dict(prm, flags=prm["flags"] | I.FLAG_NO_PAVG)
+    fbar = rng.standard_normal((nsteps, 3))
+    if prm["dim"] == 2:
+        fbar[:, 2] = 0.0
+    sim = B().Simulation(prm, s)
+    run = A().DragAdjoint(sim, nsteps, segment=7)
+    run.forward()
+    assert sim.poll_error() == 0
+    fin = sim.state()
+    ref_ids = set(fin["id"][fin["type"] != I.DEAD].tolist())
+    seed = 77
+    lam = run.backward(fbar, lam_final=lambda ids: _final_weights(
+        prm, ids, _types_by_id(sim, ids), seed))
+    assert sim.poll_error() == 0
+    n0 = len(s["p"])
+    lam0 = A().lam_to_host(lam, n0, prm["dim"], sim.cap)
+    v = _direction(prm, s, rng)
+    adj = _dot(prm, lam0, v)
+    fds = []
+    for e in (1e-6, 1e-7):
+        Ls = {k: _oracle_L(prm, {**s, **{f: s[f] + k * e * v[f] for f in v}}, nsteps, fbar,
+                           seed, ref_ids) for k in (-1, 1)}
+        fds.append((Ls[1] - Ls[-1]) / (2 * e))
+    fd = fds[1]
+    print(f"  fd(1e-6)={fds[0]:.12e} fd(1e-7)={fds[1]:.12e} adjoint={adj:.12e}", flush=True)
+    assert abs(fds[0] - fds[1]) <= 1e-6 * abs(fd), "a discrete event lies inside the FD window"
+    rel = abs(adj - fd) / abs(fd)
+    print(f"  rel={rel:.2e}", flush=True)
+    assert rel < 1e-6, (fd, adj, rel)
+
+
+def _types_by_id(sim, ids):
+    n = sim.live_count()
+    cur = sim._current()
+    t = cur["type"][:n].cpu().numpy()
+    i = cur["id"][:n].cpu().numpy()
+    m = dict(zip(i.tolist(), t.tolist()))
+    return np.array([m[int(x)] for x in ids], np.uint8)
+
+
+def test_step_record_matches_step():
+    """sph_step_record gives the same state as sph_step, bit for bit, and its
+    events cover pushes, transfers, deletions and re-spawns (the case of the
+    30-step dot-product test)."""
+    prm, s = _case("C2-small", 9)
+    a = B().Simulation(prm, s)
+    a.step(30)
+    b = B().Simulation(prm, s)
+    tape = A().StepTape(b, 30)
+    seen = 0
+    for j in range(30):
+        tape.record(j)
+        e = tape.events[j][:b.live_count()]
+        for k, bit in enumerate((1, 2, 4, 8)):
+            if bool(((e & bit) != 0).any()):
+                seen |= bit
+    assert a.poll_error() == 0 and b.poll_error() == 0
+    sa, sb = a.state(), b.state()
+    for k in sa:  # row for row: re-spawned rows are appended in parent order
+        assert np.array_equal(sa[k], sb[k]), k
+    assert seen == 15, seen
+
+
+def _fd_run(prm, s, nsteps, hw):
+    """J of one FP64 GPU run, with per-step hashes of its discrete events:
+    end-of-step events and supported boundary rows (ev), neighbour counts (nb)."""
+    sim = B().Simulation(prm, s)
+    hist = torch.zeros((nsteps, 3), dtype=torch.float64, device="cuda")
+    tape = A().StepTape(sim, 1)
+    ev, nb = [], []
+    n = sim.cap
+    for j in range(nsteps):
+        tape.record(0, drag=hist[j])
+        ev.append((sim.der["red"].to(torch.int64) * hw[1][:n]).sum() +
+                  (tape.events[0].to(torch.int64) * hw[2][:n]).sum())
+        nb.append((sim.nl_count.to(torch.int64) * hw[0][:n]).sum())
+    assert sim.poll_error() == 0
+    return (float(hist[:, 0].mean().item()), torch.stack(ev).cpu().numpy(),
+            torch.stack(nb).cpu().numpy())
+
+
+def _fd(prm, s, rows, th, v, eps, nsteps, hw):
+    Jp, ep, nbp = _fd_run(prm, I.set_inlet_profile(prm, s, rows, th + eps * v), nsteps, hw)
+    Jm, em, nbm = _fd_run(prm, I.set_inlet_profile(prm, s, rows, th - eps * v), nsteps, hw)
+    return (Jp - Jm) / (2 * eps), np.array_equal(ep, em), int((nbp != nbm).sum())
+
+
+def test_c4_drag_gradient_vs_fd():
+    """Positions jittered by 0.1 dx (on the lattice many pairs sit exactly at
+    r = 2h). The neighbour count of eq:pavg may still change inside the FD
+    window at some step; its effect on the drag is far below the gate, which
+    the agreement of the differences at two step sizes checks."""
+    nsteps = 500
+    prm, s = I.config("C4")
+    s = I.jitter(prm, s, 0.1, 5, types=MOVING)
+    prob = A().InletProfileDrag(prm, s, nsteps, segment=50)
+    th = prob.theta0()
+    J, _ = prob.value(th)
+    g = prob.gradient().cpu().numpy()
+    print(f"C4 J={J:.12e} |g|_inf={np.abs(g).max():.6e} sum g={g.sum():.6e}", flush=True)
+    cap = prob.sim.cap
+    gen = torch.Generator().manual_seed(5)
+    hw = [torch.randint(1, 1 << 20, (cap,), generator=gen, dtype=torch.int64).cuda()
+          for _ in range(3)]
+    rng = np.random.default_rng(3)
+    dirs = [("entry", k, np.eye(prob.ntheta)[k]) for k in (0, 21, 50, 77, 99)]
+    dirs.append(("random", -1, rng.standard_normal(prob.ntheta)))
+    errs, scale = [], 0.0
+    for kind, k, v in dirs:
+        ad = float(g @ v)
+        clean = []
+        for eps in (1e-6, 1e-7, 1e-8):
+            fd, same, nb = _fd(prm, s, prob.rows, th, v, eps, nsteps, hw)
+            print(f"  {kind} {k}: eps={eps:g} fd={fd:.10e} adjoint={ad:.10e} same events: "
+                  f"{same} (steps with other neighbour counts: {nb})", flush=True)
+            if same:
+                clean.append(fd)
+            if len(clean) == 2:
+                break
+        assert clean, "end-of-step events or boundary support differ at every step size"
+        if len(clean) == 2:  # no jump inside either window
+            assert abs(clean[0] - clean[1]) <= 1e-5 * abs(clean[0]), clean
+        errs.append(abs(ad - clean[0]))
+        scale = max(scale, abs(clean[0]))
+    err = max(errs) / scale
+    print(f"  max |g_adj - g_fd| / max |g_fd| = {err:.2e}", flush=True)
+    assert err <= 1e-4
+
+
+def test_small_cylinder_drag_gradient_vs_oracle():
+    """Directional derivative of the time-averaged drag (small channel with a
+    cylinder, 120 steps, positions jittered by 0.1 dx): oracle central
+    difference vs the GPU adjoint."""
+    nsteps = 120
+    prm, s = I.config("C4", small=True)
+    s = I.jitter(prm, s, 0.1, 8, types=MOVING)
+    prob = A().InletProfileDrag(prm, s, nsteps, segment=40)
+    th = prob.theta0()
+    prob.value(th)
+    g = prob.gradient().cpu().numpy()
+    v = np.random.default_rng(4).standard_normal(prob.ntheta)
+    e = 1e-6
+
+    def J(theta):
+        o = O.Oracle(prm, I.set_inlet_profile(prm, s, prob.rows, theta))
+        return o.step(nsteps)[:, 0].mean()
+
+    fd = (J(th + e * v) - J(th - e * v)) / (2 * e)
+    ad = float(g @ v)
+    rel = abs(ad - fd) / abs(fd)
+    print(f"  fd={fd:.12e} adjoint={ad:.12e} rel={rel:.2e}", flush=True)
+    assert rel < 1e-5
+
+
+def test_fp32_adjoint_close_to_fp64():
+    """The FP32 path's adjoint (FP32 pair arithmetic, FP64 accumulators of the
+    reverse) stays close to the FP64 one on the small cylinder case."""
+    nsteps = 60
+    prm, s = I.config("C4", small=True)
+    s = I.jitter(prm, s, 0.1, 8, types=MOVING)
+    gs = {}
+    for prec in ("fp64", "fp32"):
+        prob = A().InletProfileDrag(prm, s, nsteps, segment=20, prec=prec)
+        prob.value(prob.theta0())
+        gs[prec] = prob.gradient().cpu().numpy()
+    err = np.abs(gs["fp32"] - gs["fp64"]).max() / np.abs(gs["fp64"]).max()
+    print(f"  fp32 vs fp64 adjoint: {err:.2e}", flush=True)
+    assert err < 2e-2
