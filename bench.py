@@ -104,6 +104,126 @@ def cpu_baseline(prm, s, budget_s):
                        f"workload, {elapsed:.1f} s of stepping")
 
 
+def adjoint_bytes(sim, counts, types, prec_bytes):
+    """Algorithmic HBM bytes of one reverse right-hand side (sph_rhs_adjoint):
+    the forward state and stored derived fields read once per row, the weights
+    and seeds read once, the neighbour indices read once per pass that walks
+    them (pairs, neighbour average, boundary, density), every adjoint output
+    written once. Re-reads of neighbour rows are served by cache and do not
+    count."""
+    D = sim.dim
+    n = len(types)
+    nnz = int(counts.sum())
+    state = 8 * D + prec_bytes * (2 * D + 1) + 1 + 3 * prec_bytes  # x, u, ut, p, type, rho, V, pbar
+    weights = prec_bytes * (2 * D + 1) + 8 * (1 + D + 3)  # abar, bbar, pdbar, seeds
+    bnd = 8 * (D + 1) + 8 * 4 + 8  # averages, jcur/jprev, Shepard sum
+    outputs = 8 * (3 * D + 1 + D + (D + 1) + 3)  # xbar, ubar, utbar, pbar, uinbar, avgbar, jprevbar
+    internal = 2 * 8 * 10  # scratch written and read back between the four passes
+    rd = n * (state + weights + bnd + internal // 2) + 4 * nnz * 4 + 4 * n * 4
+    wr = n * (outputs + internal // 2)
+    return rd + wr
+
+
+def adjoint_bench(args):
+    """Reverse of a run of steps on the channel-with-cylinder workload: the
+    time-averaged-drag gradient (checkpointed forward, segment replay, reverse
+    of every step). value = 2 P_RHS x steps / time of the reverse sweep (replay
+    included)."""
+    import numpy as np
+    import torch
+    from paper_1907_04034_amd import adjoint as A
+    from paper_1907_04034_amd import binding as B
+    from paper_1907_04034_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    prm, s = I.config(args.config)
+    K = args.steps
+    log(f"bench adjoint: {prm['name']} n={len(s['p'])} prec={args.precision} steps={K}")
+    stream = torch.cuda.current_stream()
+    fbar = np.zeros((K, 3))
+    fbar[:, 0] = 1.0 / K
+    # warm-up: a short forward + reverse on its own simulation
+    wsim = B.Simulation(prm, s, prec=args.precision)
+    w = A.DragAdjoint(wsim, max(2, min(args.warmup, 20)), segment=args.segment)
+    w.forward()
+    w.backward(np.zeros((w.nsteps, 3)))
+    if wsim.poll_error():
+        raise SystemExit("device error during warm-up")
+    del w, wsim
+    sim = B.Simulation(prm, s, prec=args.precision)
+    run = A.DragAdjoint(sim, K, segment=args.segment)
+    torch.cuda.synchronize()
+    times = {}
+    for phase in ("forward", "backward"):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record(stream)
+        if phase == "forward":
+            hist = run.forward()
+        else:
+            run.backward(fbar)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times[phase] = max(e0.elapsed_time(e1), 1e3 * (time.perf_counter() - w0))
+        log(f"bench adjoint: {phase} {times[phase]:.1f} ms")
+    if sim.poll_error():
+        raise SystemExit("device error in the timed region")
+    J = float(hist[:, 0].mean().item())
+    # pairs per right-hand side at the start state (the reverse ends there)
+    sim2 = B.Simulation(prm, s, prec=args.precision)
+    sim2.bin()
+    sim2.neighbors()
+    sim2.rhs()
+    cnt, _ = sim2.neighbor_table()
+    types = sim2.state()["type"]
+    p_rhs = int((cnt[types == 0] - 1).sum())
+    value = 2 * p_rhs * K / (times["backward"] * 1e-3)
+    # one reverse right-hand side, timed alone
+    n = len(types)
+    rng = np.random.default_rng(0)
+    ab = rng.standard_normal((n, 3))
+    sim2.rhs_adjoint(abar=ab, bbar=ab, pdbar=ab[:, 0], fbar=(1.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    reps = args.force_reps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    st_adj = sim2._adj_struct()
+    for a_, b_ in evs:
+        a_.record(stream)
+        sim2.rhs_adjoint_launch(st_adj)
+        b_.record(stream)
+    torch.cuda.synchronize()
+    a_us = 1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs]))
+    prec_bytes = 8 if args.precision == "fp64" else 4
+    abytes = adjoint_bytes(sim2, cnt, types, prec_bytes)
+    achieved = abytes / (a_us * 1e-6) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair-interactions/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": min(args.warmup, 20),
+        "ms_per_step": times["backward"] / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 pairs / f64 positions",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS[args.config] + ", gradient of the time-averaged drag "
+                   "w.r.t. the inlet profile", "config": args.config, "form": "adjoint",
+                   "particles": int(len(s["p"])), "pairs_per_rhs": p_rhs, "rhs_per_step": 2,
+                   "precision": args.precision, "segment": run.segment,
+                   "forward_ms": times["forward"], "backward_ms": times["backward"],
+                   "J": J},
+        "roofline": {"bound": "hbm", "kernel": "sph_rhs_adjoint (4 kernels)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": abytes, "launch_us": a_us},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,11 +236,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (for counter scaling)")
+    ap.add_argument("--form", default="forward", choices=["forward", "adjoint"],
+                    help="adjoint: gradient of the time-averaged drag (default config C4)")
+    ap.add_argument("--segment", type=int, default=50, help="adjoint checkpoint interval")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1"}))
         log("bench.py: multi-GPU runs are not part of this build (one GPU only)")
         sys.exit(2)
+    if args.form == "adjoint":
+        if args.config == "C2" and "--config" not in sys.argv:
+            args.config = "C4"
+        if "--steps" not in sys.argv:
+            args.steps = 500
+        adjoint_bench(args)
+        return
 
     import numpy as np
     import torch

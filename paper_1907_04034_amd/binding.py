@@ -346,17 +346,8 @@ class Simulation:
                 view = A[name].view(comps, cap) if comps > 1 else A[name]
                 host = np.ascontiguousarray(w.T if comps > 1 else w)
                 view[..., :n].copy_(t.from_numpy(host).to(view.dtype))
-        st = SphAdjoint()
-        st.abar, st.bbar, st.pdbar = A["abar"].data_ptr(), A["bbar"].data_ptr(), A["pdbar"].data_ptr()
-        for d in range(3):
-            st.fbar[d] = float(fbar[d])
-        for k in ("pseed", "useed", "jseed", "xbar", "ubar", "utbar", "pbar", "uinbar", "avgbar",
-                  "jprevbar", "scratch"):
-            setattr(st, k, A[k].data_ptr())
-        ws, nb = self._ws()
-        _check(lib().sph_rhs_adjoint(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
-                                     C.byref(self.out), C.byref(st), ws, nb, self.stream),
-               "sph_rhs_adjoint")
+        st = self._adj_struct(fbar)
+        self.rhs_adjoint_launch(st)
         out = {}
         for k in ("xbar", "ubar", "utbar", "uinbar", "jprevbar"):
             out[k] = A[k].view(3, cap)[:, :n].cpu().numpy().T.copy()
@@ -366,6 +357,25 @@ class Simulation:
         out["avgbar"][:, :D] = av[:, :D]
         out["avgbar"][:, 3] = av[:, D]
         return out
+
+    def _adj_struct(self, fbar=(0.0, 0.0, 0.0)):
+        A = self.adj
+        st = SphAdjoint()
+        st.abar, st.bbar, st.pdbar = A["abar"].data_ptr(), A["bbar"].data_ptr(), A["pdbar"].data_ptr()
+        for d in range(3):
+            st.fbar[d] = float(fbar[d])
+        for k in ("pseed", "useed", "jseed", "xbar", "ubar", "utbar", "pbar", "uinbar", "avgbar",
+                  "jprevbar", "scratch"):
+            setattr(st, k, A[k].data_ptr())
+        return st
+
+    def rhs_adjoint_launch(self, st):
+        """Enqueue sph_rhs_adjoint with a prepared argument block (weights already on
+        the device); nothing is copied back."""
+        ws, nb = self._ws()
+        _check(lib().sph_rhs_adjoint(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
+                                     C.byref(self.out), C.byref(st), ws, nb, self.stream),
+               "sph_rhs_adjoint")
 
     # ------------------------------------------------------------ results
     def state(self):
