@@ -80,14 +80,13 @@ class StepTape:
 
     def snapshot(self):
         """Device copy of the simulation's current state."""
-        cur = self.sim._current()
-        return {k: v.clone() for k, v in cur.items()}, self.sim.n_dev.clone()
+        b = self.sim._alloc()
+        Bd.Simulation.copy_state(b, self.sim._current())
+        return b, self.sim.n_dev.clone()
 
     def restore(self, snap):
         b, n = snap
-        cur = self.sim._current()
-        for k, v in b.items():
-            cur[k].copy_(v)
+        Bd.Simulation.copy_state(self.sim._current(), b)
         self.sim.n_dev.copy_(n)
 
     # ------------------------------------------------------------ steps
@@ -95,9 +94,7 @@ class StepTape:
         """Keep the current state in slot j, then one recorded step."""
         s = self.sim
         b, n, _ = self._slot(j)
-        cur = s._current()
-        for k, v in cur.items():
-            b[k].copy_(v)
+        Bd.Simulation.copy_state(b, s._current())
         n.copy_(s.n_dev)
         ws, nb = s._ws()
         Bd._check(Bd.lib().sph_step_record(
@@ -135,15 +132,24 @@ class DragAdjoint:
         self.segment = max(1, min(int(segment), self.nsteps))
         self.tape = StepTape(sim, self.segment)
         self.ckpts = []
+        self._tape_holds_last = False
 
     def forward(self):
+        """The last segment is recorded as it runs, so the reverse starts
+        without a replay (with segment >= nsteps nothing is replayed)."""
         t = self.sim.torch
         hist = t.zeros((self.nsteps, 3), dtype=t.float64, device=self.sim.dev)
         self.ckpts = []
-        for s0 in range(0, self.nsteps, self.segment):
+        starts = list(range(0, self.nsteps, self.segment))
+        for s0 in starts:
             self.ckpts.append(self.tape.snapshot())
             k = min(self.segment, self.nsteps - s0)
-            self.sim.step(k, drag_hist=hist[s0:s0 + k])
+            if s0 == starts[-1]:
+                for j in range(k):
+                    self.tape.record(j, drag=hist[s0 + j])
+            else:
+                self.sim.step(k, drag_hist=hist[s0:s0 + k])
+        self._tape_holds_last = True
         return hist
 
     def backward(self, fbar, lam_final=None):
@@ -157,17 +163,20 @@ class DragAdjoint:
         nxt, cur = tape.lam
         for k in _LAM_FIELDS:
             nxt[k].zero_()
+        last = len(self.ckpts) - 1
         for seg in reversed(range(len(self.ckpts))):
             s0 = seg * self.segment
             k = min(self.segment, self.nsteps - s0)
-            tape.restore(self.ckpts[seg])
-            for j in range(k):
-                tape.record(j)
-            if lam_final is not None and seg == len(self.ckpts) - 1:
+            if seg != last or not self._tape_holds_last:
+                tape.restore(self.ckpts[seg])
+                for j in range(k):
+                    tape.record(j)
+            if lam_final is not None and seg == last:
                 self._upload_lam(nxt, lam_final)
             for j in reversed(range(k)):
                 tape.reverse(j, fbar[s0 + j], nxt, cur)
                 nxt, cur = cur, nxt
+        self._tape_holds_last = False
         self.lam0 = nxt
         return nxt
 

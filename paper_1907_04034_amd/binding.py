@@ -199,22 +199,23 @@ class Simulation:
 
     # ------------------------------------------------------------ memory
     def _alloc(self):
+        """One state buffer set: every array is a 256-byte aligned view of one
+        device allocation ("_buf"), so a whole state copies in one call."""
         t, cap, D = self.torch, self.cap, self.dim
-        dev = self.dev
-        return dict(
-            x=t.zeros(3 * cap, dtype=t.float64, device=dev),
-            u=t.zeros(3 * cap, dtype=self.rdt, device=dev),
-            ut=t.zeros(3 * cap, dtype=self.rdt, device=dev),
-            p=t.zeros(cap, dtype=self.rdt, device=dev),
-            uin=t.zeros(3 * cap, dtype=t.float64, device=dev),
-            ring=t.zeros(6 * (D + 1) * cap, dtype=t.float64, device=dev),
-            head=t.zeros(cap, dtype=t.uint8, device=dev),
-            avg=t.zeros((D + 1) * cap, dtype=t.float64, device=dev),
-            jprev=t.zeros(3 * cap, dtype=t.float64, device=dev),
-            red_prev=t.zeros(cap, dtype=t.uint8, device=dev),
-            type=t.full((cap,), DEAD, dtype=t.uint8, device=dev),
-            id=t.zeros(cap, dtype=t.int64, device=dev),
-        )
+        f64, rdt, u8, i64 = t.float64, self.rdt, t.uint8, t.int64
+        spec = [("x", 3, f64), ("u", 3, rdt), ("ut", 3, rdt), ("p", 1, rdt), ("uin", 3, f64),
+                ("ring", 6 * (D + 1), f64), ("head", 1, u8), ("avg", D + 1, f64),
+                ("jprev", 3, f64), ("red_prev", 1, u8), ("type", 1, u8), ("id", 1, i64)]
+        offs, total = [], 0
+        for name, comps, dt in spec:
+            nbytes = comps * cap * t.empty((), dtype=dt).element_size()
+            offs.append((name, total, nbytes, dt))
+            total += (nbytes + 255) // 256 * 256
+        buf = t.zeros(total, dtype=u8, device=self.dev)
+        out = {name: buf[o:o + nb].view(dt) for name, o, nb, dt in offs}
+        out["type"].fill_(DEAD)
+        out["_buf"] = buf
+        return out
 
     def _state_struct(self, b):
         return SphState(self.cap, self.prec, self.dim, self.n_dev.data_ptr(),
@@ -252,6 +253,11 @@ class Simulation:
             if b["x"].data_ptr() == self.st.x:
                 return b
         raise SphError("state pointers do not match any buffer set")
+
+    @staticmethod
+    def copy_state(dst, src):
+        """Device copy of a whole state buffer set (one call)."""
+        dst["_buf"].copy_(src["_buf"])
 
     # ------------------------------------------------------------ calls
     @property

@@ -219,15 +219,29 @@ __device__ inline T ldw(const void *p, int64_t i)
     return p ? ld<T>(p, i) : T(0);
 }
 
+// Lane groups: G lanes per particle (the force pass's choice), each lane a
+// subset of the neighbours; per-particle sums are reduced with lane shuffles
+// and written by lane 0. Blocks map to the XCDs in contiguous slabs.
+template <int G>
+__device__ inline int64_t adj_row(int64_t n, int &lane)
+{
+    constexpr int PB = kBlock / G;
+    lane = threadIdx.x & (G - 1);
+    const int64_t lb = xcd_block((n + PB - 1) / PB);
+    const int64_t i = lb * PB + threadIdx.x / G;
+    return lb < 0 || i >= n ? -1 : i;
+}
+
 // R1: pair reverses, gathered per particle.
-template <int DIM, typename T>
+template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields R, DevNlist nl,
                                                       DevDerived o, DevAdj A, const float *off,
                                                       const uint32_t *cpos, uint32_t *err)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int lane;
     const int64_t n = *m.n;
-    if (i >= n) return;
+    const int64_t i = adj_row<G>(n, lane);
+    if (i < 0) return;
     const int64_t C = k.cap;
     Ep<T> K;
     load_ep<DIM, T>(k, m, R, o, i, K);
@@ -248,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
     EpBar<T> Kb;
     T Pb = T(0), xb[3] = {0, 0, 0};
     const int cnt = nl.count[i];
-    for (int q = 0; q < cnt; ++q) {
+    for (int q = lane; q < cnt; q += G) {
         const int32_t j = nl.nbr[i * nl.maxnb + q];
         if (bad_index(j, n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
@@ -263,7 +277,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
         for (int d = 0; d < 3; ++d) rn[d] = -r[d];
         EpBar<T> dummy;
         T Pdummy = T(0);
-        // k as the target
+        // i as the target
         if (K.t == SPH_FLUID || (K.t == SPH_BODY && J.t == SPH_FLUID)) {
             T rb[3] = {0, 0, 0};
             if (K.t == SPH_FLUID)
@@ -273,7 +287,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
 #pragma unroll
             for (int d = 0; d < DIM; ++d) xb[d] += rb[d];
         }
-        // k as the neighbour of target j
+        // i as the neighbour of target j
         if (J.t == SPH_FLUID || (J.t == SPH_BODY && K.t == SPH_FLUID)) {
             const T PJ = ld<T>(o.pavg, j);
             T rb[3] = {0, 0, 0};
@@ -293,6 +307,17 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
             for (int d = 0; d < DIM; ++d) xb[d] -= rb[d];
         }
     }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        xb[d] = gsum<G>(xb[d]);
+        Kb.u[d] = gsum<G>(Kb.u[d]);
+        Kb.w[d] = gsum<G>(Kb.w[d]);
+    }
+    Kb.p = gsum<G>(Kb.p);
+    Kb.rho = gsum<G>(Kb.rho);
+    Kb.vol = gsum<G>(Kb.vol);
+    Pb = gsum<G>(Pb);
+    if (lane != 0) return;
     // boundary values may carry adjoints from outside this right-hand side
     // (a stage update that reads them)
     const bool seeded = K.t != SPH_FLUID;
@@ -309,17 +334,18 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
 }
 
 // R2a: pbar_i = (1/N_i) sum_{j in N(i)} p_j  ->  pbar_j += Pbar_i / N_i.
-template <int DIM, typename T>
+template <int DIM, int G>
 __global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist nl, DevAdj A,
                                                      uint32_t *err)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int lane;
     const int64_t n = *m.n;
-    if (i >= n) return;
+    const int64_t i = adj_row<G>(n, lane);
+    if (i < 0) return;
     if (k.flags & SPH_FLAG_NO_PAVG) return;
     double acc = 0.0;
     const int cnt = nl.count[i];
-    for (int q = 0; q < cnt; ++q) {
+    for (int q = lane; q < cnt; q += G) {
         const int32_t j = nl.nbr[i * nl.maxnb + q];
         if (bad_index(j, n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
@@ -328,7 +354,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist
         const int tj = m.type[j];
         if (tj == SPH_FLUID || tj == SPH_BODY) acc += A.Pbar[j] / double(nl.count[j]);
     }
-    A.pbar[i] += acc;
+    acc = gsum<G>(acc);
+    if (lane == 0) A.pbar[i] += acc;
 }
 
 // Adjoint of boundary particle b's characteristic values J = (J1, J2, J3)
@@ -419,25 +446,24 @@ __device__ inline void load_bnd(const Dev &k, const DevState &m, const Fields &R
 // neighbours (or its own): its J adjoint is split over those, here as
 // jg = Jbar / M for the neighbours to gather in R3 (or straight into its own
 // jprevbar when M = 0).
-template <int DIM, typename T>
+template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R, DevNlist nl,
                                                     DevDerived o, DevAdj A, uint32_t *err)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int lane;
     const int64_t n = *m.n;
-    if (i >= n) return;
+    const int64_t i = adj_row<G>(n, lane);
+    if (i < 0) return;
     const int64_t C = k.cap;
     const int t = m.type[i];
     const int cnt = nl.count[i];
-    double xi[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, avgb[4] = {0, 0, 0, 0};
-    double uinb[3] = {0, 0, 0}, jg[3] = {0, 0, 0}, jown[3] = {0, 0, 0};
+    // per-lane parts of the sums over neighbours
+    double xi[3] = {0, 0, 0}, dx[3] = {0, 0, 0}, du[3] = {0, 0, 0}, davg[4] = {0, 0, 0, 0};
+    double dp = 0.0, drho = 0.0, duin0 = 0.0, M = 0.0;
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        xi[d] = R.x[d * C + i];
-        xb[d] = A.xbar[d * C + i];
-        ub[d] = A.ubar[d * C + i];
-    }
-    double pb = A.pbar[i], rhob = A.rhobar[i];
+    for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
+    const bool red = o.sfl[i] > 0.0;
+    const bool blue_io = !red && (t == SPH_INLET || t == SPH_OUTLET) && A.jprevbar;
     if (t == SPH_FLUID) {
         const double pf = double(ld<T>(R.p, i)), rhof = double(ld<T>(o.rho, i));
         double uf[3] = {0, 0, 0}, avgf[4] = {0, 0, 0, 0};
@@ -445,7 +471,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
         for (int d = 0; d < DIM; ++d) uf[d] = double(ld<T>(R.u, d * C + i));
 #pragma unroll
         for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + i];
-        for (int q = 0; q < cnt; ++q) {
+        for (int q = lane; q < cnt; q += G) {
             const int32_t b = nl.nbr[i * nl.maxnb + q];
             if (bad_index(b, n)) {
                 raise_error(err, SPH_ERR_CELL_RANGE);
@@ -462,15 +488,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
             const double q2 = sqrt(r2) * k.inv_h;
             const double w = wendland_w(q2, k.wnorm), F = wendland_f(q2, k.gnorm);
             double dummy_uin = 0.0;
-            const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, pb, ub, rhob, avgb,
+            const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, dp, du, drho, davg,
                                                   dummy_uin);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xb[d] -= Wb * F * r[d];
+            for (int d = 0; d < DIM; ++d) dx[d] -= Wb * F * r[d];
         }
-    } else if (o.sfl[i] > 0.0) {
+    } else if (red) {
         BndIn B;
         load_bnd<DIM, T>(k, m, R, o, A, i, B);
-        for (int q = 0; q < cnt; ++q) {
+        for (int q = lane; q < cnt; q += G) {
             const int32_t f = nl.nbr[i * nl.maxnb + q];
             if (bad_index(f, n)) continue;
             if (m.type[f] != SPH_FLUID) continue;
@@ -488,21 +514,45 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
 #pragma unroll
             for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + f];
             const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, sink_p, sink_u,
-                                                  sink_rho, sink_avg, uinb[0]);
+                                                  sink_rho, sink_avg, duin0);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xb[d] += Wb * F * r[d];
+            for (int d = 0; d < DIM; ++d) dx[d] += Wb * F * r[d];
         }
-    } else if ((t == SPH_INLET || t == SPH_OUTLET) && A.jprevbar) {
+    } else if (blue_io) {
         // no fluid support: J = mean of the previous-step values of same-kind
         // neighbours that had support (eq:average_old), else the own value
-        BndIn B;
-        load_bnd<DIM, T>(k, m, R, o, A, i, B);
-        double M = 0.0;
-        for (int q = 0; q < cnt; ++q) {
+        for (int q = lane; q < cnt; q += G) {
             const int32_t j = nl.nbr[i * nl.maxnb + q];
             if (bad_index(j, n)) continue;
             if (m.type[j] == t && m.red_prev[j]) M += 1.0;
         }
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        dx[d] = gsum<G>(dx[d]);
+        du[d] = gsum<G>(du[d]);
+    }
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) davg[c] = gsum<G>(davg[c]);
+    dp = gsum<G>(dp);
+    drho = gsum<G>(drho);
+    duin0 = gsum<G>(duin0);
+    M = gsum<G>(M);
+    if (lane != 0) return;
+    double xb[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, avgb[4] = {0, 0, 0, 0}, uinb[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        xb[d] = A.xbar[d * C + i] + dx[d];
+        ub[d] = A.ubar[d * C + i] + du[d];
+    }
+#pragma unroll
+    for (int c = 0; c <= DIM; ++c) avgb[c] = davg[c];
+    uinb[0] = duin0;
+    const double pb = A.pbar[i] + dp, rhob = A.rhobar[i] + drho;
+    double jg[3] = {0, 0, 0}, jown[3] = {0, 0, 0};
+    if (blue_io) {
+        BndIn B;
+        load_bnd<DIM, T>(k, m, R, o, A, i, B);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (M > 0.0) jg[a] = B.Jb[a] / M;
@@ -544,27 +594,33 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
 
 // R3: density reverse, xbar_k += sum_j (Sbar_k + Sbar_j) F_kj r_kj; final
 // velocity adjoints (u enters directly and through w = ut - u).
-template <int DIM, typename T>
+template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R, DevNlist nl,
                                                      DevAdj A, uint32_t *err)
 {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int lane;
     const int64_t n = *m.n;
-    if (i >= n) return;
+    const int64_t i = adj_row<G>(n, lane);
+    if (i < 0) return;
     const int64_t C = k.cap;
-    double xi[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+    const int t = m.type[i];
+    double xi[3] = {0, 0, 0}, dx[3] = {0, 0, 0}, g[3] = {0, 0, 0};
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        xi[d] = R.x[d * C + i];
-        xb[d] = A.xbar[d * C + i];
-    }
+    for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
     const double Si = A.Sbar[i];
+    // previous-step values of i read by unsupported same-kind neighbours
+    // (i itself included), reverse of the mean taken in R2b
+    const bool gather_j = A.jprevbar && (t == SPH_INLET || t == SPH_OUTLET) && m.red_prev[i];
     const int cnt = nl.count[i];
-    for (int q = 0; q < cnt; ++q) {
+    for (int q = lane; q < cnt; q += G) {
         const int32_t j = nl.nbr[i * nl.maxnb + q];
         if (bad_index(j, n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
             continue;
+        }
+        if (gather_j && m.type[j] == t) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) g[a] += A.jg[a * C + j];
         }
         if (j == i) continue;
         double xj[3] = {0, 0, 0}, r[3];
@@ -574,54 +630,67 @@ __global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R
         const double F = wendland_f(sqrt(r2) * k.inv_h, k.gnorm);
         const double s = (Si + A.Sbar[j]) * F;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) xb[d] += s * r[d];
+        for (int d = 0; d < DIM; ++d) dx[d] += s * r[d];
     }
-    const int t = m.type[i];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) dx[d] = gsum<G>(dx[d]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[a] = gsum<G>(g[a]);
+    if (lane != 0) return;
     const bool fl = t == SPH_FLUID;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        A.xbar[d * C + i] = xb[d];
+        A.xbar[d * C + i] += dx[d];
         const double w = A.wbar[d * C + i];
         A.utbar[d * C + i] = fl ? w : 0.0;
         if (fl) A.ubar[d * C + i] -= w;
     }
-    // previous-step values of i read by unsupported same-kind neighbours
-    // (i itself included), reverse of the mean taken in R2b
-    if (A.jprevbar && (t == SPH_INLET || t == SPH_OUTLET) && m.red_prev[i]) {
-        double g[3] = {0, 0, 0};
-        for (int q = 0; q < cnt; ++q) {
-            const int32_t j = nl.nbr[i * nl.maxnb + q];
-            if (bad_index(j, n) || m.type[j] != t) continue;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) g[a] += A.jg[a * C + j];
-        }
+    if (gather_j) {
 #pragma unroll
         for (int a = 0; a < 3; ++a) A.jprevbar[a * C + i] += g[a];
     }
 }
 
 // ------------------------------------------------------------------ launchers
-#define SPH_ADJ_DISPATCH(KERNEL, ...)                                                         \
-    do {                                                                                      \
-        const dim3 g(nblocks(k.cap)), b(kBlock);                                              \
-        if (k.dim == 2 && k.prec == SPH_FP64)                                                 \
-            hipLaunchKernelGGL((KERNEL<2, double>), g, b, 0, s, __VA_ARGS__);                 \
-        else if (k.dim == 3 && k.prec == SPH_FP64)                                            \
-            hipLaunchKernelGGL((KERNEL<3, double>), g, b, 0, s, __VA_ARGS__);                 \
-        else if (k.dim == 2)                                                                  \
-            hipLaunchKernelGGL((KERNEL<2, float>), g, b, 0, s, __VA_ARGS__);                  \
-        else                                                                                  \
-            hipLaunchKernelGGL((KERNEL<3, float>), g, b, 0, s, __VA_ARGS__);                  \
-    } while (0)
+template <int DIM, typename T, int G>
+static void rhs_adjoint_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                          const DevDerived &o, const DevAdj &A, const float *off,
+                          const uint32_t *cpos, uint32_t *err, hipStream_t s)
+{
+    const dim3 g(xcd_grid((k.cap + kBlock / G - 1) / (kBlock / G))), b(kBlock);
+    hipLaunchKernelGGL((k_adj_pairs<DIM, T, G>), g, b, 0, s, k, m, R, nl, o, A, off, cpos, err);
+    hipLaunchKernelGGL((k_adj_pavg<DIM, G>), g, b, 0, s, k, m, nl, A, err);
+    hipLaunchKernelGGL((k_adj_bnd<DIM, T, G>), g, b, 0, s, k, m, R, nl, o, A, err);
+    hipLaunchKernelGGL((k_adj_dens<DIM, T, G>), g, b, 0, s, k, m, R, nl, A, err);
+}
+
+template <int DIM, typename T>
+static void rhs_adjoint_dt(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                           const DevDerived &o, const DevAdj &A, const float *off,
+                           const uint32_t *cpos, uint32_t *err, hipStream_t s)
+{
+    switch (force_group(k)) {
+    case 1: rhs_adjoint_g<DIM, T, 1>(k, m, R, nl, o, A, off, cpos, err, s); break;
+    case 2: rhs_adjoint_g<DIM, T, 2>(k, m, R, nl, o, A, off, cpos, err, s); break;
+    case 4: rhs_adjoint_g<DIM, T, 4>(k, m, R, nl, o, A, off, cpos, err, s); break;
+    case 8: rhs_adjoint_g<DIM, T, 8>(k, m, R, nl, o, A, off, cpos, err, s); break;
+    case 16: rhs_adjoint_g<DIM, T, 16>(k, m, R, nl, o, A, off, cpos, err, s); break;
+    default: rhs_adjoint_g<DIM, T, 32>(k, m, R, nl, o, A, off, cpos, err, s); break;
+    }
+}
 
 void launch_rhs_adjoint(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                         const DevDerived &o, const DevAdj &A, const float *off,
                         const uint32_t *cpos, uint32_t *err, hipStream_t s)
 {
-    SPH_ADJ_DISPATCH(k_adj_pairs, k, m, R, nl, o, A, off, cpos, err);
-    SPH_ADJ_DISPATCH(k_adj_pavg, k, m, nl, A, err);
-    SPH_ADJ_DISPATCH(k_adj_bnd, k, m, R, nl, o, A, err);
-    SPH_ADJ_DISPATCH(k_adj_dens, k, m, R, nl, A, err);
+    if (k.dim == 2 && k.prec == SPH_FP64)
+        rhs_adjoint_dt<2, double>(k, m, R, nl, o, A, off, cpos, err, s);
+    else if (k.dim == 3 && k.prec == SPH_FP64)
+        rhs_adjoint_dt<3, double>(k, m, R, nl, o, A, off, cpos, err, s);
+    else if (k.dim == 2)
+        rhs_adjoint_dt<2, float>(k, m, R, nl, o, A, off, cpos, err, s);
+    else
+        rhs_adjoint_dt<3, float>(k, m, R, nl, o, A, off, cpos, err, s);
 }
 
 }  // namespace sph

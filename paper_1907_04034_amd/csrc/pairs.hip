@@ -3,10 +3,10 @@
 // inlet) and the EDAC-TVF force pass (optionally fused with the RK2 stage
 // update) with the body force.
 //
-// Work decomposition: a group of G lanes (G = 16 in 2D, 32 in 3D; 4 or 2
-// groups per wave64) owns one target particle and each lane one neighbour, so
-// every neighbour gather of a target is in flight at once and small particle
-// counts still put thousands of waves on the 256 CUs. Per-target sums are
+// Work decomposition: a group of G lanes (a template parameter the host picks
+// from the particle count) owns one target particle and each lane a subset of
+// its neighbours, so several neighbour gathers of a target are in flight at
+// once and small particle counts still put thousands of waves on the 256 CUs. Per-target sums are
 // reduced across the group with lane shuffles; in FP32 the reduction carries
 // the rounding error of every addition (TwoSum), i.e. compensated FP32
 // accumulation. Particles are Morton-sorted, the neighbour table is row-major
@@ -31,29 +31,6 @@ struct Grp {
 // a target in flight at once), few lanes (down to one) spend no issue slots on
 // idle lanes and cross-lane reductions when the particle count alone fills
 // the chip. The host picks them from the capacity (override in sph_params).
-
-// Logical block for hardware block blockIdx.x when nb_logical blocks are
-// needed: the 8 XCDs (which receive consecutive hardware blocks round-robin)
-// each get one contiguous range of logical blocks. Returns -1 for hardware
-// blocks beyond the need.
-__device__ inline int64_t xcd_block(int64_t nb_logical)
-{
-    const int64_t per = (nb_logical + 7) / 8;
-    const int64_t b = blockIdx.x;
-    if (b / 8 >= per) return -1;
-    const int64_t lb = (b % 8) * per + b / 8;
-    return lb < nb_logical ? lb : -1;
-}
-
-inline int xcd_grid(int64_t nb_logical) { return int(((nb_logical + 7) / 8) * 8); }
-
-template <int G, typename V>
-__device__ inline V gsum(V v)
-{
-#pragma unroll
-    for (int m = G / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, G);
-    return v;
-}
 
 // Error-free addition (Knuth TwoSum): s + e == a + b exactly.
 __device__ inline void two_sum(float a, float b, float &s, float &e)

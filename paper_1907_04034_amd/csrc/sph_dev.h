@@ -71,6 +71,29 @@ struct DevAdj {
     double *wbar, *rhobar, *volbar, *Pbar, *Sbar, *jg;
 };
 
+// Logical block for hardware block blockIdx.x when nb_logical blocks are
+// needed: the 8 XCDs (which receive consecutive hardware blocks round-robin)
+// each get one contiguous range of logical blocks. Returns -1 for hardware
+// blocks beyond the need.
+__device__ inline int64_t xcd_block(int64_t nb_logical)
+{
+    const int64_t per = (nb_logical + 7) / 8;
+    const int64_t b = blockIdx.x;
+    if (b / 8 >= per) return -1;
+    const int64_t lb = (b % 8) * per + b / 8;
+    return lb < nb_logical ? lb : -1;
+}
+
+inline int xcd_grid(int64_t nb_logical) { return int(((nb_logical + 7) / 8) * 8); }
+
+template <int G, typename V>
+__device__ inline V gsum(V v)
+{
+#pragma unroll
+    for (int m = G / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, G);
+    return v;
+}
+
 // Exclusive prefix sum of one value per thread over a block of kBlock
 // threads (lds: kBlock entries); *total receives the block sum.
 __device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *lds, int32_t *total)

@@ -21,6 +21,7 @@ void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBuf
                 uint32_t *err, hipStream_t s);
 
 // pair passes
+int force_group(const Dev &k);
 int force_grid(const Dev &k);
 int force_grid_max(const Dev &k);
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
