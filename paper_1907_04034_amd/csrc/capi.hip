@@ -392,10 +392,10 @@ static void one_step(Ctx &c, sph_state *st, sph_state *alt, sph_nlist *nl, sph_d
 // Carving of the step-adjoint scratch buffer, in units of cap doubles.
 struct AdjLayout {
     size_t acc_x, acc_u, acc_ut, acc_p, acc_uin, acc_ring, acc_avg, acc_jprev;
-    size_t Lx, Lu, Lut, Lp, hut, jseed;
+    size_t hut, jseed;
     size_t abar, bbar, pdbar, pseed, useed;
     size_t xbar, ubar, utbar, pbar, uinbar, avgbar, jprevbar;
-    size_t wbar, rhobar, volbar, Pbar, Sbar, jg, inv;
+    size_t wbar, rhobar, volbar, Pbar, Sbar, jg;
     size_t total;
 };
 
@@ -416,10 +416,6 @@ static AdjLayout adj_layout()
     L.acc_ring = take(kNavg * 4);
     L.acc_avg = take(4);
     L.acc_jprev = take(3);
-    L.Lx = take(3);
-    L.Lu = take(3);
-    L.Lut = take(3);
-    L.Lp = take(1);
     L.hut = take(3);
     L.jseed = take(3);
     L.abar = take(3);
@@ -440,7 +436,6 @@ static AdjLayout adj_layout()
     L.Pbar = take(1);
     L.Sbar = take(1);
     L.jg = take(3);
-    L.inv = take(1);  // int32 entries
     L.total = o;
     return L;
 }
@@ -656,8 +651,7 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
     DevState a = dev_state(st), b = dev_state(work);
     a.n = work->n;
     launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
-    int32_t *inv = reinterpret_cast<int32_t *>(P(L.inv));
-    launch_inverse_perm(c.k, work->n, at<int32_t>(ws, c.w.tmp), inv, c.s);
+    const int32_t *perm = at<int32_t>(ws, c.w.tmp);  // sorted row -> row of st
     const Fields M = fields_of(work), H = c.half();
     do_nbrdens(c, work, M, nl1, d1, 1);
     do_boundary(c, work, M, nl1, d1);
@@ -677,13 +671,8 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
     S.acc.ring = P(L.acc_ring);
     S.acc.avg = P(L.acc_avg);
     S.acc.jprev = P(L.acc_jprev);
-    S.Lx = P(L.Lx);
-    S.Lu = P(L.Lu);
-    S.Lut = P(L.Lut);
-    S.Lp = P(L.Lp);
     S.hut = P(L.hut);
     S.jseed = P(L.jseed);
-    S.inv = inv;
     S.child = child;
     S.events = events;
     S.n_pre = st->n;
@@ -711,8 +700,7 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
 
     const DevState m = dev_state(work);
     const uint32_t *cpos_s = at<uint32_t>(ws, c.w.cpos_s);
-    launch_adj_eos(c.k, m, S, c.s);
-    launch_adj_full(c.k, m, S, A, c.s);
+    launch_adj_end(c.k, m, S, A, c.s);
     launch_rhs_adjoint(c.k, m, H, dev_nlist(nl2), dev_derived(d2), A, c.off(), cpos_s, c.err(),
                        c.s);
     launch_adj_half(c.k, m, S, A, c.s);
@@ -724,8 +712,7 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
     for (int d = 0; d < 3; ++d) A1.fbar[d] = fbar[d];
     launch_rhs_adjoint(c.k, m, M, dev_nlist(nl1), dev_derived(d1), A1, c.off(), cpos_s, c.err(),
                        c.s);
-    launch_adj_start(c.k, m, S, A1, c.s);
-    launch_adj_unbin(c.k, S, c.s);
+    launch_adj_finish(c.k, m, dev_state(st), perm, S, A1, c.s);
     return check_hip("sph_step_adjoint");
 }
 

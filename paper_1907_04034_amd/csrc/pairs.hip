@@ -22,7 +22,6 @@ template <int DIM>
 struct Grp {
     static constexpr int G = DIM == 2 ? 16 : 32;   // lanes per target
     static constexpr int NS = DIM == 2 ? 9 : 27;   // stencil cells
-    static constexpr int LOGNS = DIM == 2 ? 4 : 5; // binary-search steps
     static constexpr int PER_BLOCK = kBlock / G;   // targets per block
 };
 
@@ -73,10 +72,13 @@ struct Acc<float> {
 };
 
 // ---------------------------------------------- neighbour table + density
-// The group walks the 3^d stencil cells in (dz, dy, dx) order; for each cell
-// its lanes test members b + lane, b + lane + G, ... with the FMA-free FP64
+// The 3^d stencil cells, taken in (dz, dy, dx) order and each in member
+// order, form one candidate sequence per target; the group's lanes test
+// candidates lane, lane + G, ... of that sequence with the FMA-free FP64
 // predicate |r|^2 < (2h)^2 and hits are compacted with a ballot, so the table
-// keeps the stencil-then-cell order. The density (Sec. 2
+// keeps the stencil-then-cell order. Walking the concatenated sequence (cell
+// ranges staged in LDS by the group) leaves no lane idle at cell ends and
+// loads all cell ranges of a target at once. The density (Sec. 2
 // eq:summation-density, V = 1/sum W) is summed from the same pairs when `dens`
 // is set. FP32 mode records the cell-relative offsets the force pass uses.
 template <int DIM, typename T, int G>
@@ -88,67 +90,97 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
                                                     uint32_t *err)
 {
     constexpr int PB = kBlock / G;
+    constexpr int NS = DIM == 2 ? 9 : 27;
+    __shared__ int32_t s_beg[PB][NS], s_len[PB][NS];
     const int lane = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x / G;
     const int64_t n = *m.n;
     const int64_t lb = xcd_block((n + PB - 1) / PB);
-    const int64_t i = lb * PB + threadIdx.x / G;
-    if (lb < 0 || i >= n) return;  // uniform across the group
+    const int64_t i = lb * PB + grp;
+    const bool active = lb >= 0 && i < n;  // uniform across the group
     const int64_t C = k.cap;
     double xi[3] = {0, 0, 0};
+    int c[3] = {0, 0, 0};
+    if (active) {
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
-    int c[3];
-    unpack_cell<DIM>(cpos[i], c);
+        for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
+        unpack_cell<DIM>(cpos[i], c);
+        // cell ranges of the stencil, one cell per lane at a time
+        for (int sc = lane; sc < NS; sc += G) {
+            const int dxs = sc % 3 - 1, dys = (sc / 3) % 3 - 1, dzs = DIM == 3 ? sc / 9 - 1 : 0;
+            int cc[3] = {c[0] + dxs, c[1] + dys, c[2] + dzs};
+            bool ok = true;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                if (cc[d] < 0 || cc[d] >= k.nc[d]) {
+                    if (k.periodic[d]) cc[d] = cc[d] < 0 ? cc[d] + k.nc[d] : cc[d] - k.nc[d];
+                    else ok = false;
+                }
+            }
+            int32_t b = 0, e = 0;
+            if (ok) {
+                const uint32_t key = morton_key<DIM>(spread, cc);
+                b = cell_start[key];
+                e = cell_start[key + 1];
+                if (b < 0 || e > n || b > e) {
+                    raise_error(err, SPH_ERR_CELL_RANGE);
+                    b = e = 0;
+                }
+            }
+            s_beg[grp][sc] = b;
+            s_len[grp][sc] = e - b;
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    int total = 0;
+#pragma unroll
+    for (int sc = 0; sc < NS; ++sc) total += s_len[grp][sc];
     const int gshift = (threadIdx.x & 63) & ~(G - 1);
     const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
     const uint64_t below = (1ull << lane) - 1;
+    // this lane's position in the sequence: cell sc, member mo
+    int sc = 0, mo = lane;
+    while (sc < NS && mo >= s_len[grp][sc]) mo -= s_len[grp][sc++];
     int cnt = 0;
     Acc<T> sw;
-    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
-    for (int dz = zlo; dz <= zhi; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                int cc[3] = {c[0] + dx, c[1] + dy, c[2] + dz};
-                bool ok = true;
+    // batches of NB rounds: the NB candidate positions of a lane are loaded
+    // together (independent loads in flight), then tested in sequence order
+    constexpr int NB = 4;
+    for (int base = 0; base < total; base += NB * G) {
+        int32_t jj[NB];
+        bool hv[NB];
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    if (cc[d] < 0 || cc[d] >= k.nc[d]) {
-                        if (k.periodic[d]) cc[d] = cc[d] < 0 ? cc[d] + k.nc[d] : cc[d] - k.nc[d];
-                        else ok = false;
-                    }
-                }
-                if (!ok) continue;
-                const uint32_t key = morton_key<DIM>(spread, cc);
-                const int32_t b = cell_start[key], e = cell_start[key + 1];
-                if (b < 0 || e > n || b > e) {
-                    raise_error(err, SPH_ERR_CELL_RANGE);
-                    continue;
-                }
-                for (int32_t j0 = b; j0 < e; j0 += G) {
-                    const int32_t j = j0 + lane;
-                    bool hit = false;
-                    double r2 = 0.0;
-                    if (j < e) {
-                        double xj[3] = {0, 0, 0};
+        for (int b = 0; b < NB; ++b) {
+            hv[b] = sc < NS;
+            jj[b] = hv[b] ? s_beg[grp][sc] + mo : 0;  // row 0 as a harmless dummy
+            mo += G;
+            while (sc < NS && mo >= s_len[grp][sc]) mo -= s_len[grp][sc++];
+        }
+        double xj[NB][3];
 #pragma unroll
-                        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
-                        double r[3];
-                        r2 = dist2_exact<DIM>(k, xi, xj, r);
-                        hit = r2 < k.sup2;
-                    }
-                    int pos = cnt, nhit = hit ? 1 : 0;
-                    if (G > 1) {
-                        const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
-                        pos = cnt + __popcll(bal & below);
-                        nhit = __popcll(bal);
-                    }
-                    if (hit) {
-                        if (pos < nl.maxnb) nl.nbr[i * nl.maxnb + pos] = j;
-                        if (dens) sw.add(wendland_w<T>(T(sqrt(r2) * k.inv_h), T(k.wnorm)));
-                    }
-                    cnt += nhit;
-                }
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xj[b][d] = d < DIM ? R.x[d * C + jj[b]] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double r[3];
+            const double r2 = dist2_exact<DIM>(k, xi, xj[b], r);
+            const bool hit = hv[b] && r2 < k.sup2;
+            int pos = cnt, nhit = hit ? 1 : 0;
+            if (G > 1) {
+                const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
+                pos = cnt + __popcll(bal & below);
+                nhit = __popcll(bal);
             }
+            if (hit) {
+                if (pos < nl.maxnb) nl.nbr[i * nl.maxnb + pos] = jj[b];
+                if (dens) sw.add(wendland_w<T>(T(sqrt(r2) * k.inv_h), T(k.wnorm)));
+            }
+            cnt += nhit;
+        }
+    }
     const T S = sw.template reduce<G>();
     if (lane == 0) {
         if (cnt > nl.maxnb) {
@@ -545,19 +577,23 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
             const T rhoi = ld<T>(o.rho, i);
             const T vi = ld<T>(o.vol, i);
             const T vi2 = vi * vi;
-            // the lane's first neighbour is loaded before the pbar reduction so
-            // that with at most G neighbours all gathers form one round trip
-            const bool have0 = lane < cnt;
+            // the lane's first two neighbours are loaded before the pbar
+            // reduction (both indices first, then both rows), so that with at
+            // most 2G neighbours all gathers form two round trips
+            const bool have0 = lane < cnt, have1 = lane + G < cnt;
             const int32_t j0 = have0 ? nl.nbr[i * nl.maxnb + lane] : -1;
-            const bool ok0 = have0 && !bad_index(j0, n);
-            if (have0 && !ok0) raise_error(err, SPH_ERR_CELL_RANGE);
-            Nbr<DIM, T> nb0;
+            const int32_t j1 = have1 ? nl.nbr[i * nl.maxnb + lane + G] : -1;
+            const bool ok0 = have0 && !bad_index(j0, n), ok1 = have1 && !bad_index(j1, n);
+            if ((have0 && !ok0) || (have1 && !ok1)) raise_error(err, SPH_ERR_CELL_RANGE);
+            Nbr<DIM, T> nb0, nb1;
             if (ok0) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j0, nb0);
+            if (ok1) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j1, nb1);
             T pavg = T(0);
             if (!(k.flags & SPH_FLAG_NO_PAVG)) {
                 Acc<T> sp;
                 if (ok0) sp.add(nb0.p);
-                for (int q = lane + G; q < cnt; q += G) {
+                if (ok1) sp.add(nb1.p);
+                for (int q = lane + 2 * G; q < cnt; q += G) {
                     const int32_t j = nl.nbr[i * nl.maxnb + q];
                     if (!bad_index(j, n)) sp.add(ld<T>(R.p, j));
                 }
@@ -566,7 +602,9 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
             Acc<T> acc[3], bacc[3], pdot;
             if (ok0 && j0 != i && !(t == SPH_BODY && nb0.tj != SPH_FLUID))
                 pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb0, acc, bacc, pdot, fb);
-            for (int q = lane + G; q < cnt; q += G) {
+            if (ok1 && j1 != i && !(t == SPH_BODY && nb1.tj != SPH_FLUID))
+                pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb1, acc, bacc, pdot, fb);
+            for (int q = lane + 2 * G; q < cnt; q += G) {
                 const int32_t j = nl.nbr[i * nl.maxnb + q];
                 if (bad_index(j, n)) {
                     raise_error(err, SPH_ERR_CELL_RANGE);
@@ -665,8 +703,8 @@ static int pick(int override, int64_t cap, int small, int large)
     return cap < 300000 ? small : large;
 }
 
-int force_group(const Dev &k) { return pick(k.g_force, k.cap, k.dim == 2 ? 4 : 8, k.dim == 2 ? 2 : 4); }
-int nbr_group(const Dev &k) { return pick(k.g_nbr, k.cap, k.dim == 2 ? 4 : 8, 2); }
+int force_group(const Dev &k) { return pick(k.g_force, k.cap, k.dim == 2 ? 4 : 8, 4); }
+int nbr_group(const Dev &k) { return pick(k.g_nbr, k.cap, 8, k.dim == 2 ? 2 : 4); }
 int force_grid(const Dev &k) { return grid_for(k, force_group(k)); }
 // the most blocks any variant launches (fewest targets per block): sizes the
 // per-block drag partials

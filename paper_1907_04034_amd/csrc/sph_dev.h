@@ -127,10 +127,8 @@ struct StepAdj {
     DevLam next;  // adjoint of the state after the step (its row order)
     DevLam acc;   // accumulators of the sorted start state
     DevLam out;   // adjoint of the state before the step (its row order)
-    double *Lx, *Lu, *Lut, *Lp;  // adjoint of the values after the full update
     double *hut;                 // direct adjoint of the half-state ut
     double *jseed;               // adjoint of the stage-2 characteristic values
-    int32_t *inv;                // start-state row -> sorted row (-1: dropped)
     const int32_t *child;
     const uint8_t *events;
     const int64_t *n_pre;  // rows of the state before the step

@@ -53,16 +53,12 @@ void launch_finish_spawn(const Dev &k, const DevState &st, int32_t *nspawn, hipS
 
 // reverse of one step
 void launch_adj_prep(const int64_t *n_src, int64_t *n_dst, int32_t *nspawn, hipStream_t s);
-void launch_inverse_perm(const Dev &k, const int64_t *n_post, const int32_t *perm,
-                         int32_t *inv, hipStream_t s);
-void launch_adj_eos(const Dev &k, const DevState &m, const StepAdj &S, hipStream_t s);
-void launch_adj_full(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
-                     hipStream_t s);
+void launch_adj_end(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                    hipStream_t s);
 void launch_adj_half(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
                      hipStream_t s);
-void launch_adj_start(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
-                      hipStream_t s);
-void launch_adj_unbin(const Dev &k, const StepAdj &S, hipStream_t s);
+void launch_adj_finish(const Dev &k, const DevState &m, const DevState &pre,
+                       const int32_t *perm, const StepAdj &S, const DevAdj &A, hipStream_t s);
 void launch_profile_grad(const Dev &k, const int64_t *n, const DevLam &L, const int32_t *index,
                          int32_t ntheta, double *grad, hipStream_t s);
 

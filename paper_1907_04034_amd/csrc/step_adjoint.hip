@@ -13,16 +13,17 @@
 // force, the reverse returns the adjoint of S_n, for fixed discrete events
 // (neighbour sets, supported / unsupported boundary particles, gates,
 // transfers), which the forward recorded. The reverse recomputes the stage
-// values from S_n and runs, per row, gather-only kernels:
-//   eos    reverse of the end-of-step bookkeeping (children -> parents, ring
-//          push and mean, J -> previous-step values);
-//   full   reverse of the full update: weights on stage-2 rates, seeds on the
-//          stage-2 boundary values, direct position/velocity/pressure parts;
+// values from S_n and runs, per row:
+//   end    reverse of the end-of-step bookkeeping (children -> parents, ring
+//          push and mean, J -> previous-step values), then of the full
+//          update: weights on stage-2 rates, seeds on the stage-2 boundary
+//          values, direct position/velocity/pressure parts;
 //   (reverse of the stage-2 right-hand side)
 //   half   reverse of the half update: weights on stage-1 rates and seeds;
 //   (reverse of the stage-1 right-hand side, with the drag weight)
-//   start  sum of the start-state parts;
-//   unbin  back to the row order of S_n.
+//   finish sum of the start-state parts, written to the row of S_n that the
+//          bin moved (a permutation, so no two rows collide); rows of S_n the
+//          bin dropped get zero.
 #include "sph_launch.h"
 
 namespace sph {
@@ -36,26 +37,14 @@ __global__ void k_adj_prep(const int64_t *n_src, int64_t *n_dst, int32_t *nspawn
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_inv_fill(int64_t cap, int32_t *inv)
-{
-    const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q < cap) inv[q] = -1;
-}
-
-// inv[perm[r]] = r: the bin's permutation is injective, so no two rows write
-// the same entry
-__global__ void __launch_bounds__(kBlock) k_inv_scatter(int64_t cap, const int64_t *n_post,
-                                                        const int32_t *perm, int32_t *inv)
-{
-    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (r >= *n_post) return;
-    const int32_t q = perm[r];
-    if (q >= 0 && q < cap) inv[q] = int32_t(r);
-}
-
-// ------------------------------------------------------------ eos reverse
+// ------------------------------------------------------------ end of step
+// Reverse of the bookkeeping, then of the full update
+//   fluid:   u' = u + dt a2, ut' = u' + dt b2, x' = x + dt ut_H, p' = p + dt pdot2
+//   inlet:   x' = x + dt u_in (x only); u', ut', p' = stage-2 boundary values
+//   outlet:  x' = x + dt u_H (x only, u_H its stage-2 boundary value); same
+//   walls:   x' = x; u', p' = stage-2 boundary values
 template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_adj_eos(Dev k, DevState m, StepAdj S)
+__global__ void __launch_bounds__(kBlock) k_adj_end(Dev k, DevState m, StepAdj S, DevAdj A)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= *m.n) return;
@@ -130,59 +119,32 @@ __global__ void __launch_bounds__(kBlock) k_adj_eos(Dev k, DevState m, StepAdj S
 #pragma unroll
         for (int a = 0; a < 3; ++a) jp[a] = 0.0;
     }
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-        S.Lx[d * C + i] = Lx[d];
-        S.Lu[d * C + i] = Lu[d];
-        S.Lut[d * C + i] = Lut[d];
-        S.acc.uin[d * C + i] = uin[d];
-        S.jseed[d * C + i] = js[d];
-        S.acc.jprev[d * C + i] = jp[d];
-    }
-    S.Lp[i] = Lp;
-#pragma unroll
-    for (int q = 0; q < NR; ++q) S.acc.ring[q * C + i] = ring[q];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] = avg[c];
-}
-
-// ------------------------------------------------------------ full update
-// fluid:   u' = u + dt a2, ut' = u' + dt b2, x' = x + dt ut_H, p' = p + dt pdot2
-// inlet:   x' = x + dt u_in (x only); u', ut', p' = stage-2 boundary values
-// outlet:  x' = x + dt u_H (x only, u_H its stage-2 boundary value); same
-// walls:   x' = x; u', p' = stage-2 boundary values
-template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_adj_full(Dev k, DevState m, StepAdj S, DevAdj A)
-{
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= *m.n) return;
-    const int64_t C = k.cap;
-    const int t = m.type[i];
+    // full update
     const double dt = k.dt;
     double *useed = const_cast<double *>(A.useed), *pseed = const_cast<double *>(A.pseed);
-    double us[3] = {0, 0, 0}, ps = 0.0;
+    double us[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         const bool on = d < DIM;
-        const double Lx = on ? S.Lx[d * C + i] : 0.0;
-        const double Lu = on ? S.Lu[d * C + i] : 0.0;
-        const double Lut = on ? S.Lut[d * C + i] : 0.0;
-        S.acc.x[d * C + i] = Lx;
-        S.acc.ut[d * C + i] = 0.0;
         double au = 0.0, ab = 0.0, hut = 0.0, uacc = 0.0;
         if (t == SPH_FLUID) {
-            uacc = Lu + Lut;
+            uacc = Lu[d] + Lut[d];
             au = dt * uacc;
-            ab = dt * Lut;
-            hut = dt * Lx;
+            ab = dt * Lut[d];
+            hut = dt * Lx[d];
         } else if (t == SPH_INLET || t == SPH_OUTLET) {
-            us[d] = Lu + Lut;  // the boundary value is written to u and ut
-            if (d == 0 && t == SPH_INLET) S.acc.uin[i] += dt * Lx;
-            if (d == 0 && t == SPH_OUTLET) us[0] += dt * Lx;
+            us[d] = Lu[d] + Lut[d];  // the boundary value is written to u and ut
+            if (d == 0 && t == SPH_INLET) uin[0] += dt * Lx[0];
+            if (d == 0 && t == SPH_OUTLET) us[0] += dt * Lx[0];
         } else {
-            us[d] = Lu;
+            us[d] = Lu[d];
         }
+        S.acc.x[d * C + i] = Lx[d];
         S.acc.u[d * C + i] = uacc;
+        S.acc.ut[d * C + i] = 0.0;
+        S.acc.uin[d * C + i] = uin[d];
+        S.acc.jprev[d * C + i] = jp[d];
+        S.jseed[d * C + i] = js[d];
         S.hut[d * C + i] = hut;
         if (on) {
             st<T>(const_cast<void *>(A.abar), d * C + i, T(au));
@@ -190,17 +152,14 @@ __global__ void __launch_bounds__(kBlock) k_adj_full(Dev k, DevState m, StepAdj 
         }
         useed[d * C + i] = us[d];
     }
-    const double Lp = S.Lp[i];
-    double pd = 0.0, pacc = 0.0;
-    if (t == SPH_FLUID) {
-        pd = dt * Lp;
-        pacc = Lp;
-    } else {
-        ps = Lp;
-    }
-    st<T>(const_cast<void *>(A.pdbar), i, T(pd));
-    pseed[i] = ps;
-    S.acc.p[i] = pacc;
+    const bool fl = t == SPH_FLUID;
+    st<T>(const_cast<void *>(A.pdbar), i, T(fl ? dt * Lp : 0.0));
+    pseed[i] = fl ? 0.0 : Lp;
+    S.acc.p[i] = fl ? Lp : 0.0;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) S.acc.ring[q * C + i] = ring[q];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] = avg[c];
 }
 
 // ------------------------------------------------------------ half update
@@ -253,61 +212,51 @@ __global__ void __launch_bounds__(kBlock) k_adj_half(Dev k, DevState m, StepAdj 
     pseed[i] = 0.0;
 }
 
-// ------------------------------------------------------------ start state
-// Boundary rows' u, ut, p of the start state are overwritten by the stage-1
-// boundary values before any use, so only fluid rows take those parts.
-template <int DIM, typename T>
-__global__ void __launch_bounds__(kBlock) k_adj_start(Dev k, DevState m, StepAdj S, DevAdj A)
-{
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= *m.n) return;
-    constexpr int NC = DIM + 1;
-    const int64_t C = k.cap;
-    const bool fl = m.type[i] == SPH_FLUID;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        S.acc.x[d * C + i] += A.xbar[d * C + i];
-        S.acc.uin[d * C + i] += A.uinbar[d * C + i];
-        if (fl) {
-            S.acc.u[d * C + i] += A.ubar[d * C + i];
-            S.acc.ut[d * C + i] += A.utbar[d * C + i];
-        }
-    }
-    if (fl) S.acc.p[i] += A.pbar[i];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] += A.avgbar[c * C + i];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) S.acc.jprev[a * C + i] += A.jprevbar[a * C + i];
-}
-
-// ------------------------------------------------------------ unbin
-// Adjoint of S_n: row q takes the accumulators of its sorted row, or zero if
-// the bin dropped it (a deleted particle has no influence).
+// ------------------------------------------------------------ finish
+// Sum of the start-state parts of sorted row r, written to row perm[r] of
+// S_n; rows of S_n the bin dropped (deleted particles) get zero. Boundary
+// rows' u, ut, p of the start state are overwritten by the stage-1 boundary
+// values before any use, so only fluid rows take those parts.
 template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_adj_unbin(Dev k, StepAdj S)
+__global__ void __launch_bounds__(kBlock) k_adj_finish(Dev k, DevState m, DevState pre,
+                                                       const int32_t *perm, StepAdj S, DevAdj A)
 {
     const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (q >= *S.n_pre) return;
+    const int64_t npre = *S.n_pre, npost = *m.n;
     constexpr int NC = DIM + 1, NR = kNavg * NC;
     const int64_t C = k.cap;
-    const int32_t r = S.inv[q];
-    const bool live = r >= 0 && r < C;
-    const DevLam &A = S.acc;
     const DevLam &O = S.out;
+    if (q < npre && pre.type[q] == SPH_DEAD) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            O.x[d * C + q] = O.u[d * C + q] = O.ut[d * C + q] = O.uin[d * C + q] =
+                O.jprev[d * C + q] = 0.0;
+        O.p[q] = 0.0;
+#pragma unroll
+        for (int s = 0; s < NR; ++s) O.ring[s * C + q] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) O.avg[c * C + q] = 0.0;
+    }
+    if (q >= npost) return;
+    const int64_t r = q;  // sorted row
+    const int32_t dst = perm[r];
+    if (dst < 0 || dst >= npre) return;
+    const bool fl = m.type[r] == SPH_FLUID;
+    const DevLam &Ac = S.acc;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const bool on = live && d < DIM;
-        O.x[d * C + q] = on ? A.x[d * C + r] : 0.0;
-        O.u[d * C + q] = on ? A.u[d * C + r] : 0.0;
-        O.ut[d * C + q] = on ? A.ut[d * C + r] : 0.0;
-        O.uin[d * C + q] = on ? A.uin[d * C + r] : 0.0;
-        O.jprev[d * C + q] = live ? A.jprev[d * C + r] : 0.0;
+        const bool on = d < DIM;
+        O.x[d * C + dst] = on ? Ac.x[d * C + r] + A.xbar[d * C + r] : 0.0;
+        O.u[d * C + dst] = on ? Ac.u[d * C + r] + (fl ? A.ubar[d * C + r] : 0.0) : 0.0;
+        O.ut[d * C + dst] = on ? Ac.ut[d * C + r] + (fl ? A.utbar[d * C + r] : 0.0) : 0.0;
+        O.uin[d * C + dst] = on ? Ac.uin[d * C + r] + A.uinbar[d * C + r] : 0.0;
+        O.jprev[d * C + dst] = Ac.jprev[d * C + r] + A.jprevbar[d * C + r];
     }
-    O.p[q] = live ? A.p[r] : 0.0;
+    O.p[dst] = Ac.p[r] + (fl ? A.pbar[r] : 0.0);
 #pragma unroll
-    for (int s = 0; s < NR; ++s) O.ring[s * C + q] = live ? A.ring[s * C + r] : 0.0;
+    for (int s = 0; s < NR; ++s) O.ring[s * C + dst] = Ac.ring[s * C + r];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) O.avg[c * C + q] = live ? A.avg[c * C + r] : 0.0;
+    for (int c = 0; c < NC; ++c) O.avg[c * C + dst] = Ac.avg[c * C + r] + A.avgbar[c * C + r];
 }
 
 // ------------------------------------------------------------ inlet profile
@@ -356,23 +305,10 @@ void launch_adj_prep(const int64_t *n_src, int64_t *n_dst, int32_t *nspawn, hipS
     hipLaunchKernelGGL(k_adj_prep, dim3(1), dim3(64), 0, s, n_src, n_dst, nspawn);
 }
 
-void launch_inverse_perm(const Dev &k, const int64_t *n_post, const int32_t *perm,
-                         int32_t *inv, hipStream_t s)
+void launch_adj_end(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
+                    hipStream_t s)
 {
-    const dim3 g(nblocks(k.cap)), b(kBlock);
-    hipLaunchKernelGGL(k_inv_fill, g, b, 0, s, k.cap, inv);
-    hipLaunchKernelGGL(k_inv_scatter, g, b, 0, s, k.cap, n_post, perm, inv);
-}
-
-void launch_adj_eos(const Dev &k, const DevState &m, const StepAdj &S, hipStream_t s)
-{
-    SPH_STEP_DISPATCH(k_adj_eos, k, m, S);
-}
-
-void launch_adj_full(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
-                     hipStream_t s)
-{
-    SPH_STEP_DISPATCH(k_adj_full, k, m, S, A);
+    SPH_STEP_DISPATCH(k_adj_end, k, m, S, A);
 }
 
 void launch_adj_half(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
@@ -381,17 +317,12 @@ void launch_adj_half(const Dev &k, const DevState &m, const StepAdj &S, const De
     SPH_STEP_DISPATCH(k_adj_half, k, m, S, A);
 }
 
-void launch_adj_start(const Dev &k, const DevState &m, const StepAdj &S, const DevAdj &A,
-                      hipStream_t s)
-{
-    SPH_STEP_DISPATCH(k_adj_start, k, m, S, A);
-}
-
-void launch_adj_unbin(const Dev &k, const StepAdj &S, hipStream_t s)
+void launch_adj_finish(const Dev &k, const DevState &m, const DevState &pre,
+                       const int32_t *perm, const StepAdj &S, const DevAdj &A, hipStream_t s)
 {
     const dim3 g(nblocks(k.cap)), b(kBlock);
-    if (k.dim == 2) hipLaunchKernelGGL(k_adj_unbin<2>, g, b, 0, s, k, S);
-    else hipLaunchKernelGGL(k_adj_unbin<3>, g, b, 0, s, k, S);
+    if (k.dim == 2) hipLaunchKernelGGL(k_adj_finish<2>, g, b, 0, s, k, m, pre, perm, S, A);
+    else hipLaunchKernelGGL(k_adj_finish<3>, g, b, 0, s, k, m, pre, perm, S, A);
 }
 
 void launch_profile_grad(const Dev &k, const int64_t *n, const DevLam &L, const int32_t *index,

@@ -41,7 +41,7 @@ def test_step_adjoint_scratch_size_and_validation():
     q = B.make_params(prm)
     out = C.c_size_t(0)
     assert B.lib().sph_step_adjoint_scratch_size(C.byref(q), 1000, C.byref(out)) == 0
-    assert out.value == 102 * 8 * 1000
+    assert out.value == 91 * 8 * 1000
     st = B.SphState()
     st.cap, st.dim, st.prec = 100, 2, 0
     lam = B.SphStateAdjoint()
