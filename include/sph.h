@@ -304,6 +304,20 @@ int sph_inlet_profile_grad(const sph_params *prm, const sph_state *st,
                            const sph_state_adjoint *lam, const int32_t *index, int32_t ntheta,
                            double *grad, void *stream);
 
+/* Reverse of the boundary values alone (sph_outlet_extrapolate: walls'
+ * Shepard p and ghost velocity, outlet and inlet characteristic values
+ * eq:characteristic-vars, eq:shepard, eq:average_old, eq:acou) through the
+ * summation density the extrapolation weights use: the gradient of
+ *     L = sum over non-fluid rows (pseed p + useed . u) + sum over inlet/outlet
+ *         rows jseed . J
+ * with respect to the fluid's x, u, p, the inlet velocities, the averages and
+ * the previous-step J. Arguments as sph_rhs_adjoint; abar, bbar, pdbar and
+ * fbar are ignored. Preconditions: sph_neighbors (with density) and
+ * sph_outlet_extrapolate have run on the same state, table and buffers. */
+int sph_outlet_extrapolate_adjoint(const sph_params *prm, const sph_state *st,
+                                   const sph_nlist *nl, const sph_derived *fwd,
+                                   sph_adjoint *adj, void *ws, size_t ws_bytes, void *stream);
+
 /* Synchronises `stream`, returns the accumulated device error bits in *bits
  * and clears them. */
 int sph_poll_error(void *ws, size_t ws_bytes, uint32_t *bits, void *stream);

@@ -22,7 +22,7 @@ ERR_BITS = {1: "NBR_OVERFLOW", 2: "CAPACITY", 4: "NONFINITE", 8: "SKIN", 16: "ES
 
 EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors",
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
-            "sph_rhs_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
+            "sph_rhs_adjoint", "sph_outlet_extrapolate_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
             "sph_step_adjoint", "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count",
             "sph_last_error"]
 EV_PUSH, EV_TO_OUTLET, EV_DELETE, EV_SPAWN = 1, 2, 4, 8
@@ -97,6 +97,7 @@ def lib():
         L.sph_force.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_step.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, sz, _P]
         L.sph_rhs_adjoint.argtypes = [SP, ST, NL, DE, C.POINTER(SphAdjoint), _P, sz, _P]
+        L.sph_outlet_extrapolate_adjoint.argtypes = L.sph_rhs_adjoint.argtypes
         LA = C.POINTER(SphStateAdjoint)
         L.sph_step_record.argtypes = [SP, ST, ST, NL, DE, _P, _P, _P, _P, sz, _P]
         L.sph_step_adjoint_scratch_size.argtypes = [SP, C.c_int64, C.POINTER(C.c_size_t)]
@@ -325,8 +326,13 @@ class Simulation:
         _check(lib().sph_live_count(C.byref(self.st), C.byref(n), self.stream), "sph_live_count")
         return n.value
 
+    def outlet_extrapolate_adjoint(self, pseed=None, useed=None, jseed=None):
+        """Reverse of the boundary values alone (sph_outlet_extrapolate_adjoint); same
+        seeds and outputs as rhs_adjoint."""
+        return self.rhs_adjoint(pseed=pseed, useed=useed, jseed=jseed, boundary_only=True)
+
     def rhs_adjoint(self, abar=None, bbar=None, pdbar=None, fbar=(0.0, 0.0, 0.0), pseed=None,
-                    useed=None, jseed=None):
+                    useed=None, jseed=None, boundary_only=False):
         """Gradient of L = sum_fluid(abar.a + bbar.b + pdbar*pdot) + fbar.drag
         + sum_nonfluid(pseed*p + useed.u) + sum_inlet/outlet(jseed.J) for the current
         stage (sph_neighbors and sph_rhs must have run). Weights are host arrays in
@@ -353,7 +359,7 @@ class Simulation:
                 host = np.ascontiguousarray(w.T if comps > 1 else w)
                 view[..., :n].copy_(t.from_numpy(host).to(view.dtype))
         st = self._adj_struct(fbar)
-        self.rhs_adjoint_launch(st)
+        self.rhs_adjoint_launch(st, boundary_only)
         out = {}
         for k in ("xbar", "ubar", "utbar", "uinbar", "jprevbar"):
             out[k] = A[k].view(3, cap)[:, :n].cpu().numpy().T.copy()
@@ -375,13 +381,15 @@ class Simulation:
             setattr(st, k, A[k].data_ptr())
         return st
 
-    def rhs_adjoint_launch(self, st):
-        """Enqueue sph_rhs_adjoint with a prepared argument block (weights already on
-        the device); nothing is copied back."""
+    def rhs_adjoint_launch(self, st, boundary_only=False):
+        """Enqueue sph_rhs_adjoint (or the boundary-values reverse alone) with a
+        prepared argument block (weights already on the device); nothing is copied
+        back."""
         ws, nb = self._ws()
-        _check(lib().sph_rhs_adjoint(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
-                                     C.byref(self.out), C.byref(st), ws, nb, self.stream),
-               "sph_rhs_adjoint")
+        fn = lib().sph_outlet_extrapolate_adjoint if boundary_only else lib().sph_rhs_adjoint
+        name = "sph_outlet_extrapolate_adjoint" if boundary_only else "sph_rhs_adjoint"
+        _check(fn(C.byref(self.q), C.byref(self.st), C.byref(self.nl), C.byref(self.out),
+                  C.byref(st), ws, nb, self.stream), name)
 
     # ------------------------------------------------------------ results
     def state(self):

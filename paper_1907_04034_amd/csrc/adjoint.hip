@@ -261,7 +261,11 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
     sep.load_i(k, R, off, cpos, i);
     EpBar<T> Kb;
     T Pb = T(0), xb[3] = {0, 0, 0};
-    const int cnt = nl.count[i];
+    // without weights on the pair outputs (the boundary-values reverse alone)
+    // only the seeds pass through
+    const bool weighted = A.abar || A.bbar || A.pdbar || A.fbar[0] != 0.0 || A.fbar[1] != 0.0 ||
+                          A.fbar[2] != 0.0;
+    const int cnt = weighted ? nl.count[i] : 0;
     for (int q = lane; q < cnt; q += G) {
         const int32_t j = nl.nbr[i * nl.maxnb + q];
         if (bad_index(j, n)) {

@@ -732,9 +732,29 @@ int sph_inlet_profile_grad(const sph_params *prm, const sph_state *st,
     return check_hip("sph_inlet_profile_grad");
 }
 
+static int rhs_adjoint_impl(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+                            const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
+                            void *stream, bool boundary_only, const char *what);
+
 int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
                     const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
                     void *stream)
+{
+    return rhs_adjoint_impl(prm, st, nl, fwd, adj, ws, ws_bytes, stream, false,
+                            "sph_rhs_adjoint");
+}
+
+int sph_outlet_extrapolate_adjoint(const sph_params *prm, const sph_state *st,
+                                   const sph_nlist *nl, const sph_derived *fwd,
+                                   sph_adjoint *adj, void *ws, size_t ws_bytes, void *stream)
+{
+    return rhs_adjoint_impl(prm, st, nl, fwd, adj, ws, ws_bytes, stream, true,
+                            "sph_outlet_extrapolate_adjoint");
+}
+
+static int rhs_adjoint_impl(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
+                            const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
+                            void *stream, bool boundary_only, const char *what)
 {
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
@@ -743,14 +763,14 @@ int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist 
         !adj->avgbar || !adj->scratch)
         return fail(SPH_EINVAL, "adjoint buffers have a NULL array");
     DevAdj A;
-    A.abar = adj->abar;
-    A.bbar = adj->bbar;
-    A.pdbar = adj->pdbar;
+    A.abar = boundary_only ? nullptr : adj->abar;
+    A.bbar = boundary_only ? nullptr : adj->bbar;
+    A.pdbar = boundary_only ? nullptr : adj->pdbar;
     A.pseed = adj->pseed;
     A.useed = adj->useed;
     A.jseed = adj->jseed;
     A.jprevbar = adj->jprevbar;
-    for (int d = 0; d < 3; ++d) A.fbar[d] = adj->fbar[d];
+    for (int d = 0; d < 3; ++d) A.fbar[d] = boundary_only ? 0.0 : adj->fbar[d];
     A.xbar = adj->xbar;
     A.ubar = adj->ubar;
     A.utbar = adj->utbar;
@@ -766,7 +786,7 @@ int sph_rhs_adjoint(const sph_params *prm, const sph_state *st, const sph_nlist 
     A.jg = adj->scratch + 7 * C;       // [3][cap]
     launch_rhs_adjoint(c.k, dev_state(st), fields_of(st), dev_nlist(nl), dev_derived(fwd), A,
                        c.off(), at<uint32_t>(c.ws, c.w.cpos_s), c.err(), c.s);
-    return check_hip("sph_rhs_adjoint");
+    return check_hip(what);
 }
 
 int sph_poll_error(void *ws, size_t ws_bytes, uint32_t *bits, void *stream)

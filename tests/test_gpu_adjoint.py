@@ -206,3 +206,48 @@ def test_rhs_adjoint_seeded(name, prec, tol):
     print(f"  jprev part: fd={fd_j:.12e} adjoint={adj_j:.12e}", flush=True)
     assert abs(fd_j) > 0.0, "J_prev direction reaches no output"
     assert abs(adj_j - fd_j) <= tol * max(abs(fd_j), 1e-3 * abs(fd)), (fd_j, adj_j)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 2e-7), ("fp32", 2e-4)])
+@pytest.mark.parametrize("name", ["C2-small", "C3-small", "C4-small", "C5-small"])
+def test_outlet_extrapolate_adjoint(name, prec, tol):
+    """The boundary-values reverse alone (sph_outlet_extrapolate_adjoint): seeds on
+    p, u of non-fluid rows and on J of inlet/outlet rows only."""
+    print(f"boundary adjoint {name} {prec}", flush=True)
+    rng = np.random.default_rng(29)
+    prm, s = _case(name, 6, types=(I.FLUID, I.INLET, I.OUTLET))
+    n, D = len(s["p"]), prm["dim"]
+    t = s["type"]
+    nf = t != I.FLUID
+    io = (t == I.INLET) | (t == I.OUTLET)
+    w = dict(a=np.zeros((n, 3)), b=np.zeros((n, 3)), pdot=np.zeros(n), fbar=np.zeros(3))
+    w["pseed"] = np.where(nf, rng.standard_normal(n), 0.0)
+    w["useed"] = np.zeros((n, 3))
+    w["useed"][nf, :D] = rng.standard_normal((nf.sum(), D))
+    w["jseed"] = np.zeros((n, 3))
+    w["jseed"][io] = rng.standard_normal((io.sum(), 3)) * 0.1
+    d = _direction(prm, s, rng)
+    d["ut"][:] = 0.0
+    d["jprev"] = np.zeros((n, 3))
+    d["jprev"][io] = rng.standard_normal((io.sum(), 3))
+    sim = B().Simulation(prm, s, prec=prec)
+    sim.bin()
+    sim.neighbors()
+    sim.outlet_extrapolate()
+    gs = sim.state()
+    idx = {int(v): k for k, v in enumerate(s["id"])}
+    perm = np.array([idx[int(v)] for v in gs["id"]])
+    g = sim.outlet_extrapolate_adjoint(pseed=w["pseed"][perm], useed=w["useed"][perm],
+                                       jseed=w["jseed"][perm])
+    assert sim.poll_error() == 0
+    adj = 0.0
+    for key, gk in (("x", "xbar"), ("u", "ubar"), ("uin", "uinbar")):
+        adj += (d[key][perm][:, :D] * g[gk][:, :D]).sum()
+    adj += (d["p"][perm] * g["pbar"]).sum() + (d["jprev"][perm] * g["jprevbar"]).sum()
+    adj += (d["avg"][perm][:, :D] * g["avgbar"][:, :D]).sum() + (d["avg"][perm][:, 3] * g["avgbar"][:, 3]).sum()
+    e = 1e-6
+    Ls = {k: _seeded_L(prm, _perturbed(s, d, k * e), w) for k in (-2, -1, 1, 2)}
+    fd = (8 * (Ls[1] - Ls[-1]) - (Ls[2] - Ls[-2])) / (12 * e)
+    rel = abs(adj - fd) / max(abs(fd), 1e-300)
+    print(f"  fd={fd:.12e} adjoint={adj:.12e} rel={rel:.2e}", flush=True)
+    assert rel < tol, (fd, adj, rel)

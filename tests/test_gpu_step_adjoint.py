@@ -261,6 +261,12 @@ def test_c4_drag_gradient_vs_fd():
     J, _ = prob.value(th)
     g = prob.gradient().cpu().numpy()
     print(f"C4 J={J:.12e} |g|_inf={np.abs(g).max():.6e} sum g={g.sum():.6e}", flush=True)
+    # the FP32 form (FP32 forward and pair reverses), checked against the same
+    # FP64 differences
+    p32 = A().InletProfileDrag(prm, s, nsteps, segment=50, prec="fp32")
+    J32, _ = p32.value(th)
+    g32 = p32.gradient().cpu().numpy()
+    del p32
     cap = prob.sim.cap
     gen = torch.Generator().manual_seed(5)
     hw = [torch.randint(1, 1 << 20, (cap,), generator=gen, dtype=torch.int64).cuda()
@@ -268,7 +274,7 @@ def test_c4_drag_gradient_vs_fd():
     rng = np.random.default_rng(3)
     dirs = [("entry", k, np.eye(prob.ntheta)[k]) for k in (0, 21, 50, 77, 99)]
     dirs.append(("random", -1, rng.standard_normal(prob.ntheta)))
-    errs, scale = [], 0.0
+    errs, errs32, scale = [], [], 0.0
     for kind, k, v in dirs:
         ad = float(g @ v)
         clean = []
@@ -284,10 +290,13 @@ def test_c4_drag_gradient_vs_fd():
         if len(clean) == 2:  # no jump inside either window
             assert abs(clean[0] - clean[1]) <= 1e-5 * abs(clean[0]), clean
         errs.append(abs(ad - clean[0]))
+        errs32.append(abs(float(g32 @ v) - clean[0]))
         scale = max(scale, abs(clean[0]))
-    err = max(errs) / scale
-    print(f"  max |g_adj - g_fd| / max |g_fd| = {err:.2e}", flush=True)
+    err, err32 = max(errs) / scale, max(errs32) / scale
+    print(f"  max |g_adj - g_fd| / max |g_fd| = {err:.2e} (FP64), {err32:.2e} (FP32; "
+          f"J32 - J64 = {J32 - J:.2e})", flush=True)
     assert err <= 1e-4
+    assert err32 <= 1e-4
 
 
 def test_small_cylinder_drag_gradient_vs_oracle():
