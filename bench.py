@@ -239,6 +239,9 @@ def main():
     ap.add_argument("--form", default="forward", choices=["forward", "adjoint"],
                     help="adjoint: gradient of the time-averaged drag (default config C4)")
     ap.add_argument("--segment", type=int, default=50, help="adjoint checkpoint interval")
+    ap.add_argument("--sort-every-step", action="store_true",
+                    help="sort by cell at every step instead of keeping the cell order "
+                         "while the skin allows")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1"}))
@@ -259,7 +262,10 @@ def main():
 
     torch.cuda.set_device(0)
     prm, s = I.config(args.config)
-    log(f"bench: {prm['name']} n={len(s['p'])} prec={args.precision}")
+    if not args.sort_every_step:
+        prm["flags"] |= I.FLAG_REUSE_BINS
+    log(f"bench: {prm['name']} n={len(s['p'])} prec={args.precision} "
+        f"reuse_bins={not args.sort_every_step}")
     sim = B.Simulation(prm, s, prec=args.precision)
     stream = torch.cuda.current_stream()
 
@@ -339,7 +345,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "config": args.config,
                    "particles": int(len(s["p"])), "pairs_per_rhs": p_rhs,
-                   "rhs_per_step": 2, "precision": args.precision},
+                   "rhs_per_step": 2, "precision": args.precision,
+                   "cell_order": "sorted every step" if args.sort_every_step
+                   else "kept while the cell skin allows"},
         "roofline": {"bound": "hbm", "kernel": "k_force", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "algorithmic_bytes_per_launch": fbytes,

@@ -54,8 +54,12 @@ enum {
     SPH_DEAD = 255
 };
 
-/* sph_params.flags */
-enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4 };
+/* sph_params.flags. SPH_FLAG_REUSE_BINS lets sph_step keep the cell order of
+ * its last bin while every particle stays within the cell skin of its binned
+ * position and no particle was transferred, deleted or re-spawned (the
+ * neighbour sets are the same; sums run in a different row order). Steps
+ * recorded for the reverse pass always bin. */
+enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8 };
 
 /* device error-word bits */
 enum {

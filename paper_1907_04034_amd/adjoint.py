@@ -128,6 +128,9 @@ class DragAdjoint:
     """
 
     def __init__(self, sim, nsteps, segment=50):
+        # the replays sort at every step; the checkpointed forward must match
+        # them row for row, so it does not keep cell orders across steps
+        sim.q.flags &= ~Bd.FLAG_REUSE_BINS
         self.sim, self.nsteps = sim, int(nsteps)
         self.segment = max(1, min(int(segment), self.nsteps))
         self.tape = StepTape(sim, self.segment)

@@ -26,6 +26,7 @@ EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors
             "sph_step_adjoint", "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count",
             "sph_last_error"]
 EV_PUSH, EV_TO_OUTLET, EV_DELETE, EV_SPAWN = 1, 2, 4, 8
+FLAG_REUSE_BINS = 8
 
 
 class SphParams(C.Structure):

@@ -16,9 +16,10 @@ namespace sph {
 // the positions that axis occupies in the interleaved key. Bit b of every axis
 // is placed before bit b + 1 of any axis; axes with fewer bits drop out once
 // exhausted, so the key space is exactly the product of the padded extents.
-__global__ void k_spread(Dev k, uint32_t *spread)
+__global__ void k_spread(Dev k, uint32_t *spread, int32_t *rebin)
 {
     int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t == 0) *rebin = 1;
     if (t >= int64_t(3) * kSpreadStride) return;
     int axis = int(t / kSpreadStride);
     int c = int(t % kSpreadStride);
@@ -44,6 +45,13 @@ constexpr int kTileSlots = 8;  // sub-counters per tile total (spreads the atomi
 int64_t scan_tiles(int64_t n) { return (n + kScanTile - 1) / kScanTile; }
 int64_t tilesum_len(int64_t n) { return scan_tiles(n) * kTileSlots; }
 
+// With bin reuse, a bin that finds no request to sort keeps the current order
+// (every kernel of the bin checks the same word, written before the bin).
+__device__ inline bool bin_skips(const Dev &k, const int32_t *rebin)
+{
+    return k.reuse && *rebin == 0;
+}
+
 // live rows this bin sees: the last count plus rows re-spawned since
 __device__ inline int64_t rows_to_bin(const Dev &k, const DevState &s, const int32_t *nspawn)
 {
@@ -55,8 +63,10 @@ template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_keys(Dev k, DevState s, const int32_t *nspawn,
                                                  const uint32_t *spread, uint32_t *keys,
                                                  uint32_t *cpos, int32_t *counts,
-                                                 int32_t *tilesum, int32_t *bcount, uint32_t *err)
+                                                 int32_t *tilesum, int32_t *bcount,
+                                                 const int32_t *rebin, uint32_t *err)
 {
+    if (bin_skips(k, rebin)) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     if (i == 0) *bcount = 0;
@@ -104,9 +114,11 @@ __global__ void __launch_bounds__(kBlock) k_keys(Dev k, DevState s, const int32_
 // cell_start = exclusive scan of counts (n entries); every tile adds the sum
 // of the tile totals before it, so one launch suffices. Consumed counts are
 // zeroed for the next bin.
-__global__ void __launch_bounds__(kBlock) k_scan(int32_t *counts, int32_t *cell_start, int64_t n,
-                                                 const int32_t *tilesum)
+__global__ void __launch_bounds__(kBlock) k_scan(Dev k, int32_t *counts, int32_t *cell_start,
+                                                 int64_t n, const int32_t *tilesum,
+                                                 const int32_t *rebin)
 {
+    if (bin_skips(k, rebin)) return;
     __shared__ int32_t lds[kBlock];
     int32_t pre = 0;
     for (int64_t t = threadIdx.x; t < int64_t(blockIdx.x) * kTileSlots; t += kBlock) pre += tilesum[t];
@@ -131,8 +143,10 @@ __global__ void __launch_bounds__(kBlock) k_scan(int32_t *counts, int32_t *cell_
 }
 
 __global__ void k_scatter(Dev k, DevState s, const int32_t *nspawn, const uint32_t *keys,
-                          const int32_t *cell_start, int32_t *cursor, int32_t *tmp)
+                          const int32_t *cell_start, int32_t *cursor, int32_t *tmp,
+                          const int32_t *rebin)
 {
+    if (bin_skips(k, rebin)) return;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= rows_to_bin(k, s, nspawn)) return;
     const uint32_t key = keys[i];
@@ -156,8 +170,10 @@ __device__ inline void cswap(int64_t &ka, int32_t &va, int64_t &kb, int32_t &vb)
 }
 
 __global__ void k_cellsort(Dev k, DevState s, const int32_t *cell_start, int32_t *tmp,
-                           int32_t *cursor, int32_t *tilesum, int64_t ntiles)
+                           int32_t *cursor, int32_t *tilesum, int64_t ntiles,
+                           const int32_t *rebin)
 {
+    if (bin_skips(k, rebin)) return;
     const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c < ntiles * kTileSlots) tilesum[c] = 0;
     if (c > int64_t(k.nkeys)) return;
@@ -196,21 +212,25 @@ __global__ void k_cellsort(Dev k, DevState s, const int32_t *cell_start, int32_t
 }
 
 // Row r of the sorted state is row tmp[r] of the old one. Non-fluid rows are
-// listed for the boundary pass; the live count is published and the re-spawn
-// counter cleared.
+// listed for the boundary pass, the positions kept as the reference of the
+// cell skin; the live count is published and the re-spawn counter cleared.
+// A bin that keeps the order copies row for row.
 template <int DIM, typename T>
 __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
                          const int32_t *cell_start, const uint32_t *cpos_in, uint32_t *cpos_out,
-                         int32_t *blist, int32_t *bcount, int32_t *nspawn)
+                         int32_t *blist, int32_t *bcount, int32_t *nspawn,
+                         const int32_t *rebin, double *xbin)
 {
+    // a kept order copies row for row (the caller exchanges the two buffers)
+    const bool sorted = !bin_skips(k, rebin);
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t n = cell_start[k.nkeys];
+    const int64_t n = sorted ? int64_t(cell_start[k.nkeys]) : *a.n;  // (kept: rewritten as is)
     if (r == 0 && blockIdx.y == 0) {
         *a.n = n;
         *nspawn = 0;
     }
     if (r >= n) return;
-    const int64_t i = tmp[r];
+    const int64_t i = sorted ? int64_t(tmp[r]) : r;
     const int64_t C = k.cap;
     constexpr int NR = kNavg * (DIM + 1);  // ring words, split over slices 1 and 2
     switch (blockIdx.y) {
@@ -228,8 +248,12 @@ __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
         const uint8_t t = a.type[i];
         b.type[r] = t;
         b.id[r] = a.id[i];
-        cpos_out[r] = cpos_in[i];
-        if (t != SPH_FLUID) blist[atomicAdd(bcount, 1)] = int32_t(r);
+        if (sorted) {
+            cpos_out[r] = cpos_in[i];
+            if (t != SPH_FLUID) blist[atomicAdd(bcount, 1)] = int32_t(r);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xbin[d * C + r] = a.x[d * C + i];
+        }
         break;
     }
     case 1:
@@ -250,10 +274,10 @@ __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
 }
 
 // ------------------------------------------------------------------ launchers
-void launch_spread(const Dev &k, uint32_t *spread, hipStream_t s)
+void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s)
 {
     hipLaunchKernelGGL(k_spread, dim3(nblocks(3 * int64_t(kSpreadStride))), dim3(kBlock), 0, s,
-                       k, spread);
+                       k, spread, rebin);
 }
 
 void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBufs &w,
@@ -264,31 +288,31 @@ void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBuf
     const int64_t ntiles = scan_tiles(nscan);
     if (k.dim == 2)
         hipLaunchKernelGGL(k_keys<2>, g, blk, 0, s, k, a, w.nspawn, w.spread, w.keys, w.cpos,
-                           w.counts, w.tilesum, w.bcount, err);
+                           w.counts, w.tilesum, w.bcount, w.rebin, err);
     else
         hipLaunchKernelGGL(k_keys<3>, g, blk, 0, s, k, a, w.nspawn, w.spread, w.keys, w.cpos,
-                           w.counts, w.tilesum, w.bcount, err);
-    hipLaunchKernelGGL(k_scan, dim3(ntiles), blk, 0, s, w.counts, w.cell_start, nscan,
-                       w.tilesum);
+                           w.counts, w.tilesum, w.bcount, w.rebin, err);
+    hipLaunchKernelGGL(k_scan, dim3(ntiles), blk, 0, s, k, w.counts, w.cell_start, nscan,
+                       w.tilesum, w.rebin);
     hipLaunchKernelGGL(k_scatter, g, blk, 0, s, k, a, w.nspawn, w.keys, w.cell_start, w.cursor,
-                       w.tmp);
+                       w.tmp, w.rebin);
     const int64_t ncs = (int64_t(k.nkeys) + 1) > ntiles * kTileSlots ? int64_t(k.nkeys) + 1
                                                                      : ntiles * kTileSlots;
     hipLaunchKernelGGL(k_cellsort, dim3(nblocks(ncs)), blk, 0, s, k, a, w.cell_start, w.tmp,
-                       w.cursor, w.tilesum, ntiles);
+                       w.cursor, w.tilesum, ntiles, w.rebin);
     const dim3 gg(nblocks(k.cap), 4);
     if (k.dim == 2 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_gather<2, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
     else if (k.dim == 3 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_gather<3, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
     else if (k.dim == 2)
         hipLaunchKernelGGL((k_gather<2, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
     else
         hipLaunchKernelGGL((k_gather<3, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
 }
 
 }  // namespace sph

@@ -62,6 +62,7 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     std::memset(k, 0, sizeof *k);
     k->dim = p->dim;
     k->flags = p->flags;
+    k->reuse = (p->flags & SPH_FLAG_REUSE_BINS) ? 1 : 0;
     k->g_force = p->group_force;
     k->g_nbr = p->group_nbr;
     k->prec = prec;
@@ -178,6 +179,8 @@ static WsLayout layout(const Dev &k)
     w.dragpart = take(sizeof(double) * 3 * size_t(force_grid_max(k)));
     w.sflag = take(C);
     w.stile = take(sizeof(int32_t) * size_t(nblocks(k.cap)));
+    w.rebin = take(sizeof(int32_t));
+    w.xbin = take(sizeof(double) * 3 * C);
     w.total = off;
     return w;
 }
@@ -282,6 +285,8 @@ struct Ctx {
         b.keys = at<uint32_t>(ws, w.keys);
         b.cpos = at<uint32_t>(ws, w.cpos);
         b.cpos_s = at<uint32_t>(ws, w.cpos_s);
+        b.rebin = at<int32_t>(ws, w.rebin);
+        b.xbin = at<double>(ws, w.xbin);
         return b;
     }
     Fields half() const
@@ -343,11 +348,12 @@ static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
 }
 
 static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
-                       const sph_derived *o, int dens)
+                       const sph_derived *o, int dens, bool clear_rebin = false)
 {
     launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? dev_derived(o) : DevDerived{},
                    dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
-                   at<uint32_t>(c.ws, c.w.cpos_s), c.off(), c.err(), c.s);
+                   at<uint32_t>(c.ws, c.w.cpos_s), c.off(),
+                   clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, c.err(), c.s);
 }
 
 static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
@@ -363,7 +369,8 @@ static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields 
 {
     const int want = drag || hist;
     launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), dev_derived(o), c.off(),
-                 at<uint32_t>(c.ws, c.w.cpos_s), mode, want, c.dragpart(), c.err(), c.s);
+                 at<uint32_t>(c.ws, c.w.cpos_s), mode, want, c.dragpart(),
+                 at<double>(c.ws, c.w.xbin), at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
     if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
 }
 
@@ -377,7 +384,7 @@ static void one_step(Ctx &c, sph_state *st, sph_state *alt, sph_nlist *nl, sph_d
     do_bin(c, st, alt);
     const Fields M = fields_of(st);
     // stage 1 at the start state, written to the half state
-    do_nbrdens(c, st, M, nl, out, 1);
+    do_nbrdens(c, st, M, nl, out, 1, true);
     do_boundary(c, st, M, nl, out);
     do_force(c, st, M, H, nl, out, 1, nullptr, hist);
     // stage 2 at the half state, written back over the start state
@@ -386,7 +393,7 @@ static void one_step(Ctx &c, sph_state *st, sph_state *alt, sph_nlist *nl, sph_d
     do_force(c, st, H, M, nl, out, 2, nullptr, nullptr);
     launch_end_of_step(c.k, dev_state(st), dev_derived(out), at<int32_t>(c.ws, c.w.nspawn),
                        at<uint8_t>(c.ws, c.w.sflag), at<int32_t>(c.ws, c.w.stile), child, events,
-                       c.err(), c.s);
+                       at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
 }
 
 // Carving of the step-adjoint scratch buffer, in units of cap doubles.
@@ -497,7 +504,8 @@ int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws, size
     if (rc) return rc;
     if (alt->cap != st->cap || alt->prec != st->prec)
         return fail(SPH_EINVAL, "alt must match state in cap and precision");
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    c.k.reuse = 0;  // an explicit bin always sorts
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
     do_bin(c, st, alt);
     return check_hip("sph_bin");
 }
@@ -570,7 +578,7 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
     if (alt->cap != st->cap || alt->prec != st->prec)
         return fail(SPH_EINVAL, "alt must match state in cap and precision");
     if (nsteps < 0) return fail(SPH_EINVAL, "nsteps < 0");
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
     for (int32_t s = 0; s < nsteps; ++s)
         one_step(c, st, alt, nl, out, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr, nullptr,
                  nullptr);
@@ -590,7 +598,8 @@ int sph_step_record(const sph_params *prm, sph_state *st, sph_state *alt, sph_nl
     if (alt->cap != st->cap || alt->prec != st->prec)
         return fail(SPH_EINVAL, "alt must match state in cap and precision");
     if (!child || !events) return fail(SPH_EINVAL, "child and events must not be NULL");
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    c.k.reuse = 0;  // the reverse pass recomputes a step from a fresh sort
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
     one_step(c, st, alt, nl, out, drag, child, events);
     launch_finish_spawn(c.k, dev_state(st), at<int32_t>(ws, c.w.nspawn), c.s);
     return check_hip("sph_step_record");
@@ -646,7 +655,8 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
 
     // recompute the step from st: bin into work (st stays untouched; the
     // live count goes to work's own pointer), then both stages
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), c.s);
+    c.k.reuse = 0;
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
     launch_adj_prep(st->n, work->n, at<int32_t>(ws, c.w.nspawn), c.s);
     DevState a = dev_state(st), b = dev_state(work);
     a.n = work->n;

@@ -87,8 +87,10 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
                                                     const uint32_t *spread,
                                                     const int32_t *cell_start,
                                                     const uint32_t *cpos, float *off,
-                                                    uint32_t *err)
+                                                    int32_t *rebin_clear, uint32_t *err)
 {
+    // the step's bin has run: later updates of this step may request the next
+    if (rebin_clear && blockIdx.x == 0 && threadIdx.x == 0) *rebin_clear = 0;
     constexpr int PB = kBlock / G;
     constexpr int NS = DIM == 2 ? 9 : 27;
     __shared__ int32_t s_beg[PB][NS], s_len[PB][NS];
@@ -381,6 +383,29 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 }
 
 // ------------------------------------------------------------ stage updates
+// Cell skin along axis d. The neighbour search finds every pair within 2h as
+// long as each particle stays within disp_max of the position it had at the
+// last sort (cells are at least 2h + 2 disp_max wide). Half update (mode 1):
+// the stage-1 position xs and the half position v must stay inside, else an
+// error. Full update (mode 2, bin reuse only): ask the next bin to sort unless
+// the new position plus one more step's displacement (from the start value
+// x0) stays inside.
+__device__ inline void skin_check(const Dev &k, int d, int mode, double xs, double v, double x0,
+                                  double xb, int32_t *rebin, uint32_t *err)
+{
+#pragma clang fp contract(off)
+    if (mode == 1) {
+        const double ds = min_image(xs - xb, k.periodic[d], k.L[d], k.halfL[d]);
+        const double dh = min_image(v - xb, k.periodic[d], k.L[d], k.halfL[d]);
+        if (!(fabs(ds) <= k.disp_max && fabs(dh) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
+    } else if (k.reuse) {
+        const double db = min_image(v - xb, k.periodic[d], k.L[d], k.halfL[d]);
+        const double dn = min_image(v - x0, k.periodic[d], k.L[d], k.halfL[d]);
+        if (!(fabs(db) + fabs(dn) <= k.disp_max)) *rebin = 1;
+    }
+}
+
+
 // Explicit-midpoint RK2 (the integrator is the implementation's reading; the
 // paper defers time stepping to the EDAC paper) with eq:transport-vel applied
 // per stage and eq:advection for positions. Contraction is off so that the
@@ -388,7 +413,7 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 template <int DIM, typename T>
 __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &W, int64_t i,
                                    int mode, const T ui[3], T pi, const T a[3], const T b[3],
-                                   T pd, uint32_t *err)
+                                   T pd, const double *xbin, int32_t *rebin, uint32_t *err)
 {
 #pragma clang fp contract(off)
     const int64_t C = k.cap;
@@ -416,10 +441,8 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
             if (v >= hi) v -= k.L[d];
             else if (v < k.lo[d]) v += k.L[d];
         }
-        if (mode == 1) {
-            const double disp = min_image(v - R.x[d * C + i], k.periodic[d], k.L[d], k.halfL[d]);
-            if (!(fabs(disp) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
-        }
+        skin_check(k, d, mode, R.x[d * C + i], v, mode == 2 ? W.x[d * C + i] : 0.0,
+                   xbin[d * C + i], rebin, err);
         fin = fin && isfinite(v);
         W.x[d * C + i] = v;
         st<T>(W.u, d * C + i, T(un[d]));
@@ -435,7 +458,7 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
 template <int DIM, typename T>
 __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fields &R,
                                       const Fields &W, int64_t i, int t, int mode,
-                                      uint32_t *err)
+                                      const double *xbin, int32_t *rebin, uint32_t *err)
 {
 #pragma clang fp contract(off)
     const int64_t C = k.cap;
@@ -447,7 +470,7 @@ __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fie
         if (d == 0 && (t == SPH_INLET || t == SPH_OUTLET)) {
             const double vx = t == SPH_INLET ? m.uin[i] : double(ld<T>(R.u, i));
             v = x0 + dt * vx;
-            if (mode == 1 && !(fabs(v - x0) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
+            skin_check(k, 0, mode, R.x[i], v, x0, xbin[i], rebin, err);
             if (!isfinite(v)) raise_error(err, SPH_ERR_NONFINITE);
         }
         W.x[d * C + i] = v;
@@ -551,7 +574,8 @@ template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, Fields W,
                                                   DevNlist nl, DevDerived o, const float *off,
                                                   const uint32_t *cpos, int mode, int want_drag,
-                                                  double *dragpart, uint32_t *err)
+                                                  double *dragpart, const double *xbin,
+                                                  int32_t *rebin, uint32_t *err)
 {
     constexpr int PB = kBlock / G;
     __shared__ double red_lds[3][PB];
@@ -638,13 +662,15 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                         for (int d = 0; d < DIM; ++d) o.force[d * C + i] = fb[d];
                 } else {
                     st<T>(o.pavg, i, pavg);  // kept for a reverse pass
-                    if (t == SPH_FLUID) stage_fluid<DIM, T>(k, R, W, i, mode, ui, pi, a, b, pd, err);
+                    if (t == SPH_FLUID)
+                        stage_fluid<DIM, T>(k, R, W, i, mode, ui, pi, a, b, pd, xbin, rebin, err);
                 }
             }
         }
         // every non-fluid row (walls, bodies, inlet, outlet) takes its stage
         // position and, in the full update, its half-state boundary values
-        if (mode != 0 && t != SPH_FLUID && lane == 0) stage_boundary<DIM, T>(k, m, R, W, i, t, mode, err);
+        if (mode != 0 && t != SPH_FLUID && lane == 0)
+            stage_boundary<DIM, T>(k, m, R, W, i, t, mode, xbin, rebin, err);
     }
     if (!want_drag) return;
     // deterministic per-block partial of the body force (fixed order)
@@ -737,42 +763,49 @@ static int bnd_grid(const Dev &k)
 template <int DIM, typename T, int G>
 static void nbrdens_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                       const DevDerived &o, int dens, const uint32_t *spread,
-                      const int32_t *cell_start, const uint32_t *cpos, float *off, uint32_t *err,
-                      hipStream_t s)
+                      const int32_t *cell_start, const uint32_t *cpos, float *off,
+                      int32_t *rebin_clear, uint32_t *err, hipStream_t s)
 {
     hipLaunchKernelGGL((k_nbrdens<DIM, T, G>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m, R,
-                       nl, o, dens, spread, cell_start, cpos, off, err);
+                       nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err);
 }
 
 template <int DIM, typename T>
 static void nbrdens_dt(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                        const DevDerived &o, int dens, const uint32_t *spread,
                        const int32_t *cell_start, const uint32_t *cpos, float *off,
-                       uint32_t *err, hipStream_t s)
+                       int32_t *rebin_clear, uint32_t *err, hipStream_t s)
 {
+#define SPH_NBR_G(G) \
+    nbrdens_g<DIM, T, G>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err, s)
     switch (nbr_group(k)) {
-    case 1: nbrdens_g<DIM, T, 1>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
-    case 2: nbrdens_g<DIM, T, 2>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
-    case 4: nbrdens_g<DIM, T, 4>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
-    case 8: nbrdens_g<DIM, T, 8>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
-    case 16: nbrdens_g<DIM, T, 16>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
-    default: nbrdens_g<DIM, T, 32>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s); break;
+    case 1: SPH_NBR_G(1); break;
+    case 2: SPH_NBR_G(2); break;
+    case 4: SPH_NBR_G(4); break;
+    case 8: SPH_NBR_G(8); break;
+    case 16: SPH_NBR_G(16); break;
+    default: SPH_NBR_G(32); break;
     }
+#undef SPH_NBR_G
 }
 
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const uint32_t *spread,
-                    const int32_t *cell_start, const uint32_t *cpos, float *off, uint32_t *err,
-                    hipStream_t s)
+                    const int32_t *cell_start, const uint32_t *cpos, float *off,
+                    int32_t *rebin_clear, uint32_t *err, hipStream_t s)
 {
     if (k.dim == 2 && k.prec == SPH_FP64)
-        nbrdens_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+        nbrdens_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
+                              err, s);
     else if (k.dim == 3 && k.prec == SPH_FP64)
-        nbrdens_dt<3, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+        nbrdens_dt<3, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
+                              err, s);
     else if (k.dim == 2)
-        nbrdens_dt<2, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+        nbrdens_dt<2, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
+                             err, s);
     else
-        nbrdens_dt<3, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, err, s);
+        nbrdens_dt<3, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
+                             err, s);
 }
 
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
@@ -794,41 +827,48 @@ template <int DIM, typename T, int G>
 static void force_g(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                     const DevNlist &nl, const DevDerived &o, const float *off,
                     const uint32_t *cpos, int mode, int want_drag, double *dragpart,
-                    uint32_t *err, hipStream_t s)
+                    const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s)
 {
     hipLaunchKernelGGL((k_force<DIM, T, G>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m, R, W,
-                       nl, o, off, cpos, mode, want_drag, dragpart, err);
+                       nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, err);
 }
 
 template <int DIM, typename T>
 static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                      const DevNlist &nl, const DevDerived &o, const float *off,
                      const uint32_t *cpos, int mode, int want_drag, double *dragpart,
-                     uint32_t *err, hipStream_t s)
+                     const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s)
 {
+#define SPH_FORCE_G(G) \
+    force_g<DIM, T, G>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, err, s)
     switch (force_group(k)) {
-    case 1: force_g<DIM, T, 1>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
-    case 2: force_g<DIM, T, 2>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
-    case 4: force_g<DIM, T, 4>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
-    case 8: force_g<DIM, T, 8>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
-    case 16: force_g<DIM, T, 16>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
-    default: force_g<DIM, T, 32>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s); break;
+    case 1: SPH_FORCE_G(1); break;
+    case 2: SPH_FORCE_G(2); break;
+    case 4: SPH_FORCE_G(4); break;
+    case 8: SPH_FORCE_G(8); break;
+    case 16: SPH_FORCE_G(16); break;
+    default: SPH_FORCE_G(32); break;
     }
+#undef SPH_FORCE_G
 }
 
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
                   const uint32_t *cpos, int mode, int want_drag, double *dragpart,
-                  uint32_t *err, hipStream_t s)
+                  const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s)
 {
     if (k.dim == 2 && k.prec == SPH_FP64)
-        force_dt<2, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+        force_dt<2, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin,
+                            err, s);
     else if (k.dim == 3 && k.prec == SPH_FP64)
-        force_dt<3, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+        force_dt<3, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin,
+                            err, s);
     else if (k.dim == 2)
-        force_dt<2, float>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+        force_dt<2, float>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin,
+                           err, s);
     else
-        force_dt<3, float>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, err, s);
+        force_dt<3, float>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin,
+                           err, s);
 }
 
 void launch_drag_final(const Dev &k, const double *dragpart, double *drag, double *hist,

@@ -20,6 +20,7 @@ constexpr int64_t kIdGeneration = int64_t(1) << 40;
 // Constants derived once per call on the host and passed by value.
 struct Dev {
     int dim, flags, maxnb, prec;
+    int reuse;           // keep the last bin while the skin allows (sph_step only)
     int g_force, g_nbr;  // lanes per target requested (0 = automatic)
     int periodic[3];
     int nc[3];          // cells per axis
@@ -60,8 +61,9 @@ struct DevDerived {
     uint8_t *red;
 };
 
-// Objective weights and gradient buffers of the reverse pass (all FP64
-// storage; arithmetic in the state's precision).
+// Objective weights and gradient buffers of the reverse pass: the weights on
+// a, b, pdot in the state's element type, every other array FP64; pair
+// arithmetic in the state's precision.
 struct DevAdj {
     const void *abar, *bbar, *pdbar;
     const double *pseed, *useed;  // adjoints seeded on boundary values (non-fluid rows)
@@ -142,7 +144,7 @@ struct DevNlist {
 // Workspace carving (byte offsets from the workspace base).
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, tmp, cpos,
-        cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, total;
+        cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

@@ -11,11 +11,14 @@ inline int nblocks(int64_t n, int per = kBlock) { return int((n + per - 1) / per
 struct BinBufs {
     int32_t *nspawn, *bcount, *counts, *cell_start, *cursor, *tilesum, *tmp, *blist;
     uint32_t *spread, *keys, *cpos, *cpos_s;
+    int32_t *rebin;  // 1: the next bin sorts; 0: it keeps the order (Dev::reuse)
+    double *xbin;    // [3][cap] positions at the last sort, sorted order
 };
 
 int64_t scan_tiles(int64_t n);
 int64_t tilesum_len(int64_t n);
-void launch_spread(const Dev &k, uint32_t *spread, hipStream_t s);
+// Morton spread tables; also asks the next bin to sort (rebin = 1)
+void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s);
 // keys + histogram, scan, scatter, per-cell id order, gather a -> b
 void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBufs &w,
                 uint32_t *err, hipStream_t s);
@@ -26,8 +29,8 @@ int force_grid(const Dev &k);
 int force_grid_max(const Dev &k);
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const uint32_t *spread,
-                    const int32_t *cell_start, const uint32_t *cpos, float *off, uint32_t *err,
-                    hipStream_t s);
+                    const int32_t *cell_start, const uint32_t *cpos, float *off,
+                    int32_t *rebin_clear, uint32_t *err, hipStream_t s);
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
@@ -36,7 +39,7 @@ void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const Dev
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
                   const uint32_t *cpos, int mode, int want_drag, double *dragpart,
-                  uint32_t *err, hipStream_t s);
+                  const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s);
 void launch_drag_final(const Dev &k, const double *dragpart, double *drag, double *hist,
                        hipStream_t s);
 
@@ -48,7 +51,7 @@ void launch_rhs_adjoint(const Dev &k, const DevState &m, const Fields &R, const 
 // bookkeeping
 void launch_end_of_step(const Dev &k, const DevState &st, const DevDerived &o,
                         int32_t *nspawn, uint8_t *sflag, int32_t *stile, int32_t *child,
-                        uint8_t *events, uint32_t *err, hipStream_t s);
+                        uint8_t *events, int32_t *rebin, uint32_t *err, hipStream_t s);
 void launch_finish_spawn(const Dev &k, const DevState &st, int32_t *nspawn, hipStream_t s);
 
 // reverse of one step

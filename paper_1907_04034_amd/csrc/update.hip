@@ -28,7 +28,8 @@ __device__ inline double splitmix_uniform(uint64_t seed, int64_t id, int k)
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_end_of_step(Dev k, DevState s, DevDerived o,
                                                         uint8_t *sflag, int32_t *stile,
-                                                        int32_t *child, uint8_t *events)
+                                                        int32_t *child, uint8_t *events,
+                                                        int32_t *rebin)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = *s.n;
@@ -81,6 +82,8 @@ __global__ void __launch_bounds__(kBlock) k_end_of_step(Dev k, DevState s, DevDe
         }
         sflag[i] = spawn ? 1 : 0;
         if (events) events[i] = ev;
+        // a kind change or a new row needs a fresh sort (boundary list, cells)
+        if (k.reuse && (ev & (kEvToOutlet | kEvDelete | kEvSpawn))) *rebin = 1;
     }
     const int cnt = __syncthreads_count(spawn);
     if (threadIdx.x == 0) stile[blockIdx.x] = cnt;
@@ -172,22 +175,20 @@ __global__ void k_finish_spawn(Dev k, DevState s, int32_t *nspawn)
 // ------------------------------------------------------------------ launchers
 void launch_end_of_step(const Dev &k, const DevState &st, const DevDerived &o,
                         int32_t *nspawn, uint8_t *sflag, int32_t *stile, int32_t *child,
-                        uint8_t *events, uint32_t *err, hipStream_t s)
+                        uint8_t *events, int32_t *rebin, uint32_t *err, hipStream_t s)
 {
     const dim3 g(nblocks(k.cap)), b(kBlock);
-    if (k.dim == 2 && k.prec == SPH_FP64) {
-        hipLaunchKernelGGL((k_end_of_step<2, double>), g, b, 0, s, k, st, o, sflag, stile, child, events);
-        hipLaunchKernelGGL((k_spawn<2, double>), g, b, 0, s, k, st, sflag, stile, nspawn, child, err);
-    } else if (k.dim == 3 && k.prec == SPH_FP64) {
-        hipLaunchKernelGGL((k_end_of_step<3, double>), g, b, 0, s, k, st, o, sflag, stile, child, events);
-        hipLaunchKernelGGL((k_spawn<3, double>), g, b, 0, s, k, st, sflag, stile, nspawn, child, err);
-    } else if (k.dim == 2) {
-        hipLaunchKernelGGL((k_end_of_step<2, float>), g, b, 0, s, k, st, o, sflag, stile, child, events);
-        hipLaunchKernelGGL((k_spawn<2, float>), g, b, 0, s, k, st, sflag, stile, nspawn, child, err);
-    } else {
-        hipLaunchKernelGGL((k_end_of_step<3, float>), g, b, 0, s, k, st, o, sflag, stile, child, events);
-        hipLaunchKernelGGL((k_spawn<3, float>), g, b, 0, s, k, st, sflag, stile, nspawn, child, err);
-    }
+#define SPH_EOS(D, T)                                                                           \
+    do {                                                                                        \
+        hipLaunchKernelGGL((k_end_of_step<D, T>), g, b, 0, s, k, st, o, sflag, stile, child,    \
+                           events, rebin);                                                      \
+        hipLaunchKernelGGL((k_spawn<D, T>), g, b, 0, s, k, st, sflag, stile, nspawn, child, err); \
+    } while (0)
+    if (k.dim == 2 && k.prec == SPH_FP64) SPH_EOS(2, double);
+    else if (k.dim == 3 && k.prec == SPH_FP64) SPH_EOS(3, double);
+    else if (k.dim == 2) SPH_EOS(2, float);
+    else SPH_EOS(3, float);
+#undef SPH_EOS
 }
 
 void launch_finish_spawn(const Dev &k, const DevState &st, int32_t *nspawn, hipStream_t s)

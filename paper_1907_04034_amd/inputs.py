@@ -38,6 +38,8 @@ N_AVG = 6
 FLAG_NO_PAVG = 1   # drop the neighbour-average pressure (conservation tests)
 FLAG_DAMP_NU = 2   # use the physical viscosity in the pressure damping term
 FLAG_NOISE = 4     # add seeded velocity noise to inlet particles at spawn
+FLAG_REUSE_BINS = 8  # GPU stepping option: keep the cell order while the skin allows
+                     # (same neighbour sets; the oracle ignores it)
 
 ID_GENERATION = 1 << 40   # a spawned inlet particle's id is its parent's + this
 

@@ -155,12 +155,16 @@ TRAJ_CASES = [("C1", 100, 0.0), ("C2-small", 300, 1e-3), ("C3-small", 100, 1e-3)
               ("C4-small", 150, 1e-3), ("C5-small", 60, 1e-3)]
 
 
+@pytest.mark.parametrize("reuse", [False, True])
 @pytest.mark.parametrize("name,steps,jit", TRAJ_CASES)
-def test_trajectory_parity_fp64(name, steps, jit):
+def test_trajectory_parity_fp64(name, steps, jit, reuse):
     """GPU vs oracle after many steps, within a small multiple of the oracle's
-    own one-ulp sensitivity (floor 1e-10)."""
-    _print_case(f"trajectory fp64 {name} {steps}")
+    own one-ulp sensitivity (floor 1e-10); also with the cell order kept
+    across steps while the skin allows."""
+    _print_case(f"trajectory fp64 {name} {steps} reuse={reuse}")
     prm, s = I.config("C1") if name == "C1" else I.config(name.split("-")[0], small=True)
+    if reuse:
+        prm = dict(prm, flags=prm["flags"] | I.FLAG_REUSE_BINS)
     if jit:
         s = I.jitter(prm, s, jit, 5, types=(I.FLUID, I.INLET, I.OUTLET))
     sim = B().Simulation(prm, s)
@@ -266,3 +270,22 @@ def test_lane_group_variants(name, g):
     ref = {int(ids[i]): set(ids[col[row[i]:row[i + 1]]].tolist()) for i in range(len(row) - 1)}
     for r in range(len(cnt)):
         assert set(gs["id"][nbr[r, :cnt[r]]].tolist()) == ref[int(gs["id"][r])]
+
+
+def test_bin_reuse_matches_sorting_every_step():
+    """Full 2D channel (jittered), 300 steps: keeping the cell order across
+    steps gives the same flow as sorting every step (same neighbour sets; only
+    the summation order differs), and the same particles."""
+    prm, s = I.config("C2")
+    s = I.jitter(prm, s, 1e-3, 5, types=(I.FLUID, I.INLET, I.OUTLET))
+    out = []
+    for flags in (prm["flags"], prm["flags"] | I.FLAG_REUSE_BINS):
+        sim = B().Simulation(dict(prm, flags=flags), s)
+        sim.step(300)
+        assert sim.poll_error() == 0
+        out.append(_by_id(sim.state()))
+    assert np.array_equal(out[0]["id"], out[1]["id"])
+    assert np.array_equal(out[0]["type"], out[1]["type"])
+    err = _traj_errors(prm, out[1], out[0])
+    print(err, flush=True)
+    assert all(v < 1e-9 for v in err.values()), err
