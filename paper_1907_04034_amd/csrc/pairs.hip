@@ -276,14 +276,24 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
         for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
         const double uin0 = m.uin[i];
         const int cnt = nl.count[i];
+        const bool io = t == SPH_INLET || t == SPH_OUTLET;
+        // Shepard sums over fluid neighbours and, in the same sweep, the
+        // fallback sums over same-kind neighbours that had support
         double sw = 0.0, sp = 0.0, su[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
+        double bacc[3] = {0, 0, 0}, bM = 0.0;
         for (int q = lane; q < cnt; q += G) {
             const int32_t j = nl.nbr[i * nl.maxnb + q];
             if (bad_index(j, n)) {
                 raise_error(err, SPH_ERR_CELL_RANGE);
                 continue;
             }
-            if (m.type[j] != SPH_FLUID) continue;
+            const int tj = m.type[j];
+            if (io && tj == t && m.red_prev[j]) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) bacc[a] += m.jprev[a * C + j];
+                bM += 1.0;
+            }
+            if (tj != SPH_FLUID) continue;
             double xj[3] = {0, 0, 0};
 #pragma unroll
             for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
@@ -337,21 +347,11 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
             if (t == SPH_OUTLET) J[2] = 0.0;
         } else {
             red = 0;
-            double acc[3] = {0, 0, 0}, M = 0.0;
-            for (int q = lane; q < cnt; q += G) {
-                const int32_t j = nl.nbr[i * nl.maxnb + q];
-                if (bad_index(j, n)) continue;
-                if (m.type[j] == t && m.red_prev[j]) {
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) acc[a] += m.jprev[a * C + j];
-                    M += 1.0;
-                }
-            }
-            M = gsum<G>(M);
+            const double M = gsum<G>(bM);
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                acc[a] = gsum<G>(acc[a]);
-                J[a] = M > 0.0 ? acc[a] / M : m.jprev[a * C + i];
+                const double acc = gsum<G>(bacc[a]);
+                J[a] = M > 0.0 ? acc / M : m.jprev[a * C + i];
             }
         }
         if (lane == 0) {
