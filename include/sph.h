@@ -100,6 +100,10 @@ typedef struct sph_params {
     uint64_t noise_seed;
     int32_t group_force;  /* lanes per target in the force pass: 0 = automatic, or 1..32 (power of 2) */
     int32_t group_nbr;    /* lanes per target in the neighbour search: same convention */
+    int32_t list_cap;     /* candidate-list entries per particle of the step path
+                             (0 = automatic; a particle with more candidates is
+                             searched through its cell stencil instead) */
+    int32_t reserved;     /* must be 0 */
 } sph_params;
 
 /* Particle state. Element type of u, ut, p is double for SPH_FP64 and float
@@ -148,7 +152,8 @@ typedef struct sph_derived {
 } sph_derived;
 
 /* Bytes of workspace needed for capacity `cap` (cell grid, sort buffers,
- * start-of-step copy, scan scratch, error word). */
+ * half-state copy, scan scratch, the step path's candidate lists of
+ * list_cap (or the automatic count) entries per particle, error word). */
 int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
 
 /* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D). */
@@ -208,7 +213,14 @@ int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
  * push, fluid->outlet, outlet deletion, inlet->fluid with re-spawn).
  * drag_hist (device, [nsteps][3], may be NULL) receives the body force of
  * stage 1 of every step. out receives the density and boundary data of the
- * last stage (a, b, pdot are not written). */
+ * last stage (a, b, pdot are not written). In 3D, and in 2D below a
+ * capacity of 300000, the first search after each sort also records, per
+ * particle, the stencil members within
+ * 2h + 2 sqrt(dim) disp_max of it (disp_max: the per-axis displacement the
+ * cell width allows beyond 2h); later searches until the next sort test only
+ * those, which give the same neighbour table in the same order as long as no
+ * particle has moved more than disp_max per axis from its sorted position
+ * (checked; a violation sets SPH_ERR_SKIN). */
 int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
              sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
              size_t ws_bytes, void *stream);

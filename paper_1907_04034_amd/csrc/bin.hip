@@ -219,7 +219,7 @@ template <int DIM, typename T>
 __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
                          const int32_t *cell_start, const uint32_t *cpos_in, uint32_t *cpos_out,
                          int32_t *blist, int32_t *bcount, int32_t *nspawn,
-                         const int32_t *rebin, double *xbin)
+                         const int32_t *rebin, double *xbin, int32_t *vfresh)
 {
     // a kept order copies row for row (the caller exchanges the two buffers)
     const bool sorted = !bin_skips(k, rebin);
@@ -228,6 +228,7 @@ __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
     if (r == 0 && blockIdx.y == 0) {
         *a.n = n;
         *nspawn = 0;
+        *vfresh = sorted ? 1 : 0;
     }
     if (r >= n) return;
     const int64_t i = sorted ? int64_t(tmp[r]) : r;
@@ -303,16 +304,20 @@ void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBuf
     const dim3 gg(nblocks(k.cap), 4);
     if (k.dim == 2 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_gather<2, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin,
+                           w.vfresh);
     else if (k.dim == 3 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_gather<3, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin,
+                           w.vfresh);
     else if (k.dim == 2)
         hipLaunchKernelGGL((k_gather<2, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin,
+                           w.vfresh);
     else
         hipLaunchKernelGGL((k_gather<3, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
-                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin);
+                           w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin,
+                           w.vfresh);
 }
 
 }  // namespace sph

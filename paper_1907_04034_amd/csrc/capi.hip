@@ -44,6 +44,8 @@ int ceil_log2(int v)
 
 namespace sph {
 
+constexpr double pi_d = 3.14159265358979323846;
+
 // Validates the parameter block and derives the kernel constants.
 static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *k)
 {
@@ -58,6 +60,9 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         return fail(SPH_EINVAL, "dt = %g exceeds the acoustic bound 0.5 h / (c + U) = %g", p->dt,
                     0.5 * p->h / (p->c + p->U));
     if (cap < 1 || cap > INT32_MAX) return fail(SPH_EINVAL, "cap must be in [1, 2^31)");
+    if (p->list_cap < 0 || p->list_cap > 2048)
+        return fail(SPH_EINVAL, "list_cap must be in [0, 2048] (got %d)", p->list_cap);
+    if (p->reserved != 0) return fail(SPH_EINVAL, "reserved must be 0");
     if (prec != SPH_FP64 && prec != SPH_FP32) return fail(SPH_EINVAL, "bad precision %d", prec);
     std::memset(k, 0, sizeof *k);
     k->dim = p->dim;
@@ -107,7 +112,7 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         double s = 2.0 * p->h;
         k->sup2 = s * s;
     }
-    const double pi = 3.14159265358979323846;
+    const double pi = pi_d;
     k->wnorm = p->dim == 2 ? 7.0 / (4.0 * pi * p->h * p->h)
                            : 21.0 / (16.0 * pi * p->h * p->h * p->h);
     k->gnorm = -5.0 * k->wnorm / (p->h * p->h);
@@ -125,6 +130,25 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     k->dt = p->dt;
     k->hdt = 0.5 * p->dt;
     k->disp_max = 0.999 * 0.5 * min_slack;
+    {
+        // candidate lists: a pair closer than 2h at positions within disp_max
+        // (per axis) of the binned ones is closer than 2h + 2 sqrt(d) disp_max
+        // at the binned positions (a small relative margin covers rounding);
+        // capacity twice the lattice count of that ball, plus slack
+        const double rv = (2.0 * p->h + 2.0 * std::sqrt(double(p->dim)) * k->disp_max) *
+                          (1.0 + 1e-9);
+        k->rv2 = rv * rv;
+        const double q = rv / p->dx;
+        const double ball = p->dim == 2 ? pi_d * q * q : 4.0 / 3.0 * pi_d * q * q * q;
+        const double vm = 2.0 * ball + 16.0;
+        k->vmax = vm < 32.0 ? 32 : (vm > 2048.0 ? 2048 : int(std::ceil(vm)));
+        if (p->list_cap) k->vmax = p->list_cap;
+        // measured: in 3D a list holds about a fifth of the stencil's
+        // candidates and pays at every size; in 2D (about 2/5) it pays where
+        // the search is latency-bound (small systems), not where it is
+        // throughput-bound and re-sorts are frequent
+        k->lists = (p->dim == 3 || cap < 300000) ? 1 : 0;
+    }
     k->x_inlet = p->x_inlet;
     k->x_outlet = p->x_outlet;
     k->x_outlet_end = p->x_outlet_end;
@@ -181,6 +205,9 @@ static WsLayout layout(const Dev &k)
     w.stile = take(sizeof(int32_t) * size_t(nblocks(k.cap)));
     w.rebin = take(sizeof(int32_t));
     w.xbin = take(sizeof(double) * 3 * C);
+    w.vfresh = take(sizeof(int32_t));
+    w.vcount = take(sizeof(int32_t) * C);
+    w.vnbr = take(k.lists ? sizeof(int32_t) * size_t(k.vmax) * C : 0);
     w.total = off;
     return w;
 }
@@ -287,6 +314,7 @@ struct Ctx {
         b.cpos_s = at<uint32_t>(ws, w.cpos_s);
         b.rebin = at<int32_t>(ws, w.rebin);
         b.xbin = at<double>(ws, w.xbin);
+        b.vfresh = at<int32_t>(ws, w.vfresh);
         return b;
     }
     Fields half() const
@@ -347,13 +375,20 @@ static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
     alt->n = n_alt;
 }
 
+// vmode: 0 stencil search; 1 first search of a step (records the candidate
+// lists after a sort, else walks them); 2 walks the lists
 static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
-                       const sph_derived *o, int dens, bool clear_rebin = false)
+                       const sph_derived *o, int dens, int vmode, bool clear_rebin = false)
 {
+    if (!c.k.lists) vmode = 0;
+    VList v;
+    v.fresh = at<int32_t>(c.ws, c.w.vfresh);
+    v.count = at<int32_t>(c.ws, c.w.vcount);
+    v.nbr = at<int32_t>(c.ws, c.w.vnbr);
     launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? dev_derived(o) : DevDerived{},
                    dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
                    at<uint32_t>(c.ws, c.w.cpos_s), c.off(),
-                   clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, c.err(), c.s);
+                   clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
 }
 
 static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
@@ -384,11 +419,11 @@ static void one_step(Ctx &c, sph_state *st, sph_state *alt, sph_nlist *nl, sph_d
     do_bin(c, st, alt);
     const Fields M = fields_of(st);
     // stage 1 at the start state, written to the half state
-    do_nbrdens(c, st, M, nl, out, 1, true);
+    do_nbrdens(c, st, M, nl, out, 1, 1, true);
     do_boundary(c, st, M, nl, out);
     do_force(c, st, M, H, nl, out, 1, nullptr, hist);
     // stage 2 at the half state, written back over the start state
-    do_nbrdens(c, st, H, nl, out, 1);
+    do_nbrdens(c, st, H, nl, out, 1, 2);
     do_boundary(c, st, H, nl, out);
     do_force(c, st, H, M, nl, out, 2, nullptr, nullptr);
     launch_end_of_step(c.k, dev_state(st), dev_derived(out), at<int32_t>(c.ws, c.w.nspawn),
@@ -517,7 +552,7 @@ int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl))) return rc;
     if (out && (rc = check_derived(out, false))) return rc;
-    do_nbrdens(c, st, fields_of(st), nl, out, out != nullptr);
+    do_nbrdens(c, st, fields_of(st), nl, out, out != nullptr, 0);
     return check_hip("sph_neighbors");
 }
 
@@ -663,10 +698,10 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
     launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
     const int32_t *perm = at<int32_t>(ws, c.w.tmp);  // sorted row -> row of st
     const Fields M = fields_of(work), H = c.half();
-    do_nbrdens(c, work, M, nl1, d1, 1);
+    do_nbrdens(c, work, M, nl1, d1, 1, 1);
     do_boundary(c, work, M, nl1, d1);
     do_force(c, work, M, H, nl1, d1, 1, nullptr, nullptr);
-    do_nbrdens(c, work, H, nl2, d2, 1);
+    do_nbrdens(c, work, H, nl2, d2, 1, 2);
     do_boundary(c, work, H, nl2, d2);
     do_force(c, work, H, H, nl2, d2, 0, nullptr, nullptr);
 
@@ -715,8 +750,8 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
                        c.s);
     launch_adj_half(c.k, m, S, A, c.s);
     // the FP32 pair arithmetic reads cell-relative offsets of the stage's
-    // positions: rebuild those of the start state (same table, same values)
-    if (c.k.prec == SPH_FP32) do_nbrdens(c, work, M, nl1, d1, 1);
+    // positions: rebuild those of the start state (the same table again)
+    if (c.k.prec == SPH_FP32) do_nbrdens(c, work, M, nl1, d1, 0, 2);
     DevAdj A1 = A;
     A1.jseed = nullptr;
     for (int d = 0; d < 3; ++d) A1.fbar[d] = fbar[d];

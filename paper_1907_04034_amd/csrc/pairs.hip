@@ -81,19 +81,147 @@ struct Acc<float> {
 // loads all cell ranges of a target at once. The density (Sec. 2
 // eq:summation-density, V = 1/sum W) is summed from the same pairs when `dens`
 // is set. FP32 mode records the cell-relative offsets the force pass uses.
+//
+// Step path (vmode 1, 2): the candidate lists of VList. vmode 1 is the first
+// search of a step: after a sort (*v.fresh) it walks the stencil and also
+// records every candidate within rv of the target (a second ballot), else it
+// walks the stored list; vmode 2 always walks the stored list. A list is a
+// subsequence of the stencil sequence that holds every hit, so both walks
+// produce the same table in the same order. vmode 0 walks the stencil only.
+
+// candidates of one lane, NB at a time, from the stencil sequence
+template <int NS, int NB, int G>
+struct StencilWalk {
+    const int32_t *beg, *len;  // the group's cell ranges (LDS)
+    int sc, mo;
+    __device__ inline StencilWalk(const int32_t *b, const int32_t *l, int lane) : beg(b), len(l)
+    {
+        sc = 0;
+        mo = lane;
+        while (sc < NS && mo >= len[sc]) mo -= len[sc++];
+    }
+    __device__ inline void next(int32_t jj[NB], bool hv[NB])
+    {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            hv[b] = sc < NS;
+            jj[b] = hv[b] ? beg[sc] + mo : 0;  // row 0 as a harmless dummy
+            mo += G;
+            while (sc < NS && mo >= len[sc]) mo -= len[sc++];
+        }
+    }
+};
+
+// candidates of one lane, NB at a time, from a stored list (entries beyond the
+// live rows are reported and skipped)
+template <int NB, int G>
+struct ListWalk {
+    const int32_t *list;
+    int q, cnt;
+    int64_t n;
+    uint32_t *err;
+    __device__ inline ListWalk(const int32_t *l, int c, int lane, int64_t nrows, uint32_t *e)
+        : list(l), q(lane), cnt(c), n(nrows), err(e)
+    {
+    }
+    __device__ inline void next(int32_t jj[NB], bool hv[NB])
+    {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int32_t j = q < cnt ? list[q] : 0;
+            const bool bad = q < cnt && bad_index(j, n);
+            if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
+            hv[b] = q < cnt && !bad;
+            jj[b] = hv[b] ? j : 0;
+            q += G;
+        }
+    }
+};
+
+// Tests the candidates of one walk (total of them over the group), appends
+// hits to the table row and, with `rec`, candidates within rv to the list
+// row; returns the group's hit count. The kernel sum is accumulated in table
+// order: lane l adds the entries l, l + G, l + 2G, ... (each round's kernel
+// values are routed through the group's G slots of LDS to the lane of their
+// table position), so the density does not depend on which walk found them.
+template <int DIM, typename T, int G, int NB, typename Walk>
+__device__ inline int walk_candidates(const Dev &k, const Fields &R, Walk &w, int total,
+                                      const double xi[3], int lane, int32_t *row, int maxnb,
+                                      bool rec, int32_t *vrow, int &vcnt, int dens, Acc<T> &sw,
+                                      T *slots)
+{
+    const int64_t C = k.cap;
+    const int gshift = (threadIdx.x & 63) & ~(G - 1);
+    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
+    const uint64_t below = (1ull << lane) - 1;
+    int cnt = 0;
+    for (int base = 0; base < total; base += NB * G) {
+        int32_t jj[NB];
+        bool hv[NB];
+        w.next(jj, hv);
+        double xj[NB][3];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xj[b][d] = d < DIM ? R.x[d * C + jj[b]] : 0.0;
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            double r[3];
+            const double r2 = dist2_exact<DIM>(k, xi, xj[b], r);
+            const bool hit = hv[b] && r2 < k.sup2;
+            int pos = cnt, nhit = hit ? 1 : 0;
+            if (G > 1) {
+                const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
+                pos = cnt + __popcll(bal & below);
+                nhit = __popcll(bal);
+            }
+            if (hit && pos < maxnb) row[pos] = jj[b];
+            if (dens && nhit > 0) {
+                const T wv = hit ? wendland_w<T>(T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
+                if (G == 1) {
+                    sw.add(wv);
+                } else {
+                    if (hit) slots[pos & (G - 1)] = wv;
+                    __builtin_amdgcn_wave_barrier();
+                    const T got = slots[lane];
+                    __builtin_amdgcn_wave_barrier();
+                    if (((lane - cnt) & (G - 1)) < nhit) sw.add(got);
+                }
+            }
+            cnt += nhit;
+            if (rec) {
+                const bool vhit = hv[b] && r2 < k.rv2;
+                int vpos = vcnt, nv = vhit ? 1 : 0;
+                if (G > 1) {
+                    const uint64_t bal = (uint64_t(__ballot(vhit)) >> gshift) & gmask;
+                    vpos = vcnt + __popcll(bal & below);
+                    nv = __popcll(bal);
+                }
+                if (vhit && vpos < k.vmax) vrow[vpos] = jj[b];
+                vcnt += nv;
+            }
+        }
+    }
+    return cnt;
+}
+
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R, DevNlist nl,
                                                     DevDerived o, int dens,
                                                     const uint32_t *spread,
                                                     const int32_t *cell_start,
                                                     const uint32_t *cpos, float *off,
-                                                    int32_t *rebin_clear, uint32_t *err)
+                                                    int32_t *rebin_clear, VList v, int vmode,
+                                                    uint32_t *err)
 {
     // the step's bin has run: later updates of this step may request the next
     if (rebin_clear && blockIdx.x == 0 && threadIdx.x == 0) *rebin_clear = 0;
     constexpr int PB = kBlock / G;
     constexpr int NS = DIM == 2 ? 9 : 27;
+    constexpr int NB = 4;
     __shared__ int32_t s_beg[PB][NS], s_len[PB][NS];
+    __shared__ T s_w[PB][G];
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int64_t n = *m.n;
@@ -101,12 +229,18 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
     const int64_t i = lb * PB + grp;
     const bool active = lb >= 0 && i < n;  // uniform across the group
     const int64_t C = k.cap;
+    // walk of this target: the stored list (vc >= 0) or the stencil
+    const bool build = vmode == 1 && *v.fresh != 0;
+    int vc = -1;
+    if (active && vmode != 0 && !build) vc = v.count[i];
     double xi[3] = {0, 0, 0};
     int c[3] = {0, 0, 0};
     if (active) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
         unpack_cell<DIM>(cpos[i], c);
+    }
+    if (active && vc < 0) {
         // cell ranges of the stencil, one cell per lane at a time
         for (int sc = lane; sc < NS; sc += G) {
             const int dxs = sc % 3 - 1, dys = (sc / 3) % 3 - 1, dzs = DIM == 3 ? sc / 9 - 1 : 0;
@@ -135,53 +269,21 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
     }
     __syncthreads();
     if (!active) return;
-    int total = 0;
-#pragma unroll
-    for (int sc = 0; sc < NS; ++sc) total += s_len[grp][sc];
-    const int gshift = (threadIdx.x & 63) & ~(G - 1);
-    const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
-    const uint64_t below = (1ull << lane) - 1;
-    // this lane's position in the sequence: cell sc, member mo
-    int sc = 0, mo = lane;
-    while (sc < NS && mo >= s_len[grp][sc]) mo -= s_len[grp][sc++];
-    int cnt = 0;
+    int32_t *row = nl.nbr + i * nl.maxnb;
+    int32_t *vrow = v.nbr + i * int64_t(k.vmax);
     Acc<T> sw;
-    // batches of NB rounds: the NB candidate positions of a lane are loaded
-    // together (independent loads in flight), then tested in sequence order
-    constexpr int NB = 4;
-    for (int base = 0; base < total; base += NB * G) {
-        int32_t jj[NB];
-        bool hv[NB];
+    int cnt, vcnt = 0;
+    if (vc >= 0) {
+        ListWalk<NB, G> w(vrow, vc, lane, n, err);
+        cnt = walk_candidates<DIM, T, G, NB>(k, R, w, vc, xi, lane, row, nl.maxnb, false, vrow,
+                                             vcnt, dens, sw, s_w[grp]);
+    } else {
+        int total = 0;
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            hv[b] = sc < NS;
-            jj[b] = hv[b] ? s_beg[grp][sc] + mo : 0;  // row 0 as a harmless dummy
-            mo += G;
-            while (sc < NS && mo >= s_len[grp][sc]) mo -= s_len[grp][sc++];
-        }
-        double xj[NB][3];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-#pragma unroll
-            for (int d = 0; d < 3; ++d) xj[b][d] = d < DIM ? R.x[d * C + jj[b]] : 0.0;
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            double r[3];
-            const double r2 = dist2_exact<DIM>(k, xi, xj[b], r);
-            const bool hit = hv[b] && r2 < k.sup2;
-            int pos = cnt, nhit = hit ? 1 : 0;
-            if (G > 1) {
-                const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
-                pos = cnt + __popcll(bal & below);
-                nhit = __popcll(bal);
-            }
-            if (hit) {
-                if (pos < nl.maxnb) nl.nbr[i * nl.maxnb + pos] = jj[b];
-                if (dens) sw.add(wendland_w<T>(T(sqrt(r2) * k.inv_h), T(k.wnorm)));
-            }
-            cnt += nhit;
-        }
+        for (int sc = 0; sc < NS; ++sc) total += s_len[grp][sc];
+        StencilWalk<NS, NB, G> w(s_beg[grp], s_len[grp], lane);
+        cnt = walk_candidates<DIM, T, G, NB>(k, R, w, total, xi, lane, row, nl.maxnb, build, vrow,
+                                             vcnt, dens, sw, s_w[grp]);
     }
     const T S = sw.template reduce<G>();
     if (lane == 0) {
@@ -190,6 +292,7 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
             cnt = nl.maxnb;
         }
         nl.count[i] = cnt;
+        if (build) v.count[i] = vcnt <= k.vmax ? vcnt : -1;
         if (dens) {
             st<T>(o.rho, i, T(k.mass) * S);
             st<T>(o.vol, i, T(1) / S);
@@ -730,7 +833,7 @@ static int pick(int override, int64_t cap, int small, int large)
 }
 
 int force_group(const Dev &k) { return pick(k.g_force, k.cap, k.dim == 2 ? 4 : 8, 4); }
-int nbr_group(const Dev &k) { return pick(k.g_nbr, k.cap, 8, k.dim == 2 ? 2 : 4); }
+int nbr_group(const Dev &k) { return pick(k.g_nbr, k.cap, 8, k.lists ? 8 : (k.dim == 2 ? 2 : 4)); }
 int force_grid(const Dev &k) { return grid_for(k, force_group(k)); }
 // the most blocks any variant launches (fewest targets per block): sizes the
 // per-block drag partials
@@ -764,20 +867,23 @@ template <int DIM, typename T, int G>
 static void nbrdens_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                       const DevDerived &o, int dens, const uint32_t *spread,
                       const int32_t *cell_start, const uint32_t *cpos, float *off,
-                      int32_t *rebin_clear, uint32_t *err, hipStream_t s)
+                      int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
+                      hipStream_t s)
 {
     hipLaunchKernelGGL((k_nbrdens<DIM, T, G>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m, R,
-                       nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err);
+                       nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v, vmode, err);
 }
 
 template <int DIM, typename T>
 static void nbrdens_dt(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                        const DevDerived &o, int dens, const uint32_t *spread,
                        const int32_t *cell_start, const uint32_t *cpos, float *off,
-                       int32_t *rebin_clear, uint32_t *err, hipStream_t s)
+                       int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
+                       hipStream_t s)
 {
-#define SPH_NBR_G(G) \
-    nbrdens_g<DIM, T, G>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err, s)
+#define SPH_NBR_G(G)                                                                         \
+    nbrdens_g<DIM, T, G>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v, \
+                         vmode, err, s)
     switch (nbr_group(k)) {
     case 1: SPH_NBR_G(1); break;
     case 2: SPH_NBR_G(2); break;
@@ -792,20 +898,21 @@ static void nbrdens_dt(const Dev &k, const DevState &m, const Fields &R, const D
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const uint32_t *spread,
                     const int32_t *cell_start, const uint32_t *cpos, float *off,
-                    int32_t *rebin_clear, uint32_t *err, hipStream_t s)
+                    int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
+                    hipStream_t s)
 {
     if (k.dim == 2 && k.prec == SPH_FP64)
-        nbrdens_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                              err, s);
+        nbrdens_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v,
+                              vmode, err, s);
     else if (k.dim == 3 && k.prec == SPH_FP64)
-        nbrdens_dt<3, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                              err, s);
+        nbrdens_dt<3, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v,
+                              vmode, err, s);
     else if (k.dim == 2)
-        nbrdens_dt<2, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                             err, s);
+        nbrdens_dt<2, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v,
+                             vmode, err, s);
     else
-        nbrdens_dt<3, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                             err, s);
+        nbrdens_dt<3, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v,
+                             vmode, err, s);
 }
 
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

@@ -31,6 +31,9 @@ struct Dev {
     float csf[3];
     double h, inv_h, sup2, wnorm, gnorm, mass, inv_mass, rho0, c, c2, nu, nu_damp, eta_h2, pb;
     double dt, hdt, disp_max;
+    double rv2;  // squared radius of the step path's candidate lists
+    int vmax;    // candidate-list entries per particle
+    int lists;   // the step path keeps candidate lists (else it searches the stencil)
     double x_inlet, x_outlet, x_outlet_end, inlet_len, pgate, U, noise_amp;
     uint64_t noise_seed;
     float hf, inv_hf, sup2f, wnormf, gnormf, massf, c2f, nuf, nu_dampf, eta_h2f, pbf;
@@ -141,10 +144,22 @@ struct DevNlist {
     int32_t *count, *nbr;
 };
 
+// Candidate lists of the step path: for every particle the members of its
+// 3^d stencil within Dev::rv2 of it at the last sort (binned positions), in
+// stencil order. While every particle stays within disp_max per axis of its
+// binned position (checked by the stage updates), each pair closer than 2h is
+// in these lists, so a search may walk them instead of the stencil.
+struct VList {
+    const int32_t *fresh;  // 1: the step's bin sorted (rebuild the lists)
+    int32_t *count;        // entries per particle; -1: overflowed, search the stencil
+    int32_t *nbr;          // [cap][vmax]
+};
+
 // Workspace carving (byte offsets from the workspace base).
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, tmp, cpos,
-        cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, total;
+        cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
+        vnbr, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

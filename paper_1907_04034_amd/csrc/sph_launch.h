@@ -13,6 +13,7 @@ struct BinBufs {
     uint32_t *spread, *keys, *cpos, *cpos_s;
     int32_t *rebin;  // 1: the next bin sorts; 0: it keeps the order (Dev::reuse)
     double *xbin;    // [3][cap] positions at the last sort, sorted order
+    int32_t *vfresh; // set by the gather: 1 if it sorted
 };
 
 int64_t scan_tiles(int64_t n);
@@ -30,7 +31,8 @@ int force_grid_max(const Dev &k);
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const uint32_t *spread,
                     const int32_t *cell_start, const uint32_t *cpos, float *off,
-                    int32_t *rebin_clear, uint32_t *err, hipStream_t s);
+                    int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
+                    hipStream_t s);
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

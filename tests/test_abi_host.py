@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header_layout():
-    assert C.sizeof(B.SphParams) == 4 * 6 + 8 * 10 + 8 * 6 + 8 * 5 + 8 + 4 * 2
+    assert C.sizeof(B.SphParams) == 4 * 6 + 8 * 10 + 8 * 6 + 8 * 5 + 8 + 4 * 4
     assert C.sizeof(B.SphState) == 8 + 4 + 4 + 8 * 13
     assert C.sizeof(B.SphNlist) == 8 + 8 * 2
     assert C.sizeof(B.SphDerived) == 8 * 11

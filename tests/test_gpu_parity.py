@@ -289,3 +289,27 @@ def test_bin_reuse_matches_sorting_every_step():
     err = _traj_errors(prm, out[1], out[0])
     print(err, flush=True)
     assert all(v < 1e-9 for v in err.values()), err
+
+
+@pytest.mark.parametrize("name,caps", [("C4", (1, 14)), ("C5", (1, 52))])
+def test_candidate_lists_match_stencil_search(name, caps):
+    """The step path's searches through stored candidate lists give the same
+    neighbour tables, in the same order, as walking the cell stencil: the
+    trajectory with the lists (automatic capacity) is bit-identical to one
+    where every particle overflows its list (capacity 1: every search walks
+    the stencil) and to one where only some do."""
+    _print_case(f"candidate lists {name}")
+    prm, s = I.config(name, small=True)
+    s = I.jitter(prm, s, 0.05, 3, types=(I.FLUID, I.INLET, I.OUTLET))
+    out = []
+    for cap in (0,) + tuple(caps):
+        q = dict(prm, flags=prm["flags"] | I.FLAG_REUSE_BINS, list_cap=cap)
+        sim = B().Simulation(q, s)
+        drag = torch.zeros((80, 3), dtype=torch.float64, device="cuda")
+        sim.step(80, drag_hist=drag)
+        assert sim.poll_error() == 0
+        st = sim.state()
+        out.append(np.concatenate([st["x"].ravel(), st["u"].ravel(), st["p"],
+                                   st["id"].astype(np.float64), drag.cpu().numpy().ravel()]))
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
