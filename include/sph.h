@@ -153,7 +153,8 @@ typedef struct sph_derived {
 
 /* Bytes of workspace needed for capacity `cap` (cell grid, sort buffers,
  * half-state copy, scan scratch, the step path's candidate lists of
- * list_cap (or the automatic count) entries per particle, error word). */
+ * list_cap (or the automatic count) entries per particle, the FP32 force
+ * pass's packed neighbour records, error word); the same for both precisions. */
 int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
 
 /* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D). */

@@ -208,6 +208,9 @@ static WsLayout layout(const Dev &k)
     w.vfresh = take(sizeof(int32_t));
     w.vcount = take(sizeof(int32_t) * C);
     w.vnbr = take(k.lists ? sizeof(int32_t) * size_t(k.vmax) * C : 0);
+    // neighbour records of the FP32 force pass (sized whatever the precision:
+    // the workspace size does not depend on it)
+    w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, float>()) * C);
     w.total = off;
     return w;
 }
@@ -279,6 +282,7 @@ static DevDerived dev_derived(const sph_derived *o)
     d.drag = o->drag;
     d.sfl = o->sfl;
     d.red = o->red;
+    d.rec = nullptr;
     return d;
 }
 
@@ -327,6 +331,13 @@ struct Ctx {
         return f;
     }
     float *off() const { return at<float>(ws, w.off); }
+    // derived buffers plus the workspace's neighbour records
+    DevDerived der(const sph_derived *o) const
+    {
+        DevDerived d = dev_derived(o);
+        d.rec = k.prec == SPH_FP32 ? at<void>(ws, w.rec) : nullptr;
+        return d;
+    }
     double *dragpart() const { return at<double>(ws, w.dragpart); }
 };
 
@@ -385,7 +396,7 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
     v.fresh = at<int32_t>(c.ws, c.w.vfresh);
     v.count = at<int32_t>(c.ws, c.w.vcount);
     v.nbr = at<int32_t>(c.ws, c.w.vnbr);
-    launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? dev_derived(o) : DevDerived{},
+    launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? c.der(o) : DevDerived{},
                    dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
                    at<uint32_t>(c.ws, c.w.cpos_s), c.off(),
                    clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
@@ -394,7 +405,7 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
 static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
                         const sph_derived *o)
 {
-    launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), dev_derived(o),
+    launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), c.der(o),
                     at<int32_t>(c.ws, c.w.blist), at<int32_t>(c.ws, c.w.bcount), c.err(), c.s);
 }
 
@@ -403,7 +414,7 @@ static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields 
                      double *hist)
 {
     const int want = drag || hist;
-    launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), dev_derived(o), c.off(),
+    launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), c.der(o), c.off(),
                  at<uint32_t>(c.ws, c.w.cpos_s), mode, want, c.dragpart(),
                  at<double>(c.ws, c.w.xbin), at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
     if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
@@ -562,8 +573,8 @@ int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
-    launch_density(c.k, dev_state(st), fields_of(st), dev_nlist(nl), dev_derived(out), c.err(),
-                   c.s);
+    launch_density(c.k, dev_state(st), fields_of(st), dev_nlist(nl), c.der(out),
+                   at<uint32_t>(ws, c.w.cpos_s), c.err(), c.s);
     return check_hip("sph_density");
 }
 
@@ -584,7 +595,8 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out))) return rc;
     const Fields F = fields_of(st);
-    launch_density(c.k, dev_state(st), F, dev_nlist(nl), dev_derived(out), c.err(), c.s);
+    launch_density(c.k, dev_state(st), F, dev_nlist(nl), c.der(out), at<uint32_t>(ws, c.w.cpos_s),
+                   c.err(), c.s);
     do_boundary(c, st, F, nl, out);
     do_force(c, st, F, F, nl, out, 0, out->drag, nullptr);
     return check_hip("sph_rhs");

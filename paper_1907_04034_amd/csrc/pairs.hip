@@ -71,6 +71,46 @@ struct Acc<float> {
     }
 };
 
+// Writes the neighbour record of row i (lanes of the group split the 16-byte
+// chunks): the stage's position (FP64) or cell offset (FP32, the same value
+// as the offset array), p, u, w = ut - u, rho, V, the kind and in FP32 the
+// packed cell.
+template <int DIM, typename T, int G>
+__device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &R, void *rec,
+                                 int64_t i, T rho, T vol, const double xi[3], const int c[3],
+                                 uint32_t cposi, int lane)
+{
+    using L = Rec<DIM, T>;
+    const int64_t C = k.cap;
+    T v[L::NC * L::PER];
+#pragma unroll
+    for (int q = 0; q < L::NC * L::PER; ++q) v[q] = T(0);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        if constexpr (L::F32)
+            v[L::X + d] = T(float(xi[d] - (k.lo[d] + double(c[d]) * k.cs[d])));
+        else
+            v[L::X + d] = T(xi[d]);
+        const T u = ld<T>(R.u, d * C + i);
+        v[L::U + d] = u;
+        v[L::W + d] = ld<T>(R.ut, d * C + i) - u;
+    }
+    v[L::P] = ld<T>(R.p, i);
+    v[L::RHO] = rho;
+    v[L::VOL] = vol;
+    if constexpr (L::F32) {
+        v[L::AUX] = rec_word<T>(cposi);
+        v[L::AUX + 1] = rec_word<T>(uint32_t(m.type[i]));
+    } else {
+        v[L::AUX] = rec_word<T>(uint32_t(m.type[i]));
+    }
+    using V = typename Chunk<T>::V;
+    V *dst = reinterpret_cast<V *>(static_cast<T *>(rec) + i * L::N);
+#pragma unroll
+    for (int ch = 0; ch < L::NC; ++ch)
+        if ((ch & (G - 1)) == (lane & (G - 1))) dst[ch] = Chunk<T>::make(v + ch * L::PER);
+}
+
 // ---------------------------------------------- neighbour table + density
 // The 3^d stencil cells, taken in (dz, dy, dx) order and each in member
 // order, form one candidate sequence per target; the group's lanes test
@@ -298,6 +338,8 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
             st<T>(o.vol, i, T(1) / S);
         }
     }
+    if (dens && o.rec)
+        write_rec<DIM, T, G>(k, m, R, o.rec, i, T(k.mass) * S, T(1) / S, xi, c, cpos[i], lane);
     if (sizeof(T) == 4) {
         // offsets from the bin cell's corner, for the FP32 pair arithmetic
         for (int d = lane; d < DIM; d += G)
@@ -309,7 +351,8 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
 // path sums it while building the table).
 template <int DIM, typename T>
 __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R, DevNlist nl,
-                                                    DevDerived o, uint32_t *err)
+                                                    DevDerived o, const uint32_t *cpos,
+                                                    uint32_t *err)
 {
     using P = Grp<DIM>;
     constexpr int G = P::G;
@@ -340,6 +383,29 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
     if (lane == 0) {
         st<T>(o.rho, i, T(k.mass) * S);
         st<T>(o.vol, i, T(1) / S);
+    }
+    if (o.rec) {
+        int c[3] = {0, 0, 0};
+        const uint32_t cp = cpos[i];
+        unpack_cell<DIM>(cp, c);
+        write_rec<DIM, T, G>(k, m, R, o.rec, i, T(k.mass) * S, T(1) / S, xi, c, cp, lane);
+    }
+}
+
+// Record slots of the boundary values just written for row i (p, u, ut - u),
+// read back from the state so that record and state agree bit for bit.
+template <int DIM, typename T>
+__device__ inline void rec_set_pu(const Dev &k, const Fields &R, void *rec, int64_t i)
+{
+    using L = Rec<DIM, T>;
+    const int64_t C = k.cap;
+    T *r = static_cast<T *>(rec) + i * L::N;
+    r[L::P] = ld<T>(R.p, i);
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const T u = ld<T>(R.u, d * C + i);
+        r[L::U + d] = u;
+        r[L::W + d] = ld<T>(R.ut, d * C + i) - u;
     }
 }
 
@@ -390,25 +456,30 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 raise_error(err, SPH_ERR_CELL_RANGE);
                 continue;
             }
+            // the neighbour's kind and the fluid values are loaded together
+            // (one round trip); the values of non-fluid rows are not used
             const int tj = m.type[j];
+            double xj[3] = {0, 0, 0}, uj[3] = {0, 0, 0};
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                xj[d] = R.x[d * C + j];
+                uj[d] = double(ld<T>(R.u, d * C + j));
+            }
+            const double pj = double(ld<T>(R.p, j));
+            const double rhoj = double(ld<T>(o.rho, j));
             if (io && tj == t && m.red_prev[j]) {
 #pragma unroll
                 for (int a = 0; a < 3; ++a) bacc[a] += m.jprev[a * C + j];
                 bM += 1.0;
             }
             if (tj != SPH_FLUID) continue;
-            double xj[3] = {0, 0, 0};
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
             double r[3];
             const double w = wendland_w(sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h, k.wnorm);
-            const double pj = double(ld<T>(R.p, j));
-            const double rhoj = double(ld<T>(o.rho, j));
-            const double uj0 = double(ld<T>(R.u, j));
+            const double uj0 = uj[0];
             sw += w;
             sp += pj * w;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) su[d] += double(ld<T>(R.u, d * C + j)) * w;
+            for (int d = 0; d < DIM; ++d) su[d] += uj[d] * w;
             if (t == SPH_INLET) {
                 sJ[2] += (-rhoj * k.c * (uj0 - uin0) + pj) * w;
             } else if (t == SPH_OUTLET) {
@@ -438,6 +509,7 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 st<T>(R.p, i, T(pw));
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, T(ug[d]));
+                if (o.rec) rec_set_pu<DIM, T>(k, R, o.rec, i);
             }
             continue;
         }
@@ -481,6 +553,7 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                     st<T>(R.ut, d * C + i, T(m.uin[d * C + i]));
                 }
             }
+            if (o.rec) rec_set_pu<DIM, T>(k, R, o.rec, i);
         }
     }
 }
@@ -593,23 +666,47 @@ struct Nbr {
     T r[3], r2, u[3], w[3], p, rho, vol;  // w = ut - u
 };
 
+// One neighbour's data: FP32 from its record (Rec) in a few 16-byte loads;
+// FP64 one load per field from the state and derived arrays (measured: the
+// 128- and 80-byte FP64 records made the force pass slower, 1.93 -> 2.11 ms
+// on the 4.6M-particle duct, while FP32 records cut it 1.67 -> 1.23 ms).
 template <int DIM, typename T>
 __device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R,
                                 const DevDerived &o, const float *off, const uint32_t *cpos,
                                 const Sep<DIM, T> &sep, int32_t j, Nbr<DIM, T> &nb)
 {
-    const int64_t C = k.cap;
+    using L = Rec<DIM, T>;
     nb.j = j;
-    nb.tj = m.type[j];
-    nb.r2 = sep.get(k, R, off, cpos, j, nb.r);
+    if constexpr (L::F32) {
+        using V = typename Chunk<T>::V;
+        const V *src =
+            reinterpret_cast<const V *>(static_cast<const T *>(o.rec) + int64_t(j) * L::N);
+        T v[L::NC * L::PER];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        nb.u[d] = ld<T>(R.u, d * C + j);
-        nb.w[d] = ld<T>(R.ut, d * C + j) - nb.u[d];
+        for (int ch = 0; ch < L::NC; ++ch) Chunk<T>::get(src[ch], v + ch * L::PER);
+        nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
+        nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            nb.u[d] = v[L::U + d];
+            nb.w[d] = v[L::W + d];
+        }
+        nb.p = v[L::P];
+        nb.rho = v[L::RHO];
+        nb.vol = v[L::VOL];
+    } else {
+        const int64_t C = k.cap;
+        nb.tj = m.type[j];
+        nb.r2 = sep.get(k, R, off, cpos, j, nb.r);
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            nb.u[d] = ld<T>(R.u, d * C + j);
+            nb.w[d] = ld<T>(R.ut, d * C + j) - nb.u[d];
+        }
+        nb.p = ld<T>(R.p, j);
+        nb.rho = ld<T>(o.rho, j);
+        nb.vol = ld<T>(o.vol, j);
     }
-    nb.p = ld<T>(R.p, j);
-    nb.rho = ld<T>(o.rho, j);
-    nb.vol = ld<T>(o.vol, j);
 }
 
 // Contribution of neighbour nb to target i (see the force-pass comment).
@@ -673,7 +770,7 @@ __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3
 // Inlet particles move with their prescribed velocity, outlet particles along
 // x with their composed velocity, walls are fixed; in the full update the
 // boundary values of the half state become those of the step.
-template <int DIM, typename T, int G>
+template <int DIM, typename T, int G, int PF>
 __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, Fields W,
                                                   DevNlist nl, DevDerived o, const float *off,
                                                   const uint32_t *cpos, int mode, int want_drag,
@@ -704,35 +801,48 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
             const T rhoi = ld<T>(o.rho, i);
             const T vi = ld<T>(o.vol, i);
             const T vi2 = vi * vi;
-            // the lane's first two neighbours are loaded before the pbar
-            // reduction (both indices first, then both rows), so that with at
-            // most 2G neighbours all gathers form two round trips
-            const bool have0 = lane < cnt, have1 = lane + G < cnt;
-            const int32_t j0 = have0 ? nl.nbr[i * nl.maxnb + lane] : -1;
-            const int32_t j1 = have1 ? nl.nbr[i * nl.maxnb + lane + G] : -1;
-            const bool ok0 = have0 && !bad_index(j0, n), ok1 = have1 && !bad_index(j1, n);
-            if ((have0 && !ok0) || (have1 && !ok1)) raise_error(err, SPH_ERR_CELL_RANGE);
-            Nbr<DIM, T> nb0, nb1;
-            if (ok0) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j0, nb0);
-            if (ok1) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j1, nb1);
+            // the lane's first PF neighbours are loaded before the pbar
+            // reduction (all indices first, then all rows), so that with at
+            // most PF*G neighbours all gathers form two round trips; the
+            // indices are read whatever the count (within the row's maxnb
+            // entries; entries past the count are not used)
+            const int32_t *row = nl.nbr + i * nl.maxnb;
+            int32_t jp[PF];
+            bool okp[PF];
+#pragma unroll
+            for (int f = 0; f < PF; ++f) jp[f] = lane + f * G < nl.maxnb ? row[lane + f * G] : -1;
+            bool badp = false;
+#pragma unroll
+            for (int f = 0; f < PF; ++f) {
+                const bool have = lane + f * G < cnt;
+                okp[f] = have && !bad_index(jp[f], n);
+                badp = badp || (have && !okp[f]);
+            }
+            if (badp) raise_error(err, SPH_ERR_CELL_RANGE);
+            Nbr<DIM, T> nbp[PF];
+#pragma unroll
+            for (int f = 0; f < PF; ++f)
+                if (okp[f]) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, jp[f], nbp[f]);
             T pavg = T(0);
             if (!(k.flags & SPH_FLAG_NO_PAVG)) {
                 Acc<T> sp;
-                if (ok0) sp.add(nb0.p);
-                if (ok1) sp.add(nb1.p);
-                for (int q = lane + 2 * G; q < cnt; q += G) {
-                    const int32_t j = nl.nbr[i * nl.maxnb + q];
+#pragma unroll
+                for (int f = 0; f < PF; ++f)
+                    if (okp[f]) sp.add(nbp[f].p);
+                for (int q = lane + PF * G; q < cnt; q += G) {
+                    const int32_t j = row[q];
                     if (!bad_index(j, n)) sp.add(ld<T>(R.p, j));
                 }
                 pavg = sp.template reduce<G>() / T(cnt);
             }
             Acc<T> acc[3], bacc[3], pdot;
-            if (ok0 && j0 != i && !(t == SPH_BODY && nb0.tj != SPH_FLUID))
-                pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb0, acc, bacc, pdot, fb);
-            if (ok1 && j1 != i && !(t == SPH_BODY && nb1.tj != SPH_FLUID))
-                pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb1, acc, bacc, pdot, fb);
-            for (int q = lane + 2 * G; q < cnt; q += G) {
-                const int32_t j = nl.nbr[i * nl.maxnb + q];
+#pragma unroll
+            for (int f = 0; f < PF; ++f)
+                if (okp[f] && jp[f] != i && !(t == SPH_BODY && nbp[f].tj != SPH_FLUID))
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nbp[f], acc, bacc, pdot,
+                                     fb);
+            for (int q = lane + PF * G; q < cnt; q += G) {
+                const int32_t j = row[q];
                 if (bad_index(j, n)) {
                     raise_error(err, SPH_ERR_CELL_RANGE);
                     continue;
@@ -842,9 +952,11 @@ int force_grid_max(const Dev &k) { return grid_for(k, 32); }
 template <int DIM>
 static int bnd_grid(const Dev &k)
 {
-    // grid-stride over the device-side count of boundary rows
+    // grid-stride over the device-side count of boundary rows; enough blocks
+    // that large systems (a 3D duct's walls are a quarter of its particles)
+    // keep every CU busy (blocks past the count exit at once)
     const int64_t want = (k.cap + Grp<DIM>::PER_BLOCK - 1) / Grp<DIM>::PER_BLOCK;
-    return int(want < 1024 ? want : 1024);
+    return int(want < 16384 ? want : 16384);
 }
 
 #define SPH_PREC_DIM(KERNEL, GRID, ...)                                                       \
@@ -916,10 +1028,10 @@ void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevN
 }
 
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
-                    const DevDerived &o, uint32_t *err, hipStream_t s)
+                    const DevDerived &o, const uint32_t *cpos, uint32_t *err, hipStream_t s)
 {
     SPH_PREC_DIM(k_density, (k.dim == 2 ? grid_for(k, Grp<2>::G) : grid_for(k, Grp<3>::G)), k, m,
-                 R, nl, o, err);
+                 R, nl, o, cpos, err);
 }
 
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
@@ -930,31 +1042,36 @@ void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const Dev
                  blist, bcount, err);
 }
 
-template <int DIM, typename T, int G>
+template <int DIM, typename T, int G, int PF>
 static void force_g(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                     const DevNlist &nl, const DevDerived &o, const float *off,
                     const uint32_t *cpos, int mode, int want_drag, double *dragpart,
                     const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_force<DIM, T, G>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m, R, W,
-                       nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, err);
+    hipLaunchKernelGGL((k_force<DIM, T, G, PF>), dim3(grid_for(k, G)), dim3(kBlock), 0, s, k, m,
+                       R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, err);
 }
 
+// Two neighbours prefetched per lane (one from 16 lanes up). Measured: four
+// per lane (16 per target at 4 lanes) slows the 41k-particle channel's force
+// pass from 14.4 to 16.9 us, as 173 registers allow two waves per SIMD and the
+// grid then needs a second round.
 template <int DIM, typename T>
 static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                      const DevNlist &nl, const DevDerived &o, const float *off,
                      const uint32_t *cpos, int mode, int want_drag, double *dragpart,
                      const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s)
 {
-#define SPH_FORCE_G(G) \
-    force_g<DIM, T, G>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, err, s)
+#define SPH_FORCE_G(G, PF)                                                                   \
+    force_g<DIM, T, G, PF>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, \
+                           err, s)
     switch (force_group(k)) {
-    case 1: SPH_FORCE_G(1); break;
-    case 2: SPH_FORCE_G(2); break;
-    case 4: SPH_FORCE_G(4); break;
-    case 8: SPH_FORCE_G(8); break;
-    case 16: SPH_FORCE_G(16); break;
-    default: SPH_FORCE_G(32); break;
+    case 1: SPH_FORCE_G(1, 2); break;
+    case 2: SPH_FORCE_G(2, 2); break;
+    case 4: SPH_FORCE_G(4, 2); break;
+    case 8: SPH_FORCE_G(8, 2); break;
+    case 16: SPH_FORCE_G(16, 1); break;
+    default: SPH_FORCE_G(32, 1); break;
     }
 #undef SPH_FORCE_G
 }

@@ -62,7 +62,56 @@ struct DevDerived {
     void *rho, *vol, *pavg, *a, *b, *pdot;
     double *jcur, *force, *drag, *sfl;
     uint8_t *red;
+    void *rec;  // neighbour records of the force pass (Rec), [cap][Rec::N]
 };
+
+// Neighbour record: what the force pass gathers of a neighbour j, packed so
+// that it arrives in a few 16-byte loads instead of one load per field
+// (positions or FP32 cell offsets, p, u, w = ut - u, rho, V, kind and, in FP32,
+// the packed cell). Written by the density pass (every row) and the boundary
+// pass (the values it sets), in the state's element type; slots in T units.
+// The library keeps records for FP32 states only.
+template <int DIM, typename T>
+struct Rec {
+    static constexpr int X = 0, P = DIM, U = 4, RHO = DIM == 3 ? 7 : 3, W = DIM == 3 ? 8 : 6,
+                         VOL = DIM == 3 ? 11 : 8, AUX = DIM == 3 ? 12 : 9;
+    static constexpr bool F32 = sizeof(T) == 4;
+    static constexpr int USED = AUX + (F32 ? 2 : 1);   // FP32: cell bits, kind bits; FP64: kind
+    static constexpr int PER = 16 / int(sizeof(T));    // T per 16-byte chunk
+    static constexpr int NC = (USED + PER - 1) / PER;  // chunks that carry data
+    static constexpr int N = DIM == 3 ? 16 : (F32 ? 12 : 10);  // stride in T (16-byte multiple)
+};
+template <int DIM, typename T>
+inline size_t rec_bytes() { return sizeof(T) * Rec<DIM, T>::N; }
+
+template <typename T>
+struct Chunk;
+template <>
+struct Chunk<float> {
+    using V = float4;
+    __device__ static inline void get(const V &c, float *v) { v[0] = c.x; v[1] = c.y; v[2] = c.z; v[3] = c.w; }
+    __device__ static inline V make(const float *v) { return V{v[0], v[1], v[2], v[3]}; }
+};
+template <>
+struct Chunk<double> {
+    using V = double2;
+    __device__ static inline void get(const V &c, double *v) { v[0] = c.x; v[1] = c.y; }
+    __device__ static inline V make(const double *v) { return V{v[0], v[1]}; }
+};
+
+// kind and packed cell stored in record slots (bit copies in FP32)
+template <typename T>
+__device__ inline T rec_word(uint32_t w);
+template <>
+__device__ inline float rec_word<float>(uint32_t w) { return __uint_as_float(w); }
+template <>
+__device__ inline double rec_word<double>(uint32_t w) { return double(w); }
+template <typename T>
+__device__ inline uint32_t rec_uint(T v);
+template <>
+__device__ inline uint32_t rec_uint<float>(float v) { return __float_as_uint(v); }
+template <>
+__device__ inline uint32_t rec_uint<double>(double v) { return uint32_t(v); }
 
 // Objective weights and gradient buffers of the reverse pass: the weights on
 // a, b, pdot in the state's element type, every other array FP64; pair
@@ -159,7 +208,7 @@ struct VList {
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, tmp, cpos,
         cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
-        vnbr, total;
+        vnbr, rec, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)
@@ -287,6 +336,14 @@ struct Sep<DIM, double> {
         for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * k.cap + j];
         return dist2_exact<DIM>(k, xi, xj, r);
     }
+    // the same from a neighbour record's slots (positions at Rec::X)
+    __device__ inline double get_rec(const Dev &k, const double *v, double r[3]) const
+    {
+        double xj[3] = {0, 0, 0};
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) xj[d] = v[d];
+        return dist2_exact<DIM>(k, xi, xj, r);
+    }
 };
 
 template <int DIM>
@@ -316,6 +373,25 @@ struct Sep<DIM, float> {
                 else if (dc < -1) dc += k.nc[d];
             }
             r[d] = (oi[d] - off[d * k.cap + j]) + float(dc) * k.csf[d];
+            s += r[d] * r[d];
+        }
+        return s;
+    }
+    // the same from a neighbour record: offsets at Rec::X, packed cell cpj
+    __device__ inline float get_rec(const Dev &k, const float *v, uint32_t cpj, float r[3]) const
+    {
+        int cj[3];
+        unpack_cell<DIM>(cpj, cj);
+        float s = 0.f;
+        r[2] = 0.f;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            int dc = ci[d] - cj[d];
+            if (k.periodic[d]) {
+                if (dc > 1) dc -= k.nc[d];
+                else if (dc < -1) dc += k.nc[d];
+            }
+            r[d] = (oi[d] - v[d]) + float(dc) * k.csf[d];
             s += r[d] * r[d];
         }
         return s;

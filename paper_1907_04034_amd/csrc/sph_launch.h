@@ -34,7 +34,7 @@ void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevN
                     int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
                     hipStream_t s);
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
-                    const DevDerived &o, uint32_t *err, hipStream_t s);
+                    const DevDerived &o, const uint32_t *cpos, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                      const DevDerived &o, const int32_t *blist, const int32_t *bcount,
                      uint32_t *err, hipStream_t s);
