@@ -199,8 +199,11 @@ int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist
 int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_derived *out,
             void *ws, size_t ws_bytes, void *stream);
 
-/* The force pass alone (needs sph_density and sph_outlet_extrapolate on the
- * same neighbour table first): eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
+/* The force pass alone (needs sph_density, or sph_neighbors with out, and
+ * sph_outlet_extrapolate on the same neighbour table, state and workspace
+ * first; for FP32 states those passes leave packed copies of each particle's
+ * values in the workspace, which this pass gathers, so the state must not
+ * change in between): eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
  * eq:p-edac and the background term of eq:transport-vel for fluid particles;
  * eq:tvf-momentum_solid for body particles, reduced into out->drag (skipped
  * when out->drag is NULL, so that the call is exactly one kernel launch). */
