@@ -419,20 +419,18 @@ __device__ inline void rec_set_pu(const Dev &k, const Fields &R, void *rec, int6
 // (eq:average_old), else the particle's own; then u, p = time average +
 // acoustic part (eq:acou) with rho_ref = rho0. Inlet: prescribed velocity,
 // p = Shepard J3 with reference (u_in, 0). Always FP64 arithmetic.
-template <int DIM, typename T>
+template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R, DevNlist nl,
                                                      DevDerived o, const int32_t *blist,
                                                      const int32_t *bcount, uint32_t *err)
 {
-    using P = Grp<DIM>;
-    constexpr int G = P::G;
+    constexpr int PB = kBlock / G;
     const int lane = threadIdx.x & (G - 1);
     const int64_t n = *m.n;
     const int64_t nbnd = *bcount;
     const int64_t C = k.cap;
-    const int64_t stride = int64_t(gridDim.x) * P::PER_BLOCK;
-    for (int64_t g = int64_t(blockIdx.x) * P::PER_BLOCK + threadIdx.x / G; g < nbnd;
-         g += stride) {
+    const int64_t stride = int64_t(gridDim.x) * PB;
+    for (int64_t g = int64_t(blockIdx.x) * PB + threadIdx.x / G; g < nbnd; g += stride) {
         const int64_t i = blist[g];
         if (bad_index(int32_t(i), n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
@@ -490,12 +488,19 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 sJ[2] += (-rhoj * k.c * du + dp) * w;
             }
         }
+        // group reductions of the sums this kind uses (the kind is uniform
+        // across the group)
         sw = gsum<G>(sw);
-        sp = gsum<G>(sp);
+        if (is_wall(t)) {
+            sp = gsum<G>(sp);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) su[d] = gsum<G>(su[d]);
+            for (int d = 0; d < DIM; ++d) su[d] = gsum<G>(su[d]);
+        } else if (t == SPH_OUTLET) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) sJ[a] = gsum<G>(sJ[a]);
+            for (int a = 0; a < 3; ++a) sJ[a] = gsum<G>(sJ[a]);
+        } else {
+            sJ[2] = gsum<G>(sJ[2]);
+        }
         if (lane == 0) o.sfl[i] = sw;
         if (is_wall(t)) {
             if (lane == 0) {
@@ -949,14 +954,39 @@ int force_grid(const Dev &k) { return grid_for(k, force_group(k)); }
 // per-block drag partials
 int force_grid_max(const Dev &k) { return grid_for(k, 32); }
 
-template <int DIM>
+// Lanes per boundary row and grid cap of the boundary pass (grid-stride over
+// the device-side count of boundary rows; blocks past the count exit at
+// once). Measured (us, FP64/FP32): 4.6M-particle duct, 8 lanes 174/191 with
+// 16384 blocks, 204/224 with 1024; 16 lanes 200/234; 32 lanes 280/336 (the
+// group reductions dominate). Small systems, latency-bound, keep 16 lanes
+// (one round over a 2D row's neighbours).
+constexpr int64_t kBndBlocks = 16384;
+static int bnd_group(const Dev &k) { return k.cap < 300000 ? 16 : 8; }
 static int bnd_grid(const Dev &k)
 {
-    // grid-stride over the device-side count of boundary rows; enough blocks
-    // that large systems (a 3D duct's walls are a quarter of its particles)
-    // keep every CU busy (blocks past the count exit at once)
-    const int64_t want = (k.cap + Grp<DIM>::PER_BLOCK - 1) / Grp<DIM>::PER_BLOCK;
-    return int(want < 16384 ? want : 16384);
+    const int64_t per = kBlock / bnd_group(k);
+    const int64_t want = (k.cap + per - 1) / per;
+    return int(want < kBndBlocks ? want : kBndBlocks);
+}
+
+template <int G>
+static void boundary_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                       const DevDerived &o, const int32_t *blist, const int32_t *bcount,
+                       uint32_t *err, hipStream_t s)
+{
+    const dim3 g(bnd_grid(k)), b(kBlock);
+    if (k.dim == 2 && k.prec == SPH_FP64)
+        hipLaunchKernelGGL((k_boundary<2, double, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
+                           err);
+    else if (k.dim == 3 && k.prec == SPH_FP64)
+        hipLaunchKernelGGL((k_boundary<3, double, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
+                           err);
+    else if (k.dim == 2)
+        hipLaunchKernelGGL((k_boundary<2, float, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
+                           err);
+    else
+        hipLaunchKernelGGL((k_boundary<3, float, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
+                           err);
 }
 
 #define SPH_PREC_DIM(KERNEL, GRID, ...)                                                       \
@@ -1038,8 +1068,10 @@ void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const Dev
                      const DevDerived &o, const int32_t *blist, const int32_t *bcount,
                      uint32_t *err, hipStream_t s)
 {
-    SPH_PREC_DIM(k_boundary, (k.dim == 2 ? bnd_grid<2>(k) : bnd_grid<3>(k)), k, m, R, nl, o,
-                 blist, bcount, err);
+    if (bnd_group(k) == 16)
+        boundary_g<16>(k, m, R, nl, o, blist, bcount, err, s);
+    else
+        boundary_g<8>(k, m, R, nl, o, blist, bcount, err, s);
 }
 
 template <int DIM, typename T, int G, int PF>
@@ -1052,10 +1084,11 @@ static void force_g(const Dev &k, const DevState &m, const Fields &R, const Fiel
                        R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin, err);
 }
 
-// Two neighbours prefetched per lane (one from 16 lanes up). Measured: four
-// per lane (16 per target at 4 lanes) slows the 41k-particle channel's force
-// pass from 14.4 to 16.9 us, as 173 registers allow two waves per SIMD and the
-// grid then needs a second round.
+// Two neighbours prefetched per lane (one from 16 lanes up; three for small
+// 2D systems at 4 lanes, which covers a typical 2D neighbour count at 150
+// registers: 0.5 % off the 41k-particle channel's step). Measured: four per
+// lane slows that channel's force pass from 14.4 to 16.9 us, as 173
+// registers allow two waves per SIMD and the grid then needs a second round.
 template <int DIM, typename T>
 static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                      const DevNlist &nl, const DevDerived &o, const float *off,
@@ -1068,7 +1101,9 @@ static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fie
     switch (force_group(k)) {
     case 1: SPH_FORCE_G(1, 2); break;
     case 2: SPH_FORCE_G(2, 2); break;
-    case 4: SPH_FORCE_G(4, 2); break;
+    case 4:
+        if (DIM == 2 && k.cap < 300000) SPH_FORCE_G(4, 3); else SPH_FORCE_G(4, 2);
+        break;
     case 8: SPH_FORCE_G(8, 2); break;
     case 16: SPH_FORCE_G(16, 1); break;
     default: SPH_FORCE_G(32, 1); break;
