@@ -314,6 +314,45 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
                      const sph_state_adjoint *lam_next, sph_state_adjoint *lam, void *scratch,
                      size_t scratch_bytes, void *ws, size_t ws_bytes, void *stream);
 
+/* Stage values of one recorded step, kept so that its reverse need not
+ * recompute the step (caller-owned device buffers, capacity and precision of
+ * the simulation's state; a checkpointed reverse keeps one per step of a
+ * segment). start: the step's sorted start state with its stage-1 boundary
+ * values (own live-count pointer); perm[r]: row before the sort of sorted row
+ * r; cell[r]: packed bin cell of sorted row r; nl1/d1, nl2/d2: the stage
+ * neighbour tables and derived values (a, b, pdot, force, drag may be NULL);
+ * half_*: the half state ([3][cap] x in FP64, [3][cap] u, ut and [cap] p in
+ * the state's element type); off1/off2: [3][cap] FP32 cell offsets of the
+ * two stages' positions (FP32 states only; NULL for FP64). */
+typedef struct sph_step_store {
+    sph_state start;
+    int32_t *perm;
+    uint32_t *cell;
+    sph_nlist nl1, nl2;
+    sph_derived d1, d2;
+    double *half_x;
+    void *half_u, *half_ut, *half_p;
+    float *off1, *off2;
+} sph_step_store;
+
+/* sph_step_record that also fills *store with the step's stage values (the
+ * step itself is bit-identical to sph_step_record's; nl and out are not
+ * written: the step's tables and derived values go to the store). */
+int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
+                          sph_step_store *store, double *drag, int32_t *child, uint8_t *events,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* sph_step_adjoint from stored stage values instead of a recomputation: st
+ * is the state the step started from (as for sph_step_adjoint), store what
+ * sph_step_record_store kept for that step. Same result, bit for bit, as
+ * sph_step_adjoint on the same step. */
+int sph_step_adjoint_stored(const sph_params *prm, const sph_state *st,
+                            const sph_step_store *store, const int32_t *child,
+                            const uint8_t *events, const double fbar[3],
+                            const sph_state_adjoint *lam_next, sph_state_adjoint *lam,
+                            void *scratch, size_t scratch_bytes, void *ws, size_t ws_bytes,
+                            void *stream);
+
 /* Gradient with respect to an inlet velocity profile theta[ntheta] that set,
  * for every row q of st with index[q] = k >= 0, the x components of u_in, u,
  * ut, every ring slot and the mean to theta[k]:

@@ -2,11 +2,15 @@
 
 The forward run keeps a copy of the state every `segment` steps. The reverse
 goes segment by segment from the end: it restores the segment's checkpoint,
-replays the segment with sph_step_record (keeping the state before every step
-and the step's recorded events), then runs sph_step_adjoint from the last step
-of the segment to the first. The replay is bit-identical to the forward run
-(deterministic kernels, fixed summation orders), so the reverse sees the
-forward's discrete events.
+replays the segment with sph_step_record_store (keeping the state before every
+step, the step's recorded events and its stage values: sorted start state,
+tables, derived values, half state), then runs sph_step_adjoint_stored from the
+last step of the segment to the first. The replay is bit-identical to the
+forward run (deterministic kernels, fixed summation orders), so the reverse
+sees the forward's discrete events. With stored=False the tape keeps only the
+states and events, and sph_step_adjoint recomputes each step's stage values
+(the same result, bit for bit, for about a third more work and a few tens of
+MB per step less memory).
 
 Objective used by the wind-tunnel workload with a cylinder: the time-averaged
 stage-1 drag J = (1/N) sum_n F_x^n (the force of eq:tvf-momentum_solid on the
@@ -31,9 +35,10 @@ _LAM_FIELDS = ("x", "u", "ut", "p", "uin", "ring", "avg", "jprev")
 class StepTape:
     """Recording and reverse buffers of one Simulation (FP64 adjoint arrays)."""
 
-    def __init__(self, sim, segment):
+    def __init__(self, sim, segment, stored=True):
         t = sim.torch
-        self.sim, self.segment = sim, int(segment)
+        self.sim, self.segment, self.stored = sim, int(segment), bool(stored)
+        self.stores = []
         cap, D, dev = sim.cap, sim.dim, sim.dev
         self.work = sim._alloc()
         self.work_n = t.zeros(1, dtype=t.int64, device=dev)
@@ -78,6 +83,52 @@ class StepTape:
             self.slot_st.append(self._struct(b, n))
         return self.slots[j], self.slot_n[j], self.slot_st[j]
 
+    def reserve(self):
+        """Allocates the buffers of every slot of a segment up front (state
+        copies and, stored, stage values), so that runs allocate nothing."""
+        for j in range(self.segment):
+            self._slot(j)
+            if self.stored:
+                self._store(j)
+
+    def _store(self, j):
+        """Stage-value buffers of slot j (sph_step_store)."""
+        while len(self.stores) <= j:
+            self.stores.append(self._store_alloc())
+        return self.stores[j]
+
+    def _store_alloc(self):
+        s, t = self.sim, self.sim.torch
+        cap, dev, rdt = s.cap, s.dev, s.rdt
+        i32, f64, f32 = t.int32, t.float64, t.float32
+        b = dict(start=s._alloc(), n=t.zeros(1, dtype=t.int64, device=dev),
+                 perm=t.zeros(cap, dtype=i32, device=dev), cell=t.zeros(cap, dtype=i32, device=dev),
+                 half_x=t.zeros(3 * cap, dtype=f64, device=dev),
+                 half_u=t.zeros(3 * cap, dtype=rdt, device=dev),
+                 half_ut=t.zeros(3 * cap, dtype=rdt, device=dev),
+                 half_p=t.zeros(cap, dtype=rdt, device=dev))
+        nls, ders = [], []
+        for _ in range(2):
+            cnt = t.zeros(cap, dtype=i32, device=dev)
+            nbr = t.zeros(s.maxnb * cap, dtype=i32, device=dev)
+            nls.append((cnt, nbr, Bd.SphNlist(s.maxnb, cnt.data_ptr(), nbr.data_ptr())))
+            # a, b, pdot, force, drag are not read by the reverse: shared
+            d = {k: t.zeros_like(s.der[k]) for k in ("rho", "vol", "pavg", "jcur", "red", "sfl")}
+            d.update({k: s.der[k] for k in ("a", "b", "pdot", "force", "drag")})
+            ders.append((d, Bd.SphDerived(*[d[k].data_ptr() for k in
+                                           ("rho", "vol", "pavg", "a", "b", "pdot", "jcur", "red",
+                                            "force", "drag", "sfl")])))
+        offs = [t.zeros(3 * cap, dtype=f32, device=dev) if s.prec == Bd.FP32 else None
+                for _ in range(2)]
+        b.update(nls=nls, ders=ders, offs=offs)
+        b["_s"] = Bd.SphStepStore(
+            self._struct(b["start"], b["n"]), b["perm"].data_ptr(), b["cell"].data_ptr(),
+            nls[0][2], nls[1][2], ders[0][1], ders[1][1], b["half_x"].data_ptr(),
+            b["half_u"].data_ptr(), b["half_ut"].data_ptr(), b["half_p"].data_ptr(),
+            offs[0].data_ptr() if offs[0] is not None else None,
+            offs[1].data_ptr() if offs[1] is not None else None)
+        return b
+
     def snapshot(self):
         """Device copy of the simulation's current state."""
         b = self.sim._alloc()
@@ -97,10 +148,17 @@ class StepTape:
         Bd.Simulation.copy_state(b, s._current())
         n.copy_(s.n_dev)
         ws, nb = s._ws()
-        Bd._check(Bd.lib().sph_step_record(
-            C.byref(s.q), C.byref(s.st), C.byref(s.alt), C.byref(s.nl), C.byref(s.out),
-            drag.data_ptr() if drag is not None else None, self.child[j].data_ptr(),
-            self.events[j].data_ptr(), ws, nb, s.stream), "sph_step_record")
+        dp = drag.data_ptr() if drag is not None else None
+        if self.stored:
+            Bd._check(Bd.lib().sph_step_record_store(
+                C.byref(s.q), C.byref(s.st), C.byref(s.alt), C.byref(self._store(j)["_s"]), dp,
+                self.child[j].data_ptr(), self.events[j].data_ptr(), ws, nb, s.stream),
+                "sph_step_record_store")
+        else:
+            Bd._check(Bd.lib().sph_step_record(
+                C.byref(s.q), C.byref(s.st), C.byref(s.alt), C.byref(s.nl), C.byref(s.out), dp,
+                self.child[j].data_ptr(), self.events[j].data_ptr(), ws, nb, s.stream),
+                "sph_step_record")
         s.binned = True
 
     def reverse(self, j, fbar, lam_next, lam):
@@ -109,6 +167,13 @@ class StepTape:
         _, _, st = self._slot(j)
         fb = (C.c_double * 3)(*[float(v) for v in fbar])
         ws, nb = s._ws()
+        if self.stored:
+            Bd._check(Bd.lib().sph_step_adjoint_stored(
+                C.byref(s.q), C.byref(st), C.byref(self._store(j)["_s"]),
+                self.child[j].data_ptr(), self.events[j].data_ptr(), C.byref(fb),
+                C.byref(lam_next["_s"]), C.byref(lam["_s"]), self.scratch.data_ptr(),
+                self.scratch_bytes, ws, nb, s.stream), "sph_step_adjoint_stored")
+            return
         Bd._check(Bd.lib().sph_step_adjoint(
             C.byref(s.q), C.byref(st), C.byref(self.work_st), self.child[j].data_ptr(),
             self.events[j].data_ptr(), C.byref(s.nl), C.byref(self.nl2), C.byref(s.out),
@@ -127,13 +192,14 @@ class DragAdjoint:
     initial state's order, plus a final-state adjoint `lam_final` if given.
     """
 
-    def __init__(self, sim, nsteps, segment=50):
+    def __init__(self, sim, nsteps, segment=50, stored=True):
         # the replays sort at every step; the checkpointed forward must match
         # them row for row, so it does not keep cell orders across steps
         sim.q.flags &= ~Bd.FLAG_REUSE_BINS
         self.sim, self.nsteps = sim, int(nsteps)
         self.segment = max(1, min(int(segment), self.nsteps))
-        self.tape = StepTape(sim, self.segment)
+        self.tape = StepTape(sim, self.segment, stored=stored)
+        self.tape.reserve()
         self.ckpts = []
         self._tape_holds_last = False
 

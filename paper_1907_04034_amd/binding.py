@@ -23,8 +23,8 @@ ERR_BITS = {1: "NBR_OVERFLOW", 2: "CAPACITY", 4: "NONFINITE", 8: "SKIN", 16: "ES
 EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors",
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
             "sph_rhs_adjoint", "sph_outlet_extrapolate_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
-            "sph_step_adjoint", "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count",
-            "sph_last_error"]
+            "sph_step_adjoint", "sph_step_record_store", "sph_step_adjoint_stored",
+            "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count", "sph_last_error"]
 EV_PUSH, EV_TO_OUTLET, EV_DELETE, EV_SPAWN = 1, 2, 4, 8
 FLAG_REUSE_BINS = 8
 
@@ -75,6 +75,12 @@ class SphDerived(C.Structure):
                 ("jcur", _P), ("red", _P), ("force", _P), ("drag", _P), ("sfl", _P)]
 
 
+class SphStepStore(C.Structure):
+    _fields_ = [("start", SphState), ("perm", _P), ("cell", _P), ("nl1", SphNlist),
+                ("nl2", SphNlist), ("d1", SphDerived), ("d2", SphDerived), ("half_x", _P),
+                ("half_u", _P), ("half_ut", _P), ("half_p", _P), ("off1", _P), ("off2", _P)]
+
+
 _lib = None
 
 
@@ -105,6 +111,10 @@ def lib():
         L.sph_step_adjoint_scratch_size.argtypes = [SP, C.c_int64, C.POINTER(C.c_size_t)]
         L.sph_step_adjoint.argtypes = [SP, ST, ST, _P, _P, NL, NL, DE, DE,
                                        C.POINTER(C.c_double * 3), LA, LA, _P, sz, _P, sz, _P]
+        SS = C.POINTER(SphStepStore)
+        L.sph_step_record_store.argtypes = [SP, ST, ST, SS, _P, _P, _P, _P, sz, _P]
+        L.sph_step_adjoint_stored.argtypes = [SP, ST, SS, _P, _P, C.POINTER(C.c_double * 3), LA,
+                                              LA, _P, sz, _P, sz, _P]
         L.sph_inlet_profile_grad.argtypes = [SP, ST, LA, _P, C.c_int32, _P, _P]
         L.sph_poll_error.argtypes = [_P, sz, C.POINTER(C.c_uint32), _P]
         L.sph_live_count.argtypes = [ST, C.POINTER(C.c_int64), _P]

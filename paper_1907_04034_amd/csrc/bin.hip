@@ -281,6 +281,71 @@ void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s
                        k, spread, rebin);
 }
 
+// Row-for-row copy of the live rows of a into b (every state array and the
+// live count), plus the sort permutation and the packed cells of those rows.
+template <int DIM, typename T>
+__global__ void k_copy_rows(Dev k, DevState a, DevState b, const int32_t *perm_in,
+                            int32_t *perm_out, const uint32_t *cell_in, uint32_t *cell_out)
+{
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = *a.n;
+    if (r == 0 && blockIdx.y == 0) *b.n = n;
+    if (r >= n) return;
+    const int64_t C = k.cap;
+    constexpr int NR = kNavg * (DIM + 1);
+    switch (blockIdx.y) {
+    case 0:
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            b.x[d * C + r] = a.x[d * C + r];
+            st<T>(b.u, d * C + r, ld<T>(a.u, d * C + r));
+            st<T>(b.ut, d * C + r, ld<T>(a.ut, d * C + r));
+            b.uin[d * C + r] = a.uin[d * C + r];
+        }
+        st<T>(b.p, r, ld<T>(a.p, r));
+        b.head[r] = a.head[r];
+        b.red_prev[r] = a.red_prev[r];
+        b.type[r] = a.type[r];
+        b.id[r] = a.id[r];
+        perm_out[r] = perm_in[r];
+        cell_out[r] = cell_in[r];
+        break;
+    case 1:
+#pragma unroll
+        for (int q = 0; q < NR / 2; ++q) b.ring[q * C + r] = a.ring[q * C + r];
+        break;
+    case 2:
+#pragma unroll
+        for (int q = NR / 2; q < NR; ++q) b.ring[q * C + r] = a.ring[q * C + r];
+        break;
+    default:
+#pragma unroll
+        for (int q = 0; q < DIM + 1; ++q) b.avg[q * C + r] = a.avg[q * C + r];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b.jprev[q * C + r] = a.jprev[q * C + r];
+        break;
+    }
+}
+
+void launch_copy_rows(const Dev &k, const DevState &a, const DevState &b, const int32_t *perm_in,
+                      int32_t *perm_out, const uint32_t *cell_in, uint32_t *cell_out,
+                      hipStream_t s)
+{
+    const dim3 g(nblocks(k.cap), 4), blk(kBlock);
+    if (k.dim == 2 && k.prec == SPH_FP64)
+        hipLaunchKernelGGL((k_copy_rows<2, double>), g, blk, 0, s, k, a, b, perm_in, perm_out,
+                           cell_in, cell_out);
+    else if (k.dim == 3 && k.prec == SPH_FP64)
+        hipLaunchKernelGGL((k_copy_rows<3, double>), g, blk, 0, s, k, a, b, perm_in, perm_out,
+                           cell_in, cell_out);
+    else if (k.dim == 2)
+        hipLaunchKernelGGL((k_copy_rows<2, float>), g, blk, 0, s, k, a, b, perm_in, perm_out,
+                           cell_in, cell_out);
+    else
+        hipLaunchKernelGGL((k_copy_rows<3, float>), g, blk, 0, s, k, a, b, perm_in, perm_out,
+                           cell_in, cell_out);
+}
+
 void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBufs &w,
                 uint32_t *err, hipStream_t s)
 {

@@ -389,7 +389,8 @@ static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
 // vmode: 0 stencil search; 1 first search of a step (records the candidate
 // lists after a sort, else walks them); 2 walks the lists
 static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
-                       const sph_derived *o, int dens, int vmode, bool clear_rebin = false)
+                       const sph_derived *o, int dens, int vmode, bool clear_rebin = false,
+                       float *off = nullptr)
 {
     if (!c.k.lists) vmode = 0;
     VList v;
@@ -398,7 +399,7 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
     v.nbr = at<int32_t>(c.ws, c.w.vnbr);
     launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? c.der(o) : DevDerived{},
                    dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
-                   at<uint32_t>(c.ws, c.w.cpos_s), c.off(),
+                   at<uint32_t>(c.ws, c.w.cpos_s), off ? off : c.off(),
                    clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
 }
 
@@ -411,10 +412,10 @@ static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_
 
 static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields &W,
                      const sph_nlist *nl, const sph_derived *o, int mode, double *drag,
-                     double *hist)
+                     double *hist, const float *off = nullptr)
 {
     const int want = drag || hist;
-    launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), c.der(o), c.off(),
+    launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), c.der(o), off ? off : c.off(),
                  at<uint32_t>(c.ws, c.w.cpos_s), mode, want, c.dragpart(),
                  at<double>(c.ws, c.w.xbin), at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
     if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
@@ -662,61 +663,47 @@ int sph_step_adjoint_scratch_size(const sph_params *prm, int64_t cap, size_t *by
     return SPH_OK;
 }
 
-int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work,
-                     const int32_t *child, const uint8_t *events, sph_nlist *nl1,
-                     sph_nlist *nl2, sph_derived *d1, sph_derived *d2, const double fbar[3],
-                     const sph_state_adjoint *lam_next, sph_state_adjoint *lam, void *scratch,
-                     size_t scratch_bytes, void *ws, size_t ws_bytes, void *stream)
+// Checks shared by the two reverse entry points.
+static int check_adjoint_args(const sph_state *st, const int32_t *child, const uint8_t *events,
+                              const double fbar[3], const sph_state_adjoint *lam_next,
+                              const sph_state_adjoint *lam, void *scratch,
+                              size_t scratch_bytes)
 {
-    Ctx c;
-    int rc = prepare(prm, st, nl1 ? nl1->maxnb : 0, ws, ws_bytes, stream, &c);
-    if (rc || (rc = check_nlist(nl1)) || (rc = check_nlist(nl2)) ||
-        (rc = check_derived(d1, false)) || (rc = check_derived(d2, false)))
-        return rc;
-    if (nl1->maxnb != nl2->maxnb) return fail(SPH_EINVAL, "nl1 and nl2 differ in maxnb");
-    rc = check_state(work, prm, "work");
-    if (rc) return rc;
-    if (work->cap != st->cap || work->prec != st->prec)
-        return fail(SPH_EINVAL, "work must match state in cap and precision");
-    if (work->n == st->n) return fail(SPH_EINVAL, "work needs its own live-count pointer");
+    int rc;
     if (!child || !events || !fbar) return fail(SPH_EINVAL, "child, events, fbar must not be NULL");
     if ((rc = check_lam(lam_next, st->cap, "lam_next")) || (rc = check_lam(lam, st->cap, "lam")))
         return rc;
-    {
-        const double *a[8] = {lam->x, lam->u, lam->ut, lam->p, lam->uin, lam->ring, lam->avg,
-                              lam->jprev};
-        const double *b[8] = {lam_next->x, lam_next->u,   lam_next->ut,  lam_next->p,
-                              lam_next->uin, lam_next->ring, lam_next->avg, lam_next->jprev};
-        for (int i = 0; i < 8; ++i)
-            for (int j = 0; j < 8; ++j)
-                if (a[i] == b[j]) return fail(SPH_EINVAL, "lam and lam_next share an array");
-    }
+    const double *a[8] = {lam->x, lam->u, lam->ut, lam->p, lam->uin, lam->ring, lam->avg,
+                          lam->jprev};
+    const double *b[8] = {lam_next->x,   lam_next->u,    lam_next->ut,  lam_next->p,
+                          lam_next->uin, lam_next->ring, lam_next->avg, lam_next->jprev};
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j)
+            if (a[i] == b[j]) return fail(SPH_EINVAL, "lam and lam_next share an array");
+    const size_t need = adj_layout().total * sizeof(double) * size_t(st->cap);
+    if (!scratch) return fail(SPH_EINVAL, "scratch is NULL");
+    if (scratch_bytes < need)
+        return fail(SPH_ECAPACITY, "scratch has %zu bytes, needs %zu", scratch_bytes, need);
+    return SPH_OK;
+}
+
+// Reverse of one step from its stage values: the sorted start state m / M
+// (with the stage-1 boundary values), the half state H, the stage tables and
+// derived values, the sort permutation and cells, and the FP32 cell offsets
+// of the two stages (off1 == nullptr: rebuild those of the start state in the
+// workspace before the stage-1 reverse, the workspace then holding stage 2's).
+static void reverse_step(Ctx &c, const sph_state *st, const DevState &m, const Fields &M,
+                         const Fields &H, const int32_t *perm, const uint32_t *cell,
+                         const sph_state *work, const sph_nlist *nl1, const sph_nlist *nl2,
+                         const sph_derived *d1, const sph_derived *d2, const float *off1,
+                         const float *off2, const int32_t *child, const uint8_t *events,
+                         const double fbar[3], const sph_state_adjoint *lam_next,
+                         sph_state_adjoint *lam, void *scratch)
+{
     const AdjLayout L = adj_layout();
     const size_t C = size_t(st->cap);
-    if (!scratch) return fail(SPH_EINVAL, "scratch is NULL");
-    if (scratch_bytes < L.total * sizeof(double) * C)
-        return fail(SPH_ECAPACITY, "scratch has %zu bytes, needs %zu", scratch_bytes,
-                    L.total * sizeof(double) * C);
     double *sc = static_cast<double *>(scratch);
     auto P = [&](size_t off) { return sc + off * C; };
-
-    // recompute the step from st: bin into work (st stays untouched; the
-    // live count goes to work's own pointer), then both stages
-    c.k.reuse = 0;
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
-    launch_adj_prep(st->n, work->n, at<int32_t>(ws, c.w.nspawn), c.s);
-    DevState a = dev_state(st), b = dev_state(work);
-    a.n = work->n;
-    launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
-    const int32_t *perm = at<int32_t>(ws, c.w.tmp);  // sorted row -> row of st
-    const Fields M = fields_of(work), H = c.half();
-    do_nbrdens(c, work, M, nl1, d1, 1, 1);
-    do_boundary(c, work, M, nl1, d1);
-    do_force(c, work, M, H, nl1, d1, 1, nullptr, nullptr);
-    do_nbrdens(c, work, H, nl2, d2, 1, 2);
-    do_boundary(c, work, H, nl2, d2);
-    do_force(c, work, H, H, nl2, d2, 0, nullptr, nullptr);
-
     StepAdj S;
     S.next = dev_lam(lam_next);
     S.out = dev_lam(lam);
@@ -755,22 +742,152 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
     A.Sbar = P(L.Sbar);
     A.jg = P(L.jg);
 
-    const DevState m = dev_state(work);
-    const uint32_t *cpos_s = at<uint32_t>(ws, c.w.cpos_s);
     launch_adj_end(c.k, m, S, A, c.s);
-    launch_rhs_adjoint(c.k, m, H, dev_nlist(nl2), dev_derived(d2), A, c.off(), cpos_s, c.err(),
-                       c.s);
+    launch_rhs_adjoint(c.k, m, H, dev_nlist(nl2), dev_derived(d2), A, off2, cell, c.err(), c.s);
     launch_adj_half(c.k, m, S, A, c.s);
     // the FP32 pair arithmetic reads cell-relative offsets of the stage's
     // positions: rebuild those of the start state (the same table again)
-    if (c.k.prec == SPH_FP32) do_nbrdens(c, work, M, nl1, d1, 0, 2);
+    if (!off1 && c.k.prec == SPH_FP32) do_nbrdens(c, work, M, nl1, d1, 0, 2);
     DevAdj A1 = A;
     A1.jseed = nullptr;
     for (int d = 0; d < 3; ++d) A1.fbar[d] = fbar[d];
-    launch_rhs_adjoint(c.k, m, M, dev_nlist(nl1), dev_derived(d1), A1, c.off(), cpos_s, c.err(),
-                       c.s);
+    launch_rhs_adjoint(c.k, m, M, dev_nlist(nl1), dev_derived(d1), A1, off1 ? off1 : c.off(),
+                       cell, c.err(), c.s);
     launch_adj_finish(c.k, m, dev_state(st), perm, S, A1, c.s);
+}
+
+int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work,
+                     const int32_t *child, const uint8_t *events, sph_nlist *nl1,
+                     sph_nlist *nl2, sph_derived *d1, sph_derived *d2, const double fbar[3],
+                     const sph_state_adjoint *lam_next, sph_state_adjoint *lam, void *scratch,
+                     size_t scratch_bytes, void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl1 ? nl1->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl1)) || (rc = check_nlist(nl2)) ||
+        (rc = check_derived(d1, false)) || (rc = check_derived(d2, false)))
+        return rc;
+    if (nl1->maxnb != nl2->maxnb) return fail(SPH_EINVAL, "nl1 and nl2 differ in maxnb");
+    rc = check_state(work, prm, "work");
+    if (rc) return rc;
+    if (work->cap != st->cap || work->prec != st->prec)
+        return fail(SPH_EINVAL, "work must match state in cap and precision");
+    if (work->n == st->n) return fail(SPH_EINVAL, "work needs its own live-count pointer");
+    if ((rc = check_adjoint_args(st, child, events, fbar, lam_next, lam, scratch,
+                                 scratch_bytes)))
+        return rc;
+
+    // recompute the step from st: bin into work (st stays untouched; the
+    // live count goes to work's own pointer), then both stages
+    c.k.reuse = 0;
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
+    launch_adj_prep(st->n, work->n, at<int32_t>(ws, c.w.nspawn), c.s);
+    DevState a = dev_state(st), b = dev_state(work);
+    a.n = work->n;
+    launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
+    const int32_t *perm = at<int32_t>(ws, c.w.tmp);  // sorted row -> row of st
+    const Fields M = fields_of(work), H = c.half();
+    do_nbrdens(c, work, M, nl1, d1, 1, 1);
+    do_boundary(c, work, M, nl1, d1);
+    do_force(c, work, M, H, nl1, d1, 1, nullptr, nullptr);
+    do_nbrdens(c, work, H, nl2, d2, 1, 2);
+    do_boundary(c, work, H, nl2, d2);
+    do_force(c, work, H, H, nl2, d2, 0, nullptr, nullptr);
+
+    reverse_step(c, st, dev_state(work), M, H, perm, at<uint32_t>(ws, c.w.cpos_s), work, nl1,
+                 nl2, d1, d2, nullptr, c.off(), child, events, fbar, lam_next, lam, scratch);
     return check_hip("sph_step_adjoint");
+}
+
+static int check_store(const sph_step_store *sto, const sph_params *prm, const sph_state *st)
+{
+    if (!sto) return fail(SPH_EINVAL, "store is NULL");
+    int rc = check_state(&sto->start, prm, "store->start");
+    if (rc) return rc;
+    if (sto->start.cap != st->cap || sto->start.prec != st->prec)
+        return fail(SPH_EINVAL, "store->start must match the state in cap and precision");
+    if (sto->start.n == st->n) return fail(SPH_EINVAL, "store->start needs its own live count");
+    if ((rc = check_nlist(&sto->nl1)) || (rc = check_nlist(&sto->nl2)) ||
+        (rc = check_derived(&sto->d1, false)) || (rc = check_derived(&sto->d2, false)))
+        return rc;
+    if (sto->nl1.maxnb != sto->nl2.maxnb) return fail(SPH_EINVAL, "store tables differ in maxnb");
+    if (!sto->perm || !sto->cell || !sto->half_x || !sto->half_u || !sto->half_ut ||
+        !sto->half_p)
+        return fail(SPH_EINVAL, "store has a NULL array");
+    if (st->prec == SPH_FP32 && (!sto->off1 || !sto->off2))
+        return fail(SPH_EINVAL, "an FP32 store needs off1 and off2");
+    return SPH_OK;
+}
+
+static Fields store_half(const sph_step_store *sto)
+{
+    Fields f;
+    f.x = sto->half_x;
+    f.u = sto->half_u;
+    f.ut = sto->half_ut;
+    f.p = sto->half_p;
+    return f;
+}
+
+int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
+                          sph_step_store *store, double *drag, int32_t *child, uint8_t *events,
+                          void *ws, size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, store ? store->nl1.maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_store(store, prm, st))) return rc;
+    rc = check_state(alt, prm, "alt");
+    if (rc) return rc;
+    if (alt->cap != st->cap || alt->prec != st->prec)
+        return fail(SPH_EINVAL, "alt must match state in cap and precision");
+    if (!child || !events) return fail(SPH_EINVAL, "child and events must not be NULL");
+    c.k.reuse = 0;  // as sph_step_record: every recorded step sorts
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
+    const bool f32 = c.k.prec == SPH_FP32;
+    sph_nlist *nl1 = &store->nl1, *nl2 = &store->nl2;
+    sph_derived *d1 = &store->d1, *d2 = &store->d2;
+    const Fields H = store_half(store);
+    // the step of one_step, with the store's tables, derived values, half
+    // state and offsets, and a copy of the start state once stage 1 has set
+    // its boundary values
+    do_bin(c, st, alt);
+    const Fields M = fields_of(st);
+    do_nbrdens(c, st, M, nl1, d1, 1, 1, true, f32 ? store->off1 : nullptr);
+    do_boundary(c, st, M, nl1, d1);
+    do_force(c, st, M, H, nl1, d1, 1, nullptr, drag, f32 ? store->off1 : nullptr);
+    launch_copy_rows(c.k, dev_state(st), dev_state(&store->start), at<int32_t>(ws, c.w.tmp),
+                     store->perm, at<uint32_t>(ws, c.w.cpos_s), store->cell, c.s);
+    do_nbrdens(c, st, H, nl2, d2, 1, 2, false, f32 ? store->off2 : nullptr);
+    do_boundary(c, st, H, nl2, d2);
+    do_force(c, st, H, M, nl2, d2, 2, nullptr, nullptr, f32 ? store->off2 : nullptr);
+    launch_end_of_step(c.k, dev_state(st), dev_derived(d2), at<int32_t>(c.ws, c.w.nspawn),
+                       at<uint8_t>(c.ws, c.w.sflag), at<int32_t>(c.ws, c.w.stile), child, events,
+                       at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
+    launch_finish_spawn(c.k, dev_state(st), at<int32_t>(ws, c.w.nspawn), c.s);
+    return check_hip("sph_step_record_store");
+}
+
+int sph_step_adjoint_stored(const sph_params *prm, const sph_state *st,
+                            const sph_step_store *store, const int32_t *child,
+                            const uint8_t *events, const double fbar[3],
+                            const sph_state_adjoint *lam_next, sph_state_adjoint *lam,
+                            void *scratch, size_t scratch_bytes, void *ws, size_t ws_bytes,
+                            void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, store ? store->nl1.maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_store(store, prm, st))) return rc;
+    if ((rc = check_adjoint_args(st, child, events, fbar, lam_next, lam, scratch,
+                                 scratch_bytes)))
+        return rc;
+    c.k.reuse = 0;
+    const bool f32 = c.k.prec == SPH_FP32;
+    const sph_state *work = &store->start;
+    reverse_step(c, st, dev_state(work), fields_of(work), store_half(store), store->perm,
+                 store->cell, work, &store->nl1, &store->nl2, &store->d1, &store->d2,
+                 f32 ? store->off1 : c.off(), f32 ? store->off2 : c.off(), child, events, fbar,
+                 lam_next, lam, scratch);
+    return check_hip("sph_step_adjoint_stored");
 }
 
 int sph_inlet_profile_grad(const sph_params *prm, const sph_state *st,

@@ -153,22 +153,31 @@ struct StencilWalk {
 };
 
 // candidates of one lane, NB at a time, from a stored list (entries beyond the
-// live rows are reported and skipped)
+// live rows are reported and skipped). Entries are read up to the row's
+// capacity whatever the count, so that the loads need not wait for it;
+// entries past the count are not used.
 template <int NB, int G>
 struct ListWalk {
     const int32_t *list;
-    int q, cnt;
+    int32_t pre[NB];  // the first batch, read ahead by the caller
+    bool first;
+    int q, cnt, cap;
     int64_t n;
     uint32_t *err;
-    __device__ inline ListWalk(const int32_t *l, int c, int lane, int64_t nrows, uint32_t *e)
-        : list(l), q(lane), cnt(c), n(nrows), err(e)
+    __device__ inline ListWalk(const int32_t *l, const int32_t ahead[NB], int c, int rowcap,
+                               int lane, int64_t nrows, uint32_t *e)
+        : list(l), first(true), q(lane), cnt(c), cap(rowcap), n(nrows), err(e)
     {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) pre[b] = ahead[b];
     }
     __device__ inline void next(int32_t jj[NB], bool hv[NB])
     {
+        const bool use_pre = first;
+        first = false;
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int32_t j = q < cnt ? list[q] : 0;
+            const int32_t j = use_pre ? pre[b] : (q < cap ? list[q] : 0);
             const bool bad = q < cnt && bad_index(j, n);
             if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
             hv[b] = q < cnt && !bad;
@@ -280,6 +289,13 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
         for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
         unpack_cell<DIM>(cpos[i], c);
     }
+    // first batch of a stored list, read in the same round trip as its count
+    int32_t *vrow = v.nbr + i * int64_t(k.vmax);
+    int32_t vpre[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+        vpre[b] = (active && vmode != 0 && !build && lane + b * G < k.vmax) ? vrow[lane + b * G]
+                                                                            : 0;
     if (active && vc < 0) {
         // cell ranges of the stencil, one cell per lane at a time
         for (int sc = lane; sc < NS; sc += G) {
@@ -310,11 +326,10 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
     __syncthreads();
     if (!active) return;
     int32_t *row = nl.nbr + i * nl.maxnb;
-    int32_t *vrow = v.nbr + i * int64_t(k.vmax);
     Acc<T> sw;
     int cnt, vcnt = 0;
     if (vc >= 0) {
-        ListWalk<NB, G> w(vrow, vc, lane, n, err);
+        ListWalk<NB, G> w(vrow, vpre, vc, k.vmax, lane, n, err);
         cnt = walk_candidates<DIM, T, G, NB>(k, R, w, vc, xi, lane, row, nl.maxnb, false, vrow,
                                              vcnt, dens, sw, s_w[grp]);
     } else {
@@ -430,26 +445,35 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
     const int64_t nbnd = *bcount;
     const int64_t C = k.cap;
     const int64_t stride = int64_t(gridDim.x) * PB;
-    for (int64_t g = int64_t(blockIdx.x) * PB + threadIdx.x / G; g < nbnd; g += stride) {
-        const int64_t i = blist[g];
+    // each row index is read one iteration ahead (the first before the count
+    // of rows arrives; the list holds cap entries, those past the count are
+    // not used)
+    int64_t g = int64_t(blockIdx.x) * PB + threadIdx.x / G;
+    int32_t inext = g < C ? blist[g] : -1;
+    for (; g < nbnd; g += stride) {
+        const int64_t i = inext;
+        inext = g + stride < C ? blist[g + stride] : -1;
         if (bad_index(int32_t(i), n)) {
             raise_error(err, SPH_ERR_CELL_RANGE);
             continue;
         }
+        // the row's kind, values, neighbour count and first neighbour index
+        // in one round trip
         const int t = m.type[i];
-        if (t == SPH_FLUID) continue;
         double xi[3] = {0, 0, 0};
 #pragma unroll
         for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
         const double uin0 = m.uin[i];
         const int cnt = nl.count[i];
+        const int32_t j0 = lane < nl.maxnb ? nl.nbr[i * nl.maxnb + lane] : -1;
+        if (t == SPH_FLUID) continue;
         const bool io = t == SPH_INLET || t == SPH_OUTLET;
         // Shepard sums over fluid neighbours and, in the same sweep, the
         // fallback sums over same-kind neighbours that had support
         double sw = 0.0, sp = 0.0, su[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
         double bacc[3] = {0, 0, 0}, bM = 0.0;
         for (int q = lane; q < cnt; q += G) {
-            const int32_t j = nl.nbr[i * nl.maxnb + q];
+            const int32_t j = q == lane ? j0 : nl.nbr[i * nl.maxnb + q];
             if (bad_index(j, n)) {
                 raise_error(err, SPH_ERR_CELL_RANGE);
                 continue;

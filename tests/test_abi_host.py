@@ -34,6 +34,8 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(B.SphDerived) == 8 * 11
     assert C.sizeof(B.SphAdjoint) == 8 * 6 + 8 * 3 + 8 * 8
     assert C.sizeof(B.SphStateAdjoint) == 8 + 8 * 8
+    assert C.sizeof(B.SphStepStore) == C.sizeof(B.SphState) + 8 * 2 + 2 * C.sizeof(
+        B.SphNlist) + 2 * C.sizeof(B.SphDerived) + 8 * 6
 
 
 def test_step_adjoint_scratch_size_and_validation():
@@ -54,6 +56,15 @@ def test_step_adjoint_scratch_size_and_validation():
     assert rc == -1
     rc = B.lib().sph_inlet_profile_grad(C.byref(q), C.byref(st), C.byref(lam), None, 10, None,
                                         None)
+    assert rc == -1
+    # the stored-stage entry points reject a missing store or incomplete state
+    rc = B.lib().sph_step_record_store(C.byref(q), C.byref(st), C.byref(st), None, None, None,
+                                       None, None, 0, None)
+    assert rc == -1
+    store = B.SphStepStore()
+    rc = B.lib().sph_step_adjoint_stored(C.byref(q), C.byref(st), C.byref(store), None, None,
+                                         C.byref(fb), C.byref(lam), C.byref(lam), None, 0, None,
+                                         0, None)
     assert rc == -1
 
 

@@ -201,15 +201,16 @@ def _types_by_id(sim, ids):
     return np.array([m[int(x)] for x in ids], np.uint8)
 
 
-def test_step_record_matches_step():
-    """sph_step_record gives the same state as sph_step, bit for bit, and its
-    events cover pushes, transfers, deletions and re-spawns (the case of the
-    30-step dot-product test)."""
+@pytest.mark.parametrize("stored", [True, False])
+def test_step_record_matches_step(stored):
+    """sph_step_record (and sph_step_record_store) give the same state as
+    sph_step, bit for bit, and the events cover pushes, transfers, deletions
+    and re-spawns (the case of the 30-step dot-product test)."""
     prm, s = _case("C2-small", 9)
     a = B().Simulation(prm, s)
     a.step(30)
     b = B().Simulation(prm, s)
-    tape = A().StepTape(b, 30)
+    tape = A().StepTape(b, 30, stored=stored)
     seen = 0
     for j in range(30):
         tape.record(j)
@@ -222,6 +223,34 @@ def test_step_record_matches_step():
     for k in sa:  # row for row: re-spawned rows are appended in parent order
         assert np.array_equal(sa[k], sb[k]), k
     assert seen == 15, seen
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["C4-small", "C5-small"])
+def test_stored_stage_reverse_matches_recompute(name, prec):
+    """The reverse from stored stage values (sph_step_record_store +
+    sph_step_adjoint_stored) equals the reverse that recomputes every step
+    (sph_step_record + sph_step_adjoint), bit for bit, over two segments and
+    a final-state adjoint."""
+    print(f"stored vs recomputed reverse {name} {prec}", flush=True)
+    prm, s = _case(name, 9)
+    nsteps = 12
+    fbar = np.random.default_rng(5).standard_normal((nsteps, 3))
+    if prm["dim"] == 2:
+        fbar[:, 2] = 0.0
+    n0 = len(s["p"])
+    out = []
+    for stored in (True, False):
+        sim = B().Simulation(prm, s, prec=prec)
+        run = A().DragAdjoint(sim, nsteps, segment=5, stored=stored)
+        run.forward()
+        lam = run.backward(fbar, lam_final=lambda ids: _final_weights(
+            prm, ids, _types_by_id(sim, ids), 77))
+        assert sim.poll_error() == 0
+        out.append(A().lam_to_host(lam, n0, prm["dim"], sim.cap))
+    for k in out[0]:
+        assert np.array_equal(out[0][k], out[1][k]), k
+    assert np.abs(out[0]["x"]).max() > 0
 
 
 def _fd_run(prm, s, nsteps, hw):
