@@ -83,6 +83,19 @@ def test_rhs_parity_fp32(name):
         assert v <= TOL32, (key, v)
 
 
+@pytest.mark.parametrize("cfg", ["C2", "C3", "C5"])
+def test_full_size_rhs_parity_fp32(cfg):
+    """FP32 form at the full workload sizes (41k, 1.2M, 4.6M particles), one
+    right-hand side against the FP64 oracle, every particle."""
+    print(f"full-size rhs fp32 {cfg}", flush=True)
+    prm, s = I.config(cfg)
+    s = I.random_fields(prm, I.jitter(prm, s, 0.1, 1), 2)
+    e, _ = fp32_errors(prm, s)
+    print({k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for key, v in e.items():
+        assert v <= TOL32, (key, v)
+
+
 def test_fp32_neighbor_sets_match_fp64():
     prm, s = _case("C2-small")
     out = []

@@ -227,9 +227,10 @@ def test_neighbor_overflow_sets_error_bit():
     assert cnt.max() == 4
 
 
-@pytest.mark.parametrize("cfg", ["C2", "C3"])
+@pytest.mark.parametrize("cfg", ["C2", "C3", "C5"])
 def test_full_size_rhs_parity(cfg):
-    """Full workload size, single right-hand side, every particle."""
+    """Full workload size (41k, 1.2M and 4.6M particles), single right-hand
+    side, every particle."""
     _print_case(f"full-size rhs {cfg}")
     prm, s = I.config(cfg)
     s = I.random_fields(prm, I.jitter(prm, s, 0.1, 1), 2)
@@ -313,3 +314,23 @@ def test_candidate_lists_match_stencil_search(name, caps):
                                    st["id"].astype(np.float64), drag.cpu().numpy().ravel()]))
     for o in out[1:]:
         assert np.array_equal(out[0], o)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name", ["C4", "C5"])
+def test_empty_state(name, prec):
+    """No particles: every entry point runs, finds nothing and raises no
+    error bit (the degenerate case of the bin, the searches, the boundary
+    values, the force pass and the bookkeeping)."""
+    _print_case(f"empty state {name} {prec}")
+    prm, s = I.config(name, small=True)
+    s0 = {k: v[:0] for k, v in s.items()}
+    sim = B().Simulation(prm, s0, prec=prec)
+    sim.bin()
+    sim.neighbors()
+    sim.rhs()
+    drag = torch.zeros((5, 3), dtype=torch.float64, device="cuda")
+    sim.step(5, drag_hist=drag)
+    assert sim.poll_error() == 0
+    assert sim.live_count() == 0
+    assert float(drag.abs().max().item()) == 0.0
