@@ -335,12 +335,17 @@ typedef struct sph_step_store {
     float *off1, *off2;
 } sph_step_store;
 
-/* sph_step_record that also fills *store with the step's stage values (the
- * step itself is bit-identical to sph_step_record's; nl and out are not
- * written: the step's tables and derived values go to the store). */
+/* sph_step_record that also fills *store with the step's stage values (nl
+ * and out are not written: the step's tables and derived values go to the
+ * store). With first != 0 or without SPH_FLAG_REUSE_BINS the step sorts, as
+ * sph_step_record's does (bit-identical step). With the flag and first == 0
+ * it continues a run as sph_step does from its second step on: the cell
+ * order is kept while the cell skin allows, so a sequence of calls with first
+ * set on the first one reproduces one sph_step call row for row (store->perm
+ * is then the identity for steps that kept the order). */
 int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
-                          sph_step_store *store, double *drag, int32_t *child, uint8_t *events,
-                          void *ws, size_t ws_bytes, void *stream);
+                          sph_step_store *store, int32_t first, double *drag, int32_t *child,
+                          uint8_t *events, void *ws, size_t ws_bytes, void *stream);
 
 /* sph_step_adjoint from stored stage values instead of a recomputation: st
  * is the state the step started from (as for sph_step_adjoint), store what

@@ -141,8 +141,10 @@ class StepTape:
         self.sim.n_dev.copy_(n)
 
     # ------------------------------------------------------------ steps
-    def record(self, j, drag=None):
-        """Keep the current state in slot j, then one recorded step."""
+    def record(self, j, drag=None, first=True):
+        """Keep the current state in slot j, then one recorded step (first:
+        the step starts a run and sorts; otherwise, with the simulation's
+        bin-reuse flag, it keeps the cell order while the skin allows)."""
         s = self.sim
         b, n, _ = self._slot(j)
         Bd.Simulation.copy_state(b, s._current())
@@ -151,9 +153,9 @@ class StepTape:
         dp = drag.data_ptr() if drag is not None else None
         if self.stored:
             Bd._check(Bd.lib().sph_step_record_store(
-                C.byref(s.q), C.byref(s.st), C.byref(s.alt), C.byref(self._store(j)["_s"]), dp,
-                self.child[j].data_ptr(), self.events[j].data_ptr(), ws, nb, s.stream),
-                "sph_step_record_store")
+                C.byref(s.q), C.byref(s.st), C.byref(s.alt), C.byref(self._store(j)["_s"]),
+                1 if first else 0, dp, self.child[j].data_ptr(), self.events[j].data_ptr(), ws,
+                nb, s.stream), "sph_step_record_store")
         else:
             Bd._check(Bd.lib().sph_step_record(
                 C.byref(s.q), C.byref(s.st), C.byref(s.alt), C.byref(s.nl), C.byref(s.out), dp,
@@ -192,10 +194,18 @@ class DragAdjoint:
     initial state's order, plus a final-state adjoint `lam_final` if given.
     """
 
-    def __init__(self, sim, nsteps, segment=50, stored=True):
-        # the replays sort at every step; the checkpointed forward must match
-        # them row for row, so it does not keep cell orders across steps
-        sim.q.flags &= ~Bd.FLAG_REUSE_BINS
+    def __init__(self, sim, nsteps, segment=50, stored=True, keep_order=None):
+        # the replays must match the checkpointed forward row for row: both
+        # sort at the first step of every segment and, with stored stage
+        # values (keep_order, default), keep the cell order while the skin
+        # allows after it; the recomputing reverse needs a sort at every step
+        keep_order = stored if keep_order is None else bool(keep_order)
+        if keep_order and not stored:
+            raise ValueError("keeping the cell order needs stored stage values")
+        if keep_order:
+            sim.q.flags |= Bd.FLAG_REUSE_BINS
+        else:
+            sim.q.flags &= ~Bd.FLAG_REUSE_BINS
         self.sim, self.nsteps = sim, int(nsteps)
         self.segment = max(1, min(int(segment), self.nsteps))
         self.tape = StepTape(sim, self.segment, stored=stored)
@@ -215,7 +225,7 @@ class DragAdjoint:
             k = min(self.segment, self.nsteps - s0)
             if s0 == starts[-1]:
                 for j in range(k):
-                    self.tape.record(j, drag=hist[s0 + j])
+                    self.tape.record(j, drag=hist[s0 + j], first=(j == 0))
             else:
                 self.sim.step(k, drag_hist=hist[s0:s0 + k])
         self._tape_holds_last = True
@@ -239,7 +249,7 @@ class DragAdjoint:
             if seg != last or not self._tape_holds_last:
                 tape.restore(self.ckpts[seg])
                 for j in range(k):
-                    tape.record(j)
+                    tape.record(j, first=(j == 0))
             if lam_final is not None and seg == last:
                 self._upload_lam(nxt, lam_final)
             for j in reversed(range(k)):

@@ -112,7 +112,7 @@ def lib():
         L.sph_step_adjoint.argtypes = [SP, ST, ST, _P, _P, NL, NL, DE, DE,
                                        C.POINTER(C.c_double * 3), LA, LA, _P, sz, _P, sz, _P]
         SS = C.POINTER(SphStepStore)
-        L.sph_step_record_store.argtypes = [SP, ST, ST, SS, _P, _P, _P, _P, sz, _P]
+        L.sph_step_record_store.argtypes = [SP, ST, ST, SS, C.c_int32, _P, _P, _P, _P, sz, _P]
         L.sph_step_adjoint_stored.argtypes = [SP, ST, SS, _P, _P, C.POINTER(C.c_double * 3), LA,
                                               LA, _P, sz, _P, sz, _P]
         L.sph_inlet_profile_grad.argtypes = [SP, ST, LA, _P, C.c_int32, _P, _P]

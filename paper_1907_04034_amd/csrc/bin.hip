@@ -282,13 +282,16 @@ void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s
 }
 
 // Row-for-row copy of the live rows of a into b (every state array and the
-// live count), plus the sort permutation and the packed cells of those rows.
+// live count), plus the sort permutation (the identity if the last bin kept
+// the order: *sorted == 0) and the packed cells of those rows.
 template <int DIM, typename T>
 __global__ void k_copy_rows(Dev k, DevState a, DevState b, const int32_t *perm_in,
-                            int32_t *perm_out, const uint32_t *cell_in, uint32_t *cell_out)
+                            const int32_t *sorted, int32_t *perm_out, const uint32_t *cell_in,
+                            uint32_t *cell_out)
 {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t n = *a.n;
+    const bool moved = *sorted != 0;
     if (r == 0 && blockIdx.y == 0) *b.n = n;
     if (r >= n) return;
     const int64_t C = k.cap;
@@ -307,7 +310,7 @@ __global__ void k_copy_rows(Dev k, DevState a, DevState b, const int32_t *perm_i
         b.red_prev[r] = a.red_prev[r];
         b.type[r] = a.type[r];
         b.id[r] = a.id[r];
-        perm_out[r] = perm_in[r];
+        perm_out[r] = moved ? perm_in[r] : int32_t(r);
         cell_out[r] = cell_in[r];
         break;
     case 1:
@@ -328,22 +331,22 @@ __global__ void k_copy_rows(Dev k, DevState a, DevState b, const int32_t *perm_i
 }
 
 void launch_copy_rows(const Dev &k, const DevState &a, const DevState &b, const int32_t *perm_in,
-                      int32_t *perm_out, const uint32_t *cell_in, uint32_t *cell_out,
-                      hipStream_t s)
+                      const int32_t *sorted, int32_t *perm_out, const uint32_t *cell_in,
+                      uint32_t *cell_out, hipStream_t s)
 {
     const dim3 g(nblocks(k.cap), 4), blk(kBlock);
     if (k.dim == 2 && k.prec == SPH_FP64)
-        hipLaunchKernelGGL((k_copy_rows<2, double>), g, blk, 0, s, k, a, b, perm_in, perm_out,
-                           cell_in, cell_out);
+        hipLaunchKernelGGL((k_copy_rows<2, double>), g, blk, 0, s, k, a, b, perm_in, sorted,
+                           perm_out, cell_in, cell_out);
     else if (k.dim == 3 && k.prec == SPH_FP64)
-        hipLaunchKernelGGL((k_copy_rows<3, double>), g, blk, 0, s, k, a, b, perm_in, perm_out,
-                           cell_in, cell_out);
+        hipLaunchKernelGGL((k_copy_rows<3, double>), g, blk, 0, s, k, a, b, perm_in, sorted,
+                           perm_out, cell_in, cell_out);
     else if (k.dim == 2)
-        hipLaunchKernelGGL((k_copy_rows<2, float>), g, blk, 0, s, k, a, b, perm_in, perm_out,
-                           cell_in, cell_out);
+        hipLaunchKernelGGL((k_copy_rows<2, float>), g, blk, 0, s, k, a, b, perm_in, sorted,
+                           perm_out, cell_in, cell_out);
     else
-        hipLaunchKernelGGL((k_copy_rows<3, float>), g, blk, 0, s, k, a, b, perm_in, perm_out,
-                           cell_in, cell_out);
+        hipLaunchKernelGGL((k_copy_rows<3, float>), g, blk, 0, s, k, a, b, perm_in, sorted,
+                           perm_out, cell_in, cell_out);
 }
 
 void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBufs &w,

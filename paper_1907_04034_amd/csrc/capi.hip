@@ -830,8 +830,8 @@ static Fields store_half(const sph_step_store *sto)
 }
 
 int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
-                          sph_step_store *store, double *drag, int32_t *child, uint8_t *events,
-                          void *ws, size_t ws_bytes, void *stream)
+                          sph_step_store *store, int32_t first, double *drag, int32_t *child,
+                          uint8_t *events, void *ws, size_t ws_bytes, void *stream)
 {
     Ctx c;
     int rc = prepare(prm, st, store ? store->nl1.maxnb : 0, ws, ws_bytes, stream, &c);
@@ -841,8 +841,10 @@ int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
     if (alt->cap != st->cap || alt->prec != st->prec)
         return fail(SPH_EINVAL, "alt must match state in cap and precision");
     if (!child || !events) return fail(SPH_EINVAL, "child and events must not be NULL");
-    c.k.reuse = 0;  // as sph_step_record: every recorded step sorts
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
+    // the first step of a run sorts (spread tables and a sort request, as at
+    // the start of sph_step); later ones keep the order while the skin allows
+    if (first || !c.k.reuse)
+        launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
     const bool f32 = c.k.prec == SPH_FP32;
     sph_nlist *nl1 = &store->nl1, *nl2 = &store->nl2;
     sph_derived *d1 = &store->d1, *d2 = &store->d2;
@@ -856,7 +858,8 @@ int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
     do_boundary(c, st, M, nl1, d1);
     do_force(c, st, M, H, nl1, d1, 1, nullptr, drag, f32 ? store->off1 : nullptr);
     launch_copy_rows(c.k, dev_state(st), dev_state(&store->start), at<int32_t>(ws, c.w.tmp),
-                     store->perm, at<uint32_t>(ws, c.w.cpos_s), store->cell, c.s);
+                     at<int32_t>(ws, c.w.vfresh), store->perm, at<uint32_t>(ws, c.w.cpos_s),
+                     store->cell, c.s);
     do_nbrdens(c, st, H, nl2, d2, 1, 2, false, f32 ? store->off2 : nullptr);
     do_boundary(c, st, H, nl2, d2);
     do_force(c, st, H, M, nl2, d2, 2, nullptr, nullptr, f32 ? store->off2 : nullptr);

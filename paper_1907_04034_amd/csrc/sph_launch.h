@@ -26,8 +26,8 @@ void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBuf
 
 // copy of the live rows of a into b, with the sort permutation and cells
 void launch_copy_rows(const Dev &k, const DevState &a, const DevState &b, const int32_t *perm_in,
-                      int32_t *perm_out, const uint32_t *cell_in, uint32_t *cell_out,
-                      hipStream_t s);
+                      const int32_t *sorted, int32_t *perm_out, const uint32_t *cell_in,
+                      uint32_t *cell_out, hipStream_t s);
 
 // pair passes
 int force_group(const Dev &k);

@@ -58,8 +58,8 @@ def test_step_adjoint_scratch_size_and_validation():
                                         None)
     assert rc == -1
     # the stored-stage entry points reject a missing store or incomplete state
-    rc = B.lib().sph_step_record_store(C.byref(q), C.byref(st), C.byref(st), None, None, None,
-                                       None, None, 0, None)
+    rc = B.lib().sph_step_record_store(C.byref(q), C.byref(st), C.byref(st), None, 1, None,
+                                       None, None, None, 0, None)
     assert rc == -1
     store = B.SphStepStore()
     rc = B.lib().sph_step_adjoint_stored(C.byref(q), C.byref(st), C.byref(store), None, None,
