@@ -245,7 +245,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this path runs on one GPU; --gpus must be 1"}))
-        log("bench.py: multi-GPU runs are not part of this build (one GPU only)")
+        log("bench.py: the benchmark runs on one GPU; --gpus above 1 is not supported")
         sys.exit(2)
     if args.form == "adjoint":
         if args.config == "C2" and "--config" not in sys.argv:
