@@ -162,9 +162,10 @@ int32_t sph_default_maxnb(const sph_params *prm);
 
 /* Cell-linked list (no paper passage; the neighbour structure is the
  * implementation's): cell = floor((x - lo) / cs) with cells at least 2.2h
- * wide, Morton key, counting sort with ties ordered by id, then gathers
- * every state array into *alt and exchanges the buffers of *st and *alt.
- * Dead particles are dropped and *st->n updated. */
+ * wide, Morton key, counting sort with ties ordered by id; every state array
+ * is gathered into *alt's buffers (scratch of the same capacity and
+ * precision) and the sorted rows are copied back, so *st is sorted in place
+ * and keeps its buffers. Dead particles are dropped and *st->n updated. */
 int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws,
             size_t ws_bytes, void *stream);
 

@@ -221,16 +221,17 @@ __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
                          int32_t *blist, int32_t *bcount, int32_t *nspawn,
                          const int32_t *rebin, double *xbin, int32_t *vfresh)
 {
-    // a kept order copies row for row (the caller exchanges the two buffers)
+    // a sort gathers a -> b; a kept order leaves the rows where they are
     const bool sorted = !bin_skips(k, rebin);
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t n = sorted ? int64_t(cell_start[k.nkeys]) : *a.n;  // (kept: rewritten as is)
+    const int64_t n = sorted ? int64_t(cell_start[k.nkeys]) : *a.n;
     if (r == 0 && blockIdx.y == 0) {
         *a.n = n;
         *nspawn = 0;
         *vfresh = sorted ? 1 : 0;
     }
-    if (r >= n) return;
+    // a kept order needs no copy: the state stays where it is
+    if (!sorted || r >= n) return;
     const int64_t i = sorted ? int64_t(tmp[r]) : r;
     const int64_t C = k.cap;
     constexpr int NR = kNavg * (DIM + 1);  // ring words, split over slices 1 and 2
@@ -279,6 +280,63 @@ void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s
 {
     hipLaunchKernelGGL(k_spread, dim3(nblocks(3 * int64_t(kSpreadStride))), dim3(kBlock), 0, s,
                        k, spread, rebin);
+}
+
+// The sorted rows back into the state they came from (a sort gathers into the
+// second buffer set; this returns them, so the caller's state keeps its
+// buffers). Nothing to do when the bin kept the order (*sorted == 0).
+template <int DIM, typename T>
+__global__ void k_copy_back(Dev k, DevState src, DevState dst, const int32_t *sorted)
+{
+    if (*sorted == 0) return;
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= *dst.n) return;
+    const int64_t C = k.cap;
+    constexpr int NR = kNavg * (DIM + 1);
+    switch (blockIdx.y) {
+    case 0:
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            dst.x[d * C + r] = src.x[d * C + r];
+            st<T>(dst.u, d * C + r, ld<T>(src.u, d * C + r));
+            st<T>(dst.ut, d * C + r, ld<T>(src.ut, d * C + r));
+            dst.uin[d * C + r] = src.uin[d * C + r];
+        }
+        st<T>(dst.p, r, ld<T>(src.p, r));
+        dst.head[r] = src.head[r];
+        dst.red_prev[r] = src.red_prev[r];
+        dst.type[r] = src.type[r];
+        dst.id[r] = src.id[r];
+        break;
+    case 1:
+#pragma unroll
+        for (int q = 0; q < NR / 2; ++q) dst.ring[q * C + r] = src.ring[q * C + r];
+        break;
+    case 2:
+#pragma unroll
+        for (int q = NR / 2; q < NR; ++q) dst.ring[q * C + r] = src.ring[q * C + r];
+        break;
+    default:
+#pragma unroll
+        for (int q = 0; q < DIM + 1; ++q) dst.avg[q * C + r] = src.avg[q * C + r];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) dst.jprev[q * C + r] = src.jprev[q * C + r];
+        break;
+    }
+}
+
+void launch_copy_back(const Dev &k, const DevState &src, const DevState &dst,
+                      const int32_t *sorted, hipStream_t s)
+{
+    const dim3 g(nblocks(k.cap), 4), blk(kBlock);
+    if (k.dim == 2 && k.prec == SPH_FP64)
+        hipLaunchKernelGGL((k_copy_back<2, double>), g, blk, 0, s, k, src, dst, sorted);
+    else if (k.dim == 3 && k.prec == SPH_FP64)
+        hipLaunchKernelGGL((k_copy_back<3, double>), g, blk, 0, s, k, src, dst, sorted);
+    else if (k.dim == 2)
+        hipLaunchKernelGGL((k_copy_back<2, float>), g, blk, 0, s, k, src, dst, sorted);
+    else
+        hipLaunchKernelGGL((k_copy_back<3, float>), g, blk, 0, s, k, src, dst, sorted);
 }
 
 // Row-for-row copy of the live rows of a into b (every state array and the

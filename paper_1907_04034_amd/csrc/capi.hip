@@ -369,21 +369,14 @@ static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws
     return SPH_OK;
 }
 
-// Sorts *st into *alt and exchanges their buffers (the live-count pointer of
-// each struct stays with it).
+// Sorts *st in place: a sort gathers into *alt's buffers and the rows come
+// back (one more copy); a bin that keeps the order copies nothing.
 static void do_bin(Ctx &c, sph_state *st, sph_state *alt)
 {
     DevState a = dev_state(st), b = dev_state(alt);
     b.n = a.n;
     launch_bin(c.k, a, b, c.bins(), c.err(), c.s);
-    if (alt->n != st->n)
-        (void)hipMemcpyAsync(alt->n, st->n, sizeof(int64_t), hipMemcpyDeviceToDevice, c.s);
-    sph_state tmp = *st;
-    int64_t *n_st = st->n, *n_alt = alt->n;
-    *st = *alt;
-    *alt = tmp;
-    st->n = n_st;
-    alt->n = n_alt;
+    launch_copy_back(c.k, b, a, at<int32_t>(c.ws, c.w.vfresh), c.s);
 }
 
 // vmode: 0 stencil search; 1 first search of a step (records the candidate

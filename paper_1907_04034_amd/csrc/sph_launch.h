@@ -24,6 +24,9 @@ void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s
 void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBufs &w,
                 uint32_t *err, hipStream_t s);
 
+// the sorted rows back from the second buffer set when the bin sorted
+void launch_copy_back(const Dev &k, const DevState &src, const DevState &dst,
+                      const int32_t *sorted, hipStream_t s);
 // copy of the live rows of a into b, with the sort permutation and cells
 void launch_copy_rows(const Dev &k, const DevState &a, const DevState &b, const int32_t *perm_in,
                       const int32_t *sorted, int32_t *perm_out, const uint32_t *cell_in,
