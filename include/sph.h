@@ -161,8 +161,9 @@ int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
 int32_t sph_default_maxnb(const sph_params *prm);
 
 /* Cell-linked list (no paper passage; the neighbour structure is the
- * implementation's): cell = floor((x - lo) / cs) with cells at least 2.2h
- * wide, Morton key, counting sort with ties ordered by id; every state array
+ * implementation's): cell = floor((x - lo) / cs) with cells at least 2.6h
+ * wide in 2D and 2.2h in 3D, Morton key, counting sort with ties ordered by
+ * id; every state array
  * is gathered into *alt's buffers (scratch of the same capacity and
  * precision) and the sorted rows are copied back, so *st is sorted in place
  * and keeps its buffers. Dead particles are dropped and *st->n updated. */

@@ -74,7 +74,12 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     k->maxnb = maxnb;
     k->cap = cap;
     k->h = p->h;
-    const double cell_min = 2.0 * p->h * (1.0 + kSkin);
+    // cells are at least 2h (1 + skin) wide. A wider skin sorts less often
+    // but widens the candidate search; measured per step: in 2D a skin of
+    // 0.3 beats 0.1, 0.2 and 0.5 (41k and 1.2M particles), in 3D 0.1 beats
+    // 0.2, 0.3 and 0.5 (4.6M), where the candidate ball grows as its cube
+    const double skin = p->dim == 2 ? 0.3 : 0.1;
+    const double cell_min = 2.0 * p->h * (1.0 + skin);
     int total_bits = 0;
     double min_slack = 1e300;
     for (int d = 0; d < 3; ++d) {
@@ -92,7 +97,8 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         int nc = int(std::floor(L / cell_min));
         if (nc < 1) nc = 1;
         if (k->periodic[d] && nc < 3)
-            return fail(SPH_EINVAL, "periodic axis %d needs at least 3 cells of 2.2h", d);
+            return fail(SPH_EINVAL, "periodic axis %d needs at least 3 cells of %gh", d,
+                        2.0 * (1.0 + skin));
         const int max_nc = p->dim == 2 ? 65535 : 1023;
         if (nc > max_nc) return fail(SPH_EINVAL, "axis %d has %d cells (max %d)", d, nc, max_nc);
         k->nc[d] = nc;

@@ -14,7 +14,6 @@ namespace sph {
 
 constexpr int kBlock = 256;        // 4 waves of 64
 constexpr int kNavg = 6;           // time-average window (Sec. 3.4, eq:N)
-constexpr double kSkin = 0.1;      // cells are at least 2h (1 + kSkin) wide
 constexpr int64_t kIdGeneration = int64_t(1) << 40;
 
 // Constants derived once per call on the host and passed by value.
