@@ -61,6 +61,27 @@ enum {
  * recorded for the reverse pass always bin. */
 enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8 };
 
+/* sph_params.outlet: how outlet particles get their values and move. Every
+ * rule advects outlet particles along x only; u, p are those of the rule, ut = u.
+ *   HYBRID (default, Sec. 3.4): fluid characteristic variables with each fluid
+ *     particle's own time averages as references (eq:characteristic-vars),
+ *     Shepard-interpolated (eq:shepard), J3 = 0, previous-step red mean
+ *     without fluid support (eq:average_old); u, p = the particle's frozen
+ *     time average + acoustic part (eq:acou); advected with that u.
+ *   MOC (Sec. 3.3): the same interpolation with fixed references u_ref = U,
+ *     p_ref = 0, rho_ref = rho0; u, p = reference + acoustic part, transverse
+ *     velocity unchanged; advected with that u.
+ *   DO_NOTHING (Sec. 3.1, eq:nrbc2): u, p frozen at the values the particle
+ *     had when it left the fluid; advected with its frozen u.
+ *   MOD_DO_NOTHING (Sec. 3.1.1): u, p frozen; advected with the Shepard mean
+ *     of the fluid x velocity (eq:shepard0), without fluid support with the
+ *     previous-step red mean of that velocity (as eq:average_old).
+ * jcur holds (J1, J2, J3) for HYBRID and MOC and (u_ex, 0, 0) for
+ * MOD_DO_NOTHING; DO_NOTHING extrapolates nothing (red particles hold zeros).
+ * Inlets use the characteristic inlet in all four. */
+enum { SPH_OUTLET_HYBRID = 0, SPH_OUTLET_MOC = 1, SPH_OUTLET_DO_NOTHING = 2,
+       SPH_OUTLET_MOD_DO_NOTHING = 3 };
+
 /* device error-word bits */
 enum {
     SPH_ERR_NBR_OVERFLOW = 1u,  /* a particle has more than maxnb neighbours */
@@ -103,7 +124,8 @@ typedef struct sph_params {
     int32_t list_cap;     /* candidate-list entries per particle of the step path
                              (0 = automatic; a particle with more candidates is
                              searched through its cell stencil instead) */
-    int32_t reserved;     /* must be 0 */
+    int32_t outlet;       /* SPH_OUTLET_*: the outlet rule (forward only; the
+                             adjoint entry points accept the hybrid alone) */
 } sph_params;
 
 /* Particle state. Element type of u, ut, p is double for SPH_FP64 and float

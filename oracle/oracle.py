@@ -38,6 +38,7 @@ class OrcParams(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("x_inlet", C.c_double), ("x_outlet", C.c_double), ("x_outlet_end", C.c_double),
         ("inlet_len", C.c_double), ("noise_amp", C.c_double), ("noise_seed", C.c_uint64),
+        ("outlet", C.c_int32),
     ]
 
 
@@ -52,6 +53,7 @@ def make_params(prm):
               "x_outlet", "x_outlet_end", "inlet_len", "noise_amp"):
         setattr(q, k, float(prm[k]))
     q.noise_seed = int(prm["noise_seed"])
+    q.outlet = int(prm.get("outlet", 0))
     return q
 
 

@@ -25,6 +25,10 @@
  *                 previous-step red average eq:average_old; Sec. 3.4 (hybrid):
  *                 time-average references eq:timeevg, acoustic-intensity gate
  *                 eq:acouinten, composition eq:acou, x-only advection
+ *   other outlets selected by orc_params.outlet: pure method of
+ *                 characteristics with fixed references (Sec. 3.3),
+ *                 do-nothing (Sec. 3.1, eq:nrbc2) and modified do-nothing
+ *                 (Sec. 3.1.1, eq:shepard0)
  *   inlet         prescribed velocity; pressure from the incoming
  *                 characteristic J3 (reference: inlet velocity, zero pressure)
  *   force pass    Sec. 2: eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
@@ -61,6 +65,12 @@
 #define F_NOISE 4
 #define ID_GENERATION ((int64_t)1 << 40)
 
+/* outlet rules */
+#define OUT_HYBRID 0
+#define OUT_MOC 1
+#define OUT_DO_NOTHING 2
+#define OUT_MOD_DO_NOTHING 3
+
 typedef struct {
     int32_t dim, n_avg, flags, periodic[3];
     double h, dx, rho0, c, U, nu, alpha, eta, dt, pb;
@@ -68,6 +78,7 @@ typedef struct {
     double x_inlet, x_outlet, x_outlet_end, inlet_len;
     double noise_amp;
     uint64_t noise_seed;
+    int32_t outlet;
 } orc_params;
 
 typedef struct {
@@ -359,11 +370,14 @@ static void density(sim *S)
 
 /* Sec. 3.3 eq:characteristic-vars at a fluid particle, with the hybrid
  * references of Sec. 3.4: u_ref, p_ref are the particle's own time averages
- * and rho_ref = rho0.  Only the x (outlet-normal) velocity enters. */
+ * and rho_ref = rho0.  Only the x (outlet-normal) velocity enters.
+ * reading: the pure method of characteristics takes the fixed references
+ * u_ref = U (the inlet speed), p_ref = 0, rho_ref = rho0. */
 static void fluid_J(const orc_params *q, const part *f, double J[3])
 {
-    double dp = f->p - f->avg[3];
-    double du = f->u[0] - f->avg[0];
+    int moc = q->outlet == OUT_MOC;
+    double dp = f->p - (moc ? 0.0 : f->avg[3]);
+    double du = f->u[0] - (moc ? q->U : f->avg[0]);
     J[0] = -q->c * q->c * (f->rho - q->rho0) + dp;
     J[1] = f->rho * q->c * du + dp;
     J[2] = -f->rho * q->c * du + dp;
@@ -414,6 +428,14 @@ static void boundary_values(sim *S)
                 J[0] = 0.0;
                 J[1] = 0.0;
                 J[2] = -f->rho * q->c * (f->u[0] - pi->uin[0]) + f->p;
+            } else if (q->outlet == OUT_MOD_DO_NOTHING) {
+                /* Sec. 3.1.1 eq:shepard0: the fluid x velocity, carried in
+                 * the first slot */
+                J[0] = f->u[0];
+                J[1] = 0.0;
+                J[2] = 0.0;
+            } else if (q->outlet == OUT_DO_NOTHING) {
+                J[0] = J[1] = J[2] = 0.0; /* nothing is extrapolated */
             } else {
                 fluid_J(q, f, J);
             }
@@ -441,7 +463,7 @@ static void boundary_values(sim *S)
             fallback_J(S, i, Jh);
         }
         for (int a = 0; a < 3; ++a) pi->jcur[a] = Jh[a];
-        if (t == T_OUTLET) {
+        if (t == T_OUTLET && q->outlet == OUT_HYBRID) {
             /* invert eq:characteristic-vars with rho_ref = rho0, then compose
              * with the frozen time averages, Sec. 3.4 eq:acou */
             double p_ac = 0.5 * (Jh[1] + Jh[2]);
@@ -449,6 +471,15 @@ static void boundary_values(sim *S)
             pi->p = pi->avg[3] + p_ac;
             pi->u[0] = pi->avg[0] + u_ac;
             for (int d = 1; d < dim; ++d) pi->u[d] = pi->avg[d];
+        } else if (t == T_OUTLET && q->outlet == OUT_MOC) {
+            /* Sec. 3.3: invert eq:characteristic-vars about the fixed
+             * references; the transverse velocity passes unchanged */
+            double p_ac = 0.5 * (Jh[1] + Jh[2]);
+            double u_ac = (Jh[1] - Jh[2]) / (2.0 * q->rho0 * q->c);
+            pi->p = 0.0 + p_ac;
+            pi->u[0] = q->U + u_ac;
+        } else if (t == T_OUTLET) {
+            /* Sec. 3.1 and 3.1.1: velocity and pressure stay frozen */
         } else if (t == T_INLET) {
             /* prescribed velocity: u - u_ref = 0, so p = J3 */
             pi->p = Jh[2];
@@ -707,12 +738,20 @@ static void end_of_step(sim *S)
     S->n = w;
 }
 
+/* Speed along x of an outlet particle at this stage: its own x velocity
+ * (hybrid eq:acou, characteristics, do-nothing eq:nrbc2) or, for the modified
+ * do-nothing rule, the extrapolated fluid velocity of Sec. 3.1.1. */
+static double outlet_speed(const orc_params *q, const part *pi)
+{
+    return q->outlet == OUT_MOD_DO_NOTHING ? pi->jcur[0] : pi->u[0];
+}
+
 /* Explicit midpoint RK2 (reading of the integrator, which the paper defers to
  * the EDAC paper): stage 1 at t^n, half state, stage 2 at t^{n+1/2}. The
  * transport velocity of eq:transport-vel is formed with the stage's sub-step
  * and positions follow eq:advection.  Inlet particles move with their
- * prescribed velocity, outlet particles along x with their composed velocity,
- * walls stay fixed. */
+ * prescribed velocity, outlet particles along x with the speed of their
+ * outlet rule (outlet_speed), walls stay fixed. */
 static void step(sim *S, int brute, double *drag_out)
 {
     const orc_params *q = &S->q;
@@ -738,7 +777,7 @@ static void step(sim *S, int brute, double *drag_out)
         } else if (pi->type == T_INLET) {
             pi->x[0] = pi->x0[0] + hdt * pi->uin[0];
         } else if (pi->type == T_OUTLET) {
-            pi->x[0] = pi->x0[0] + hdt * pi->u[0];
+            pi->x[0] = pi->x0[0] + hdt * outlet_speed(q, pi);
         }
     }
     rhs(S, brute);
@@ -755,7 +794,7 @@ static void step(sim *S, int brute, double *drag_out)
         } else if (pi->type == T_INLET) {
             pi->x[0] = pi->x0[0] + dt * pi->uin[0];
         } else if (pi->type == T_OUTLET) {
-            pi->x[0] = pi->x0[0] + dt * pi->u[0];
+            pi->x[0] = pi->x0[0] + dt * outlet_speed(q, pi);
         }
     }
     end_of_step(S);

@@ -40,7 +40,7 @@ class SphParams(C.Structure):
         ("x_inlet", C.c_double), ("x_outlet", C.c_double), ("x_outlet_end", C.c_double),
         ("inlet_len", C.c_double), ("noise_amp", C.c_double), ("noise_seed", C.c_uint64),
         ("group_force", C.c_int32), ("group_nbr", C.c_int32),
-        ("list_cap", C.c_int32), ("reserved", C.c_int32),
+        ("list_cap", C.c_int32), ("outlet", C.c_int32),
     ]
 
 
@@ -149,6 +149,7 @@ def make_params(prm):
     q.group_force = int(prm.get("group_force", 0))
     q.group_nbr = int(prm.get("group_nbr", 0))
     q.list_cap = int(prm.get("list_cap", 0))
+    q.outlet = int(prm.get("outlet", 0))
     return q
 
 

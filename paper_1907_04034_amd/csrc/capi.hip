@@ -62,12 +62,14 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     if (cap < 1 || cap > INT32_MAX) return fail(SPH_EINVAL, "cap must be in [1, 2^31)");
     if (p->list_cap < 0 || p->list_cap > 2048)
         return fail(SPH_EINVAL, "list_cap must be in [0, 2048] (got %d)", p->list_cap);
-    if (p->reserved != 0) return fail(SPH_EINVAL, "reserved must be 0");
+    if (p->outlet < SPH_OUTLET_HYBRID || p->outlet > SPH_OUTLET_MOD_DO_NOTHING)
+        return fail(SPH_EINVAL, "outlet must be an SPH_OUTLET_* rule (got %d)", p->outlet);
     if (prec != SPH_FP64 && prec != SPH_FP32) return fail(SPH_EINVAL, "bad precision %d", prec);
     std::memset(k, 0, sizeof *k);
     k->dim = p->dim;
     k->flags = p->flags;
     k->reuse = (p->flags & SPH_FLAG_REUSE_BINS) ? 1 : 0;
+    k->outlet = p->outlet;
     k->g_force = p->group_force;
     k->g_nbr = p->group_nbr;
     k->prec = prec;
@@ -613,6 +615,14 @@ int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     return check_hip("sph_force");
 }
 
+// The reverse passes differentiate the hybrid outlet only.
+static int hybrid_only(const sph_params *prm, const char *what)
+{
+    if (prm && prm->outlet != SPH_OUTLET_HYBRID)
+        return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the hybrid outlet only", what);
+    return SPH_OK;
+}
+
 int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
              sph_derived *out, int32_t nsteps, double *drag_hist, void *ws, size_t ws_bytes,
              void *stream)
@@ -637,6 +647,7 @@ int sph_step_record(const sph_params *prm, sph_state *st, sph_state *alt, sph_nl
                     sph_derived *out, double *drag, int32_t *child, uint8_t *events, void *ws,
                     size_t ws_bytes, void *stream)
 {
+    if (int rc0 = hybrid_only(prm, "sph_step_record")) return rc0;
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
@@ -761,6 +772,7 @@ int sph_step_adjoint(const sph_params *prm, const sph_state *st, sph_state *work
                      const sph_state_adjoint *lam_next, sph_state_adjoint *lam, void *scratch,
                      size_t scratch_bytes, void *ws, size_t ws_bytes, void *stream)
 {
+    if (int rc0 = hybrid_only(prm, "sph_step_adjoint")) return rc0;
     Ctx c;
     int rc = prepare(prm, st, nl1 ? nl1->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl1)) || (rc = check_nlist(nl2)) ||
@@ -832,6 +844,7 @@ int sph_step_record_store(const sph_params *prm, sph_state *st, sph_state *alt,
                           sph_step_store *store, int32_t first, double *drag, int32_t *child,
                           uint8_t *events, void *ws, size_t ws_bytes, void *stream)
 {
+    if (int rc0 = hybrid_only(prm, "sph_step_record_store")) return rc0;
     Ctx c;
     int rc = prepare(prm, st, store ? store->nl1.maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_store(store, prm, st))) return rc;
@@ -876,6 +889,7 @@ int sph_step_adjoint_stored(const sph_params *prm, const sph_state *st,
                             void *scratch, size_t scratch_bytes, void *ws, size_t ws_bytes,
                             void *stream)
 {
+    if (int rc0 = hybrid_only(prm, "sph_step_adjoint_stored")) return rc0;
     Ctx c;
     int rc = prepare(prm, st, store ? store->nl1.maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_store(store, prm, st))) return rc;
@@ -932,6 +946,7 @@ static int rhs_adjoint_impl(const sph_params *prm, const sph_state *st, const sp
                             const sph_derived *fwd, sph_adjoint *adj, void *ws, size_t ws_bytes,
                             void *stream, bool boundary_only, const char *what)
 {
+    if (int rc0 = hybrid_only(prm, what)) return rc0;
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(fwd, false))) return rc;

@@ -432,8 +432,12 @@ __device__ inline void rec_set_pu(const Dev &k, const Fields &R, void *rec, int6
 // Shepard-interpolated (eq:shepard), J3 = 0; without fluid support the mean
 // previous-step value of same-kind neighbours that had support
 // (eq:average_old), else the particle's own; then u, p = time average +
-// acoustic part (eq:acou) with rho_ref = rho0. Inlet: prescribed velocity,
-// p = Shepard J3 with reference (u_in, 0). Always FP64 arithmetic.
+// acoustic part (eq:acou) with rho_ref = rho0. The other outlet rules: fixed
+// references u = U, p = 0 with the transverse velocity unchanged (Sec. 3.3);
+// u, p frozen (Sec. 3.1), with the Shepard mean of the fluid x velocity as
+// the advection speed (Sec. 3.1.1, eq:shepard0; the blue fallback as above).
+// Inlet: prescribed velocity, p = Shepard J3 with reference (u_in, 0). Always
+// FP64 arithmetic.
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R, DevNlist nl,
                                                      DevDerived o, const int32_t *blist,
@@ -504,9 +508,14 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
             for (int d = 0; d < DIM; ++d) su[d] += uj[d] * w;
             if (t == SPH_INLET) {
                 sJ[2] += (-rhoj * k.c * (uj0 - uin0) + pj) * w;
-            } else if (t == SPH_OUTLET) {
-                const double dp = pj - m.avg[DIM * C + j];
-                const double du = uj0 - m.avg[j];
+            } else if (t == SPH_OUTLET && k.outlet == SPH_OUTLET_MOD_DO_NOTHING) {
+                sJ[0] += uj0 * w;  // eq:shepard0, the fluid x velocity
+            } else if (t == SPH_OUTLET && k.outlet != SPH_OUTLET_DO_NOTHING) {
+                // references: the fluid particle's time averages (hybrid) or
+                // the fixed u = U, p = 0 (characteristics)
+                const bool moc = k.outlet == SPH_OUTLET_MOC;
+                const double dp = pj - (moc ? 0.0 : m.avg[DIM * C + j]);
+                const double du = uj0 - (moc ? k.U : m.avg[j]);
                 sJ[0] += (-k.c2 * (rhoj - k.rho0) + dp) * w;
                 sJ[1] += (rhoj * k.c * du + dp) * w;
                 sJ[2] += (-rhoj * k.c * du + dp) * w;
@@ -562,7 +571,7 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 #pragma unroll
             for (int a = 0; a < 3; ++a) o.jcur[a * C + i] = J[a];
             o.red[i] = red;
-            if (t == SPH_OUTLET) {
+            if (t == SPH_OUTLET && k.outlet == SPH_OUTLET_HYBRID) {
                 const double p_ac = 0.5 * (J[1] + J[2]);
                 const double u_ac = (J[1] - J[2]) / (2.0 * k.rho0 * k.c);
                 st<T>(R.p, i, T(m.avg[DIM * C + i] + p_ac));
@@ -574,6 +583,20 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                     st<T>(R.u, d * C + i, T(m.avg[d * C + i]));
                     st<T>(R.ut, d * C + i, T(m.avg[d * C + i]));
                 }
+            } else if (t == SPH_OUTLET && k.outlet == SPH_OUTLET_MOC) {
+                // about the fixed references; transverse velocity unchanged
+                const double p_ac = 0.5 * (J[1] + J[2]);
+                const double u_ac = (J[1] - J[2]) / (2.0 * k.rho0 * k.c);
+                st<T>(R.p, i, T(0.0 + p_ac));
+                const double u0v = k.U + u_ac;
+                st<T>(R.u, i, T(u0v));
+                st<T>(R.ut, i, T(u0v));
+#pragma unroll
+                for (int d = 1; d < DIM; ++d) st<T>(R.ut, d * C + i, ld<T>(R.u, d * C + i));
+            } else if (t == SPH_OUTLET) {
+                // do-nothing rules: u, p stay frozen
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) st<T>(R.ut, d * C + i, ld<T>(R.u, d * C + i));
             } else {  // inlet: prescribed velocity, p = J3
                 st<T>(R.p, i, T(J[2]));
 #pragma unroll
@@ -658,22 +681,35 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
 }
 
 // Inlet rows move with their prescribed velocity and outlet rows along x with
-// their composed velocity (Sec. 3.4: no transverse motion); walls are fixed.
+// the speed of their rule (Sec. 3.4: no transverse motion); walls are fixed.
 // The full update also makes the half state's boundary values the step's.
 template <int DIM, typename T>
 __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fields &R,
                                       const Fields &W, int64_t i, int t, int mode,
-                                      const double *xbin, int32_t *rebin, uint32_t *err)
+                                      const double *jcur, const double *xbin, int32_t *rebin,
+                                      uint32_t *err)
 {
 #pragma clang fp contract(off)
     const int64_t C = k.cap;
     const double dt = mode == 2 ? k.dt : k.hdt;
+    // outlet rules other than the hybrid keep (part of) the start values: the
+    // half state carries them into stage 2
+    const bool keep = mode == 1 && t == SPH_OUTLET && k.outlet != SPH_OUTLET_HYBRID;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const double x0 = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
         double v = x0;
+        if (keep) {
+            st<T>(W.u, d * C + i, ld<T>(R.u, d * C + i));
+            st<T>(W.ut, d * C + i, ld<T>(R.ut, d * C + i));
+        }
         if (d == 0 && (t == SPH_INLET || t == SPH_OUTLET)) {
-            const double vx = t == SPH_INLET ? m.uin[i] : double(ld<T>(R.u, i));
+            // outlet speed: its own x velocity, or the extrapolated fluid
+            // velocity of the modified do-nothing rule
+            const double vx = t == SPH_INLET ? m.uin[i]
+                              : k.outlet == SPH_OUTLET_MOD_DO_NOTHING
+                                  ? jcur[i]
+                                  : double(ld<T>(R.u, i));
             v = x0 + dt * vx;
             skin_check(k, 0, mode, R.x[i], v, x0, xbin[i], rebin, err);
             if (!isfinite(v)) raise_error(err, SPH_ERR_NONFINITE);
@@ -684,7 +720,7 @@ __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fie
             st<T>(W.ut, d * C + i, ld<T>(R.ut, d * C + i));
         }
     }
-    if (mode == 2) st<T>(W.p, i, ld<T>(R.p, i));
+    if (mode == 2 || keep) st<T>(W.p, i, ld<T>(R.p, i));
 }
 
 // One neighbour's data as a lane of the force pass needs it.
@@ -912,7 +948,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
         // every non-fluid row (walls, bodies, inlet, outlet) takes its stage
         // position and, in the full update, its half-state boundary values
         if (mode != 0 && t != SPH_FLUID && lane == 0)
-            stage_boundary<DIM, T>(k, m, R, W, i, t, mode, xbin, rebin, err);
+            stage_boundary<DIM, T>(k, m, R, W, i, t, mode, o.jcur, xbin, rebin, err);
     }
     if (!want_drag) return;
     // deterministic per-block partial of the body force (fixed order)

@@ -20,6 +20,7 @@ constexpr int64_t kIdGeneration = int64_t(1) << 40;
 struct Dev {
     int dim, flags, maxnb, prec;
     int reuse;           // keep the last bin while the skin allows (sph_step only)
+    int outlet;          // SPH_OUTLET_* rule
     int g_force, g_nbr;  // lanes per target requested (0 = automatic)
     int periodic[3];
     int nc[3];          // cells per axis

@@ -43,6 +43,11 @@ FLAG_REUSE_BINS = 8  # GPU stepping option: keep the cell order while the skin a
 
 ID_GENERATION = 1 << 40   # a spawned inlet particle's id is its parent's + this
 
+# outlet rules (the "outlet" entry of a parameter dict; absent = hybrid)
+OUTLET_HYBRID, OUTLET_MOC, OUTLET_DO_NOTHING, OUTLET_MOD_DO_NOTHING = 0, 1, 2, 3
+OUTLETS = {"hybrid": OUTLET_HYBRID, "moc": OUTLET_MOC, "do-nothing": OUTLET_DO_NOTHING,
+           "mod-do-nothing": OUTLET_MOD_DO_NOTHING}
+
 
 def base_params(*, dim, dx, U=1.0, c_factor=10.0, rho0=1.0, nu=0.01, alpha=0.5,
                 h_over_dx=1.0, name="custom"):

@@ -104,3 +104,32 @@ def test_null_state_rejected_before_launch():
     rc = B.lib().sph_bin(C.byref(q), C.byref(st), C.byref(st), None, 0, None)
     assert rc == -1
     assert b"NULL" in B.lib().sph_last_error()
+
+
+def test_outlet_rule_validation():
+    """An unknown outlet rule is rejected; the reverse entry points accept the
+    hybrid outlet only (SPH_EUNSUPPORTED for the others, before any launch)."""
+    prm, _ = I.config("C2", small=True)
+    _bad(prm, outlet=4)
+    _bad(prm, outlet=-1)
+    for rule in (I.OUTLET_MOC, I.OUTLET_DO_NOTHING, I.OUTLET_MOD_DO_NOTHING):
+        assert B.workspace_size(dict(prm, outlet=rule), 1000) > 0
+    q = B.make_params(dict(prm, outlet=I.OUTLET_MOC))
+    st = B.SphState()
+    st.cap, st.dim, st.prec = 100, 2, 0
+    lam = B.SphStateAdjoint()
+    fb = (C.c_double * 3)(0.0, 0.0, 0.0)
+    nl = B.SphNlist()
+    de = B.SphDerived()
+    adj = B.SphAdjoint()
+    L = B.lib()
+    assert L.sph_rhs_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de), C.byref(adj),
+                             None, 0, None) == -6
+    assert b"hybrid" in L.sph_last_error()
+    assert L.sph_outlet_extrapolate_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de),
+                                            C.byref(adj), None, 0, None) == -6
+    assert L.sph_step_adjoint(C.byref(q), C.byref(st), C.byref(st), None, None, C.byref(nl),
+                              C.byref(nl), C.byref(de), C.byref(de), C.byref(fb),
+                              C.byref(lam), C.byref(lam), None, 0, None, 0, None) == -6
+    assert L.sph_step_record_store(C.byref(q), C.byref(st), C.byref(st), None, 1, None, None,
+                                   None, None, 0, None) == -6

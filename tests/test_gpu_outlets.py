@@ -1,0 +1,168 @@
+"""The outlet rules beside the hybrid (method of characteristics with fixed
+references, do-nothing, modified do-nothing): HIP path against the oracle.
+
+* One right-hand side (FP64 to 1e-12, FP32 to 1e-5 of the field scale, as the
+  hybrid's parity tests): boundary values, red flags, jcur and the fluid's
+  pair sums, with outlet particles carrying their own random u and p so that
+  frozen values are visible.
+* Trajectories with the cell order kept between sorts (the stepping path the
+  benchmark times): ids, kinds and fields within a small multiple of the
+  oracle's own one-ulp sensitivity.
+* The acoustic pulse of the 2D channel (2000 steps): the outlet reflection of
+  every rule, with the hybrid's below both do-nothing rules', which freeze the
+  velocity that an arriving wave would need to leave.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1907_04034_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+RULES = ["moc", "do-nothing", "mod-do-nothing"]
+
+
+def B():
+    from paper_1907_04034_amd import binding
+    return binding
+
+
+def _match(gs, os_):
+    idx = {int(v): k for k, v in enumerate(os_["id"])}
+    return np.array([idx[int(v)] for v in gs["id"]])
+
+
+def _nerr(got, ref, floor=0.0):
+    scale = max(np.abs(ref).max() if ref.size else 0.0, floor, 1e-300)
+    return np.abs(got - ref).max() / scale if ref.size else 0.0
+
+
+def _case(name, rule, seed=11):
+    prm, s = I.config(name.split("-")[0], small=True)
+    prm = dict(prm, outlet=I.OUTLETS[rule])
+    s = I.random_fields(prm, I.jitter(prm, s, 0.15, 7), seed)
+    rng = np.random.default_rng(seed + 1)
+    out = s["type"] == I.OUTLET
+    D = prm["dim"]
+    s["u"][out, 0] = rng.uniform(0.5, 1.5, size=out.sum())
+    s["u"][out, 1:D] = rng.uniform(-0.2, 0.2, size=(out.sum(), D - 1))
+    s["ut"][out] = s["u"][out]
+    s["p"][out] = rng.uniform(-0.3, 0.3, size=out.sum())
+    return prm, s
+
+
+def _rhs_errors(prm, s, prec):
+    gs, gd, sim = B().rhs_once(prm, s, prec=prec)
+    assert sim.poll_error() == 0
+    os_, od, _ = O.rhs_once(prm, s)
+    perm = _match(gs, os_)
+    t = gs["type"]
+    fl = t == I.FLUID
+    D = prm["dim"]
+    e = {}
+    for key in ("a", "b"):
+        e[key] = _nerr(gd[key][fl, :D], od[key][perm][fl, :D],
+                       np.abs(od["abs_" + key][perm][fl]).max())
+    e["pdot"] = _nerr(gd["pdot"][fl], od["pdot"][perm][fl], np.abs(od["abs_pdot"][perm][fl]).max())
+    nf = ~fl
+    e["p_bnd"] = _nerr(gs["p"][nf], os_["p"][perm][nf])
+    e["u_bnd"] = _nerr(gs["u"][nf, :D], os_["u"][perm][nf, :D])
+    e["ut_bnd"] = _nerr(gs["ut"][nf, :D], os_["ut"][perm][nf, :D])
+    io = (t == I.INLET) | (t == I.OUTLET)
+    assert np.array_equal(gd["red"][io], od["red"][perm][io])
+    e["jcur"] = _nerr(gd["jcur"][io], od["jcur"][perm][io])
+    return e
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("name", ["C2-small", "C5-small"])
+@pytest.mark.parametrize("rule", RULES)
+def test_outlet_rule_rhs_parity(rule, name, prec, tol):
+    print(f"outlet rule {rule} rhs {name} {prec}", flush=True)
+    prm, s = _case(name, rule)
+    e = _rhs_errors(prm, s, prec)
+    print({k: f"{v:.2e}" for k, v in e.items()}, flush=True)
+    for key, v in e.items():
+        assert v <= tol, (key, v)
+
+
+TRAJ_KEYS = (("x", True), ("u", True), ("p", False), ("avg", False), ("jprev", False))
+
+
+def _by_id(st):
+    idx = np.argsort(st["id"])
+    return {k: v[idx] for k, v in st.items()}
+
+
+def _traj_errors(prm, a, b):
+    D = prm["dim"]
+    out = {}
+    for key, vec in TRAJ_KEYS:
+        x, y = (a[key][:, :D], b[key][:, :D]) if vec else (a[key], b[key])
+        out[key] = _nerr(x, y)
+    return out
+
+
+def _oracle_state(prm, s, steps):
+    o = O.Oracle(prm, s)
+    o.step(steps)
+    return _by_id(o.state())
+
+
+@pytest.mark.parametrize("name,steps", [("C2-small", 300), ("C5-small", 60)])
+@pytest.mark.parametrize("rule", RULES)
+def test_outlet_rule_trajectory_parity(rule, name, steps):
+    """GPU (cell order kept between sorts) vs oracle after many steps, within
+    20 times the oracle's own sensitivity to a one-ulp position change (floor
+    1e-10)."""
+    print(f"outlet rule {rule} trajectory {name} {steps}", flush=True)
+    prm, s = I.config(name.split("-")[0], small=True)
+    prm = dict(prm, outlet=I.OUTLETS[rule], flags=prm["flags"] | I.FLAG_REUSE_BINS)
+    s = I.jitter(prm, s, 1e-3, 5, types=(I.FLUID, I.INLET, I.OUTLET))
+    sim = B().Simulation(prm, s)
+    sim.step(steps)
+    assert sim.poll_error() == 0
+    gs = _by_id(sim.state())
+    ref = _oracle_state(prm, s, steps)
+    assert np.array_equal(gs["id"], ref["id"])
+    assert np.array_equal(gs["type"], ref["type"])
+    assert np.array_equal(gs["red_prev"], ref["red_prev"])
+    s2 = I.snapshot_copy(s)
+    s2["x"][:, :prm["dim"]] *= 1.0 + 2.0 ** -52
+    sens = _traj_errors(prm, _oracle_state(prm, s2, steps), ref)
+    err = _traj_errors(prm, gs, ref)
+    print({k: f"{err[k]:.2e} (sens {sens[k]:.2e})" for k in err}, flush=True)
+    for key in err:
+        assert err[key] <= max(1e-10, 20 * sens[key]), (key, err[key], sens[key])
+    assert (gs["id"] >= I.ID_GENERATION).any()
+
+
+def _reflection(rule):
+    """Outlet reflection of the 2D channel pulse: max |p| over fluid probes at
+    x in [3.0, 3.5] for t in [0.18, 0.4545] s over the right-going half
+    amplitude (the window sees outlet reflections only)."""
+    prm, s = I.config("C2")
+    prm = dict(prm, outlet=I.OUTLETS[rule])
+    first = int(np.ceil(0.18 / prm["dt"]))
+    sim = B().Simulation(prm, s)
+    sim.step(first)
+    peak = torch.zeros((), dtype=torch.float64, device="cuda")
+    for _ in range(first, 2000):
+        sim.step(1)
+        n = sim.live_count()
+        b = sim._current()
+        x, p, typ = b["x"][:n], b["p"][:n], b["type"][:n]
+        win = (x >= 3.0) & (x <= 3.5) & (typ == I.FLUID)
+        peak = torch.maximum(peak, torch.where(win, p.abs(), torch.zeros_like(p)).max())
+    assert sim.poll_error() == 0
+    return float(peak.item()) / 0.05
+
+
+def test_pulse_reflection_by_outlet_rule():
+    R = {rule: _reflection(rule) for rule in ["hybrid", "moc", "do-nothing", "mod-do-nothing"]}
+    print("reflection " + ", ".join(f"{k} {v:.4f}" for k, v in R.items()), flush=True)
+    assert R["hybrid"] < R["do-nothing"]
+    assert R["hybrid"] < R["mod-do-nothing"]
+    assert all(v < 1.0 for v in R.values())

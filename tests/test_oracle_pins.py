@@ -407,6 +407,124 @@ def test_blue_fallback_previous_red_average():
     assert np.array_equal(d["jcur"][blue], s["jprev"][blue])
 
 
+# ------------------------------------------------------------ other outlet rules
+
+def test_moc_outlet_fixed_references():
+    """Sec. 3.3 with fixed references (u, p, rho) = (U, 0, rho0): fluid with
+    u = U + du, p = dp everywhere gives red outlet particles J2 = rho c du + dp
+    whatever the time averages hold, p = J2/2, u = U + J2/(2 rho0 c), and an
+    unchanged transverse velocity."""
+    du, dp = 0.003, 0.02
+    prm, s = _perturbed_channel(du, dp)
+    prm = dict(prm, outlet=I.OUTLET_MOC)
+    rng = np.random.default_rng(4)
+    n = len(s["p"])
+    s["avg"][:, :2] = rng.uniform(0.5, 1.5, size=(n, 2))  # ignored by this rule
+    s["avg"][:, 3] = rng.uniform(-0.3, 0.3, size=n)
+    out0 = s["type"] == I.OUTLET
+    s["u"][out0, 1] = rng.uniform(-0.1, 0.1, size=out0.sum())
+    s["ut"] = s["u"].copy()
+    st, d, _ = O.rhs_once(prm, s)
+    rho_f = prm["rho0"] * lattice_constants(2)[0]
+    c, rho0, U = prm["c"], prm["rho0"], prm["U"]
+    out = (st["type"] == I.OUTLET) & (d["red"] == 1)
+    assert out.sum() == 10
+    J2 = rho_f * c * du + dp
+    J1 = -c * c * (rho_f - rho0) + dp
+    assert np.allclose(d["jcur"][out, 1], J2, rtol=1e-12, atol=1e-13)
+    assert np.allclose(d["jcur"][out, 0], J1, rtol=1e-11, atol=1e-12)
+    assert np.all(d["jcur"][out, 2] == 0.0)
+    assert np.allclose(st["p"][out], J2 / 2, rtol=1e-12, atol=1e-14)
+    assert np.allclose(st["u"][out, 0], U + J2 / (2 * rho0 * c), rtol=0, atol=1e-14)
+    alls = st["type"] == I.OUTLET
+    assert np.array_equal(st["u"][alls, 1], s["u"][out0, 1])
+    assert np.array_equal(st["ut"][alls, :2], st["u"][alls, :2])
+
+
+def test_do_nothing_outlet_frozen_and_advected():
+    """Sec. 3.1 eq:nrbc2: outlet u and p keep the values they had, and the
+    position follows the exact solution x = x0 + t u of advection at constant
+    speed, along x only."""
+    prm, s = I.config("C2", small=True)
+    prm = dict(prm, outlet=I.OUTLET_DO_NOTHING)
+    rng = np.random.default_rng(6)
+    out0 = s["type"] == I.OUTLET
+    k = int(out0.sum())
+    s["u"][out0, 0] = rng.uniform(0.5, 1.5, size=k)
+    s["u"][out0, 1] = rng.uniform(-0.2, 0.2, size=k)
+    s["p"][out0] = rng.uniform(-0.3, 0.3, size=k)
+    s["ut"][out0] = s["u"][out0]
+    steps = 30
+    o = O.Oracle(prm, s)
+    o.step(steps)
+    st = o.state()
+    idx = {int(v): i for i, v in enumerate(st["id"])}
+    seen = 0
+    for i in np.where(out0)[0]:
+        j = idx.get(int(s["id"][i]))
+        if j is None:
+            continue  # left the outlet and was deleted
+        seen += 1
+        assert st["type"][j] == I.OUTLET
+        assert np.array_equal(st["u"][j], s["u"][i])
+        assert st["p"][j] == s["p"][i]
+        assert st["x"][j, 1] == s["x"][i, 1]
+        exact = s["x"][i, 0] + steps * prm["dt"] * s["u"][i, 0]
+        assert abs(st["x"][j, 0] - exact) <= 1e-13
+    assert seen > 0.7 * k
+
+
+def _brute_blue_mean(prm, st, i, col_of):
+    """eq:average_old by brute force: mean previous value of the same-kind
+    particles within 2h that were red at the previous step."""
+    dx = st["x"][:, :2] - st["x"][i, :2]
+    for a in range(2):
+        if prm["periodic"][a]:
+            L = prm["hi"][a] - prm["lo"][a]
+            dx[:, a] -= L * np.round(dx[:, a] / L)
+    r2 = (dx ** 2).sum(axis=1)
+    m = (r2 < (2 * prm["h"]) ** 2) & (st["type"] == st["type"][i]) & (st["red_prev"] == 1)
+    return st["jprev"][m, col_of].mean() if m.any() else st["jprev"][i, col_of]
+
+
+def test_mod_do_nothing_outlet():
+    """Sec. 3.1.1: u and p stay frozen, the advection speed is the Shepard mean
+    of the fluid x velocity (eq:shepard0; exact for a uniform stream), and a
+    particle without fluid support takes the previous-step mean of its red
+    neighbours (eq:average_old, checked by brute force)."""
+    prm, s = I.channel(Lx=0.3, Ly=0.1, dx=0.01)
+    prm = dict(prm, outlet=I.OUTLET_MOD_DO_NOTHING)
+    rng = np.random.default_rng(8)
+    out0 = s["type"] == I.OUTLET
+    k = int(out0.sum())
+    s["u"][out0, 0] = rng.uniform(0.3, 0.6, size=k)
+    s["u"][out0, 1] = rng.uniform(-0.1, 0.1, size=k)
+    s["ut"][out0] = s["u"][out0]
+    s["jprev"][out0, 0] = rng.uniform(0.8, 1.2, size=k)
+    s["red_prev"][out0] = (rng.uniform(size=k) < 0.5).astype(np.uint8)
+    st, d, _ = O.rhs_once(prm, s)
+    out = st["type"] == I.OUTLET
+    red = out & (d["red"] == 1)
+    blue = out & (d["red"] == 0)
+    assert red.sum() == 10 and blue.sum() == 40
+    assert np.allclose(d["jcur"][red, 0], prm["U"], rtol=1e-14, atol=0)
+    assert np.all(d["jcur"][out, 1:] == 0.0)
+    for i in np.where(blue)[0]:
+        assert abs(d["jcur"][i, 0] - _brute_blue_mean(prm, s, i, 0)) <= 1e-15
+    assert np.array_equal(st["u"][out], s["u"][out0])
+    assert np.array_equal(st["p"][out], s["p"][out0])
+    # one step: a red particle moves with about U, not with its frozen 0.3-0.6
+    o = O.Oracle(prm, s)
+    o.step(1)
+    s1 = o.state()
+    idx = {int(v): i for i, v in enumerate(s1["id"])}
+    for i in np.where(red)[0]:
+        j = idx[int(s["id"][i])]
+        speed = (s1["x"][j, 0] - s["x"][i, 0]) / prm["dt"]
+        assert abs(speed - prm["U"]) < 1e-2
+        assert np.array_equal(s1["u"][j], s["u"][i])
+
+
 def test_wall_ghost_values_shepard():
     """Constant fluid p and u: walls get p_w = p and u_g = -u exactly."""
     prm, s = I.config("C3", small=True)
