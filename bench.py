@@ -35,6 +35,8 @@ WORKLOADS = {
     "C3": "2D cylinder D=2 Re=200 in 60x32, dx=D/50, 3-layer slip walls",
     "C4": "2D channel 4x1 dx=0.01 with D=0.2 cylinder, Re=20",
     "C5": "3D duct 4x1x1 dx=0.01, no-slip walls, inlet noise 1%",
+    "C2Q": "2D channel 4x1 dx=0.01 with the C2 pulse, the paper's quintic spline "
+           "(support 3h) at h=1.2 dx",
 }
 
 

@@ -58,8 +58,13 @@ enum {
  * its last bin while every particle stays within the cell skin of its binned
  * position and no particle was transferred, deleted or re-spawned (the
  * neighbour sets are the same; sums run in a different row order). Steps
- * recorded for the reverse pass always bin. */
-enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8 };
+ * recorded for the reverse pass always bin. SPH_FLAG_QUINTIC selects the
+ * paper's quintic spline (Sec. 2 eq:quintic-spline, support 3h, alpha =
+ * 7/(478 pi h^2) in 2D and the normalising 1/(120 pi h^3) in 3D) instead of
+ * Wendland C2 (support 2h); the neighbour predicate becomes |r|^2 < (3h)^2
+ * (forward only: the adjoint entry points return SPH_EUNSUPPORTED). */
+enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8,
+       SPH_FLAG_QUINTIC = 16 };
 
 /* sph_params.outlet: how outlet particles get their values and move. Every
  * rule advects outlet particles along x only; u, p are those of the rule, ut = u.
@@ -101,8 +106,9 @@ enum {
 };
 
 /* Host parameter block (copied by value). Symbols follow Sec. 2 of the paper:
- * h smoothing length (support 2h of the Wendland C2 kernel), c the artificial
- * speed of sound c_s, nu the kinematic viscosity, alpha the EDAC damping
+ * h smoothing length (support 2h of the Wendland C2 kernel, 3h of the quintic
+ * spline), c the artificial speed of sound c_s, nu the kinematic viscosity,
+ * alpha the EDAC damping
  * coefficient (nu_edac = alpha h c / 8), eta the 0.01 regulariser, pb the
  * background pressure of the transport velocity, U the inlet reference speed
  * (also sets the acoustic-intensity gate |p| > rho0 U^2 / 2). */
@@ -179,7 +185,9 @@ typedef struct sph_derived {
  * pass's packed neighbour records, error word); the same for both precisions. */
 int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
 
-/* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D). */
+/* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D; with
+ * SPH_FLAG_QUINTIC 1.6 times the lattice count of the 3h ball plus 12, in
+ * multiples of 16: 80 in 2D and 336 in 3D at h = 1.2 dx). */
 int32_t sph_default_maxnb(const sph_params *prm);
 
 /* Cell-linked list (no paper passage; the neighbour structure is the

@@ -83,8 +83,10 @@ def lib():
         L.orc_w.argtypes = [C.c_double, C.c_double, C.c_int]
         L.orc_gradw_factor.restype = C.c_double
         L.orc_gradw_factor.argtypes = [C.c_double, C.c_double, C.c_int]
-        L.orc_quintic_spline.restype = C.c_double
-        L.orc_quintic_spline.argtypes = [C.c_double, C.c_double]
+        L.orc_quintic_w.restype = C.c_double
+        L.orc_quintic_w.argtypes = [C.c_double, C.c_double, C.c_int]
+        L.orc_quintic_gradw_factor.restype = C.c_double
+        L.orc_quintic_gradw_factor.argtypes = [C.c_double, C.c_double, C.c_int]
         L.orc_num_threads.restype = C.c_int
         _lib = L
     return _lib
@@ -108,8 +110,12 @@ def gradw_factor(r, h, dim):
     return lib().orc_gradw_factor(r, h, dim)
 
 
-def quintic_spline(r, h):
-    return lib().orc_quintic_spline(r, h)
+def quintic_w(r, h, dim):
+    return lib().orc_quintic_w(r, h, dim)
+
+
+def quintic_gradw_factor(r, h, dim):
+    return lib().orc_quintic_gradw_factor(r, h, dim)
 
 
 def num_threads():

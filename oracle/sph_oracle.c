@@ -13,9 +13,9 @@
  * not depend on the thread count.
  *
  * What is computed (symbols of the paper):
- *   kernel        Wendland C2 quintic, support 2h (the workloads' kernel; the
- *                 paper's own quintic spline of Sec. 2 eq:quintic-spline is
- *                 provided as well for its normalisation pin)
+ *   kernel        Wendland C2 quintic, support 2h (the workloads' kernel), or
+ *                 the paper's own quintic spline of Sec. 2 eq:quintic-spline,
+ *                 support 3h (flag F_QUINTIC)
  *   density       Sec. 2 eq:summation-density and the number-density volume
  *                 V_i = 1 / sum_j W_ij given below eq:tvf-momentum
  *   walls         ghost pressure / velocity by Shepard averaging of the fluid
@@ -63,6 +63,7 @@
 #define F_NO_PAVG 1
 #define F_DAMP_NU 2
 #define F_NOISE 4
+#define F_QUINTIC 16 /* the paper's quintic spline instead of Wendland C2 */
 #define ID_GENERATION ((int64_t)1 << 40)
 
 /* outlet rules */
@@ -136,17 +137,58 @@ double orc_gradw_factor(double r, double h, int dim)
     return -5.0 * wendland_norm(dim, h) * t * t * t / (h * h);
 }
 
-/* The paper's own quintic spline, Sec. 2 eq:quintic-spline (2D), support 3h. */
-double orc_quintic_spline(double r, double h)
+/* The paper's own quintic spline, Sec. 2 eq:quintic-spline, support 3h:
+ * W = a [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5] with each bracket dropped past its
+ * range. a_2 = 7 / (478 pi h^2) as printed; reading: a_3 = 1 / (120 pi h^3),
+ * the constant that normalises it in 3D (the paper gives the 2D one only). */
+static double quintic_norm(int dim, double h)
+{
+    if (dim == 3) return 1.0 / (120.0 * M_PI * h * h * h);
+    return 7.0 / (478.0 * M_PI * h * h);
+}
+
+double orc_quintic_w(double r, double h, int dim)
 {
     double q = r / h;
-    double a2 = 7.0 / (478.0 * M_PI * h * h);
     double t3 = 3.0 - q, t2 = 2.0 - q, t1 = 1.0 - q;
     if (q > 3.0) return 0.0;
     double w = t3 * t3 * t3 * t3 * t3;
     if (q <= 2.0) w -= 6.0 * t2 * t2 * t2 * t2 * t2;
     if (q <= 1.0) w += 15.0 * t1 * t1 * t1 * t1 * t1;
-    return a2 * w;
+    return quintic_norm(dim, h) * w;
+}
+
+/* dW/dr divided by r for the quintic spline: a w'(q) / (h^2 q), with
+ * w'(q) = -5 [(3-q)^4 - 6 (2-q)^4 + 15 (1-q)^4] (brackets dropped as in W);
+ * at r = 0 its limit, -120 a / h^2 (w' vanishes there like -120 q). */
+double orc_quintic_gradw_factor(double r, double h, int dim)
+{
+    double q = r / h;
+    double t3 = 3.0 - q, t2 = 2.0 - q, t1 = 1.0 - q;
+    double a = quintic_norm(dim, h);
+    if (q >= 3.0) return 0.0;
+    if (q == 0.0) return -120.0 * a / (h * h);
+    double dw = t3 * t3 * t3 * t3;
+    if (q <= 2.0) dw -= 6.0 * t2 * t2 * t2 * t2;
+    if (q <= 1.0) dw += 15.0 * t1 * t1 * t1 * t1;
+    return a * (-5.0 * dw) / (h * h * q);
+}
+
+/* The kernel of the run and its support radius in units of h. */
+static double support_factor(const orc_params *q)
+{
+    return (q->flags & F_QUINTIC) ? 3.0 : 2.0;
+}
+
+static double kernel_w(const orc_params *q, double r)
+{
+    return (q->flags & F_QUINTIC) ? orc_quintic_w(r, q->h, q->dim) : orc_w(r, q->h, q->dim);
+}
+
+static double kernel_f(const orc_params *q, double r)
+{
+    return (q->flags & F_QUINTIC) ? orc_quintic_gradw_factor(r, q->h, q->dim)
+                                  : orc_gradw_factor(r, q->h, q->dim);
 }
 
 /* ------------------------------------------------------- geometry helpers */
@@ -187,7 +229,7 @@ static int is_wall(int t) { return t == T_WALL_SLIP || t == T_WALL_NOSLIP || t =
 
 static double support2(const orc_params *q)
 {
-    double s = 2.0 * q->h;
+    double s = support_factor(q) * q->h;
     return s * s;
 }
 
@@ -213,7 +255,8 @@ static void ensure_nnz(sim *S, int64_t need)
     S->col = (int32_t *)realloc(S->col, sizeof(int32_t) * S->nnz_cap);
 }
 
-/* O(N^2) search: j is a neighbour of i iff |r_ij|^2 < (2h)^2 (self included). */
+/* O(N^2) search: j is a neighbour of i iff |r_ij|^2 < (k h)^2 with k h the
+ * kernel's support (self included). */
 static void neighbours_brute(sim *S)
 {
     int64_t n = S->n;
@@ -239,7 +282,7 @@ static void neighbours_brute(sim *S)
     free(cnt);
 }
 
-/* Uniform bucket grid with cells of at least 2h; each target scans the 3^d
+/* Uniform bucket grid with cells of at least the support; each target scans the 3^d
  * surrounding buckets and keeps the same predicate as the brute-force search.
  * Rows are sorted by particle index so both searches give identical lists. */
 static void neighbours_cells(sim *S)
@@ -251,7 +294,7 @@ static void neighbours_cells(sim *S)
     for (int d = 0; d < q->dim; ++d) {
         double L = q->hi[d] - q->lo[d];
         /* cells strictly wider than the support so a 3^d stencil suffices */
-        nc[d] = (int)floor(L / (2.0 * q->h * (1.0 + 1e-9)));
+        nc[d] = (int)floor(L / (support_factor(q) * q->h * (1.0 + 1e-9)));
         if (nc[d] < 1) nc[d] = 1;
         if (q->periodic[d] && nc[d] < 3) {
             fprintf(stderr, "oracle: periodic axis needs at least 3 cells\n");
@@ -359,7 +402,7 @@ static void density(sim *S)
             part *pj = &S->P[S->col[k]];
             double r[3];
             diff(q, pi->x, pj->x, r);
-            sw += orc_w(sqrt(dot_self(q->dim, r)), q->h, q->dim);
+            sw += kernel_w(q, sqrt(dot_self(q->dim, r)));
         }
         pi->rho = m * sw;
         pi->vol = 1.0 / sw;
@@ -417,7 +460,7 @@ static void boundary_values(sim *S)
             if (f->type != T_FLUID) continue;
             double r[3];
             diff(q, pi->x, f->x, r);
-            double w = orc_w(sqrt(dot_self(dim, r)), q->h, dim);
+            double w = kernel_w(q, sqrt(dot_self(dim, r)));
             sw += w;
             sp += f->p * w;
             for (int d = 0; d < dim; ++d) su[d] += f->u[d] * w;
@@ -506,7 +549,7 @@ static void pair_terms(const orc_params *q, const part *pi, const part *pj,
     double r[3];
     diff(q, pi->x, pj->x, r);
     double r2 = dot_self(dim, r);
-    double F = orc_gradw_factor(sqrt(r2), q->h, dim);
+    double F = kernel_f(q, sqrt(r2));
     double gw[3] = {F * r[0], F * r[1], F * r[2]};
     double vsq = pi->vol * pi->vol + pj->vol * pj->vol;
     double ri = pi->rho, rj = pj->rho;
@@ -591,7 +634,7 @@ static void forces(sim *S)
                 double r[3];
                 diff(q, pi->x, pj->x, r);
                 double r2 = dot_self(dim, r);
-                double F = orc_gradw_factor(sqrt(r2), q->h, dim);
+                double F = kernel_f(q, sqrt(r2));
                 double vsq = pi->vol * pi->vol + pj->vol * pj->vol;
                 double ri = pi->rho, rj = pj->rho;
                 double ptil = (rj * (pi->p - pavg) + ri * (pj->p - pavg)) / (ri + rj);

@@ -70,18 +70,21 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     k->flags = p->flags;
     k->reuse = (p->flags & SPH_FLAG_REUSE_BINS) ? 1 : 0;
     k->outlet = p->outlet;
+    k->quintic = (p->flags & SPH_FLAG_QUINTIC) ? 1 : 0;
     k->g_force = p->group_force;
     k->g_nbr = p->group_nbr;
     k->prec = prec;
     k->maxnb = maxnb;
     k->cap = cap;
     k->h = p->h;
-    // cells are at least 2h (1 + skin) wide. A wider skin sorts less often
+    // the kernel's support: 2h (Wendland C2) or 3h (the paper's quintic spline)
+    const double sup = (k->quintic ? 3.0 : 2.0) * p->h;
+    // cells are at least sup (1 + skin) wide. A wider skin sorts less often
     // but widens the candidate search; measured per step: in 2D a skin of
     // 0.3 beats 0.1, 0.2 and 0.5 (41k and 1.2M particles), in 3D 0.1 beats
     // 0.2, 0.3 and 0.5 (4.6M), where the candidate ball grows as its cube
     const double skin = p->dim == 2 ? 0.3 : 0.1;
-    const double cell_min = 2.0 * p->h * (1.0 + skin);
+    const double cell_min = sup * (1.0 + skin);
     int total_bits = 0;
     double min_slack = 1e300;
     for (int d = 0; d < 3; ++d) {
@@ -100,7 +103,7 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         if (nc < 1) nc = 1;
         if (k->periodic[d] && nc < 3)
             return fail(SPH_EINVAL, "periodic axis %d needs at least 3 cells of %gh", d,
-                        2.0 * (1.0 + skin));
+                        cell_min / p->h);
         const int max_nc = p->dim == 2 ? 65535 : 1023;
         if (nc > max_nc) return fail(SPH_EINVAL, "axis %d has %d cells (max %d)", d, nc, max_nc);
         k->nc[d] = nc;
@@ -112,17 +115,18 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         k->cs[d] = L / nc;
         k->csf[d] = float(k->cs[d]);
         k->inv_cs[d] = nc / L;
-        min_slack = std::fmin(min_slack, k->cs[d] - 2.0 * p->h);
+        min_slack = std::fmin(min_slack, k->cs[d] - sup);
     }
     if (total_bits > 30) return fail(SPH_EINVAL, "cell grid too large (%d key bits)", total_bits);
     k->nkeys = uint32_t(1) << total_bits;
-    {
-        double s = 2.0 * p->h;
-        k->sup2 = s * s;
-    }
+    k->sup2 = sup * sup;
     const double pi = pi_d;
-    k->wnorm = p->dim == 2 ? 7.0 / (4.0 * pi * p->h * p->h)
-                           : 21.0 / (16.0 * pi * p->h * p->h * p->h);
+    if (k->quintic)  // Sec. 2 eq:quintic-spline: 7/(478 pi h^2); in 3D the normalising 1/(120 pi h^3)
+        k->wnorm = p->dim == 2 ? 7.0 / (478.0 * pi * p->h * p->h)
+                               : 1.0 / (120.0 * pi * p->h * p->h * p->h);
+    else
+        k->wnorm = p->dim == 2 ? 7.0 / (4.0 * pi * p->h * p->h)
+                               : 21.0 / (16.0 * pi * p->h * p->h * p->h);
     k->gnorm = -5.0 * k->wnorm / (p->h * p->h);
     k->inv_h = 1.0 / p->h;
     k->mass = p->dim == 2 ? p->rho0 * p->dx * p->dx : p->rho0 * p->dx * p->dx * p->dx;
@@ -139,12 +143,11 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     k->hdt = 0.5 * p->dt;
     k->disp_max = 0.999 * 0.5 * min_slack;
     {
-        // candidate lists: a pair closer than 2h at positions within disp_max
-        // (per axis) of the binned ones is closer than 2h + 2 sqrt(d) disp_max
+        // candidate lists: a pair closer than sup at positions within disp_max
+        // (per axis) of the binned ones is closer than sup + 2 sqrt(d) disp_max
         // at the binned positions (a small relative margin covers rounding);
         // capacity twice the lattice count of that ball, plus slack
-        const double rv = (2.0 * p->h + 2.0 * std::sqrt(double(p->dim)) * k->disp_max) *
-                          (1.0 + 1e-9);
+        const double rv = (sup + 2.0 * std::sqrt(double(p->dim)) * k->disp_max) * (1.0 + 1e-9);
         k->rv2 = rv * rv;
         const double q = rv / p->dx;
         const double ball = p->dim == 2 ? pi_d * q * q : 4.0 / 3.0 * pi_d * q * q * q;
@@ -529,6 +532,14 @@ const char *sph_last_error(void) { return g_err.c_str(); }
 
 int32_t sph_default_maxnb(const sph_params *prm)
 {
+    if (prm && (prm->flags & SPH_FLAG_QUINTIC) && prm->h > 0 && prm->dx > 0) {
+        // 1.6 times the lattice count of the 3h ball plus 12, in multiples of
+        // 16 (80 in 2D and 336 in 3D at h = 1.2 dx)
+        const double R = 3.0 * prm->h / prm->dx;
+        const double ball = prm->dim == 3 ? 4.0 / 3.0 * pi_d * R * R * R : pi_d * R * R;
+        const int m = int(std::ceil((1.6 * ball + 12.0) / 16.0)) * 16;
+        return m < 32 ? 32 : (m > 1024 ? 1024 : m);
+    }
     return prm && prm->dim == 3 ? 80 : 32;
 }
 
@@ -615,11 +626,14 @@ int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     return check_hip("sph_force");
 }
 
-// The reverse passes differentiate the hybrid outlet only.
+// The reverse passes differentiate the hybrid outlet and the Wendland C2
+// kernel only.
 static int hybrid_only(const sph_params *prm, const char *what)
 {
     if (prm && prm->outlet != SPH_OUTLET_HYBRID)
         return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the hybrid outlet only", what);
+    if (prm && (prm->flags & SPH_FLAG_QUINTIC))
+        return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the Wendland C2 kernel only", what);
     return SPH_OK;
 }
 

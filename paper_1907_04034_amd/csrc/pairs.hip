@@ -227,7 +227,7 @@ __device__ inline int walk_candidates(const Dev &k, const Fields &R, Walk &w, in
             }
             if (hit && pos < maxnb) row[pos] = jj[b];
             if (dens && nhit > 0) {
-                const T wv = hit ? wendland_w<T>(T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
+                const T wv = hit ? kernel_w<T>(k, T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
                 if (G == 1) {
                     sw.add(wv);
                 } else {
@@ -392,7 +392,7 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
 #pragma unroll
         for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
         double r[3];
-        sw.add(wendland_w<T>(T(sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h), T(k.wnorm)));
+        sw.add(kernel_w<T>(k, T(sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h), T(k.wnorm)));
     }
     const T S = sw.template reduce<G>();
     if (lane == 0) {
@@ -500,7 +500,8 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
             }
             if (tj != SPH_FLUID) continue;
             double r[3];
-            const double w = wendland_w(sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h, k.wnorm);
+            const double w =
+                kernel_w<double>(k, sqrt(dist2_exact<DIM>(k, xi, xj, r)) * k.inv_h, k.wnorm);
             const double uj0 = uj[0];
             sw += w;
             sp += pj * w;
@@ -780,7 +781,7 @@ __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3
                                 T vi2, T pavg, const Nbr<DIM, T> &nb, Acc<T> acc[3],
                                 Acc<T> bacc[3], Acc<T> &pdot, double fb[3])
 {
-    const T F = wendland_f<T>(T(sqrt(nb.r2)) * T(k.inv_h), T(k.gnorm));
+    const T F = kernel_f<T>(k, T(sqrt(nb.r2)) * T(k.inv_h), T(k.gnorm));
     T gw[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) gw[d] = F * nb.r[d];

@@ -21,6 +21,7 @@ struct Dev {
     int dim, flags, maxnb, prec;
     int reuse;           // keep the last bin while the skin allows (sph_step only)
     int outlet;          // SPH_OUTLET_* rule
+    int quintic;         // 1: the paper's quintic spline (support 3h), 0: Wendland C2 (2h)
     int g_force, g_nbr;  // lanes per target requested (0 = automatic)
     int periodic[3];
     int nc[3];          // cells per axis
@@ -232,6 +233,53 @@ __device__ inline T wendland_f(T q, T gnorm)  // gnorm = -5 a / h^2
 {
     T t = T(1) - T(0.5) * q;
     return q < T(2) ? gnorm * t * t * t : T(0);
+}
+
+// The paper's quintic spline (Sec. 2 eq:quintic-spline), support 3h:
+// W = a [(3-q)^5 - 6 (2-q)^5 + 15 (1-q)^5], each power taken as zero past its
+// range; F = W'(r)/r = (-5 a / h^2) [(3-q)^4 - 6 (2-q)^4 + 15 (1-q)^4] / q,
+// where for q < 1 the bracket over q is the polynomial 24 - 24 q^2 + 10 q^3
+// (no division near q = 0). a = 7/(478 pi h^2) in 2D, 1/(120 pi h^3) in 3D.
+template <typename T>
+__device__ inline T pow5(T t)
+{
+    const T t2 = t * t;
+    return t2 * t2 * t;
+}
+
+template <typename T>
+__device__ inline T quintic_w(T q, T wnorm)
+{
+    const T t3 = q < T(3) ? T(3) - q : T(0);
+    const T t2 = q < T(2) ? T(2) - q : T(0);
+    const T t1 = q < T(1) ? T(1) - q : T(0);
+    return wnorm * (pow5(t3) - T(6) * pow5(t2) + T(15) * pow5(t1));
+}
+
+template <typename T>
+__device__ inline T quintic_f(T q, T gnorm)  // gnorm = -5 a / h^2
+{
+    if (q < T(1)) {
+        const T q2 = q * q;
+        return gnorm * (T(24) - T(24) * q2 + T(10) * q2 * q);
+    }
+    const T t3 = q < T(3) ? T(3) - q : T(0);
+    const T t2 = q < T(2) ? T(2) - q : T(0);
+    const T a3 = t3 * t3, a2 = t2 * t2;
+    return gnorm * (a3 * a3 - T(6) * a2 * a2) / q;
+}
+
+// The run's kernel (the flag is uniform over a launch).
+template <typename T>
+__device__ inline T kernel_w(const Dev &k, T q, T wnorm)
+{
+    return k.quintic ? quintic_w<T>(q, wnorm) : wendland_w<T>(q, wnorm);
+}
+
+template <typename T>
+__device__ inline T kernel_f(const Dev &k, T q, T gnorm)
+{
+    return k.quintic ? quintic_f<T>(q, gnorm) : wendland_f<T>(q, gnorm);
 }
 
 // ------------------------------------------------------------------ geometry

@@ -40,6 +40,7 @@ FLAG_DAMP_NU = 2   # use the physical viscosity in the pressure damping term
 FLAG_NOISE = 4     # add seeded velocity noise to inlet particles at spawn
 FLAG_REUSE_BINS = 8  # GPU stepping option: keep the cell order while the skin allows
                      # (same neighbour sets; the oracle ignores it)
+FLAG_QUINTIC = 16  # the paper's quintic spline (support 3h) instead of Wendland C2 (2h)
 
 ID_GENERATION = 1 << 40   # a spawned inlet particle's id is its parent's + this
 
@@ -116,10 +117,14 @@ def taylor_green_box(n_side=40, L=1.0, U=1.0, nu=0.01):
     return prm, _finish([b])
 
 
-def periodic_lattice(n_side=12, dim=2, dx=0.1, U=0.0):
-    """Perfect periodic lattice with zero fields (used for closed-form checks)."""
+def periodic_lattice(n_side=12, dim=2, dx=0.1, U=0.0, quintic=False):
+    """Perfect periodic lattice with zero fields (used for closed-form checks);
+    quintic: the paper's kernel and h/dx = 1.2."""
     L = n_side * dx
-    prm = base_params(dim=dim, dx=dx, U=max(U, 1.0), name=f"lattice{dim}d")
+    prm = base_params(dim=dim, dx=dx, U=max(U, 1.0), h_over_dx=1.2 if quintic else 1.0,
+                      name=f"lattice{dim}d")
+    if quintic:
+        prm["flags"] |= FLAG_QUINTIC
     prm.update(lo=[0.0] * 3, hi=[L, L, L if dim == 3 else 0.0],
                periodic=[1, 1, 1 if dim == 3 else 0])
     zs = centres(0, n_side, dx) if dim == 3 else [0.0]
@@ -130,7 +135,7 @@ def periodic_lattice(n_side=12, dim=2, dx=0.1, U=0.0):
 def channel(Lx=4.0, Ly=1.0, Lz=None, dx=0.01, layers=5, U=1.0, nu=0.01,
             pulse_amp=None, pulse_x=None, pulse_w=0.1, cyl=None,
             side_walls=None, wall_layers=3, noise=0.0, noise_seed=1907,
-            name="channel"):
+            quintic=False, name="channel"):
     """Wind-tunnel channel: inlet layers | fluid | hybrid outlet layers.
 
     Lz=None gives 2D. side_walls: None (periodic lateral directions),
@@ -138,9 +143,13 @@ def channel(Lx=4.0, Ly=1.0, Lz=None, dx=0.01, layers=5, U=1.0, nu=0.01,
     face, spanning the whole x range). cyl=(xc, yc, D) adds a no-slip body
     made of wall_layers concentric rings spaced dx inward from D/2 - dx/2.
     pulse_amp adds p = A exp(-((x - pulse_x)/pulse_w)^2) to the fluid.
+    quintic: the paper's kernel with its h/dx = 1.2 (support 3.6 dx, within the
+    5 inlet and outlet layers; walls need 4 layers).
     """
     dim = 2 if Lz is None else 3
-    prm = base_params(dim=dim, dx=dx, U=U, nu=nu, name=name)
+    prm = base_params(dim=dim, dx=dx, U=U, nu=nu, h_over_dx=1.2 if quintic else 1.0, name=name)
+    if quintic:
+        prm["flags"] |= FLAG_QUINTIC
     nx, ny = int(round(Lx / dx)), int(round(Ly / dx))
     nz = int(round(Lz / dx)) if dim == 3 else 0
     wl = wall_layers if side_walls else 0
@@ -236,6 +245,23 @@ def config(name, small=False):
             prm, s = channel(Lx=4.0, Ly=1.0, dx=0.01, pulse_amp=0.1, pulse_x=2.0,
                              pulse_w=0.1, name="C2 channel 4x1 dx0.01 pulse")
         prm["steps"] = 2000
+        return prm, s
+    if name == "C2Q":
+        # the 2D channel with the paper's own kernel and resolution ratio
+        if small:
+            prm, s = channel(Lx=0.4, Ly=0.2, dx=0.01, pulse_amp=0.1, pulse_x=0.2,
+                             pulse_w=0.02, quintic=True, name="C2Q-small channel quintic")
+        else:
+            prm, s = channel(Lx=4.0, Ly=1.0, dx=0.01, pulse_amp=0.1, pulse_x=2.0,
+                             pulse_w=0.1, quintic=True,
+                             name="C2Q channel 4x1 dx0.01 pulse quintic h/dx1.2")
+        prm["steps"] = 2000
+        return prm, s
+    if name == "C5Q":
+        # small 3D duct with the paper's kernel (parity only)
+        prm, s = channel(Lx=0.16, Ly=0.08, Lz=0.08, dx=0.01, side_walls="noslip",
+                         wall_layers=4, noise=0.01, quintic=True, name="C5Q-small duct quintic")
+        prm["steps"] = 500
         return prm, s
     if name == "C3":
         if small:

@@ -133,3 +133,23 @@ def test_outlet_rule_validation():
                               C.byref(lam), C.byref(lam), None, 0, None, 0, None) == -6
     assert L.sph_step_record_store(C.byref(q), C.byref(st), C.byref(st), None, 1, None, None,
                                    None, None, 0, None) == -6
+
+
+def test_quintic_kernel_parameters():
+    """The paper's kernel: deeper default tables (1.6 x the 3h ball + 12, in
+    multiples of 16), a workspace for the wider cells, no adjoint."""
+    prm, _ = I.config("C2Q", small=True)
+    q = B.make_params(prm)
+    assert B.lib().sph_default_maxnb(C.byref(q)) == 80
+    prm3, _ = I.config("C5Q", small=True)
+    q3 = B.make_params(prm3)
+    assert B.lib().sph_default_maxnb(C.byref(q3)) == 336
+    assert B.workspace_size(prm, 1000) > 0
+    st = B.SphState()
+    st.cap, st.dim, st.prec = 100, 2, 0
+    nl = B.SphNlist()
+    de = B.SphDerived()
+    adj = B.SphAdjoint()
+    assert B.lib().sph_rhs_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de),
+                                   C.byref(adj), None, 0, None) == -6
+    assert b"Wendland" in B.lib().sph_last_error()

@@ -97,12 +97,31 @@ def test_kernel_gradient_matches_fd(dim):
     assert O.w(2 * h, h, dim) == 0.0 and O.gradw_factor(2 * h, h, dim) == 0.0
 
 
-def test_paper_quintic_spline_normalisation():
-    """The paper's printed alpha_2 = 7/(478 pi h^2) normalises its quintic spline."""
+@pytest.mark.parametrize("dim", [2, 3])
+def test_paper_quintic_spline_normalisation(dim):
+    """The paper's printed alpha_2 = 7/(478 pi h^2) normalises its quintic spline
+    in 2D; alpha_3 = 1/(120 pi h^3) does in 3D."""
     h = 0.8
-    val, _ = integrate.quad(lambda r: O.quintic_spline(r, h) * 2 * math.pi * r, 0, 3 * h,
+    shell = {2: lambda r: 2 * math.pi * r, 3: lambda r: 4 * math.pi * r * r}[dim]
+    val, _ = integrate.quad(lambda r: O.quintic_w(r, h, dim) * shell(r), 0, 3 * h,
                             points=[h, 2 * h], epsabs=1e-14, epsrel=1e-13)
     assert abs(val - 1.0) < 1e-11
+    assert O.quintic_w(3 * h, h, dim) == 0.0 and O.quintic_w(3.01 * h, h, dim) == 0.0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_quintic_gradient_matches_fd(dim):
+    """W'(r)/r of the quintic spline against central differences of W across
+    all three pieces, and its finite limit at r = 0."""
+    h = 0.5
+    scale = abs(O.quintic_w(0, h, dim) / h)
+    for r in np.linspace(0.01, 2.99, 61) * h:
+        e = 1e-6 * h
+        fd = (O.quintic_w(r + e, h, dim) - O.quintic_w(r - e, h, dim)) / (2 * e)
+        assert abs(O.quintic_gradw_factor(r, h, dim) * r - fd) < 1e-7 * scale
+    f0 = O.quintic_gradw_factor(0.0, h, dim)
+    assert abs(f0 - O.quintic_gradw_factor(1e-5 * h, h, dim)) < 1e-8 * abs(f0)
+    assert O.quintic_gradw_factor(3 * h, h, dim) == 0.0
 
 
 # ------------------------------------------------------------ lattice closed forms
@@ -179,6 +198,81 @@ def test_viscous_laplacian(dim):
     m = _interior(prm, s, 1)
     assert np.allclose(d["a"][m, 0], lap * prm["nu"], rtol=1e-10, atol=0)
     assert np.abs(d["a"][m, 1:]).max() < 1e-11
+
+
+def _wq_hat(q, dim):
+    """The paper's quintic spline with h = 1 (mpmath), from its printed pieces,
+    with the normalising constants pinned above."""
+    a = mp.mpf(7) / (478 * mp.pi) if dim == 2 else 1 / (120 * mp.pi)
+    if q >= 3:
+        return mp.mpf(0)
+    w = (3 - q) ** 5
+    if q <= 2:
+        w -= 6 * (2 - q) ** 5
+    if q <= 1:
+        w += 15 * (1 - q) ** 5
+    return a * w
+
+
+def quintic_lattice_constants(dim, hdx=mp.mpf("1.2")):
+    """s, g and the viscous factor of lattice_constants for the quintic spline
+    at h = hdx dx (dx = 1), summed over every lattice offset within 3h."""
+    R = int(mp.floor(3 * hdx))
+    offs = [o for o in itertools.product(range(-R, R + 1), repeat=dim)
+            if sum(v * v for v in o) < (3 * hdx) ** 2]
+    s = g = lap = mp.mpf(0)
+    for o in offs:
+        r = mp.sqrt(sum(v * v for v in o))
+        s += _wq_hat(r / hdx, dim) / hdx ** dim
+        if r == 0:
+            continue
+        dw = mp.diff(lambda z: _wq_hat(z, dim), r / hdx)
+        F = dw / hdx ** (dim + 1) / r
+        g += -F * o[0] ** 2
+        lap += -F * r ** 2 / (r ** 2 + mp.mpf("0.01") * hdx ** 2) * o[1] ** 2
+    return float(s), float(g), float(2 * lap / s), len(offs)
+
+
+def _quintic_lattice(dim):
+    n = 16 if dim == 2 else 12
+    return I.periodic_lattice(n_side=n, dim=dim, dx=1.0 / n, quintic=True)
+
+
+def _deep(prm, s, axis, margin=4):
+    x = s["x"][:, axis]
+    L = prm["hi"][axis] - prm["lo"][axis]
+    return (x > margin * prm["dx"]) & (x < L - margin * prm["dx"])
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_quintic_density_and_pressure_gradient_on_lattice(dim):
+    """The paper's kernel at h/dx = 1.2 on a periodic lattice: rho = rho0 s and,
+    for p = G x, a_x = -(g/s^2) G / rho0 with pbar = p (lattice sums over the
+    3.6 dx support evaluated independently)."""
+    prm, s = _quintic_lattice(dim)
+    sv, g, _, n = quintic_lattice_constants(dim)
+    assert n == (37 if dim == 2 else 179)  # points with |o|^2 <= 12: sums of r_2(n), r_3(n)
+    st, d, _ = O.rhs_once(prm, s)
+    assert np.allclose(d["rho"], prm["rho0"] * sv, rtol=1e-13, atol=0)
+    G = 0.7
+    s["p"] = G * s["x"][:, 0]
+    st, d, _ = O.rhs_once(prm, s)
+    m = _deep(prm, s, 0)
+    assert m.sum() > 10
+    assert np.allclose(d["pavg"][m], s["p"][m], rtol=0, atol=1e-13)
+    assert np.allclose(d["a"][m, 0], -(g / sv ** 2) * G / prm["rho0"], rtol=1e-10, atol=0)
+    assert np.abs(d["a"][m, 1:]).max() < 1e-10
+
+
+def test_quintic_viscous_laplacian():
+    """u_x = y^2 with the paper's kernel: a_x = lap nu (lattice factor above)."""
+    prm, s = _quintic_lattice(2)
+    s["u"][:, 0] = s["x"][:, 1] ** 2
+    s["ut"] = s["u"].copy()
+    st, d, _ = O.rhs_once(prm, s)
+    _, _, lap, _ = quintic_lattice_constants(2)
+    m = _deep(prm, s, 1)
+    assert np.allclose(d["a"][m, 0], lap * prm["nu"], rtol=1e-10, atol=0)
 
 
 def test_pressure_damping_and_neighbour_average():
