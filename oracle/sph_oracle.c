@@ -619,7 +619,11 @@ static void forces(sim *S)
         pi->pdot = pi->abs_pdot = 0.0;
         pi->pavg = 0.0;
         if (pi->type != T_FLUID && pi->type != T_BODY) continue;
-        double pavg = neighbour_pavg(S, i);
+        /* reading: the body force of eq:tvf-momentum_solid takes p~ with a
+         * zero average; subtracting the body particle's own neighbour mean
+         * would cancel the pressure it integrates (and the paper's printed
+         * drag coefficients include that pressure) */
+        double pavg = pi->type == T_FLUID ? neighbour_pavg(S, i) : 0.0;
         pi->pavg = pavg;
         for (int64_t k = S->row[i]; k < S->row[i + 1]; ++k) {
             int64_t j = S->col[k];

@@ -337,7 +337,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
     A.Pbar[i] = double(Pb);
 }
 
-// R2a: pbar_i = (1/N_i) sum_{j in N(i)} p_j  ->  pbar_j += Pbar_i / N_i.
+// R2a: pbar_i = (1/N_i) sum_{j in N(i)} p_j  ->  pbar_j += Pbar_i / N_i, for
+// fluid targets i (body rows take p~ about zero: no neighbour average).
 template <int DIM, int G>
 __global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist nl, DevAdj A,
                                                      uint32_t *err)
@@ -356,7 +357,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist
             continue;
         }
         const int tj = m.type[j];
-        if (tj == SPH_FLUID || tj == SPH_BODY) acc += A.Pbar[j] / double(nl.count[j]);
+        if (tj == SPH_FLUID) acc += A.Pbar[j] / double(nl.count[j]);
     }
     acc = gsum<G>(acc);
     if (lane == 0) A.pbar[i] += acc;

@@ -889,8 +889,11 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
 #pragma unroll
             for (int f = 0; f < PF; ++f)
                 if (okp[f]) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, jp[f], nbp[f]);
+            // the neighbour average of eq:pavg enters the fluid's momentum;
+            // the body force takes p~ about zero (the average of a surface
+            // particle's neighbours would cancel the pressure on the body)
             T pavg = T(0);
-            if (!(k.flags & SPH_FLAG_NO_PAVG)) {
+            if (t == SPH_FLUID && !(k.flags & SPH_FLAG_NO_PAVG)) {
                 Acc<T> sp;
 #pragma unroll
                 for (int f = 0; f < PF; ++f)

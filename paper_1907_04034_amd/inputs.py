@@ -135,13 +135,15 @@ def periodic_lattice(n_side=12, dim=2, dx=0.1, U=0.0, quintic=False):
 def channel(Lx=4.0, Ly=1.0, Lz=None, dx=0.01, layers=5, U=1.0, nu=0.01,
             pulse_amp=None, pulse_x=None, pulse_w=0.1, cyl=None,
             side_walls=None, wall_layers=3, noise=0.0, noise_seed=1907,
-            quintic=False, name="channel"):
+            quintic=False, cyl_layers=None, name="channel"):
     """Wind-tunnel channel: inlet layers | fluid | hybrid outlet layers.
 
     Lz=None gives 2D. side_walls: None (periodic lateral directions),
     'slip' or 'noslip' (wall_layers layers of wall particles on every lateral
     face, spanning the whole x range). cyl=(xc, yc, D) adds a no-slip body
-    made of wall_layers concentric rings spaced dx inward from D/2 - dx/2.
+    made of cyl_layers (default wall_layers; 0 = down to the centre)
+    concentric rings spaced dx inward from D/2 - dx/2, each with particles
+    about dx apart.
     pulse_amp adds p = A exp(-((x - pulse_x)/pulse_w)^2) to the fluid.
     quintic: the paper's kernel with its h/dx = 1.2 (support 3.6 dx, within the
     5 inlet and outlet layers; walls need 4 layers).
@@ -207,7 +209,8 @@ def channel(Lx=4.0, Ly=1.0, Lz=None, dx=0.01, layers=5, U=1.0, nu=0.01,
     if cyl is not None:
         xc, yc, D = cyl
         pts = []
-        for k in range(wall_layers):
+        nring = wall_layers if cyl_layers is None else (cyl_layers or 1 << 30)
+        for k in range(nring):
             rk = 0.5 * D - (k + 0.5) * dx
             if rk <= 0:
                 break
@@ -225,6 +228,22 @@ def channel(Lx=4.0, Ly=1.0, Lz=None, dx=0.01, layers=5, U=1.0, nu=0.01,
         prm["flags"] |= FLAG_NOISE
         prm["noise_amp"] = noise
         prm["noise_seed"] = noise_seed
+    return prm, s
+
+
+def cylinder_tunnel(D=2.0, Re=20.0, dx=0.1, U=1.0, quintic=True, outlet=None):
+    """The paper's flow past a circular cylinder (Sec. 4.6): a 15D x 15D fluid
+    region, the cylinder centred 5D behind the inlet interface and midway
+    between slip walls, 6 layers of inlet, outlet and wall particles, the
+    body filled with rings down to its centre, nu = U D / Re, and the paper's
+    kernel at h = 1.2 dx (quintic=False: Wendland C2 at h = dx)."""
+    L = 15.0 * D
+    prm, s = channel(Lx=L, Ly=L, dx=dx, layers=6, U=U, nu=U * D / Re,
+                     cyl=(5.0 * D, 0.5 * L, D), side_walls="slip", wall_layers=6,
+                     cyl_layers=0, quintic=quintic,
+                     name=f"cylinder tunnel D={D} Re={Re:g} dx={dx:g}")
+    if outlet is not None:
+        prm["outlet"] = outlet
     return prm, s
 
 
