@@ -77,7 +77,7 @@ struct Acc<float> {
 // packed cell.
 template <int DIM, typename T, int G>
 __device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &R, void *rec,
-                                 int64_t i, T rho, T vol, const double xi[3], const int c[3],
+                                 int64_t i, T S, const double xi[3], const int c[3],
                                  uint32_t cposi, int lane)
 {
     using L = Rec<DIM, T>;
@@ -96,12 +96,17 @@ __device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &
         v[L::W + d] = ld<T>(R.ut, d * C + i) - u;
     }
     v[L::P] = ld<T>(R.p, i);
-    v[L::RHO] = rho;
-    v[L::VOL] = vol;
-    if constexpr (L::F32) {
+    if constexpr (L::PACKED) {
+        v[L::VOL] = S;
+        v[L::AUX] = rec_word<T>(cposi | (kind_class(m.type[i]) << 30));
+    } else if constexpr (L::F32) {
+        v[L::RHO] = T(k.mass) * S;
+        v[L::VOL] = T(1) / S;
         v[L::AUX] = rec_word<T>(cposi);
         v[L::AUX + 1] = rec_word<T>(uint32_t(m.type[i]));
     } else {
+        v[L::RHO] = T(k.mass) * S;
+        v[L::VOL] = T(1) / S;
         v[L::AUX] = rec_word<T>(uint32_t(m.type[i]));
     }
     using V = typename Chunk<T>::V;
@@ -354,7 +359,7 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
         }
     }
     if (dens && o.rec)
-        write_rec<DIM, T, G>(k, m, R, o.rec, i, T(k.mass) * S, T(1) / S, xi, c, cpos[i], lane);
+        write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cpos[i], lane);
     if (sizeof(T) == 4) {
         // offsets from the bin cell's corner, for the FP32 pair arithmetic
         for (int d = lane; d < DIM; d += G)
@@ -403,7 +408,7 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
         int c[3] = {0, 0, 0};
         const uint32_t cp = cpos[i];
         unpack_cell<DIM>(cp, c);
-        write_rec<DIM, T, G>(k, m, R, o.rec, i, T(k.mass) * S, T(1) / S, xi, c, cp, lane);
+        write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cp, lane);
     }
 }
 
@@ -750,16 +755,25 @@ __device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R
         T v[L::NC * L::PER];
 #pragma unroll
         for (int ch = 0; ch < L::NC; ++ch) Chunk<T>::get(src[ch], v + ch * L::PER);
-        nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
-        nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
+        if constexpr (L::PACKED) {
+            const uint32_t word = rec_uint<T>(v[L::AUX]);
+            nb.tj = class_kind(word >> 30);
+            nb.r2 = sep.get_rec(k, v + L::X, word & kCellBits, nb.r);
+            const T S = v[L::VOL];
+            nb.rho = T(k.mass) * S;
+            nb.vol = T(1) / S;
+        } else {
+            nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
+            nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
+            nb.rho = v[L::RHO];
+            nb.vol = v[L::VOL];
+        }
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             nb.u[d] = v[L::U + d];
             nb.w[d] = v[L::W + d];
         }
         nb.p = v[L::P];
-        nb.rho = v[L::RHO];
-        nb.vol = v[L::VOL];
     } else {
         const int64_t C = k.cap;
         nb.tj = m.type[j];

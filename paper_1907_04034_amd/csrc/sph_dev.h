@@ -71,17 +71,39 @@ struct DevDerived {
 // (positions or FP32 cell offsets, p, u, w = ut - u, rho, V, kind and, in FP32,
 // the packed cell). Written by the density pass (every row) and the boundary
 // pass (the values it sets), in the state's element type; slots in T units.
-// The library keeps records for FP32 states only.
+// The library keeps records for FP32 states only. In 3D FP32 the record is
+// packed into 48 bytes: the Shepard sum S stands for rho = m S and V = 1/S
+// (formed per pair by the operations that give the stored fields, so the
+// values are the same) and the kind's class (kind_class) shares the word of
+// the 30-bit packed cell: three 16-byte loads instead of four (measured on
+// the 4.6M-particle duct: force pass 1.26 -> 1.19 ms).
 template <int DIM, typename T>
 struct Rec {
-    static constexpr int X = 0, P = DIM, U = 4, RHO = DIM == 3 ? 7 : 3, W = DIM == 3 ? 8 : 6,
-                         VOL = DIM == 3 ? 11 : 8, AUX = DIM == 3 ? 12 : 9;
     static constexpr bool F32 = sizeof(T) == 4;
-    static constexpr int USED = AUX + (F32 ? 2 : 1);   // FP32: cell bits, kind bits; FP64: kind
+    static constexpr bool PACKED = F32 && DIM == 3;
+    static constexpr int X = 0, P = DIM, U = 4, RHO = PACKED ? -1 : (DIM == 3 ? 7 : 3),
+                         W = PACKED ? 7 : (DIM == 3 ? 8 : 6),
+                         VOL = PACKED ? 10 : (DIM == 3 ? 11 : 8),  // PACKED: S
+                         AUX = PACKED ? 11 : (DIM == 3 ? 12 : 9);
+    // FP32: cell bits and kind bits (one word when PACKED); FP64: kind
+    static constexpr int USED = PACKED ? 12 : AUX + (F32 ? 2 : 1);
     static constexpr int PER = 16 / int(sizeof(T));    // T per 16-byte chunk
     static constexpr int NC = (USED + PER - 1) / PER;  // chunks that carry data
-    static constexpr int N = DIM == 3 ? 16 : (F32 ? 12 : 10);  // stride in T (16-byte multiple)
+    static constexpr int N = PACKED ? 12 : (DIM == 3 ? 16 : (F32 ? 12 : 10));  // stride in T
 };
+
+// What the force pass distinguishes of a neighbour's kind: fluid, inlet or
+// outlet (and rows already marked dead), slip wall, no-slip wall or body.
+__device__ inline uint32_t kind_class(int t)
+{
+    return t == SPH_FLUID ? 0u : t == SPH_WALL_SLIP ? 2u
+                             : (t == SPH_WALL_NOSLIP || t == SPH_BODY) ? 3u : 1u;
+}
+__device__ inline int class_kind(uint32_t c)
+{
+    return c == 0u ? SPH_FLUID : c == 2u ? SPH_WALL_SLIP : c == 3u ? SPH_WALL_NOSLIP : SPH_INLET;
+}
+constexpr uint32_t kCellBits = 0x3FFFFFFFu;  // the 3D packed cell (3 x 10 bits)
 template <int DIM, typename T>
 inline size_t rec_bytes() { return sizeof(T) * Rec<DIM, T>::N; }
 
