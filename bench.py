@@ -242,8 +242,10 @@ def main():
                     help="adjoint: gradient of the time-averaged drag (default config C4)")
     ap.add_argument("--segment", type=int, default=50, help="adjoint checkpoint interval")
     ap.add_argument("--outlet", default="hybrid",
-                    choices=["hybrid", "moc", "do-nothing", "mod-do-nothing"],
+                    choices=["hybrid", "moc", "do-nothing", "mod-do-nothing", "mirror"],
                     help="outlet rule (forward form only)")
+    ap.add_argument("--mirror-inlet", action="store_true",
+                    help="inlet pressure mirrored from the fluid (forward form only)")
     ap.add_argument("--sort-every-step", action="store_true",
                     help="sort by cell at every step instead of keeping the cell order "
                          "while the skin allows")
@@ -253,8 +255,9 @@ def main():
         log("bench.py: the benchmark runs on one GPU; --gpus above 1 is not supported")
         sys.exit(2)
     if args.form == "adjoint":
-        if args.outlet != "hybrid":
-            raise SystemExit("the adjoint form covers the hybrid outlet only")
+        if args.outlet != "hybrid" or args.mirror_inlet:
+            raise SystemExit("the adjoint form covers the hybrid outlet and the "
+                             "characteristic inlet only")
         if args.config == "C2" and "--config" not in sys.argv:
             args.config = "C4"
         if "--steps" not in sys.argv:
@@ -270,6 +273,8 @@ def main():
     torch.cuda.set_device(0)
     prm, s = I.config(args.config)
     prm["outlet"] = I.OUTLETS[args.outlet]
+    if args.mirror_inlet:
+        prm["flags"] |= I.FLAG_MIRROR_INLET
     if not args.sort_every_step:
         prm["flags"] |= I.FLAG_REUSE_BINS
     log(f"bench: {prm['name']} n={len(s['p'])} prec={args.precision} "
@@ -354,6 +359,7 @@ def main():
         "config": {"workload": WORKLOADS[args.config], "config": args.config,
                    "particles": int(len(s["p"])), "pairs_per_rhs": p_rhs,
                    "rhs_per_step": 2, "precision": args.precision, "outlet": args.outlet,
+                   "inlet": "mirror" if args.mirror_inlet else "characteristic",
                    "cell_order": "sorted every step" if args.sort_every_step
                    else "kept while the cell skin allows"},
         "roofline": {"bound": "hbm", "kernel": "k_force", "achieved": achieved,

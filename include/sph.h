@@ -62,9 +62,12 @@ enum {
  * paper's quintic spline (Sec. 2 eq:quintic-spline, support 3h, alpha =
  * 7/(478 pi h^2) in 2D and the normalising 1/(120 pi h^3) in 3D) instead of
  * Wendland C2 (support 2h); the neighbour predicate becomes |r|^2 < (3h)^2
- * (forward only: the adjoint entry points return SPH_EUNSUPPORTED). */
+ * (forward only: the adjoint entry points return SPH_EUNSUPPORTED).
+ * SPH_FLAG_MIRROR_INLET gives inlet particles the pressure mirrored from the
+ * fluid (Sec. 3 with Sec. 3.2, as SPH_OUTLET_MIRROR describes, pressure
+ * only) instead of the characteristic J3 (forward only). */
 enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8,
-       SPH_FLAG_QUINTIC = 16 };
+       SPH_FLAG_QUINTIC = 16, SPH_FLAG_MIRROR_INLET = 32 };
 
 /* sph_params.outlet: how outlet particles get their values and move. Every
  * rule advects outlet particles along x only; u, p are those of the rule, ut = u.
@@ -81,11 +84,20 @@ enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_
  *   MOD_DO_NOTHING (Sec. 3.1.1): u, p frozen; advected with the Shepard mean
  *     of the fluid x velocity (eq:shepard0), without fluid support with the
  *     previous-step red mean of that velocity (as eq:average_old).
+ *   MIRROR (Sec. 3.2): the particle reflected about x_outlet into the fluid;
+ *     p and u and their gradients at that point from the first-order
+ *     corrected system eq:matform over fluid particles within the support
+ *     (x_lk = x_l - x_k, V_l = 1/sum W), extrapolated back with the paper's
+ *     eq:taylor2, f = f_k - (r - r_k) . grad f_k; a near-singular system (a
+ *     pivot below 1e-3 of the largest entry of the system made dimensionless
+ *     with h) gives the Shepard value, no fluid at the mirror point keeps
+ *     the previous values; advected with u.
  * jcur holds (J1, J2, J3) for HYBRID and MOC and (u_ex, 0, 0) for
- * MOD_DO_NOTHING; DO_NOTHING extrapolates nothing (red particles hold zeros).
+ * MOD_DO_NOTHING; DO_NOTHING and MIRROR keep no characteristic values (red
+ * particles hold zeros).
  * Inlets use the characteristic inlet in all four. */
 enum { SPH_OUTLET_HYBRID = 0, SPH_OUTLET_MOC = 1, SPH_OUTLET_DO_NOTHING = 2,
-       SPH_OUTLET_MOD_DO_NOTHING = 3 };
+       SPH_OUTLET_MOD_DO_NOTHING = 3, SPH_OUTLET_MIRROR = 4 };
 
 /* device error-word bits */
 enum {

@@ -27,8 +27,10 @@
  *                 eq:acouinten, composition eq:acou, x-only advection
  *   other outlets selected by orc_params.outlet: pure method of
  *                 characteristics with fixed references (Sec. 3.3),
- *                 do-nothing (Sec. 3.1, eq:nrbc2) and modified do-nothing
- *                 (Sec. 3.1.1, eq:shepard0)
+ *                 do-nothing (Sec. 3.1, eq:nrbc2), modified do-nothing
+ *                 (Sec. 3.1.1, eq:shepard0) and mirroring (Sec. 3.2,
+ *                 eq:matform, eq:taylor2), which can also give the inlet
+ *                 pressure (flag F_MIRROR_INLET)
  *   inlet         prescribed velocity; pressure from the incoming
  *                 characteristic J3 (reference: inlet velocity, zero pressure)
  *   force pass    Sec. 2: eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
@@ -64,6 +66,7 @@
 #define F_DAMP_NU 2
 #define F_NOISE 4
 #define F_QUINTIC 16 /* the paper's quintic spline instead of Wendland C2 */
+#define F_MIRROR_INLET 32 /* inlet pressure by mirroring (Sec. 3, Sec. 3.2) */
 #define ID_GENERATION ((int64_t)1 << 40)
 
 /* outlet rules */
@@ -71,6 +74,7 @@
 #define OUT_MOC 1
 #define OUT_DO_NOTHING 2
 #define OUT_MOD_DO_NOTHING 3
+#define OUT_MIRROR 4
 
 typedef struct {
     int32_t dim, n_avg, flags, periodic[3];
@@ -444,6 +448,110 @@ static void fallback_J(const sim *S, int64_t i, double J[3])
     for (int a = 0; a < 3; ++a) J[a] = M ? s[a] / (double)M : pi->jprev[a];
 }
 
+/* Sec. 3.2, eq:matform: first-order corrected SPH estimate of a field and
+ * its gradient at the point xk from the fluid particles l within the
+ * kernel support of xk: sum_l [W, x_lk W, ...; W_x, x_lk W_x, ...; ...] V_l
+ * times (f_k, grad f_k) equals sum_l f_l [W, W_x, ...] V_l, with
+ * x_lk = x_l - x_k, W_b = dW/dx_b at x_l - x_k and V_l = 1 / sum_j W_lj,
+ * for the fields p, u_x, u_y (, u_z). Solved by Gaussian elimination with
+ * partial pivoting on the dimensionless system (x_lk / h in the columns, the
+ * derivative rows times h, so that every entry is of order one). reading:
+ * where a pivot falls below 1e-3 of the largest entry (sources nearly on a
+ * line, as for a point about one spacing beyond the last fluid column with
+ * a 2h support) the zeroth-order Shepard value with zero gradient is taken.
+ * Returns 0 when no fluid particle lies within the support of xk. sol[f][0]
+ * is the value of field f, sol[f][1 + b] its derivative along b. */
+static int mirror_fit(const sim *S, const double xk[3], double sol[4][4])
+{
+    const orc_params *q = &S->q;
+    const int dim = q->dim, ne = dim + 1;
+    double A[4][4] = {{0}}, B[4][4] = {{0}}; /* B[row][field] */
+    for (int64_t l = 0; l < S->n; ++l) {
+        const part *pl = &S->P[l];
+        if (pl->type != T_FLUID) continue;
+        double r[3];
+        diff(q, pl->x, xk, r); /* x_l - x_k */
+        double r2 = dot_self(dim, r);
+        if (!(r2 < support2(q))) continue;
+        double w = kernel_w(q, sqrt(r2)), F = kernel_f(q, sqrt(r2));
+        double rowm[4] = {w * pl->vol, 0, 0, 0}, col[4] = {1.0, 0, 0, 0};
+        double fl[4] = {pl->p, 0, 0, 0};
+        for (int b = 0; b < dim; ++b) {
+            rowm[1 + b] = q->h * F * r[b] * pl->vol;
+            col[1 + b] = r[b] / q->h;
+            fl[1 + b] = pl->u[b];
+        }
+        for (int a = 0; a < ne; ++a) {
+            for (int c = 0; c < ne; ++c) A[a][c] += rowm[a] * col[c];
+            for (int f = 0; f < ne; ++f) B[a][f] += rowm[a] * fl[f];
+        }
+    }
+    if (!(A[0][0] > 0.0)) return 0;
+    double shep[4];
+    for (int f = 0; f < ne; ++f) shep[f] = B[0][f] / A[0][0];
+    double amax = 0.0;
+    for (int a = 0; a < ne; ++a)
+        for (int c = 0; c < ne; ++c) amax = fmax(amax, fabs(A[a][c]));
+    int singular = 0;
+    for (int c = 0; c < ne && !singular; ++c) {
+        int pr = c;
+        for (int a = c + 1; a < ne; ++a)
+            if (fabs(A[a][c]) > fabs(A[pr][c])) pr = a;
+        if (!(fabs(A[pr][c]) > 1e-3 * amax)) {
+            singular = 1;
+            break;
+        }
+        if (pr != c) {
+            for (int x = 0; x < ne; ++x) {
+                double t = A[c][x]; A[c][x] = A[pr][x]; A[pr][x] = t;
+                t = B[c][x]; B[c][x] = B[pr][x]; B[pr][x] = t;
+            }
+        }
+        for (int a = c + 1; a < ne; ++a) {
+            double m = A[a][c] / A[c][c];
+            for (int x = c; x < ne; ++x) A[a][x] -= m * A[c][x];
+            for (int f = 0; f < ne; ++f) B[a][f] -= m * B[c][f];
+        }
+    }
+    for (int f = 0; f < ne; ++f) {
+        if (singular) {
+            sol[f][0] = shep[f];
+            for (int b = 0; b < dim; ++b) sol[f][1 + b] = 0.0;
+            continue;
+        }
+        double x[4] = {0, 0, 0, 0};
+        for (int a = ne - 1; a >= 0; --a) {
+            double v = B[a][f];
+            for (int c = a + 1; c < ne; ++c) v -= A[a][c] * x[c];
+            x[a] = v / A[a][a];
+        }
+        sol[f][0] = x[0];
+        for (int b = 0; b < dim; ++b) sol[f][1 + b] = x[1 + b] / q->h;
+    }
+    return 1;
+}
+
+/* Sec. 3.2: boundary particle i mirrored about the interface x = xif into the
+ * fluid (x_k = 2 xif - x_i, other coordinates kept); its fields are those of
+ * the mirror point extrapolated with the paper's sign-flipped expansion
+ * eq:taylor2, f_i = f_k - (r_i - r_k) . grad f_k. out[0] = p, out[1 + b] =
+ * u_b. Returns 0 (out untouched) without fluid at the mirror point. */
+static int mirror_value(const sim *S, int64_t i, double xif, double out[4])
+{
+    const part *pi = &S->P[i];
+    const int dim = S->q.dim;
+    double xk[3] = {pi->x[0], pi->x[1], pi->x[2]};
+    xk[0] = 2.0 * xif - pi->x[0];
+    double sol[4][4];
+    if (!mirror_fit(S, xk, sol)) return 0;
+    for (int f = 0; f <= dim; ++f) {
+        double v = sol[f][0];
+        for (int b = 0; b < dim; ++b) v -= (pi->x[b] - xk[b]) * sol[f][1 + b];
+        out[f] = v;
+    }
+    return 1;
+}
+
 static void boundary_values(sim *S)
 {
     const orc_params *q = &S->q;
@@ -465,7 +573,9 @@ static void boundary_values(sim *S)
             sp += f->p * w;
             for (int d = 0; d < dim; ++d) su[d] += f->u[d] * w;
             double J[3];
-            if (t == T_INLET) {
+            if (t == T_INLET && (q->flags & F_MIRROR_INLET)) {
+                J[0] = J[1] = J[2] = 0.0; /* the pressure comes from the mirror */
+            } else if (t == T_INLET) {
                 /* reading: incoming characteristic J3 with reference
                  * (u, p) = (prescribed inlet velocity of i, 0) */
                 J[0] = 0.0;
@@ -477,8 +587,8 @@ static void boundary_values(sim *S)
                 J[0] = f->u[0];
                 J[1] = 0.0;
                 J[2] = 0.0;
-            } else if (q->outlet == OUT_DO_NOTHING) {
-                J[0] = J[1] = J[2] = 0.0; /* nothing is extrapolated */
+            } else if (q->outlet == OUT_DO_NOTHING || q->outlet == OUT_MIRROR) {
+                J[0] = J[1] = J[2] = 0.0; /* no characteristic values */
             } else {
                 fluid_J(q, f, J);
             }
@@ -521,11 +631,25 @@ static void boundary_values(sim *S)
             double u_ac = (Jh[1] - Jh[2]) / (2.0 * q->rho0 * q->c);
             pi->p = 0.0 + p_ac;
             pi->u[0] = q->U + u_ac;
+        } else if (t == T_OUTLET && q->outlet == OUT_MIRROR) {
+            /* Sec. 3.2: p and every velocity component from the mirror
+             * point, extrapolated with eq:taylor2; no fluid there: kept */
+            double f[4];
+            if (mirror_value(S, i, q->x_outlet, f)) {
+                pi->p = f[0];
+                for (int d = 0; d < dim; ++d) pi->u[d] = f[1 + d];
+            }
         } else if (t == T_OUTLET) {
             /* Sec. 3.1 and 3.1.1: velocity and pressure stay frozen */
         } else if (t == T_INLET) {
-            /* prescribed velocity: u - u_ref = 0, so p = J3 */
-            pi->p = Jh[2];
+            if (q->flags & F_MIRROR_INLET) {
+                /* Sec. 3: the inlet pressure mirrored from the fluid */
+                double f[4];
+                if (mirror_value(S, i, q->x_inlet, f)) pi->p = f[0];
+            } else {
+                /* prescribed velocity: u - u_ref = 0, so p = J3 */
+                pi->p = Jh[2];
+            }
             for (int d = 0; d < dim; ++d) pi->u[d] = pi->uin[d];
         }
         for (int d = 0; d < dim; ++d) pi->ut[d] = pi->u[d];

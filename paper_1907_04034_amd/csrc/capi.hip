@@ -62,7 +62,7 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     if (cap < 1 || cap > INT32_MAX) return fail(SPH_EINVAL, "cap must be in [1, 2^31)");
     if (p->list_cap < 0 || p->list_cap > 2048)
         return fail(SPH_EINVAL, "list_cap must be in [0, 2048] (got %d)", p->list_cap);
-    if (p->outlet < SPH_OUTLET_HYBRID || p->outlet > SPH_OUTLET_MOD_DO_NOTHING)
+    if (p->outlet < SPH_OUTLET_HYBRID || p->outlet > SPH_OUTLET_MIRROR)
         return fail(SPH_EINVAL, "outlet must be an SPH_OUTLET_* rule (got %d)", p->outlet);
     if (prec != SPH_FP64 && prec != SPH_FP32) return fail(SPH_EINVAL, "bad precision %d", prec);
     std::memset(k, 0, sizeof *k);
@@ -411,7 +411,9 @@ static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_
                         const sph_derived *o)
 {
     launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), c.der(o),
-                    at<int32_t>(c.ws, c.w.blist), at<int32_t>(c.ws, c.w.bcount), c.err(), c.s);
+                    at<int32_t>(c.ws, c.w.blist), at<int32_t>(c.ws, c.w.bcount),
+                    at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start), c.err(),
+                    c.s);
 }
 
 static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields &W,
@@ -634,6 +636,9 @@ static int hybrid_only(const sph_params *prm, const char *what)
         return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the hybrid outlet only", what);
     if (prm && (prm->flags & SPH_FLAG_QUINTIC))
         return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the Wendland C2 kernel only", what);
+    if (prm && (prm->flags & SPH_FLAG_MIRROR_INLET))
+        return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the characteristic inlet only",
+                    what);
     return SPH_OK;
 }
 

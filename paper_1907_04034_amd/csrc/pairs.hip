@@ -429,6 +429,159 @@ __device__ inline void rec_set_pu(const Dev &k, const Fields &R, void *rec, int6
     }
 }
 
+// ------------------------------------------------------------------ mirror
+// Sec. 3.2, eq:matform: first-order corrected estimate of p and the velocity
+// components and their gradients at the point xk from the fluid particles l
+// within the kernel support of xk (x_lk = x_l - x_k, W_b = F (x_l - x_k)_b,
+// V_l = 1/S_l), found by walking the 3^d cells around xk's cell (cells are
+// at least support + 2 disp_max wide, so binned rows within the skin are
+// covered); the group's lanes take cells in turn and the sums are reduced
+// over the group. Gaussian elimination with partial pivoting on the
+// dimensionless system (x_lk / h in the columns, the derivative rows times
+// h); where a pivot falls below 1e-3 of the largest entry (sources nearly on
+// a line), the zeroth-order Shepard value with zero gradient. Returns false
+// without fluid in the support; sol[f][0] is field f (p, u_x, u_y[, u_z]),
+// sol[f][1 + b] its derivative along b.
+template <int DIM, typename T, int G>
+__device__ inline bool mirror_fit(const Dev &k, const DevState &m, const Fields &R,
+                                  const DevDerived &o, const uint32_t *spread,
+                                  const int32_t *cell_start, int64_t n, const double xk[3],
+                                  int lane, uint32_t *err, double sol[DIM + 1][DIM + 1])
+{
+    constexpr int NE = DIM + 1;
+    constexpr int NS = DIM == 2 ? 9 : 27;
+    const int64_t C = k.cap;
+    double A[NE][NE], B[NE][NE];  // B[row][field]
+#pragma unroll
+    for (int a = 0; a < NE; ++a)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) A[a][c] = B[a][c] = 0.0;
+    int ck[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double f = floor((xk[d] - k.lo[d]) * k.inv_cs[d]);
+        ck[d] = !(f >= 0.0) ? 0 : (f >= double(k.nc[d]) ? k.nc[d] - 1 : int(f));
+    }
+    for (int sc = lane; sc < NS; sc += G) {
+        const int dxs = sc % 3 - 1, dys = (sc / 3) % 3 - 1, dzs = DIM == 3 ? sc / 9 - 1 : 0;
+        int cc[3] = {ck[0] + dxs, ck[1] + dys, ck[2] + dzs};
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            if (cc[d] < 0 || cc[d] >= k.nc[d]) {
+                if (k.periodic[d]) cc[d] = cc[d] < 0 ? cc[d] + k.nc[d] : cc[d] - k.nc[d];
+                else ok = false;
+            }
+        }
+        if (!ok) continue;
+        const uint32_t key = morton_key<DIM>(spread, cc);
+        const int32_t b = cell_start[key], e = cell_start[key + 1];
+        if (b < 0 || e > n || b > e) {
+            raise_error(err, SPH_ERR_CELL_RANGE);
+            continue;
+        }
+        for (int32_t l = b; l < e; ++l) {
+            if (m.type[l] != SPH_FLUID) continue;
+            double xl[3] = {0, 0, 0}, r[3];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) xl[d] = R.x[d * C + l];
+            const double r2 = dist2_exact<DIM>(k, xl, xk, r);  // r = x_l - x_k
+            if (!(r2 < k.sup2)) continue;
+            const double q = sqrt(r2) * k.inv_h;
+            const double V = double(ld<T>(o.vol, l));
+            const double w = kernel_w<double>(k, q, k.wnorm) * V;
+            const double F = k.h * kernel_f<double>(k, q, k.gnorm) * V;
+            double rowm[NE], col[NE], fl[NE];
+            rowm[0] = w;
+            col[0] = 1.0;
+            fl[0] = double(ld<T>(R.p, l));
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                rowm[1 + d] = F * r[d];
+                col[1 + d] = r[d] * k.inv_h;
+                fl[1 + d] = double(ld<T>(R.u, d * C + l));
+            }
+#pragma unroll
+            for (int a = 0; a < NE; ++a)
+#pragma unroll
+                for (int c = 0; c < NE; ++c) {
+                    A[a][c] += rowm[a] * col[c];
+                    B[a][c] += rowm[a] * fl[c];
+                }
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < NE; ++a)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) {
+            A[a][c] = gsum<G>(A[a][c]);
+            B[a][c] = gsum<G>(B[a][c]);
+        }
+    if (!(A[0][0] > 0.0)) return false;
+    double amax = 0.0;
+#pragma unroll
+    for (int a = 0; a < NE; ++a)
+#pragma unroll
+        for (int c = 0; c < NE; ++c) amax = fmax(amax, fabs(A[a][c]));
+    double shep[NE];
+#pragma unroll
+    for (int f = 0; f < NE; ++f) shep[f] = B[0][f] / A[0][0];
+    bool singular = false;
+#pragma unroll
+    for (int c = 0; c < NE; ++c) {
+        if (singular) break;
+        int pr = c;
+#pragma unroll
+        for (int a = c + 1; a < NE; ++a)
+            if (fabs(A[a][c]) > fabs(A[pr][c])) pr = a;
+        if (!(fabs(A[pr][c]) > 1e-3 * amax)) {
+            singular = true;
+            break;
+        }
+        if (pr != c) {
+#pragma unroll
+            for (int x = 0; x < NE; ++x) {
+                double t = A[c][x];
+                A[c][x] = A[pr][x];
+                A[pr][x] = t;
+                t = B[c][x];
+                B[c][x] = B[pr][x];
+                B[pr][x] = t;
+            }
+        }
+#pragma unroll
+        for (int a = c + 1; a < NE; ++a) {
+            const double mul = A[a][c] / A[c][c];
+#pragma unroll
+            for (int x = 0; x < NE; ++x) {
+                if (x >= c) A[a][x] -= mul * A[c][x];
+                B[a][x] -= mul * B[c][x];
+            }
+        }
+    }
+#pragma unroll
+    for (int f = 0; f < NE; ++f) {
+        if (singular) {
+            sol[f][0] = shep[f];
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) sol[f][1 + d] = 0.0;
+            continue;
+        }
+        double xs[NE];
+#pragma unroll
+        for (int a = NE - 1; a >= 0; --a) {
+            double v = B[a][f];
+#pragma unroll
+            for (int c = a + 1; c < NE; ++c) v -= A[a][c] * xs[c];
+            xs[a] = v / A[a][a];
+        }
+        sol[f][0] = xs[0];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) sol[f][1 + d] = xs[1 + d] * k.inv_h;
+    }
+    return true;
+}
+
 // ---------------------------------------------------------- boundary values
 // Over the non-fluid rows listed at bin time. Walls: Shepard-averaged fluid
 // pressure and ghost velocity u_g = -<u_f> (static walls, no body force).
@@ -446,7 +599,9 @@ __device__ inline void rec_set_pu(const Dev &k, const Fields &R, void *rec, int6
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R, DevNlist nl,
                                                      DevDerived o, const int32_t *blist,
-                                                     const int32_t *bcount, uint32_t *err)
+                                                     const int32_t *bcount,
+                                                     const uint32_t *spread,
+                                                     const int32_t *cell_start, uint32_t *err)
 {
     constexpr int PB = kBlock / G;
     const int lane = threadIdx.x & (G - 1);
@@ -512,11 +667,12 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
             sp += pj * w;
 #pragma unroll
             for (int d = 0; d < DIM; ++d) su[d] += uj[d] * w;
-            if (t == SPH_INLET) {
+            if (t == SPH_INLET && !(k.flags & SPH_FLAG_MIRROR_INLET)) {
                 sJ[2] += (-rhoj * k.c * (uj0 - uin0) + pj) * w;
             } else if (t == SPH_OUTLET && k.outlet == SPH_OUTLET_MOD_DO_NOTHING) {
                 sJ[0] += uj0 * w;  // eq:shepard0, the fluid x velocity
-            } else if (t == SPH_OUTLET && k.outlet != SPH_OUTLET_DO_NOTHING) {
+            } else if (t == SPH_OUTLET && k.outlet != SPH_OUTLET_DO_NOTHING &&
+                       k.outlet != SPH_OUTLET_MIRROR) {
                 // references: the fluid particle's time averages (hybrid) or
                 // the fixed u = U, p = 0 (characteristics)
                 const bool moc = k.outlet == SPH_OUTLET_MOC;
@@ -573,6 +729,28 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 J[a] = M > 0.0 ? acc / M : m.jprev[a * C + i];
             }
         }
+        // mirroring (Sec. 3.2): the row reflected about its interface into
+        // the fluid; the group fits p and u there (eq:matform)
+        const bool mir = (t == SPH_OUTLET && k.outlet == SPH_OUTLET_MIRROR) ||
+                         (t == SPH_INLET && (k.flags & SPH_FLAG_MIRROR_INLET));
+        double mval[4] = {0, 0, 0, 0};
+        bool mok = false;
+        if (mir) {
+            double xk[3] = {xi[0], xi[1], xi[2]};
+            xk[0] = 2.0 * (t == SPH_OUTLET ? k.x_outlet : k.x_inlet) - xi[0];
+            double sol[DIM + 1][DIM + 1];
+            mok = mirror_fit<DIM, T, G>(k, m, R, o, spread, cell_start, n, xk, lane, err, sol);
+            if (mok) {
+                // eq:taylor2: f_i = f_k - (r_i - r_k) . grad f_k
+#pragma unroll
+                for (int f = 0; f <= DIM; ++f) {
+                    double v = sol[f][0];
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) v -= (xi[d] - xk[d]) * sol[f][1 + d];
+                    mval[f] = v;
+                }
+            }
+        }
         if (lane == 0) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) o.jcur[a * C + i] = J[a];
@@ -600,11 +778,18 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 #pragma unroll
                 for (int d = 1; d < DIM; ++d) st<T>(R.ut, d * C + i, ld<T>(R.u, d * C + i));
             } else if (t == SPH_OUTLET) {
-                // do-nothing rules: u, p stay frozen
+                // mirror: p and u from the mirror point (kept without fluid
+                // there); do-nothing rules: u, p stay frozen
+                if (mok) {
+                    st<T>(R.p, i, T(mval[0]));
+#pragma unroll
+                    for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, T(mval[1 + d]));
+                }
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) st<T>(R.ut, d * C + i, ld<T>(R.u, d * C + i));
-            } else {  // inlet: prescribed velocity, p = J3
-                st<T>(R.p, i, T(J[2]));
+            } else {  // inlet: prescribed velocity, p = J3 or mirrored
+                if (!mir) st<T>(R.p, i, T(J[2]));
+                else if (mok) st<T>(R.p, i, T(mval[0]));
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
                     st<T>(R.u, d * C + i, T(m.uin[d * C + i]));
@@ -698,9 +883,10 @@ __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fie
 #pragma clang fp contract(off)
     const int64_t C = k.cap;
     const double dt = mode == 2 ? k.dt : k.hdt;
-    // outlet rules other than the hybrid keep (part of) the start values: the
-    // half state carries them into stage 2
-    const bool keep = mode == 1 && t == SPH_OUTLET && k.outlet != SPH_OUTLET_HYBRID;
+    // outlet rules other than the hybrid and a mirrored inlet keep (part of)
+    // the start values: the half state carries them into stage 2
+    const bool keep = mode == 1 && ((t == SPH_OUTLET && k.outlet != SPH_OUTLET_HYBRID) ||
+                                    (t == SPH_INLET && (k.flags & SPH_FLAG_MIRROR_INLET)));
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         const double x0 = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
@@ -1050,21 +1236,22 @@ static int bnd_grid(const Dev &k)
 template <int G>
 static void boundary_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                        const DevDerived &o, const int32_t *blist, const int32_t *bcount,
-                       uint32_t *err, hipStream_t s)
+                       const uint32_t *spread, const int32_t *cell_start, uint32_t *err,
+                       hipStream_t s)
 {
     const dim3 g(bnd_grid(k)), b(kBlock);
     if (k.dim == 2 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_boundary<2, double, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
-                           err);
+                           spread, cell_start, err);
     else if (k.dim == 3 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_boundary<3, double, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
-                           err);
+                           spread, cell_start, err);
     else if (k.dim == 2)
         hipLaunchKernelGGL((k_boundary<2, float, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
-                           err);
+                           spread, cell_start, err);
     else
         hipLaunchKernelGGL((k_boundary<3, float, G>), g, b, 0, s, k, m, R, nl, o, blist, bcount,
-                           err);
+                           spread, cell_start, err);
 }
 
 #define SPH_PREC_DIM(KERNEL, GRID, ...)                                                       \
@@ -1144,12 +1331,13 @@ void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevN
 
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                      const DevDerived &o, const int32_t *blist, const int32_t *bcount,
-                     uint32_t *err, hipStream_t s)
+                     const uint32_t *spread, const int32_t *cell_start, uint32_t *err,
+                     hipStream_t s)
 {
     if (bnd_group(k) == 16)
-        boundary_g<16>(k, m, R, nl, o, blist, bcount, err, s);
+        boundary_g<16>(k, m, R, nl, o, blist, bcount, spread, cell_start, err, s);
     else
-        boundary_g<8>(k, m, R, nl, o, blist, bcount, err, s);
+        boundary_g<8>(k, m, R, nl, o, blist, bcount, spread, cell_start, err, s);
 }
 
 template <int DIM, typename T, int G, int PF>

@@ -45,7 +45,8 @@ void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevN
                     const DevDerived &o, const uint32_t *cpos, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                      const DevDerived &o, const int32_t *blist, const int32_t *bcount,
-                     uint32_t *err, hipStream_t s);
+                     const uint32_t *spread, const int32_t *cell_start, uint32_t *err,
+                     hipStream_t s);
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
                   const uint32_t *cpos, int mode, int want_drag, double *dragpart,

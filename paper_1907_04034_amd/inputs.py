@@ -41,13 +41,14 @@ FLAG_NOISE = 4     # add seeded velocity noise to inlet particles at spawn
 FLAG_REUSE_BINS = 8  # GPU stepping option: keep the cell order while the skin allows
                      # (same neighbour sets; the oracle ignores it)
 FLAG_QUINTIC = 16  # the paper's quintic spline (support 3h) instead of Wendland C2 (2h)
+FLAG_MIRROR_INLET = 32  # inlet pressure mirrored from the fluid instead of the characteristic J3
 
 ID_GENERATION = 1 << 40   # a spawned inlet particle's id is its parent's + this
 
 # outlet rules (the "outlet" entry of a parameter dict; absent = hybrid)
-OUTLET_HYBRID, OUTLET_MOC, OUTLET_DO_NOTHING, OUTLET_MOD_DO_NOTHING = 0, 1, 2, 3
+OUTLET_HYBRID, OUTLET_MOC, OUTLET_DO_NOTHING, OUTLET_MOD_DO_NOTHING, OUTLET_MIRROR = 0, 1, 2, 3, 4
 OUTLETS = {"hybrid": OUTLET_HYBRID, "moc": OUTLET_MOC, "do-nothing": OUTLET_DO_NOTHING,
-           "mod-do-nothing": OUTLET_MOD_DO_NOTHING}
+           "mod-do-nothing": OUTLET_MOD_DO_NOTHING, "mirror": OUTLET_MIRROR}
 
 
 def base_params(*, dim, dx, U=1.0, c_factor=10.0, rho0=1.0, nu=0.01, alpha=0.5,

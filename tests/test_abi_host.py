@@ -110,7 +110,7 @@ def test_outlet_rule_validation():
     """An unknown outlet rule is rejected; the reverse entry points accept the
     hybrid outlet only (SPH_EUNSUPPORTED for the others, before any launch)."""
     prm, _ = I.config("C2", small=True)
-    _bad(prm, outlet=4)
+    _bad(prm, outlet=5)
     _bad(prm, outlet=-1)
     for rule in (I.OUTLET_MOC, I.OUTLET_DO_NOTHING, I.OUTLET_MOD_DO_NOTHING):
         assert B.workspace_size(dict(prm, outlet=rule), 1000) > 0
@@ -153,3 +153,16 @@ def test_quintic_kernel_parameters():
     assert B.lib().sph_rhs_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de),
                                    C.byref(adj), None, 0, None) == -6
     assert b"Wendland" in B.lib().sph_last_error()
+
+
+def test_mirror_rule_validation():
+    prm, _ = I.config("C2", small=True)
+    assert B.workspace_size(dict(prm, outlet=I.OUTLET_MIRROR), 1000) > 0
+    _bad(prm, outlet=I.OUTLET_MIRROR + 1)
+    q = B.make_params(dict(prm, flags=prm["flags"] | I.FLAG_MIRROR_INLET))
+    st = B.SphState()
+    st.cap, st.dim, st.prec = 100, 2, 0
+    nl, de, adj = B.SphNlist(), B.SphDerived(), B.SphAdjoint()
+    assert B.lib().sph_rhs_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de),
+                                   C.byref(adj), None, 0, None) == -6
+    assert b"inlet" in B.lib().sph_last_error()

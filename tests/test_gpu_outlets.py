@@ -1,5 +1,6 @@
 """The outlet rules beside the hybrid (method of characteristics with fixed
-references, do-nothing, modified do-nothing): HIP path against the oracle.
+references, do-nothing, modified do-nothing, mirroring) and the mirrored
+inlet pressure: HIP path against the oracle.
 
 * One right-hand side (FP64 to 1e-12, FP32 to 1e-5 of the field scale, as the
   hybrid's parity tests): boundary values, red flags, jcur and the fluid's
@@ -21,7 +22,16 @@ from paper_1907_04034_amd import inputs as I
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-RULES = ["moc", "do-nothing", "mod-do-nothing"]
+RULES = ["moc", "do-nothing", "mod-do-nothing", "mirror", "hybrid+mirror-inlet"]
+
+
+def _with_rule(prm, rule):
+    """A rule name; "+mirror-inlet" adds the mirrored inlet pressure."""
+    outlet, _, extra = rule.partition("+")
+    prm = dict(prm, outlet=I.OUTLETS[outlet])
+    if extra == "mirror-inlet":
+        prm["flags"] = prm["flags"] | I.FLAG_MIRROR_INLET
+    return prm
 
 
 def B():
@@ -41,7 +51,7 @@ def _nerr(got, ref, floor=0.0):
 
 def _case(name, rule, seed=11):
     prm, s = I.config(name.split("-")[0], small=True)
-    prm = dict(prm, outlet=I.OUTLETS[rule])
+    prm = _with_rule(prm, rule)
     s = I.random_fields(prm, I.jitter(prm, s, 0.15, 7), seed)
     rng = np.random.default_rng(seed + 1)
     out = s["type"] == I.OUTLET
@@ -111,15 +121,26 @@ def _oracle_state(prm, s, steps):
     return _by_id(o.state())
 
 
-@pytest.mark.parametrize("name,steps", [("C2-small", 300), ("C5-small", 60)])
-@pytest.mark.parametrize("rule", RULES)
+# The mirror outlet in the small 3D duct: near the corner of a no-slip wall
+# and the outlet the fit drives a spike (the oracle reaches p = 28 and
+# u_x = 30 after 44 steps), so particles outrun the 3D cell skin and the HIP
+# path reports SPH_ERR_SKIN; the rule is compared there for one RHS only.
+TRAJ_CASES = [pytest.param(rule, name, steps, marks=pytest.mark.skip(
+                  reason="mirror outlet diverges at the wall corner of the small 3D duct "
+                         "(oracle and HIP path alike); one-RHS parity covers it"))
+              if (rule == "mirror" and name == "C5-small") else (rule, name, steps)
+              for rule in RULES for name, steps in [("C2-small", 300), ("C5-small", 60)]]
+
+
+@pytest.mark.parametrize("rule,name,steps", TRAJ_CASES)
 def test_outlet_rule_trajectory_parity(rule, name, steps):
     """GPU (cell order kept between sorts) vs oracle after many steps, within
     20 times the oracle's own sensitivity to a one-ulp position change (floor
     1e-10)."""
     print(f"outlet rule {rule} trajectory {name} {steps}", flush=True)
     prm, s = I.config(name.split("-")[0], small=True)
-    prm = dict(prm, outlet=I.OUTLETS[rule], flags=prm["flags"] | I.FLAG_REUSE_BINS)
+    prm = _with_rule(prm, rule)
+    prm["flags"] |= I.FLAG_REUSE_BINS
     s = I.jitter(prm, s, 1e-3, 5, types=(I.FLUID, I.INLET, I.OUTLET))
     sim = B().Simulation(prm, s)
     sim.step(steps)
@@ -161,8 +182,10 @@ def _reflection(rule):
 
 
 def test_pulse_reflection_by_outlet_rule():
-    R = {rule: _reflection(rule) for rule in ["hybrid", "moc", "do-nothing", "mod-do-nothing"]}
+    R = {rule: _reflection(rule)
+         for rule in ["hybrid", "moc", "do-nothing", "mod-do-nothing", "mirror"]}
     print("reflection " + ", ".join(f"{k} {v:.4f}" for k, v in R.items()), flush=True)
     assert R["hybrid"] < R["do-nothing"]
     assert R["hybrid"] < R["mod-do-nothing"]
-    assert all(v < 1.0 for v in R.values())
+    assert all(np.isfinite(v) for v in R.values())
+    assert all(R[k] < 1.0 for k in ["hybrid", "moc", "do-nothing", "mod-do-nothing"])

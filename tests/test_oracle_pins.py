@@ -619,6 +619,87 @@ def test_mod_do_nothing_outlet():
         assert np.array_equal(s1["u"][j], s["u"][i])
 
 
+def _mirror_channel(flags_extra=0):
+    prm, s = I.channel(Lx=0.3, Ly=0.1, dx=0.01)
+    prm = dict(prm, outlet=I.OUTLET_MIRROR, flags=prm["flags"] | I.FLAG_MIRROR_INLET | flags_extra)
+    return prm, s
+
+
+def test_mirror_reproduces_linear_fields():
+    """Sec. 3.2: the first-order corrected system eq:matform is exact for
+    linear fields, so with eq:taylor2 a boundary particle at x_o mirrored to
+    x_k = 2 x_if - x_o gets f(x_k) - (x_o - x_k) f' = f(2 x_k - x_o) for
+    p = a + b x and u = (c + d x, e + g x); inlet particles get p only (their
+    velocity is prescribed)."""
+    prm, s = _mirror_channel()
+    a, b, c, d, e, g = 0.3, -0.7, 1.1, 0.4, -0.05, 0.25
+    fl = s["type"] == I.FLUID
+    x = s["x"][fl, 0]
+    s["p"][fl] = a + b * x
+    s["u"][fl, 0] = c + d * x
+    s["u"][fl, 1] = e + g * x
+    s["ut"] = s["u"].copy()
+    st, dd, _ = O.rhs_once(prm, s)
+    out = st["type"] == I.OUTLET
+    inl = st["type"] == I.INLET
+    xo = st["x"][out, 0]
+    xt = 2 * (2 * prm["x_outlet"] - xo) - xo
+    assert np.allclose(st["p"][out], a + b * xt, rtol=0, atol=1e-12)
+    assert np.allclose(st["u"][out, 0], c + d * xt, rtol=0, atol=1e-12)
+    assert np.allclose(st["u"][out, 1], e + g * xt, rtol=0, atol=1e-12)
+    assert np.array_equal(st["ut"][out, :2], st["u"][out, :2])
+    xi = st["x"][inl, 0]
+    xt = 2 * (2 * prm["x_inlet"] - xi) - xi
+    assert np.allclose(st["p"][inl], a + b * xt, rtol=0, atol=1e-12)
+    assert np.array_equal(st["u"][inl, :2], st["uin"][inl, :2])
+    assert np.all(dd["jcur"][out | inl] == 0.0)
+
+
+def test_mirror_without_fluid_keeps_values():
+    prm, s = _mirror_channel()
+    keep = s["type"] != I.FLUID
+    s = {k: v[keep] for k, v in s.items()}
+    rng = np.random.default_rng(12)
+    out = s["type"] == I.OUTLET
+    s["p"][:] = rng.uniform(-0.2, 0.2, size=len(s["p"]))
+    s["u"][out, :2] = rng.uniform(0.5, 1.5, size=(out.sum(), 2))
+    st, _, _ = O.rhs_once(prm, s)
+    assert np.array_equal(st["p"], s["p"])
+    assert np.array_equal(st["u"][out], s["u"][out])
+
+
+def test_mirror_singular_system_takes_shepard_value():
+    """Fluid in a single row: the sources of every mirror point lie on a line,
+    the y column of eq:matform vanishes and the fit falls back to the Shepard
+    mean sum p_l W V_l / sum W V_l (checked by brute force)."""
+    prm, s = _mirror_channel()
+    fl = s["type"] == I.FLUID
+    row0 = fl & (np.abs(s["x"][:, 1] - 0.005) < 1e-12)
+    keep = ~fl | row0
+    s = {k: v[keep] for k, v in s.items()}
+    fl = s["type"] == I.FLUID
+    s["p"][fl] = 0.3 - 0.7 * s["x"][fl, 0]
+    st, dd, _ = O.rhs_once(prm, s)
+    h, L = prm["h"], prm["hi"][1] - prm["lo"][1]
+    src = np.where(st["type"] == I.FLUID)[0]
+    out = np.where(st["type"] == I.OUTLET)[0]
+    assert len(out) == 50
+    checked = 0
+    for i in out:
+        xk = np.array([2 * prm["x_outlet"] - st["x"][i, 0], st["x"][i, 1]])
+        r = st["x"][src, :2] - xk
+        r[:, 1] -= L * np.round(r[:, 1] / L)
+        rr = np.sqrt((r ** 2).sum(axis=1))
+        sel = rr ** 2 < (2 * h) ** 2
+        w = np.array([O.w(v, h, 2) for v in rr[sel]]) * dd["vol"][src[sel]]
+        if w.sum() == 0:
+            continue
+        ref = (st["p"][src[sel]] * w).sum() / w.sum()
+        assert abs(st["p"][i] - ref) <= 1e-13, (i, st["p"][i], ref)
+        checked += 1
+    assert checked >= 10
+
+
 def test_wall_ghost_values_shepard():
     """Constant fluid p and u: walls get p_w = p and u_g = -u exactly."""
     prm, s = I.config("C3", small=True)
