@@ -76,6 +76,7 @@ def lib():
         L.orc_get_derived.argtypes = [P] * 10
         L.orc_get_abs.argtypes = [P] * 4
         L.orc_rhs.argtypes = [P, C.c_int, P]
+        L.orc_set_uin.argtypes = [P, P]
         L.orc_step.argtypes = [P, C.c_int32, C.c_int, P]
         L.orc_neighbors.restype = C.c_int64
         L.orc_neighbors.argtypes = [P, C.c_int, P, P, C.c_int64]
@@ -165,6 +166,12 @@ class Oracle:
         d["abs_a"], d["abs_b"], d["abs_pdot"] = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
         lib().orc_get_abs(self.h, _ptr(d["abs_a"]), _ptr(d["abs_b"]), _ptr(d["abs_pdot"]))
         return d
+
+    def set_uin(self, uin):
+        """Prescribed inlet velocities, one row of 3 per particle in state() order."""
+        a = np.ascontiguousarray(uin, dtype=np.float64)
+        assert a.shape == (self.n, 3)
+        lib().orc_set_uin(self.h, _ptr(a))
 
     def rhs(self, brute=False):
         F = np.zeros(3)

@@ -1041,6 +1041,16 @@ void orc_get(void *h, double *x, double *u, double *ut, double *p, double *uin, 
     }
 }
 
+/* Prescribed inlet velocities for the following steps, one row of 3 per
+ * particle in the order of orc_get (a boundary condition that changes in time
+ * is set between steps). */
+void orc_set_uin(void *h, const double *uin)
+{
+    sim *S = (sim *)h;
+    for (int64_t i = 0; i < S->n; ++i)
+        for (int d = 0; d < 3; ++d) S->P[i].uin[d] = uin[3 * i + d];
+}
+
 /* Derived fields of the last right-hand-side evaluation. */
 void orc_get_derived(void *h, double *rho, double *vol, double *pavg, double *a, double *b,
                      double *pdot, double *jcur, uint8_t *red, double *force)

@@ -248,6 +248,33 @@ def cylinder_tunnel(D=2.0, Re=20.0, dx=0.1, U=1.0, quintic=True, outlet=None):
     return prm, s
 
 
+def vortex_tunnel(dx=0.1, L=2.0, W=4.0, T=4.0, probe=1.7, long=False, U=1.0):
+    """The paper's moving-vortex problem (Sec. 4.4): a fluid region L long and
+    W wide between inviscid (slip) walls, 6 layers of inlet, outlet and wall
+    particles, inviscid fluid, the paper's kernel at h = 1.2 dx. long=True
+    gives the reference domain of length probe + c T (Sec. 4), whose outlet
+    no wave from the probe region reaches within the time T."""
+    c = 10.0 * U
+    Lx = probe + c * T if long else L
+    prm, s = channel(Lx=Lx, Ly=W, dx=dx, layers=6, U=U, nu=0.0, side_walls="slip",
+                     wall_layers=6, quintic=True,
+                     name=f"vortex tunnel {Lx:g}x{W:g} dx={dx:g}")
+    prm["probe"] = [probe, 0.5 * W, 0.0]
+    return prm, s
+
+
+def vortex_inlet_velocity(y, t, W=4.0, U=1.0, gamma=0.1):
+    """Prescribed inlet velocity of the vortex problem at time t (Sec. 4.4
+    eq:vortex with eq:vortexx): (u, v) = (U + G y'/(r^2 + 0.2), -G x'/(r^2 + 0.2))
+    with x' = U (1 - t), the distance of the vortex centre from the start of
+    the inlet, y' = y - W/2 and r^2 = x'^2 + y'^2. Works on numpy arrays and
+    torch tensors alike."""
+    xv = U * (1.0 - t)
+    yv = y - 0.5 * W
+    den = xv * xv + yv * yv + 0.2
+    return U + gamma * yv / den, -gamma * xv / den
+
+
 # ---------------------------------------------------------------- workloads
 
 def config(name, small=False):
