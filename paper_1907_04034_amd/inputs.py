@@ -263,6 +263,30 @@ def vortex_tunnel(dx=0.1, L=2.0, W=4.0, T=4.0, probe=1.7, long=False, U=1.0):
     return prm, s
 
 
+def ramp_tunnel(dx=0.1, L=2.0, W=2.0, T=3.0, probe=1.7, long=False, U=1.0):
+    """The paper's ramp-inlet problem (Sec. 4.3): the 2D-pulse tunnel (L x W
+    fluid, slip walls, 6 layers of inlet, outlet and wall particles, inviscid,
+    the paper's kernel at h = 1.2 dx) with everything at rest at t = 0; the
+    inlet velocity then follows ramp_inlet_velocity. long=True: the reference
+    domain of length probe + c T."""
+    c = 10.0 * U
+    Lx = probe + c * T if long else L
+    prm, s = channel(Lx=Lx, Ly=W, dx=dx, layers=6, U=U, nu=0.0, side_walls="slip",
+                     wall_layers=6, quintic=True, name=f"ramp tunnel {Lx:g}x{W:g} dx={dx:g}")
+    s["u"][:] = 0.0
+    s["ut"][:] = 0.0
+    s["uin"][:] = 0.0
+    s["ring"][:] = 0.0
+    s["avg"][:] = 0.0
+    prm["probe"] = [probe, 0.5 * W, 0.0]
+    return prm, s
+
+
+def ramp_inlet_velocity(t, U=1.0):
+    """Inlet x velocity of the ramp problem: U t for t < 1 s, then U."""
+    return U * min(max(t, 0.0), 1.0)
+
+
 def vortex_inlet_velocity(y, t, W=4.0, U=1.0, gamma=0.1):
     """Prescribed inlet velocity of the vortex problem at time t (Sec. 4.4
     eq:vortex with eq:vortexx): (u, v) = (U + G y'/(r^2 + 0.2), -G x'/(r^2 + 0.2))
