@@ -155,10 +155,11 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         k->vmax = vm < 32.0 ? 32 : (vm > 2048.0 ? 2048 : int(std::ceil(vm)));
         if (p->list_cap) k->vmax = p->list_cap;
         // measured: in 3D a list holds about a fifth of the stencil's
-        // candidates and pays at every size; in 2D (about 2/5) it pays where
-        // the search is latency-bound (small systems), not where it is
-        // throughput-bound and re-sorts are frequent
-        k->lists = (p->dim == 3 || cap < 300000) ? 1 : 0;
+        // candidates and pays at every size; in 2D (about 2/5 with the 0.3
+        // skin) it pays in small systems and in large FP64 ones (1.2M
+        // particles: 0.998 -> 0.943 ms per step), not in large FP32 ones
+        // (0.936 -> 0.942 ms)
+        k->lists = (p->dim == 3 || cap < 300000 || prec == SPH_FP64) ? 1 : 0;
     }
     k->x_inlet = p->x_inlet;
     k->x_outlet = p->x_outlet;
