@@ -226,13 +226,17 @@ int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph
 int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
                 sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
-/* Boundary values from the fluid (needs sph_density first): wall ghost
- * pressure/velocity by Shepard averaging; outlet particles by the hybrid rule
- * of Sec. 3.4 (J1, J2 of eq:characteristic-vars with time-average references,
+/* Boundary values from the fluid (needs sph_bin, sph_neighbors and
+ * sph_density first, in the same workspace: the rows and cells of the last
+ * bin are used): wall ghost pressure/velocity by Shepard averaging; outlet
+ * particles by the rule in prm->outlet, by default the hybrid rule of
+ * Sec. 3.4 (J1, J2 of eq:characteristic-vars with time-average references,
  * Shepard eq:shepard, J3 = 0, previous-step red average eq:average_old,
- * f_o = f_ac + f_avg eq:acou); inlet particles keep their prescribed velocity
- * and take p from the Shepard-extrapolated J3. Computed in FP64 for both
- * precisions. Writes u, ut, p of non-fluid particles and jcur, red. */
+ * f_o = f_ac + f_avg eq:acou; the other rules are described at
+ * SPH_OUTLET_*); inlet particles keep their prescribed velocity and take p
+ * from the Shepard-extrapolated J3 (or the mirror, SPH_FLAG_MIRROR_INLET).
+ * Computed in FP64 for both precisions. Writes u, ut, p of non-fluid
+ * particles and jcur, red. */
 int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist *nl,
                            sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
