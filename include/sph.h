@@ -62,7 +62,7 @@ enum {
  * paper's quintic spline (Sec. 2 eq:quintic-spline, support 3h, alpha =
  * 7/(478 pi h^2) in 2D and the normalising 1/(120 pi h^3) in 3D) instead of
  * Wendland C2 (support 2h); the neighbour predicate becomes |r|^2 < (3h)^2
- * (forward only: the adjoint entry points return SPH_EUNSUPPORTED).
+ * (the reverse passes use the kernel's own derivatives).
  * SPH_FLAG_MIRROR_INLET gives inlet particles the pressure mirrored from the
  * fluid (Sec. 3 with Sec. 3.2, as SPH_OUTLET_MIRROR describes, pressure
  * only) instead of the characteristic J3 (forward only). */

@@ -65,11 +65,9 @@ struct PairFwd {
                               T P)
     {
         const T q = T(sqrt(r2)) * T(k.inv_h);
-        const T t = T(1) - T(0.5) * q;
         const T gn = T(k.gnorm);
-        F = gn * t * t * t;
-        // (dF/dr)/|r| with dF/dr = -1.5 gnorm t^2 / h
-        G = T(-1.5) * gn * t * t * T(k.inv_h) * T(k.inv_h) / q;
+        F = kernel_f<T>(k, q, gn);
+        G = kernel_g<T>(k, q, gn, T(k.inv_h));  // (dF/dr)/|r|
 #pragma unroll
         for (int d = 0; d < 3; ++d) gw[d] = F * r[d];
         V2 = I.vol * I.vol + J.vol * J.vol;
@@ -491,7 +489,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
             for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + b];
             const double r2 = dist2_exact<DIM>(k, xj, xi, r);  // r = x_b - x_f
             const double q2 = sqrt(r2) * k.inv_h;
-            const double w = wendland_w(q2, k.wnorm), F = wendland_f(q2, k.gnorm);
+            const double w = kernel_w<double>(k, q2, k.wnorm);
+            const double F = kernel_f<double>(k, q2, k.gnorm);
             double dummy_uin = 0.0;
             const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, dp, du, drho, davg,
                                                   dummy_uin);
@@ -510,7 +509,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
             for (int d = 0; d < DIM; ++d) xf[d] = R.x[d * C + f];
             const double r2 = dist2_exact<DIM>(k, xi, xf, r);  // r = x_b - x_f
             const double q2 = sqrt(r2) * k.inv_h;
-            const double w = wendland_w(q2, k.wnorm), F = wendland_f(q2, k.gnorm);
+            const double w = kernel_w<double>(k, q2, k.wnorm);
+            const double F = kernel_f<double>(k, q2, k.gnorm);
             const double pf = double(ld<T>(R.p, f)), rhof = double(ld<T>(o.rho, f));
             double uf[3] = {0, 0, 0}, avgf[4] = {0, 0, 0, 0}, sink_u[3] = {0, 0, 0},
                    sink_avg[4] = {0, 0, 0, 0}, sink_p = 0.0, sink_rho = 0.0;
@@ -632,7 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R
 #pragma unroll
         for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
         const double r2 = dist2_exact<DIM>(k, xi, xj, r);
-        const double F = wendland_f(sqrt(r2) * k.inv_h, k.gnorm);
+        const double F = kernel_f<double>(k, sqrt(r2) * k.inv_h, k.gnorm);
         const double s = (Si + A.Sbar[j]) * F;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) dx[d] += s * r[d];

@@ -629,14 +629,12 @@ int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     return check_hip("sph_force");
 }
 
-// The reverse passes differentiate the hybrid outlet and the Wendland C2
-// kernel only.
+// The reverse passes differentiate the hybrid outlet with the characteristic
+// inlet (either kernel).
 static int hybrid_only(const sph_params *prm, const char *what)
 {
     if (prm && prm->outlet != SPH_OUTLET_HYBRID)
         return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the hybrid outlet only", what);
-    if (prm && (prm->flags & SPH_FLAG_QUINTIC))
-        return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the Wendland C2 kernel only", what);
     if (prm && (prm->flags & SPH_FLAG_MIRROR_INLET))
         return fail(SPH_EUNSUPPORTED, "%s: the adjoint covers the characteristic inlet only",
                     what);

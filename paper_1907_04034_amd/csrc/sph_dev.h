@@ -291,7 +291,35 @@ __device__ inline T quintic_f(T q, T gnorm)  // gnorm = -5 a / h^2
     return gnorm * (a3 * a3 - T(6) * a2 * a2) / q;
 }
 
+// (dF/dr)/r, needed by the reverse passes: Wendland C2 -1.5 gnorm t^2 / (h^2 q)
+// with t = 1 - q/2; quintic spline gnorm (-48 + 30 q) / h^2 for q < 1 and
+// gnorm (P' q - P) / (h^2 q^3) with P = (3-q)^4 - 6 (2-q)^4 beyond (each
+// power zero past its range), the derivative of F over r.
+template <typename T>
+__device__ inline T wendland_g(T q, T gnorm, T inv_h)
+{
+    const T t = T(1) - T(0.5) * q;
+    return q < T(2) ? T(-1.5) * gnorm * t * t * inv_h * inv_h / q : T(0);
+}
+
+template <typename T>
+__device__ inline T quintic_g(T q, T gnorm, T inv_h)
+{
+    if (q < T(1)) return gnorm * (T(-48) + T(30) * q) * inv_h * inv_h;
+    const T t3 = q < T(3) ? T(3) - q : T(0);
+    const T t2 = q < T(2) ? T(2) - q : T(0);
+    const T P = t3 * t3 * t3 * t3 - T(6) * t2 * t2 * t2 * t2;
+    const T dP = T(-4) * (t3 * t3 * t3 - T(6) * t2 * t2 * t2);
+    return gnorm * (dP * q - P) * inv_h * inv_h / (q * q * q);
+}
+
 // The run's kernel (the flag is uniform over a launch).
+template <typename T>
+__device__ inline T kernel_g(const Dev &k, T q, T gnorm, T inv_h)
+{
+    return k.quintic ? quintic_g<T>(q, gnorm, inv_h) : wendland_g<T>(q, gnorm, inv_h);
+}
+
 template <typename T>
 __device__ inline T kernel_w(const Dev &k, T q, T wnorm)
 {

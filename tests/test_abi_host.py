@@ -137,7 +137,8 @@ def test_outlet_rule_validation():
 
 def test_quintic_kernel_parameters():
     """The paper's kernel: deeper default tables (1.6 x the 3h ball + 12, in
-    multiples of 16), a workspace for the wider cells, no adjoint."""
+    multiples of 16) and a workspace for the wider cells; the reverse passes
+    accept it (here they stop at the missing buffers instead)."""
     prm, _ = I.config("C2Q", small=True)
     q = B.make_params(prm)
     assert B.lib().sph_default_maxnb(C.byref(q)) == 80
@@ -151,8 +152,7 @@ def test_quintic_kernel_parameters():
     de = B.SphDerived()
     adj = B.SphAdjoint()
     assert B.lib().sph_rhs_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de),
-                                   C.byref(adj), None, 0, None) == -6
-    assert b"Wendland" in B.lib().sph_last_error()
+                                   C.byref(adj), None, 0, None) == -1
 
 
 def test_mirror_rule_validation():

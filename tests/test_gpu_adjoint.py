@@ -84,7 +84,8 @@ def _perturbed(s, d, e):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 2e-7), ("fp32", 2e-4)])
-@pytest.mark.parametrize("name", ["C1-jit", "C2-small", "C3-small", "C4-small", "C5-small"])
+@pytest.mark.parametrize("name", ["C1-jit", "C2-small", "C3-small", "C4-small", "C5-small",
+                                  "C2Q-small", "C5Q-small"])
 def test_rhs_adjoint_dot_product(name, prec, tol):
     print(f"adjoint {name} {prec}", flush=True)
     rng = np.random.default_rng(7)
@@ -153,7 +154,7 @@ def _seeded_L(prm, s, w):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 2e-7), ("fp32", 2e-4)])
-@pytest.mark.parametrize("name", ["C2-small", "C3-small", "C4-small", "C5-small"])
+@pytest.mark.parametrize("name", ["C2-small", "C3-small", "C4-small", "C5-small", "C2Q-small"])
 def test_rhs_adjoint_seeded(name, prec, tol):
     """Seeds on boundary values and J (as a stage update and the next step read
     them) and the previous-step values J_prev of unsupported inlet/outlet rows
@@ -209,7 +210,7 @@ def test_rhs_adjoint_seeded(name, prec, tol):
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 2e-7), ("fp32", 2e-4)])
-@pytest.mark.parametrize("name", ["C2-small", "C3-small", "C4-small", "C5-small"])
+@pytest.mark.parametrize("name", ["C2-small", "C3-small", "C4-small", "C5-small", "C2Q-small"])
 def test_outlet_extrapolate_adjoint(name, prec, tol):
     """The boundary-values reverse alone (sph_outlet_extrapolate_adjoint): seeds on
     p, u of non-fluid rows and on J of inlet/outlet rows only."""

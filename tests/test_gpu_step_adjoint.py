@@ -149,7 +149,8 @@ def _oracle_L(prm, s, nsteps, fbar, seed, ref_ids):
 @pytest.mark.parametrize("name,nsteps,pavg", [
     ("C4-small", 30, False), ("C2-small", 30, False), ("C3-small", 26, False),
     ("C5-small", 30, False), ("C4-small", 4, True), ("C2-small", 4, True),
-    ("C3-small", 3, True), ("C5-small", 4, True)])
+    ("C3-small", 3, True), ("C5-small", 4, True), ("C2Q-small", 30, False),
+    ("C2Q-small", 4, True)])
 def test_step_adjoint_dot_product(name, nsteps, pavg):
     """Long runs (every end-of-step event) with the neighbour average of
     eq:pavg off, short runs with it on: its neighbour count N_i jumps when a
