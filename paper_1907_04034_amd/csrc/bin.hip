@@ -4,9 +4,9 @@
 //
 // The sort is deterministic and stable without a radix sort: histogram and
 // scan are integer (exact), the scatter writes each cell's members in
-// arbitrary order, and one thread per cell then orders its few members by
-// their unique id, so the result depends only on (cell, id), never on the
-// order in which atomics land. No launch is spent on clearing: every counter
+// arbitrary order, and every member then takes its place in the cell by
+// counting the members with a smaller id, so the result depends only on
+// (cell, id), never on the order in which atomics land. No launch is spent on clearing: every counter
 // is zeroed by the kernel that consumes it (the workspace starts zeroed).
 #include "sph_launch.h"
 
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) k_scan(Dev k, int32_t *counts, int32_t
 }
 
 __global__ void k_scatter(Dev k, DevState s, const int32_t *nspawn, const uint32_t *keys,
-                          const int32_t *cell_start, int32_t *cursor, int32_t *tmp,
+                          const int32_t *cell_start, int32_t *cursor, int32_t *scat,
                           const int32_t *rebin)
 {
     if (bin_skips(k, rebin)) return;
@@ -151,64 +151,43 @@ __global__ void k_scatter(Dev k, DevState s, const int32_t *nspawn, const uint32
     if (i >= rows_to_bin(k, s, nspawn)) return;
     const uint32_t key = keys[i];
     const int32_t slot = cell_start[key] + atomicAdd(&cursor[key], 1);
-    tmp[slot] = int32_t(i);
+    scat[slot] = int32_t(i);
 }
 
-// One thread per cell orders its members by id (ids are unique), then
-// clears the scatter cursor and the tile sums for the next bin. Cells of up to
-// 16 members are sorted in registers by an odd-even transposition network
-// (static indices only); larger cells fall back to insertion sort in memory.
-__device__ inline void cswap(int64_t &ka, int32_t &va, int64_t &kb, int32_t &vb)
-{
-    const bool sw = ka > kb;
-    const int64_t k0 = sw ? kb : ka, k1 = sw ? ka : kb;
-    const int32_t v0 = sw ? vb : va, v1 = sw ? va : vb;
-    ka = k0;
-    kb = k1;
-    va = v0;
-    vb = v1;
-}
-
-__global__ void k_cellsort(Dev k, DevState s, const int32_t *cell_start, int32_t *tmp,
-                           int32_t *cursor, int32_t *tilesum, int64_t ntiles,
-                           const int32_t *rebin)
+// One thread per slot of the scatter: its row goes to the cell's start plus
+// the number of the cell's rows with a smaller id (ids are unique; equal ids,
+// which valid input does not hold, are ranked by slot so the result is still
+// a permutation). O(m) independent loads per row for a cell of m rows, so the
+// quintic kernel's larger cells (about 22 rows in 2D, 60 in 3D) cost no more
+// than a few extra loads. The same threads clear the scatter cursor and the
+// scan's tile sums for the next bin.
+__global__ void __launch_bounds__(kBlock) k_cellrank(Dev k, DevState s, const int32_t *nspawn,
+                                                     const uint32_t *keys,
+                                                     const int32_t *cell_start,
+                                                     const int32_t *scat, int32_t *tmp,
+                                                     int32_t *cursor, int32_t *tilesum,
+                                                     int64_t ntiles, const int32_t *rebin)
 {
     if (bin_skips(k, rebin)) return;
-    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c < ntiles * kTileSlots) tilesum[c] = 0;
-    if (c > int64_t(k.nkeys)) return;
-    cursor[c] = 0;
-    if (c == int64_t(k.nkeys)) return;  // dead particles need no order
-    const int32_t b = cell_start[c], e = cell_start[c + 1];
-    const int m = e - b;
-    if (m <= 1) return;
-    constexpr int R = 16;
-    if (m <= R) {
-        int32_t v[R];
-        int64_t key[R];
-#pragma unroll
-        for (int q = 0; q < R; ++q) v[q] = q < m ? tmp[b + q] : 0;
-#pragma unroll
-        for (int q = 0; q < R; ++q) key[q] = q < m ? s.id[v[q]] : INT64_MAX;
-#pragma unroll
-        for (int pass = 0; pass < R; ++pass)
-#pragma unroll
-            for (int q = pass & 1; q + 1 < R; q += 2) cswap(key[q], v[q], key[q + 1], v[q + 1]);
-#pragma unroll
-        for (int q = 0; q < R; ++q)
-            if (q < m) tmp[b + q] = v[q];
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t < ntiles * kTileSlots) tilesum[t] = 0;
+    if (t <= int64_t(k.nkeys)) cursor[t] = 0;
+    if (t >= rows_to_bin(k, s, nspawn)) return;
+    const int32_t v = scat[t];
+    const uint32_t key = keys[v];
+    if (key == k.nkeys) {  // dead rows need no order
+        tmp[t] = v;
         return;
     }
-    for (int32_t q = b + 1; q < e; ++q) {
-        const int32_t v = tmp[q];
-        const int64_t key = s.id[v];
-        int32_t r = q - 1;
-        while (r >= b && s.id[tmp[r]] > key) {
-            tmp[r + 1] = tmp[r];
-            --r;
-        }
-        tmp[r + 1] = v;
+    const int32_t b = cell_start[key], e = cell_start[key + 1];
+    const int64_t mine = s.id[v];
+    int32_t rank = 0;
+#pragma unroll 4
+    for (int32_t q = b; q < e; ++q) {
+        const int64_t other = s.id[scat[q]];
+        rank += (other < mine || (other == mine && q < t)) ? 1 : 0;
     }
+    tmp[b + rank] = v;
 }
 
 // Row r of the sorted state is row tmp[r] of the old one. Non-fluid rows are
@@ -422,11 +401,12 @@ void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBuf
     hipLaunchKernelGGL(k_scan, dim3(ntiles), blk, 0, s, k, w.counts, w.cell_start, nscan,
                        w.tilesum, w.rebin);
     hipLaunchKernelGGL(k_scatter, g, blk, 0, s, k, a, w.nspawn, w.keys, w.cell_start, w.cursor,
-                       w.tmp, w.rebin);
-    const int64_t ncs = (int64_t(k.nkeys) + 1) > ntiles * kTileSlots ? int64_t(k.nkeys) + 1
-                                                                     : ntiles * kTileSlots;
-    hipLaunchKernelGGL(k_cellsort, dim3(nblocks(ncs)), blk, 0, s, k, a, w.cell_start, w.tmp,
-                       w.cursor, w.tilesum, ntiles, w.rebin);
+                       w.scat, w.rebin);
+    int64_t nrank = int64_t(k.nkeys) + 1;  // rows, cursor entries and tile sums
+    if (nrank < ntiles * kTileSlots) nrank = ntiles * kTileSlots;
+    if (nrank < k.cap) nrank = k.cap;
+    hipLaunchKernelGGL(k_cellrank, dim3(nblocks(nrank)), blk, 0, s, k, a, w.nspawn, w.keys,
+                       w.cell_start, w.scat, w.tmp, w.cursor, w.tilesum, ntiles, w.rebin);
     const dim3 gg(nblocks(k.cap), 4);
     if (k.dim == 2 && k.prec == SPH_FP64)
         hipLaunchKernelGGL((k_gather<2, double>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,

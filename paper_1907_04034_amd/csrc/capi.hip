@@ -203,6 +203,7 @@ static WsLayout layout(const Dev &k)
     w.cursor = take(sizeof(int32_t) * (size_t(k.nkeys) + 1));
     w.tilesum = take(sizeof(int32_t) * size_t(tilesum_len(int64_t(nscan))));
     w.keys = take(sizeof(uint32_t) * C);
+    w.scat = take(sizeof(int32_t) * C);
     w.tmp = take(sizeof(int32_t) * C);
     w.cpos = take(sizeof(uint32_t) * C);
     w.cpos_s = take(sizeof(uint32_t) * C);
@@ -322,6 +323,7 @@ struct Ctx {
         b.cell_start = at<int32_t>(ws, w.cell_start);
         b.cursor = at<int32_t>(ws, w.cursor);
         b.tilesum = at<int32_t>(ws, w.tilesum);
+        b.scat = at<int32_t>(ws, w.scat);
         b.tmp = at<int32_t>(ws, w.tmp);
         b.blist = at<int32_t>(ws, w.blist);
         b.spread = at<uint32_t>(ws, w.spread);

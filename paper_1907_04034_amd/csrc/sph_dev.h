@@ -229,8 +229,8 @@ struct VList {
 
 // Workspace carving (byte offsets from the workspace base).
 struct WsLayout {
-    size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, tmp, cpos,
-        cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
+    size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, scat, tmp,
+        cpos, cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
         vnbr, rec, total;
 };
 

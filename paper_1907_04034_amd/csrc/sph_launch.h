@@ -9,7 +9,9 @@ inline int nblocks(int64_t n, int per = kBlock) { return int((n + per - 1) / per
 
 // workspace buffers of the binning pipeline
 struct BinBufs {
-    int32_t *nspawn, *bcount, *counts, *cell_start, *cursor, *tilesum, *tmp, *blist;
+    int32_t *nspawn, *bcount, *counts, *cell_start, *cursor, *tilesum, *blist;
+    int32_t *scat;  // scatter output: each cell's rows in arbitrary order
+    int32_t *tmp;   // sorted row -> row of the state before the sort
     uint32_t *spread, *keys, *cpos, *cpos_s;
     int32_t *rebin;  // 1: the next bin sorts; 0: it keeps the order (Dev::reuse)
     double *xbin;    // [3][cap] positions at the last sort, sorted order
