@@ -230,6 +230,32 @@ __device__ inline int64_t adj_row(int64_t n, int &lane)
     return lb < 0 || i >= n ? -1 : i;
 }
 
+// Neighbour slots q0, q0 + G, q0 + 2G, q0 + 3G of row i, read together so
+// that the loads which depend on them go out in one round trip: ok[u] says
+// the slot exists and holds a valid row (an invalid row raises the error
+// word), js[u] is that row or, where not ok, row i itself (always valid, so
+// dependent loads need no branch).
+constexpr int kAdjBatch = 4;
+template <int G>
+__device__ inline void adj_slots(const DevNlist &nl, int64_t i, int cnt, int q0, int64_t n,
+                                 uint32_t *err, int32_t jj[kAdjBatch], bool ok[kAdjBatch],
+                                 int32_t js[kAdjBatch])
+{
+#pragma unroll
+    for (int u = 0; u < kAdjBatch; ++u) {
+        const int q = q0 + u * G;
+        jj[u] = q < cnt ? nl.nbr[i * nl.maxnb + q] : int32_t(i);
+    }
+#pragma unroll
+    for (int u = 0; u < kAdjBatch; ++u) {
+        const bool in = q0 + u * G < cnt;
+        const bool bad = bad_index(jj[u], n);
+        if (in && bad) raise_error(err, SPH_ERR_CELL_RANGE);
+        ok[u] = in && !bad;
+        js[u] = ok[u] ? jj[u] : int32_t(i);
+    }
+}
+
 // R1: pair reverses, gathered per particle.
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields R, DevNlist nl,
@@ -348,14 +374,21 @@ __global__ void __launch_bounds__(kBlock) k_adj_pavg(Dev k, DevState m, DevNlist
     if (k.flags & SPH_FLAG_NO_PAVG) return;
     double acc = 0.0;
     const int cnt = nl.count[i];
-    for (int q = lane; q < cnt; q += G) {
-        const int32_t j = nl.nbr[i * nl.maxnb + q];
-        if (bad_index(j, n)) {
-            raise_error(err, SPH_ERR_CELL_RANGE);
-            continue;
+    for (int q0 = lane; q0 < cnt; q0 += kAdjBatch * G) {
+        int32_t jj[kAdjBatch], js[kAdjBatch];
+        bool ok[kAdjBatch];
+        adj_slots<G>(nl, i, cnt, q0, n, err, jj, ok, js);
+        int tj[kAdjBatch], cj[kAdjBatch];
+        double pj[kAdjBatch];
+#pragma unroll
+        for (int u = 0; u < kAdjBatch; ++u) {
+            tj[u] = m.type[js[u]];
+            pj[u] = A.Pbar[js[u]];
+            cj[u] = nl.count[js[u]];
         }
-        const int tj = m.type[j];
-        if (tj == SPH_FLUID) acc += A.Pbar[j] / double(nl.count[j]);
+#pragma unroll
+        for (int u = 0; u < kAdjBatch; ++u)
+            if (ok[u] && tj[u] == SPH_FLUID) acc += pj[u] / double(cj[u]);
     }
     acc = gsum<G>(acc);
     if (lane == 0) A.pbar[i] += acc;
@@ -474,54 +507,82 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
         for (int d = 0; d < DIM; ++d) uf[d] = double(ld<T>(R.u, d * C + i));
 #pragma unroll
         for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + i];
-        for (int q = lane; q < cnt; q += G) {
-            const int32_t b = nl.nbr[i * nl.maxnb + q];
-            if (bad_index(b, n)) {
-                raise_error(err, SPH_ERR_CELL_RANGE);
-                continue;
+        for (int q0 = lane; q0 < cnt; q0 += kAdjBatch * G) {
+            int32_t jj[kAdjBatch], js[kAdjBatch];
+            bool ok[kAdjBatch];
+            adj_slots<G>(nl, i, cnt, q0, n, err, jj, ok, js);
+            int tb[kAdjBatch];
+            double sb[kAdjBatch];
+#pragma unroll
+            for (int u = 0; u < kAdjBatch; ++u) {
+                tb[u] = m.type[js[u]];
+                sb[u] = o.sfl[js[u]];
             }
-            const int tb = m.type[b];
-            if (tb == SPH_FLUID || !(o.sfl[b] > 0.0)) continue;
-            BndIn B;
-            load_bnd<DIM, T>(k, m, R, o, A, b, B);
-            double xj[3] = {0, 0, 0}, r[3];
+            // boundary neighbours with fluid support, in slot order
+            uint32_t hit = 0;
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + b];
-            const double r2 = dist2_exact<DIM>(k, xj, xi, r);  // r = x_b - x_f
-            const double q2 = sqrt(r2) * k.inv_h;
-            const double w = kernel_w<double>(k, q2, k.wnorm);
-            const double F = kernel_f<double>(k, q2, k.gnorm);
-            double dummy_uin = 0.0;
-            const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, dp, du, drho, davg,
-                                                  dummy_uin);
+            for (int u = 0; u < kAdjBatch; ++u)
+                if (ok[u] && tb[u] != SPH_FLUID && sb[u] > 0.0) hit |= 1u << u;
+            while (hit) {
+                const int u = __builtin_ctz(hit);
+                hit &= hit - 1;
+                const int32_t b = u == 0 ? jj[0] : u == 1 ? jj[1] : u == 2 ? jj[2] : jj[3];
+                BndIn B;
+                load_bnd<DIM, T>(k, m, R, o, A, b, B);
+                double xj[3] = {0, 0, 0}, r[3];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) dx[d] -= Wb * F * r[d];
+                for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + b];
+                const double r2 = dist2_exact<DIM>(k, xj, xi, r);  // r = x_b - x_f
+                const double q2 = sqrt(r2) * k.inv_h;
+                const double w = kernel_w<double>(k, q2, k.wnorm);
+                const double F = kernel_f<double>(k, q2, k.gnorm);
+                double dummy_uin = 0.0;
+                const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, dp, du, drho,
+                                                      davg, dummy_uin);
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) dx[d] -= Wb * F * r[d];
+            }
         }
     } else if (red) {
         BndIn B;
         load_bnd<DIM, T>(k, m, R, o, A, i, B);
-        for (int q = lane; q < cnt; q += G) {
-            const int32_t f = nl.nbr[i * nl.maxnb + q];
-            if (bad_index(f, n)) continue;
-            if (m.type[f] != SPH_FLUID) continue;
-            double xf[3] = {0, 0, 0}, r[3];
+        for (int q0 = lane; q0 < cnt; q0 += kAdjBatch * G) {
+            int32_t jj[kAdjBatch], js[kAdjBatch];
+            bool ok[kAdjBatch];
+            adj_slots<G>(nl, i, cnt, q0, n, err, jj, ok, js);
+            // every fluid value of the batch in one round trip
+            int tf[kAdjBatch];
+            double xf[kAdjBatch][3], pf[kAdjBatch], rhof[kAdjBatch], uf[kAdjBatch][3],
+                avgf[kAdjBatch][4];
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) xf[d] = R.x[d * C + f];
-            const double r2 = dist2_exact<DIM>(k, xi, xf, r);  // r = x_b - x_f
-            const double q2 = sqrt(r2) * k.inv_h;
-            const double w = kernel_w<double>(k, q2, k.wnorm);
-            const double F = kernel_f<double>(k, q2, k.gnorm);
-            const double pf = double(ld<T>(R.p, f)), rhof = double(ld<T>(o.rho, f));
-            double uf[3] = {0, 0, 0}, avgf[4] = {0, 0, 0, 0}, sink_u[3] = {0, 0, 0},
-                   sink_avg[4] = {0, 0, 0, 0}, sink_p = 0.0, sink_rho = 0.0;
+            for (int u = 0; u < kAdjBatch; ++u) {
+                const int32_t f = js[u];
+                tf[u] = m.type[f];
+                pf[u] = double(ld<T>(R.p, f));
+                rhof[u] = double(ld<T>(o.rho, f));
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) uf[d] = double(ld<T>(R.u, d * C + f));
+                for (int d = 0; d < 3; ++d) {
+                    xf[u][d] = d < DIM ? R.x[d * C + f] : 0.0;
+                    uf[u][d] = d < DIM ? double(ld<T>(R.u, d * C + f)) : 0.0;
+                }
 #pragma unroll
-            for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + f];
-            const double Wb = bnd_weight_adj<DIM>(k, B, w, pf, uf, rhof, avgf, sink_p, sink_u,
-                                                  sink_rho, sink_avg, duin0);
+                for (int c = 0; c < 4; ++c) avgf[u][c] = c <= DIM ? m.avg[c * C + f] : 0.0;
+            }
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) dx[d] += Wb * F * r[d];
+            for (int u = 0; u < kAdjBatch; ++u) {
+                if (!ok[u] || tf[u] != SPH_FLUID) continue;
+                double r[3];
+                const double r2 = dist2_exact<DIM>(k, xi, xf[u], r);  // r = x_b - x_f
+                const double q2 = sqrt(r2) * k.inv_h;
+                const double w = kernel_w<double>(k, q2, k.wnorm);
+                const double F = kernel_f<double>(k, q2, k.gnorm);
+                double sink_u[3] = {0, 0, 0}, sink_avg[4] = {0, 0, 0, 0}, sink_p = 0.0,
+                       sink_rho = 0.0;
+                const double Wb = bnd_weight_adj<DIM>(k, B, w, pf[u], uf[u], rhof[u], avgf[u],
+                                                      sink_p, sink_u, sink_rho, sink_avg, duin0);
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) dx[d] += Wb * F * r[d];
+            }
         }
     } else if (blue_io) {
         // no fluid support: J = mean of the previous-step values of same-kind
@@ -617,25 +678,33 @@ __global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R
     // (i itself included), reverse of the mean taken in R2b
     const bool gather_j = A.jprevbar && (t == SPH_INLET || t == SPH_OUTLET) && m.red_prev[i];
     const int cnt = nl.count[i];
-    for (int q = lane; q < cnt; q += G) {
-        const int32_t j = nl.nbr[i * nl.maxnb + q];
-        if (bad_index(j, n)) {
-            raise_error(err, SPH_ERR_CELL_RANGE);
-            continue;
+    for (int q0 = lane; q0 < cnt; q0 += kAdjBatch * G) {
+        int32_t jj[kAdjBatch], js[kAdjBatch];
+        bool ok[kAdjBatch];
+        adj_slots<G>(nl, i, cnt, q0, n, err, jj, ok, js);
+        double xs[kAdjBatch][3], Sj[kAdjBatch];
+#pragma unroll
+        for (int u = 0; u < kAdjBatch; ++u) {
+#pragma unroll
+            for (int d = 0; d < 3; ++d) xs[u][d] = d < DIM ? R.x[d * C + js[u]] : 0.0;
+            Sj[u] = A.Sbar[js[u]];
         }
-        if (gather_j && m.type[j] == t) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) g[a] += A.jg[a * C + j];
+        for (int u = 0; u < kAdjBatch; ++u) {
+            if (!ok[u]) continue;
+            const int32_t j = jj[u];
+            if (gather_j && m.type[j] == t) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) g[a] += A.jg[a * C + j];
+            }
+            if (j == i) continue;
+            double r[3];
+            const double r2 = dist2_exact<DIM>(k, xi, xs[u], r);
+            const double F = kernel_f<double>(k, sqrt(r2) * k.inv_h, k.gnorm);
+            const double s = (Si + Sj[u]) * F;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) dx[d] += s * r[d];
         }
-        if (j == i) continue;
-        double xj[3] = {0, 0, 0}, r[3];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) xj[d] = R.x[d * C + j];
-        const double r2 = dist2_exact<DIM>(k, xi, xj, r);
-        const double F = kernel_f<double>(k, sqrt(r2) * k.inv_h, k.gnorm);
-        const double s = (Si + A.Sbar[j]) * F;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) dx[d] += s * r[d];
     }
 #pragma unroll
     for (int d = 0; d < DIM; ++d) dx[d] = gsum<G>(dx[d]);
