@@ -36,36 +36,53 @@ __global__ void __launch_bounds__(kBlock) k_end_of_step(Dev k, DevState s, DevDe
     const int64_t C = k.cap;
     bool spawn = false;
     if (i < n) {
+        // Every load before the first store: the stores below could alias
+        // the arrays read, so loads placed after them would each wait for the
+        // store before (one round trip per load instead of two in all).
         const int t = s.type[i];
+        const double x = s.x[i];
+        const double pv = double(ld<T>(s.p, i));
+        const int h = s.head[i];
+        double v[DIM + 1];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) v[d] = double(ld<T>(s.u, d * C + i));
+        v[DIM] = pv;
+        const bool io = t == SPH_OUTLET || t == SPH_INLET;
+        const bool push = (t == SPH_FLUID || t == SPH_INLET) && !(fabs(pv) > k.pgate);
+        double jc[3] = {0, 0, 0};
+        uint8_t rd = 0;
+        if (io) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) jc[a] = o.jcur[a * C + i];
+            rd = o.red[i];
+        }
+        double old[kNavg][DIM + 1];  // the window, slot h included (overwritten)
+        if (push) {
+#pragma unroll
+            for (int q = 0; q < kNavg; ++q)
+#pragma unroll
+                for (int c = 0; c <= DIM; ++c)
+                    old[q][c] = s.ring[(int64_t(q) * (DIM + 1) + c) * C + i];
+        }
         uint8_t ev = 0;
         if (child) child[i] = -1;
-        if (t == SPH_OUTLET || t == SPH_INLET) {
+        if (io) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a) s.jprev[a * C + i] = o.jcur[a * C + i];
-            s.red_prev[i] = o.red[i];
+            for (int a = 0; a < 3; ++a) s.jprev[a * C + i] = jc[a];
+            s.red_prev[i] = rd;
         }
-        if (t == SPH_FLUID || t == SPH_INLET) {
-            const double pv = double(ld<T>(s.p, i));
-            if (!(fabs(pv) > k.pgate)) {
-                const int h = s.head[i];
-                double v[DIM + 1];
+        if (push) {
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) v[d] = double(ld<T>(s.u, d * C + i));
-                v[DIM] = pv;
+            for (int c = 0; c <= DIM; ++c) {
+                s.ring[(int64_t(h) * (DIM + 1) + c) * C + i] = v[c];
+                double sum = 0.0;
 #pragma unroll
-                for (int c = 0; c <= DIM; ++c) {
-                    s.ring[(int64_t(h) * (DIM + 1) + c) * C + i] = v[c];
-                    double sum = 0.0;
-#pragma unroll
-                    for (int q = 0; q < kNavg; ++q)
-                        sum += q == h ? v[c] : s.ring[(int64_t(q) * (DIM + 1) + c) * C + i];
-                    s.avg[c * C + i] = sum / double(kNavg);
-                }
-                s.head[i] = uint8_t((h + 1) % kNavg);
-                ev |= kEvPush;
+                for (int q = 0; q < kNavg; ++q) sum += q == h ? v[c] : old[q][c];
+                s.avg[c * C + i] = sum / double(kNavg);
             }
+            s.head[i] = uint8_t((h + 1) % kNavg);
+            ev |= kEvPush;
         }
-        const double x = s.x[i];
         if (t == SPH_FLUID && x > k.x_outlet) {
             s.type[i] = SPH_OUTLET;
 #pragma unroll
