@@ -190,6 +190,66 @@ __global__ void __launch_bounds__(kBlock) k_cellrank(Dev k, DevState s, const in
     tmp[b + rank] = v;
 }
 
+// Slice `slice` (0: x, u, ut, u_in, p, head, red_prev, kind, id; 1 and 2:
+// the two halves of the ring; 3: the averages and previous-step J) of row i
+// of a, copied to row r of b. Every load of the slice is issued before its
+// first store: as far as the compiler knows a and b may alias, and a load
+// placed after a store waits for it, one round trip per field. Slice 0
+// returns the row's position and kind through x_out and t_out.
+template <int DIM, typename T>
+__device__ inline void copy_slice(const Dev &k, const DevState &a, int64_t i, const DevState &b,
+                                  int64_t r, int slice, double x_out[3], int &t_out)
+{
+    const int64_t C = k.cap;
+    constexpr int NR = kNavg * (DIM + 1);  // ring words, an even count
+    constexpr int H = NR / 2;
+    if (slice == 0) {
+        double x[DIM], uin[DIM];
+        T u[DIM], ut[DIM];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            x[d] = a.x[d * C + i];
+            u[d] = ld<T>(a.u, d * C + i);
+            ut[d] = ld<T>(a.ut, d * C + i);
+            uin[d] = a.uin[d * C + i];
+        }
+        const T p = ld<T>(a.p, i);
+        const uint8_t hd = a.head[i], rp = a.red_prev[i], t = a.type[i];
+        const int64_t id = a.id[i];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            b.x[d * C + r] = x[d];
+            st<T>(b.u, d * C + r, u[d]);
+            st<T>(b.ut, d * C + r, ut[d]);
+            b.uin[d * C + r] = uin[d];
+            x_out[d] = x[d];
+        }
+        st<T>(b.p, r, p);
+        b.head[r] = hd;
+        b.red_prev[r] = rp;
+        b.type[r] = t;
+        b.id[r] = id;
+        t_out = t;
+    } else if (slice <= 2) {
+        const int q0 = slice == 1 ? 0 : H;
+        double v[H];
+#pragma unroll
+        for (int q = 0; q < H; ++q) v[q] = a.ring[int64_t(q0 + q) * C + i];
+#pragma unroll
+        for (int q = 0; q < H; ++q) b.ring[int64_t(q0 + q) * C + r] = v[q];
+    } else {
+        double v[DIM + 1], j[3];
+#pragma unroll
+        for (int q = 0; q < DIM + 1; ++q) v[q] = a.avg[q * C + i];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) j[q] = a.jprev[q * C + i];
+#pragma unroll
+        for (int q = 0; q < DIM + 1; ++q) b.avg[q * C + r] = v[q];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) b.jprev[q * C + r] = j[q];
+    }
+}
+
 // Row r of the sorted state is row tmp[r] of the old one. Non-fluid rows are
 // listed for the boundary pass, the positions kept as the reference of the
 // cell skin; the live count is published and the re-spawn counter cleared.
@@ -211,46 +271,17 @@ __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
     }
     // a kept order needs no copy: the state stays where it is
     if (!sorted || r >= n) return;
-    const int64_t i = sorted ? int64_t(tmp[r]) : r;
-    const int64_t C = k.cap;
-    constexpr int NR = kNavg * (DIM + 1);  // ring words, split over slices 1 and 2
-    switch (blockIdx.y) {
-    case 0: {
+    const int64_t i = int64_t(tmp[r]);
+    const uint32_t cp = blockIdx.y == 0 ? cpos_in[i] : 0u;
+    double x[3];
+    int t = SPH_DEAD;
+    copy_slice<DIM, T>(k, a, i, b, r, int(blockIdx.y), x, t);
+    if (blockIdx.y == 0) {
+        const int64_t C = k.cap;
+        cpos_out[r] = cp;
+        if (t != SPH_FLUID) blist[atomicAdd(bcount, 1)] = int32_t(r);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            b.x[d * C + r] = a.x[d * C + i];
-            st<T>(b.u, d * C + r, ld<T>(a.u, d * C + i));
-            st<T>(b.ut, d * C + r, ld<T>(a.ut, d * C + i));
-            b.uin[d * C + r] = a.uin[d * C + i];
-        }
-        st<T>(b.p, r, ld<T>(a.p, i));
-        b.head[r] = a.head[i];
-        b.red_prev[r] = a.red_prev[i];
-        const uint8_t t = a.type[i];
-        b.type[r] = t;
-        b.id[r] = a.id[i];
-        if (sorted) {
-            cpos_out[r] = cpos_in[i];
-            if (t != SPH_FLUID) blist[atomicAdd(bcount, 1)] = int32_t(r);
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) xbin[d * C + r] = a.x[d * C + i];
-        }
-        break;
-    }
-    case 1:
-#pragma unroll
-        for (int q = 0; q < NR / 2; ++q) b.ring[q * C + r] = a.ring[q * C + i];
-        break;
-    case 2:
-#pragma unroll
-        for (int q = NR / 2; q < NR; ++q) b.ring[q * C + r] = a.ring[q * C + i];
-        break;
-    default:
-#pragma unroll
-        for (int q = 0; q < DIM + 1; ++q) b.avg[q * C + r] = a.avg[q * C + i];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) b.jprev[q * C + r] = a.jprev[q * C + i];
-        break;
+        for (int d = 0; d < DIM; ++d) xbin[d * C + r] = x[d];
     }
 }
 
@@ -270,38 +301,9 @@ __global__ void k_copy_back(Dev k, DevState src, DevState dst, const int32_t *so
     if (*sorted == 0) return;
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= *dst.n) return;
-    const int64_t C = k.cap;
-    constexpr int NR = kNavg * (DIM + 1);
-    switch (blockIdx.y) {
-    case 0:
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            dst.x[d * C + r] = src.x[d * C + r];
-            st<T>(dst.u, d * C + r, ld<T>(src.u, d * C + r));
-            st<T>(dst.ut, d * C + r, ld<T>(src.ut, d * C + r));
-            dst.uin[d * C + r] = src.uin[d * C + r];
-        }
-        st<T>(dst.p, r, ld<T>(src.p, r));
-        dst.head[r] = src.head[r];
-        dst.red_prev[r] = src.red_prev[r];
-        dst.type[r] = src.type[r];
-        dst.id[r] = src.id[r];
-        break;
-    case 1:
-#pragma unroll
-        for (int q = 0; q < NR / 2; ++q) dst.ring[q * C + r] = src.ring[q * C + r];
-        break;
-    case 2:
-#pragma unroll
-        for (int q = NR / 2; q < NR; ++q) dst.ring[q * C + r] = src.ring[q * C + r];
-        break;
-    default:
-#pragma unroll
-        for (int q = 0; q < DIM + 1; ++q) dst.avg[q * C + r] = src.avg[q * C + r];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) dst.jprev[q * C + r] = src.jprev[q * C + r];
-        break;
-    }
+    double x[3];
+    int t = 0;
+    copy_slice<DIM, T>(k, src, r, dst, r, int(blockIdx.y), x, t);
 }
 
 void launch_copy_back(const Dev &k, const DevState &src, const DevState &dst,
@@ -331,39 +333,18 @@ __global__ void k_copy_rows(Dev k, DevState a, DevState b, const int32_t *perm_i
     const bool moved = *sorted != 0;
     if (r == 0 && blockIdx.y == 0) *b.n = n;
     if (r >= n) return;
-    const int64_t C = k.cap;
-    constexpr int NR = kNavg * (DIM + 1);
-    switch (blockIdx.y) {
-    case 0:
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            b.x[d * C + r] = a.x[d * C + r];
-            st<T>(b.u, d * C + r, ld<T>(a.u, d * C + r));
-            st<T>(b.ut, d * C + r, ld<T>(a.ut, d * C + r));
-            b.uin[d * C + r] = a.uin[d * C + r];
-        }
-        st<T>(b.p, r, ld<T>(a.p, r));
-        b.head[r] = a.head[r];
-        b.red_prev[r] = a.red_prev[r];
-        b.type[r] = a.type[r];
-        b.id[r] = a.id[r];
-        perm_out[r] = moved ? perm_in[r] : int32_t(r);
-        cell_out[r] = cell_in[r];
-        break;
-    case 1:
-#pragma unroll
-        for (int q = 0; q < NR / 2; ++q) b.ring[q * C + r] = a.ring[q * C + r];
-        break;
-    case 2:
-#pragma unroll
-        for (int q = NR / 2; q < NR; ++q) b.ring[q * C + r] = a.ring[q * C + r];
-        break;
-    default:
-#pragma unroll
-        for (int q = 0; q < DIM + 1; ++q) b.avg[q * C + r] = a.avg[q * C + r];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) b.jprev[q * C + r] = a.jprev[q * C + r];
-        break;
+    int32_t pr = int32_t(r);
+    uint32_t cell = 0u;
+    if (blockIdx.y == 0) {
+        if (moved) pr = perm_in[r];
+        cell = cell_in[r];
+    }
+    double x[3];
+    int t = 0;
+    copy_slice<DIM, T>(k, a, r, b, r, int(blockIdx.y), x, t);
+    if (blockIdx.y == 0) {
+        perm_out[r] = pr;
+        cell_out[r] = cell;
     }
 }
 

@@ -56,13 +56,13 @@ __global__ void __launch_bounds__(kBlock) k_end_of_step(Dev k, DevState s, DevDe
             for (int a = 0; a < 3; ++a) jc[a] = o.jcur[a * C + i];
             rd = o.red[i];
         }
-        double old[kNavg][DIM + 1];  // the window, slot h included (overwritten)
+        double old[kNavg][DIM + 1];  // the window but slot h, which is overwritten
         if (push) {
 #pragma unroll
             for (int q = 0; q < kNavg; ++q)
 #pragma unroll
                 for (int c = 0; c <= DIM; ++c)
-                    old[q][c] = s.ring[(int64_t(q) * (DIM + 1) + c) * C + i];
+                    old[q][c] = q == h ? 0.0 : s.ring[(int64_t(q) * (DIM + 1) + c) * C + i];
         }
         uint8_t ev = 0;
         if (child) child[i] = -1;
