@@ -412,20 +412,18 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
     }
 }
 
-// Record slots of the boundary values just written for row i (p, u, ut - u),
-// read back from the state so that record and state agree bit for bit.
+// Record slots of the boundary values of row i (p, u, ut - u), from the very
+// values the state receives, so that record and state agree bit for bit.
 template <int DIM, typename T>
-__device__ inline void rec_set_pu(const Dev &k, const Fields &R, void *rec, int64_t i)
+__device__ inline void rec_put_pu(void *rec, int64_t i, T p, const T u[3], const T ut[3])
 {
     using L = Rec<DIM, T>;
-    const int64_t C = k.cap;
     T *r = static_cast<T *>(rec) + i * L::N;
-    r[L::P] = ld<T>(R.p, i);
+    r[L::P] = p;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const T u = ld<T>(R.u, d * C + i);
-        r[L::U + d] = u;
-        r[L::W + d] = ld<T>(R.ut, d * C + i) - u;
+        r[L::U + d] = u[d];
+        r[L::W + d] = ut[d] - u[d];
     }
 }
 
@@ -632,6 +630,27 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
         const int32_t j0 = lane < nl.maxnb ? nl.nbr[i * nl.maxnb + lane] : -1;
         if (t == SPH_FLUID) continue;
         const bool io = t == SPH_INLET || t == SPH_OUTLET;
+        // What the write-out below reads of the row itself, loaded with the
+        // neighbours: loads placed after its stores would each wait for them
+        // (the compiler cannot rule out aliasing). Inlet/outlet rows: p, u,
+        // u_in, the averages and the previous-step J; walls with records: ut.
+        T p_old = T(0), u_old[3] = {T(0), T(0), T(0)}, ut_old[3] = {T(0), T(0), T(0)};
+        double avg_i[4] = {0, 0, 0, 0}, uin_i[3] = {0, 0, 0}, jprev_i[3] = {0, 0, 0};
+        if (io) {
+            p_old = ld<T>(R.p, i);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                u_old[d] = ld<T>(R.u, d * C + i);
+                uin_i[d] = m.uin[d * C + i];
+            }
+#pragma unroll
+            for (int c = 0; c <= DIM; ++c) avg_i[c] = m.avg[c * C + i];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) jprev_i[a] = m.jprev[a * C + i];
+        } else if (o.rec) {
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) ut_old[d] = ld<T>(R.ut, d * C + i);
+        }
         // Shepard sums over fluid neighbours and, in the same sweep, the
         // fallback sums over same-kind neighbours that had support
         double sw = 0.0, sp = 0.0, su[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
@@ -696,7 +715,6 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
         } else {
             sJ[2] = gsum<G>(sJ[2]);
         }
-        if (lane == 0) o.sfl[i] = sw;
         if (is_wall(t)) {
             if (lane == 0) {
                 double pw = 0.0;
@@ -706,10 +724,14 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 #pragma unroll
                     for (int d = 0; d < DIM; ++d) ug[d] = -(su[d] / sw);
                 }
+                T uw[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) uw[d] = T(ug[d]);
+                o.sfl[i] = sw;
                 st<T>(R.p, i, T(pw));
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, T(ug[d]));
-                if (o.rec) rec_set_pu<DIM, T>(k, R, o.rec, i);
+                for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, uw[d]);
+                if (o.rec) rec_put_pu<DIM, T>(o.rec, i, T(pw), uw, ut_old);
             }
             continue;
         }
@@ -726,7 +748,7 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 const double acc = gsum<G>(bacc[a]);
-                J[a] = M > 0.0 ? acc / M : m.jprev[a * C + i];
+                J[a] = M > 0.0 ? acc / M : jprev_i[a];
             }
         }
         // mirroring (Sec. 3.2): the row reflected about its interface into
@@ -754,51 +776,50 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
             }
         }
         if (lane == 0) {
+            // the row's new p, u, ut (kept where the rule leaves them)
+            T pv = p_old, uv[3], utv[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) o.jcur[a * C + i] = J[a];
-            o.red[i] = red;
+            for (int d = 0; d < 3; ++d) uv[d] = utv[d] = u_old[d];
             if (t == SPH_OUTLET && k.outlet == SPH_OUTLET_HYBRID) {
                 const double p_ac = 0.5 * (J[1] + J[2]);
                 const double u_ac = (J[1] - J[2]) / (2.0 * k.rho0 * k.c);
-                st<T>(R.p, i, T(m.avg[DIM * C + i] + p_ac));
-                const double u0v = m.avg[i] + u_ac;
-                st<T>(R.u, i, T(u0v));
-                st<T>(R.ut, i, T(u0v));
+                pv = T(avg_i[DIM] + p_ac);
+                uv[0] = utv[0] = T(avg_i[0] + u_ac);
 #pragma unroll
-                for (int d = 1; d < DIM; ++d) {
-                    st<T>(R.u, d * C + i, T(m.avg[d * C + i]));
-                    st<T>(R.ut, d * C + i, T(m.avg[d * C + i]));
-                }
+                for (int d = 1; d < DIM; ++d) uv[d] = utv[d] = T(avg_i[d]);
             } else if (t == SPH_OUTLET && k.outlet == SPH_OUTLET_MOC) {
                 // about the fixed references; transverse velocity unchanged
                 const double p_ac = 0.5 * (J[1] + J[2]);
                 const double u_ac = (J[1] - J[2]) / (2.0 * k.rho0 * k.c);
-                st<T>(R.p, i, T(0.0 + p_ac));
-                const double u0v = k.U + u_ac;
-                st<T>(R.u, i, T(u0v));
-                st<T>(R.ut, i, T(u0v));
-#pragma unroll
-                for (int d = 1; d < DIM; ++d) st<T>(R.ut, d * C + i, ld<T>(R.u, d * C + i));
+                pv = T(0.0 + p_ac);
+                uv[0] = utv[0] = T(k.U + u_ac);
             } else if (t == SPH_OUTLET) {
                 // mirror: p and u from the mirror point (kept without fluid
                 // there); do-nothing rules: u, p stay frozen
                 if (mok) {
-                    st<T>(R.p, i, T(mval[0]));
+                    pv = T(mval[0]);
 #pragma unroll
-                    for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, T(mval[1 + d]));
+                    for (int d = 0; d < DIM; ++d) uv[d] = T(mval[1 + d]);
                 }
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) st<T>(R.ut, d * C + i, ld<T>(R.u, d * C + i));
+                for (int d = 0; d < DIM; ++d) utv[d] = uv[d];
             } else {  // inlet: prescribed velocity, p = J3 or mirrored
-                if (!mir) st<T>(R.p, i, T(J[2]));
-                else if (mok) st<T>(R.p, i, T(mval[0]));
+                if (!mir) pv = T(J[2]);
+                else if (mok) pv = T(mval[0]);
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    st<T>(R.u, d * C + i, T(m.uin[d * C + i]));
-                    st<T>(R.ut, d * C + i, T(m.uin[d * C + i]));
-                }
+                for (int d = 0; d < DIM; ++d) uv[d] = utv[d] = T(uin_i[d]);
             }
-            if (o.rec) rec_set_pu<DIM, T>(k, R, o.rec, i);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) o.jcur[a * C + i] = J[a];
+            o.red[i] = red;
+            o.sfl[i] = sw;
+            st<T>(R.p, i, pv);
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                st<T>(R.u, d * C + i, uv[d]);
+                st<T>(R.ut, d * C + i, utv[d]);
+            }
+            if (o.rec) rec_put_pu<DIM, T>(o.rec, i, pv, uv, utv);
         }
     }
 }
@@ -830,7 +851,9 @@ __device__ inline void skin_check(const Dev &k, int d, int mode, double xs, doub
 // Explicit-midpoint RK2 (the integrator is the implementation's reading; the
 // paper defers time stepping to the EDAC paper) with eq:transport-vel applied
 // per stage and eq:advection for positions. Contraction is off so that the
-// update evaluates the formula as written.
+// update evaluates the formula as written. Every load comes before the first
+// store: the stores could alias the arrays read as far as the compiler knows,
+// and a load placed after a store waits for it.
 template <int DIM, typename T>
 __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &W, int64_t i,
                                    int mode, const T ui[3], T pi, const T a[3], const T b[3],
@@ -839,19 +862,35 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
 #pragma clang fp contract(off)
     const int64_t C = k.cap;
     const double dt = mode == 2 ? k.dt : k.hdt;
+    // stage position xs, start position xw (full update), skin reference xb,
+    // start velocity u0 and, in the full update, the half-state advection
+    // velocity and start pressure
+    double xs[3] = {0, 0, 0}, xw[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, u0[3] = {0, 0, 0},
+           uth[3] = {0, 0, 0};
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        xs[d] = R.x[d * C + i];
+        xb[d] = xbin[d * C + i];
+        if (mode == 2) {
+            xw[d] = W.x[d * C + i];
+            u0[d] = double(ld<T>(W.u, d * C + i));
+            uth[d] = double(ld<T>(R.ut, d * C + i));
+        } else {
+            u0[d] = double(ui[d]);
+        }
+    }
+    const double p0 = mode == 2 ? double(ld<T>(W.p, i)) : double(pi);
     bool fin = true;
     double xn[3] = {0, 0, 0}, un[3] = {0, 0, 0}, utn[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const double x0 = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
-        const double u0 = mode == 2 ? double(ld<T>(W.u, d * C + i)) : double(ui[d]);
-        un[d] = u0 + dt * double(a[d]);
+        const double x0 = mode == 2 ? xw[d] : xs[d];
+        un[d] = u0[d] + dt * double(a[d]);
         utn[d] = un[d] + dt * double(b[d]);
-        const double adv = mode == 2 ? double(ld<T>(R.ut, d * C + i)) : utn[d];
+        const double adv = mode == 2 ? uth[d] : utn[d];
         xn[d] = x0 + dt * adv;
         fin = fin && isfinite(un[d]) && isfinite(utn[d]);
     }
-    const double p0 = mode == 2 ? double(ld<T>(W.p, i)) : double(pi);
     const double pn = p0 + dt * double(pd);
     fin = fin && isfinite(pn);
 #pragma unroll
@@ -862,8 +901,7 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
             if (v >= hi) v -= k.L[d];
             else if (v < k.lo[d]) v += k.L[d];
         }
-        skin_check(k, d, mode, R.x[d * C + i], v, mode == 2 ? W.x[d * C + i] : 0.0,
-                   xbin[d * C + i], rebin, err);
+        skin_check(k, d, mode, xs[d], v, mode == 2 ? xw[d] : 0.0, xb[d], rebin, err);
         fin = fin && isfinite(v);
         W.x[d * C + i] = v;
         st<T>(W.u, d * C + i, T(un[d]));
@@ -889,32 +927,45 @@ __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fie
     // the start values: the half state carries them into stage 2
     const bool keep = mode == 1 && ((t == SPH_OUTLET && k.outlet != SPH_OUTLET_HYBRID) ||
                                     (t == SPH_INLET && (k.flags & SPH_FLAG_MIRROR_INLET)));
+    const bool copy = mode == 2 || keep;  // u, ut, p of R carried into W
+    const bool moves = t == SPH_INLET || t == SPH_OUTLET;
+    // every load before the first store (as in stage_fluid)
+    double x0[3] = {0, 0, 0};
+    T uc[3] = {T(0), T(0), T(0)}, utc[3] = {T(0), T(0), T(0)}, pc = T(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const double x0 = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
-        double v = x0;
-        if (keep) {
-            st<T>(W.u, d * C + i, ld<T>(R.u, d * C + i));
-            st<T>(W.ut, d * C + i, ld<T>(R.ut, d * C + i));
+        x0[d] = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
+        if (copy) {
+            uc[d] = ld<T>(R.u, d * C + i);
+            utc[d] = ld<T>(R.ut, d * C + i);
         }
-        if (d == 0 && (t == SPH_INLET || t == SPH_OUTLET)) {
-            // outlet speed: its own x velocity, or the extrapolated fluid
-            // velocity of the modified do-nothing rule
-            const double vx = t == SPH_INLET ? m.uin[i]
-                              : k.outlet == SPH_OUTLET_MOD_DO_NOTHING
-                                  ? jcur[i]
-                                  : double(ld<T>(R.u, i));
-            v = x0 + dt * vx;
-            skin_check(k, 0, mode, R.x[i], v, x0, xbin[i], rebin, err);
+    }
+    if (copy) pc = ld<T>(R.p, i);
+    double vx = 0.0, xs0 = 0.0, xb0 = 0.0;
+    if (moves) {
+        // outlet speed: its own x velocity, or the extrapolated fluid
+        // velocity of the modified do-nothing rule
+        vx = t == SPH_INLET ? m.uin[i]
+             : k.outlet == SPH_OUTLET_MOD_DO_NOTHING ? jcur[i]
+                                                     : double(ld<T>(R.u, i));
+        xs0 = R.x[i];
+        xb0 = xbin[i];
+    }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        double v = x0[d];
+        if (d == 0 && moves) {
+            v = x0[0] + dt * vx;
+            skin_check(k, 0, mode, xs0, v, x0[0], xb0, rebin, err);
             if (!isfinite(v)) raise_error(err, SPH_ERR_NONFINITE);
         }
         W.x[d * C + i] = v;
-        if (mode == 2) {
-            st<T>(W.u, d * C + i, ld<T>(R.u, d * C + i));
-            st<T>(W.ut, d * C + i, ld<T>(R.ut, d * C + i));
+        if (copy) {
+            st<T>(W.u, d * C + i, uc[d]);
+            st<T>(W.ut, d * C + i, utc[d]);
         }
     }
-    if (mode == 2 || keep) st<T>(W.p, i, ld<T>(R.p, i));
+    if (copy) st<T>(W.p, i, pc);
 }
 
 // One neighbour's data as a lane of the force pass needs it.
@@ -1145,9 +1196,9 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
 #pragma unroll
                         for (int d = 0; d < DIM; ++d) o.force[d * C + i] = fb[d];
                 } else {
-                    st<T>(o.pavg, i, pavg);  // kept for a reverse pass
                     if (t == SPH_FLUID)
                         stage_fluid<DIM, T>(k, R, W, i, mode, ui, pi, a, b, pd, xbin, rebin, err);
+                    st<T>(o.pavg, i, pavg);  // kept for a reverse pass
                 }
             }
         }
