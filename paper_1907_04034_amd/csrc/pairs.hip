@@ -651,6 +651,9 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 #pragma unroll
             for (int d = 0; d < DIM; ++d) ut_old[d] = ld<T>(R.ut, d * C + i);
         }
+        // the hybrid outlet's characteristic references are the neighbours'
+        // time averages
+        const bool hyb_avg = t == SPH_OUTLET && k.outlet == SPH_OUTLET_HYBRID;
         // Shepard sums over fluid neighbours and, in the same sweep, the
         // fallback sums over same-kind neighbours that had support
         double sw = 0.0, sp = 0.0, su[3] = {0, 0, 0}, sJ[3] = {0, 0, 0};
@@ -672,9 +675,23 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
             }
             const double pj = double(ld<T>(R.p, j));
             const double rhoj = double(ld<T>(o.rho, j));
-            if (io && tj == t && m.red_prev[j]) {
+            // inlet/outlet rows: the neighbour's red flag, previous-step J and
+            // (hybrid outlet) time averages go out with its kind, so that no
+            // load waits for it; wall rows skip them
+            uint8_t rpj = 0;
+            double jpj[3] = {0, 0, 0}, avu = 0.0, avp = 0.0;
+            if (io) {
+                rpj = m.red_prev[j];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) bacc[a] += m.jprev[a * C + j];
+                for (int a = 0; a < 3; ++a) jpj[a] = m.jprev[a * C + j];
+                if (hyb_avg) {
+                    avu = m.avg[j];
+                    avp = m.avg[DIM * C + j];
+                }
+            }
+            if (io && tj == t && rpj) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) bacc[a] += jpj[a];
                 bM += 1.0;
             }
             if (tj != SPH_FLUID) continue;
@@ -695,8 +712,8 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 // references: the fluid particle's time averages (hybrid) or
                 // the fixed u = U, p = 0 (characteristics)
                 const bool moc = k.outlet == SPH_OUTLET_MOC;
-                const double dp = pj - (moc ? 0.0 : m.avg[DIM * C + j]);
-                const double du = uj0 - (moc ? k.U : m.avg[j]);
+                const double dp = pj - (moc ? 0.0 : avp);
+                const double du = uj0 - (moc ? k.U : avu);
                 sJ[0] += (-k.c2 * (rhoj - k.rho0) + dp) * w;
                 sJ[1] += (rhoj * k.c * du + dp) * w;
                 sJ[2] += (-rhoj * k.c * du + dp) * w;
