@@ -349,13 +349,19 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
     // boundary values may carry adjoints from outside this right-hand side
     // (a stage update that reads them)
     const bool seeded = K.t != SPH_FLUID;
+    // the seeds are read before any store (the stores could alias them)
+    double us[3] = {0, 0, 0}, ps = 0.0;
+    if (seeded && A.useed)
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) us[d] = A.useed[d * C + i];
+    if (seeded && A.pseed) ps = A.pseed[i];
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         A.xbar[d * C + i] = double(xb[d]);
-        A.ubar[d * C + i] = double(Kb.u[d]) + (seeded && A.useed ? A.useed[d * C + i] : 0.0);
+        A.ubar[d * C + i] = double(Kb.u[d]) + us[d];
         A.wbar[d * C + i] = double(Kb.w[d]);
     }
-    A.pbar[i] = double(Kb.p) + (seeded && A.pseed ? A.pseed[i] : 0.0);
+    A.pbar[i] = double(Kb.p) + ps;
     A.rhobar[i] = double(Kb.rho);
     A.volbar[i] = double(Kb.vol);
     A.Pbar[i] = double(Pb);
@@ -712,16 +718,26 @@ __global__ void __launch_bounds__(kBlock) k_adj_dens(Dev k, DevState m, Fields R
     for (int a = 0; a < 3; ++a) g[a] = gsum<G>(g[a]);
     if (lane != 0) return;
     const bool fl = t == SPH_FLUID;
+    // every read of the write-out before its first store (they could alias)
+    double xb[3] = {0, 0, 0}, wb[3] = {0, 0, 0}, ub[3] = {0, 0, 0}, jb[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        A.xbar[d * C + i] += dx[d];
-        const double w = A.wbar[d * C + i];
-        A.utbar[d * C + i] = fl ? w : 0.0;
-        if (fl) A.ubar[d * C + i] -= w;
+        xb[d] = A.xbar[d * C + i];
+        wb[d] = A.wbar[d * C + i];
+        if (fl) ub[d] = A.ubar[d * C + i];
+    }
+    if (gather_j)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) jb[a] = A.jprevbar[a * C + i];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        A.xbar[d * C + i] = xb[d] + dx[d];
+        A.utbar[d * C + i] = fl ? wb[d] : 0.0;
+        if (fl) A.ubar[d * C + i] = ub[d] - wb[d];
     }
     if (gather_j) {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) A.jprevbar[a * C + i] += g[a];
+        for (int a = 0; a < 3; ++a) A.jprevbar[a * C + i] = jb[a] + g[a];
     }
 }
 

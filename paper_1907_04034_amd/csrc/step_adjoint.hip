@@ -175,38 +175,71 @@ __global__ void __launch_bounds__(kBlock) k_adj_half(Dev k, DevState m, StepAdj 
     constexpr int NC = DIM + 1;
     const int64_t C = k.cap;
     const int t = m.type[i];
+    const bool fl = t == SPH_FLUID;
     const double hdt = k.hdt;
     double *useed = const_cast<double *>(A.useed), *pseed = const_cast<double *>(A.pseed);
+    // every load before the first store: the stores could alias the arrays
+    // read, and a load after a store waits for it
+    double avg[NC], avgb[NC], jp[3], jpb[3];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] += A.avgbar[c * C + i];
+    for (int c = 0; c < NC; ++c) {
+        avg[c] = S.acc.avg[c * C + i];
+        avgb[c] = A.avgbar[c * C + i];
+    }
 #pragma unroll
-    for (int a = 0; a < 3; ++a) S.acc.jprev[a * C + i] += A.jprevbar[a * C + i];
+    for (int a = 0; a < 3; ++a) {
+        jp[a] = S.acc.jprev[a * C + i];
+        jpb[a] = A.jprevbar[a * C + i];
+    }
+    double xH[3] = {0, 0, 0}, ax[3] = {0, 0, 0}, ain[3] = {0, 0, 0}, uinb[3] = {0, 0, 0},
+           utb[3] = {0, 0, 0}, hut[3] = {0, 0, 0}, ubr[3] = {0, 0, 0}, au_acc[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        const double xH = A.xbar[d * C + i];
-        S.acc.x[d * C + i] += xH;
-        S.acc.uin[d * C + i] += A.uinbar[d * C + i];
+        xH[d] = A.xbar[d * C + i];
+        ax[d] = S.acc.x[d * C + i];
+        ain[d] = S.acc.uin[d * C + i];
+        uinb[d] = A.uinbar[d * C + i];
+        if (fl) {
+            utb[d] = A.utbar[d * C + i];
+            hut[d] = S.hut[d * C + i];
+            ubr[d] = A.ubar[d * C + i];
+            au_acc[d] = S.acc.u[d * C + i];
+        }
+    }
+    double pH = 0.0, ap = 0.0;
+    if (fl) {
+        pH = A.pbar[i];
+        ap = S.acc.p[i];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) S.acc.avg[c * C + i] = avg[c] + avgb[c];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) S.acc.jprev[a * C + i] = jp[a] + jpb[a];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        S.acc.x[d * C + i] = ax[d] + xH[d];
+        double uin_acc = ain[d] + uinb[d];
         double au = 0.0, ab = 0.0, us = 0.0;
-        if (t == SPH_FLUID) {
-            const double utot = A.utbar[d * C + i] + S.hut[d * C + i] + hdt * xH;
-            const double uu = A.ubar[d * C + i] + utot;
+        if (fl) {
+            const double utot = utb[d] + hut[d] + hdt * xH[d];
+            const double uu = ubr[d] + utot;
             au = hdt * uu;
             ab = hdt * utot;
-            S.acc.u[d * C + i] += uu;
+            S.acc.u[d * C + i] = au_acc[d] + uu;
         } else if (d == 0 && t == SPH_INLET) {
-            S.acc.uin[i] += hdt * xH;
+            uin_acc += hdt * xH[d];
         } else if (d == 0 && t == SPH_OUTLET) {
-            us = hdt * xH;
+            us = hdt * xH[d];
         }
+        S.acc.uin[d * C + i] = uin_acc;
         st<T>(const_cast<void *>(A.abar), d * C + i, T(au));
         st<T>(const_cast<void *>(A.bbar), d * C + i, T(ab));
         useed[d * C + i] = us;
     }
     double pd = 0.0;
-    if (t == SPH_FLUID) {
-        const double pH = A.pbar[i];
+    if (fl) {
         pd = hdt * pH;
-        S.acc.p[i] += pH;
+        S.acc.p[i] = ap + pH;
     }
     st<T>(const_cast<void *>(A.pdbar), i, T(pd));
     pseed[i] = 0.0;
@@ -243,20 +276,38 @@ __global__ void __launch_bounds__(kBlock) k_adj_finish(Dev k, DevState m, DevSta
     if (dst < 0 || dst >= npre) return;
     const bool fl = m.type[r] == SPH_FLUID;
     const DevLam &Ac = S.acc;
+    // every load before the first store (the stores could alias them, and a
+    // load after a store waits for it)
+    double x[3] = {0, 0, 0}, u[3] = {0, 0, 0}, ut[3] = {0, 0, 0}, uin[3] = {0, 0, 0}, jp[3];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const bool on = d < DIM;
-        O.x[d * C + dst] = on ? Ac.x[d * C + r] + A.xbar[d * C + r] : 0.0;
-        O.u[d * C + dst] = on ? Ac.u[d * C + r] + (fl ? A.ubar[d * C + r] : 0.0) : 0.0;
-        O.ut[d * C + dst] = on ? Ac.ut[d * C + r] + (fl ? A.utbar[d * C + r] : 0.0) : 0.0;
-        O.uin[d * C + dst] = on ? Ac.uin[d * C + r] + A.uinbar[d * C + r] : 0.0;
-        O.jprev[d * C + dst] = Ac.jprev[d * C + r] + A.jprevbar[d * C + r];
+        if (d < DIM) {
+            x[d] = Ac.x[d * C + r] + A.xbar[d * C + r];
+            u[d] = Ac.u[d * C + r] + (fl ? A.ubar[d * C + r] : 0.0);
+            ut[d] = Ac.ut[d * C + r] + (fl ? A.utbar[d * C + r] : 0.0);
+            uin[d] = Ac.uin[d * C + r] + A.uinbar[d * C + r];
+        }
+        jp[d] = Ac.jprev[d * C + r] + A.jprevbar[d * C + r];
     }
-    O.p[dst] = Ac.p[r] + (fl ? A.pbar[r] : 0.0);
+    const double p = Ac.p[r] + (fl ? A.pbar[r] : 0.0);
+    double ring[NR], avg[NC];
 #pragma unroll
-    for (int s = 0; s < NR; ++s) O.ring[s * C + dst] = Ac.ring[s * C + r];
+    for (int s = 0; s < NR; ++s) ring[s] = Ac.ring[s * C + r];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) O.avg[c * C + dst] = Ac.avg[c * C + r] + A.avgbar[c * C + r];
+    for (int c = 0; c < NC; ++c) avg[c] = Ac.avg[c * C + r] + A.avgbar[c * C + r];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        O.x[d * C + dst] = x[d];
+        O.u[d * C + dst] = u[d];
+        O.ut[d * C + dst] = ut[d];
+        O.uin[d * C + dst] = uin[d];
+        O.jprev[d * C + dst] = jp[d];
+    }
+    O.p[dst] = p;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) O.ring[s * C + dst] = ring[s];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) O.avg[c * C + dst] = avg[c];
 }
 
 // ------------------------------------------------------------ inlet profile
