@@ -126,6 +126,22 @@ def adjoint_bytes(sim, counts, types, prec_bytes):
     return rd + wr
 
 
+def timed_launches(stream, reps, launch):
+    """Average GPU time in ms of one call of `launch` over `reps` calls queued
+    back to back on `stream` between one pair of HIP events (one pair per call
+    would add the events' own cost, about 2.5 us, to every call)."""
+    import torch
+    launch()  # warm
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def adjoint_bench(args):
     """Reverse of a run of steps on the channel-with-cylinder workload: the
     time-averaged-drag gradient (checkpointed forward, segment replay, reverse
@@ -187,15 +203,8 @@ def adjoint_bench(args):
     sim2.rhs_adjoint(abar=ab, bbar=ab, pdbar=ab[:, 0], fbar=(1.0, 0.0, 0.0))
     torch.cuda.synchronize()
     reps = args.force_reps
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
     st_adj = sim2._adj_struct()
-    for a_, b_ in evs:
-        a_.record(stream)
-        sim2.rhs_adjoint_launch(st_adj)
-        b_.record(stream)
-    torch.cuda.synchronize()
-    a_us = 1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs]))
+    a_us = 1e3 * timed_launches(stream, reps, lambda: sim2.rhs_adjoint_launch(st_adj))
     prec_bytes = 8 if args.precision == "fp64" else 4
     abytes = adjoint_bytes(sim2, cnt, types, prec_bytes)
     achieved = abytes / (a_us * 1e-6) / 1e9
@@ -328,14 +337,7 @@ def main():
     types = sim.state()["type"]
     torch.cuda.synchronize()
     reps = args.force_reps
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(reps)]
-    for a_, b_ in evs:
-        a_.record(stream)
-        sim.force(reduce_drag=False)
-        b_.record(stream)
-    torch.cuda.synchronize()
-    f_us = 1e3 * float(np.mean([a_.elapsed_time(b_) for a_, b_ in evs]))
+    f_us = 1e3 * timed_launches(stream, reps, lambda: sim.force(reduce_drag=False))
     prec_bytes = 8 if args.precision == "fp64" else 4
     fbytes, fdetail = force_bytes(sim, cnt, types, prec_bytes)
     achieved = fbytes / (f_us * 1e-6) / 1e9
