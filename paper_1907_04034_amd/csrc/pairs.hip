@@ -180,15 +180,24 @@ struct ListWalk {
     {
         const bool use_pre = first;
         first = false;
+        // every entry loaded before the error word is touched (an atomic
+        // between them would keep each load behind the one before)
+        int32_t j[NB];
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-            const int32_t j = use_pre ? pre[b] : (q < cap ? list[q] : 0);
-            const bool bad = q < cnt && bad_index(j, n);
-            if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
+            const int qb = q + b * G;
+            j[b] = use_pre ? pre[b] : (qb < cap ? list[qb] : 0);
+        }
+        bool any_bad = false;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const bool bad = q < cnt && bad_index(j[b], n);
+            any_bad = any_bad || bad;
             hv[b] = q < cnt && !bad;
-            jj[b] = hv[b] ? j : 0;
+            jj[b] = hv[b] ? j[b] : 0;
             q += G;
         }
+        if (any_bad) raise_error(err, SPH_ERR_CELL_RANGE);
     }
 };
 
@@ -302,8 +311,16 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
         vpre[b] = (active && vmode != 0 && !build && lane + b * G < k.vmax) ? vrow[lane + b * G]
                                                                             : 0;
     if (active && vc < 0) {
-        // cell ranges of the stencil, one cell per lane at a time
-        for (int sc = lane; sc < NS; sc += G) {
+        // cell ranges of the stencil, one cell per lane at a time; all ranges
+        // of a lane are loaded before the error word is touched (an atomic
+        // between them would keep each load behind the one before)
+        constexpr int NSL = (NS + G - 1) / G;  // stencil cells per lane, at most
+        int32_t cb[NSL], ce[NSL];
+#pragma unroll
+        for (int u = 0; u < NSL; ++u) {
+            const int sc = lane + u * G;
+            cb[u] = ce[u] = 0;
+            if (sc >= NS) continue;
             const int dxs = sc % 3 - 1, dys = (sc / 3) % 3 - 1, dzs = DIM == 3 ? sc / 9 - 1 : 0;
             int cc[3] = {c[0] + dxs, c[1] + dys, c[2] + dzs};
             bool ok = true;
@@ -314,19 +331,26 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
                     else ok = false;
                 }
             }
-            int32_t b = 0, e = 0;
             if (ok) {
                 const uint32_t key = morton_key<DIM>(spread, cc);
-                b = cell_start[key];
-                e = cell_start[key + 1];
-                if (b < 0 || e > n || b > e) {
-                    raise_error(err, SPH_ERR_CELL_RANGE);
-                    b = e = 0;
-                }
+                cb[u] = cell_start[key];
+                ce[u] = cell_start[key + 1];
+            }
+        }
+        bool any_bad = false;
+#pragma unroll
+        for (int u = 0; u < NSL; ++u) {
+            const int sc = lane + u * G;
+            if (sc >= NS) continue;
+            int32_t b = cb[u], e = ce[u];
+            if (b < 0 || e > n || b > e) {
+                any_bad = true;
+                b = e = 0;
             }
             s_beg[grp][sc] = b;
             s_len[grp][sc] = e - b;
         }
+        if (any_bad) raise_error(err, SPH_ERR_CELL_RANGE);
     }
     __syncthreads();
     if (!active) return;
