@@ -1021,20 +1021,56 @@ struct Nbr {
 // FP64 one load per field from the state and derived arrays (measured: the
 // 128- and 80-byte FP64 records made the force pass slower, 1.93 -> 2.11 ms
 // on the 4.6M-particle duct, while FP32 records cut it 1.67 -> 1.23 ms).
+// fetch_nbr only issues the loads and finish_nbr does the arithmetic on them,
+// so a lane that prefetches several neighbours issues every fetch before the
+// first finish and their gathers overlap (a separation computed right after
+// its loads makes the next neighbour's loads wait for them).
 template <int DIM, typename T>
-__device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R,
-                                const DevDerived &o, const float *off, const uint32_t *cpos,
-                                const Sep<DIM, T> &sep, int32_t j, Nbr<DIM, T> &nb)
+struct NbrRaw {
+    using L = Rec<DIM, T>;
+    T v[L::F32 ? L::NC * L::PER : 1];  // FP32: the record
+    double xj[3];                      // FP64: the fields
+    T u[3], ut[3], p, rho, vol;
+    int tj;
+    int32_t j;
+};
+
+template <int DIM, typename T>
+__device__ inline void fetch_nbr(const Dev &k, const DevState &m, const Fields &R,
+                                 const DevDerived &o, int32_t j, NbrRaw<DIM, T> &w)
 {
     using L = Rec<DIM, T>;
-    nb.j = j;
+    w.j = j;
     if constexpr (L::F32) {
         using V = typename Chunk<T>::V;
         const V *src =
             reinterpret_cast<const V *>(static_cast<const T *>(o.rec) + int64_t(j) * L::N);
-        T v[L::NC * L::PER];
 #pragma unroll
-        for (int ch = 0; ch < L::NC; ++ch) Chunk<T>::get(src[ch], v + ch * L::PER);
+        for (int ch = 0; ch < L::NC; ++ch) Chunk<T>::get(src[ch], w.v + ch * L::PER);
+    } else {
+        const int64_t C = k.cap;
+        w.tj = m.type[j];
+        w.xj[2] = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) {
+            w.xj[d] = R.x[d * C + j];
+            w.u[d] = ld<T>(R.u, d * C + j);
+            w.ut[d] = ld<T>(R.ut, d * C + j);
+        }
+        w.p = ld<T>(R.p, j);
+        w.rho = ld<T>(o.rho, j);
+        w.vol = ld<T>(o.vol, j);
+    }
+}
+
+template <int DIM, typename T>
+__device__ inline void finish_nbr(const Dev &k, const Sep<DIM, T> &sep, const NbrRaw<DIM, T> &w,
+                                  Nbr<DIM, T> &nb)
+{
+    using L = Rec<DIM, T>;
+    nb.j = w.j;
+    if constexpr (L::F32) {
+        const T *v = w.v;
         if constexpr (L::PACKED) {
             const uint32_t word = rec_uint<T>(v[L::AUX]);
             nb.tj = class_kind(word >> 30);
@@ -1055,18 +1091,27 @@ __device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R
         }
         nb.p = v[L::P];
     } else {
-        const int64_t C = k.cap;
-        nb.tj = m.type[j];
-        nb.r2 = sep.get(k, R, off, cpos, j, nb.r);
+        nb.tj = w.tj;
+        nb.r2 = dist2_exact<DIM>(k, sep.xi, w.xj, nb.r);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            nb.u[d] = ld<T>(R.u, d * C + j);
-            nb.w[d] = ld<T>(R.ut, d * C + j) - nb.u[d];
+            nb.u[d] = w.u[d];
+            nb.w[d] = w.ut[d] - w.u[d];
         }
-        nb.p = ld<T>(R.p, j);
-        nb.rho = ld<T>(o.rho, j);
-        nb.vol = ld<T>(o.vol, j);
+        nb.p = w.p;
+        nb.rho = w.rho;
+        nb.vol = w.vol;
     }
+}
+
+template <int DIM, typename T>
+__device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R,
+                                const DevDerived &o, const Sep<DIM, T> &sep, int32_t j,
+                                Nbr<DIM, T> &nb)
+{
+    NbrRaw<DIM, T> w;
+    fetch_nbr<DIM, T>(k, m, R, o, j, w);
+    finish_nbr<DIM, T>(k, sep, w, nb);
 }
 
 // Contribution of neighbour nb to target i (see the force-pass comment).
@@ -1179,10 +1224,16 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                 badp = badp || (have && !okp[f]);
             }
             if (badp) raise_error(err, SPH_ERR_CELL_RANGE);
-            Nbr<DIM, T> nbp[PF];
+            // rows fetched without a branch (row i itself stands in for an
+            // absent slot, whose data is never used) and all before the first
+            // is used, so that the gathers of all PF slots go out together
+            NbrRaw<DIM, T> raw[PF];
 #pragma unroll
             for (int f = 0; f < PF; ++f)
-                if (okp[f]) load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, jp[f], nbp[f]);
+                fetch_nbr<DIM, T>(k, m, R, o, okp[f] ? jp[f] : int32_t(i), raw[f]);
+            Nbr<DIM, T> nbp[PF];
+#pragma unroll
+            for (int f = 0; f < PF; ++f) finish_nbr<DIM, T>(k, sep, raw[f], nbp[f]);
             // the neighbour average of eq:pavg enters the fluid's momentum;
             // the body force takes p~ about zero (the average of a surface
             // particle's neighbours would cancel the pressure on the body)
@@ -1212,7 +1263,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                 }
                 if (j == i) continue;
                 Nbr<DIM, T> nb;
-                load_nbr<DIM, T>(k, m, R, o, off, cpos, sep, j, nb);
+                load_nbr<DIM, T>(k, m, R, o, sep, j, nb);
                 if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
                 pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
             }
