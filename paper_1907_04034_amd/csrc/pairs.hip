@@ -1183,6 +1183,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                                                   int32_t *rebin, uint32_t *err)
 {
     constexpr int PB = kBlock / G;
+    constexpr bool kBatchTail = DIM == 3 || sizeof(T) == 4;
     __shared__ double red_lds[3][PB];
     const int lane = threadIdx.x & (G - 1);
     const int64_t n = *m.n;
@@ -1243,9 +1244,27 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
 #pragma unroll
                 for (int f = 0; f < PF; ++f)
                     if (okp[f]) sp.add(nbp[f].p);
-                for (int q = lane + PF * G; q < cnt; q += G) {
-                    const int32_t j = row[q];
-                    if (!bad_index(j, n)) sp.add(ld<T>(R.p, j));
+                // the rest: in batches of PF slots (indices, then pressures)
+                // where the tail is long (3D) or the rows are records (FP32);
+                // in 2D FP64 the batch's registers cost more than it saves
+                // (1.2M particles: 4 -> 3 waves per SIMD, 188 -> 207 us)
+                if constexpr (!kBatchTail)
+                    for (int q = lane + PF * G; q < cnt; q += G) {
+                        const int32_t j = row[q];
+                        if (!bad_index(j, n)) sp.add(ld<T>(R.p, j));
+                    }
+                else
+                for (int q0 = lane + PF * G; q0 < cnt; q0 += PF * G) {
+                    int32_t jb[PF];
+                    T pb[PF];
+#pragma unroll
+                    for (int f = 0; f < PF; ++f) jb[f] = q0 + f * G < cnt ? row[q0 + f * G] : -1;
+#pragma unroll
+                    for (int f = 0; f < PF; ++f)
+                        pb[f] = ld<T>(R.p, bad_index(jb[f], n) ? int32_t(i) : jb[f]);
+#pragma unroll
+                    for (int f = 0; f < PF; ++f)
+                        if (q0 + f * G < cnt && !bad_index(jb[f], n)) sp.add(pb[f]);
                 }
                 pavg = sp.template reduce<G>() / T(cnt);
             }
@@ -1255,17 +1274,47 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                 if (okp[f] && jp[f] != i && !(t == SPH_BODY && nbp[f].tj != SPH_FLUID))
                     pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nbp[f], acc, bacc, pdot,
                                      fb);
-            for (int q = lane + PF * G; q < cnt; q += G) {
-                const int32_t j = row[q];
-                if (bad_index(j, n)) {
-                    raise_error(err, SPH_ERR_CELL_RANGE);
-                    continue;
+            // the rest, batched as for pbar: each batch fetched like the first
+            // slots (indices, then every row, then the arithmetic in slot order)
+            if constexpr (!kBatchTail)
+                for (int q = lane + PF * G; q < cnt; q += G) {
+                    const int32_t j = row[q];
+                    if (bad_index(j, n)) {
+                        raise_error(err, SPH_ERR_CELL_RANGE);
+                        continue;
+                    }
+                    if (j == i) continue;
+                    Nbr<DIM, T> nb;
+                    load_nbr<DIM, T>(k, m, R, o, sep, j, nb);
+                    if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
                 }
-                if (j == i) continue;
-                Nbr<DIM, T> nb;
-                load_nbr<DIM, T>(k, m, R, o, sep, j, nb);
-                if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
-                pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
+            else
+            for (int q0 = lane + PF * G; q0 < cnt; q0 += PF * G) {
+                int32_t jb[PF];
+                bool okb[PF];
+                bool bad = false;
+#pragma unroll
+                for (int f = 0; f < PF; ++f) jb[f] = q0 + f * G < cnt ? row[q0 + f * G] : -1;
+#pragma unroll
+                for (int f = 0; f < PF; ++f) {
+                    const bool have = q0 + f * G < cnt;
+                    okb[f] = have && !bad_index(jb[f], n);
+                    bad = bad || (have && !okb[f]);
+                }
+                if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
+                NbrRaw<DIM, T> rb[PF];
+#pragma unroll
+                for (int f = 0; f < PF; ++f)
+                    fetch_nbr<DIM, T>(k, m, R, o, okb[f] ? jb[f] : int32_t(i), rb[f]);
+#pragma unroll
+                for (int f = 0; f < PF; ++f) {
+                    if (!okb[f] || jb[f] == i) continue;
+                    Nbr<DIM, T> nb;
+                    finish_nbr<DIM, T>(k, sep, rb[f], nb);
+                    if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
+                }
             }
             T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
 #pragma unroll
