@@ -334,3 +334,30 @@ def test_empty_state(name, prec):
     assert sim.poll_error() == 0
     assert sim.live_count() == 0
     assert float(drag.abs().max().item()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_capacity_exhausted_sets_error_bit(prec):
+    """Capacity equal to the initial count: an inlet re-spawn finds no free
+    row, so the step raises SPH_ERR_CAPACITY (bit 2), writes no row past the
+    capacity and never counts more live rows than it holds; with room for the
+    re-spawns the same run raises nothing."""
+    _print_case(f"capacity exhausted C2-small {prec}")
+    prm, s = I.config("C2", small=True)
+    # without the outermost outlet column the first deletion (step 66 in the
+    # oracle) comes well after the first inlet re-spawn (step 23), so no row
+    # is freed before the re-spawn needs one
+    out = s["type"] == I.OUTLET
+    xo = s["x"][:, 0]
+    keep = ~(out & (xo > xo[out].max() - 0.5 * prm["dx"]))
+    s = {k: v[keep] for k, v in s.items()}
+    n = len(s["p"])
+    steps = int(np.ceil(prm["dx"] / (prm["U"] * prm["dt"]))) + 5  # 49: one inlet column crosses
+    full = B().Simulation(prm, s, prec=prec, cap=n)
+    full.step(steps)
+    assert full.poll_error() & 2
+    assert full.live_count() <= n
+    roomy = B().Simulation(prm, s, prec=prec, cap=2 * n)
+    roomy.step(steps)
+    assert roomy.poll_error() == 0
+    assert roomy.live_count() > n  # the re-spawned inlet column
