@@ -361,3 +361,21 @@ def test_capacity_exhausted_sets_error_bit(prec):
     roomy.step(steps)
     assert roomy.poll_error() == 0
     assert roomy.live_count() > n  # the re-spawned inlet column
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nonfinite_value_sets_error_bit(prec):
+    """A NaN pressure on one fluid particle: the stage update flags the
+    non-finite result (SPH_ERR_NONFINITE, bit 4), and the step completes (NaN
+    positions are clamped into a valid cell by the bin, which flags them)."""
+    _print_case(f"non-finite pressure C2-small {prec}")
+    prm, s = I.config("C2", small=True)
+    s = I.snapshot_copy(s)
+    fl = np.flatnonzero(s["type"] == I.FLUID)
+    s["p"][fl[len(fl) // 2]] = np.nan
+    sim = B().Simulation(prm, s, prec=prec)
+    sim.step(2)
+    assert sim.poll_error() & 4
+    clean = B().Simulation(prm, I.config("C2", small=True)[1], prec=prec)
+    clean.step(2)
+    assert clean.poll_error() == 0
