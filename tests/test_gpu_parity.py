@@ -379,3 +379,21 @@ def test_nonfinite_value_sets_error_bit(prec):
     clean = B().Simulation(prm, I.config("C2", small=True)[1], prec=prec)
     clean.step(2)
     assert clean.poll_error() == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_escaped_particle_sets_error_bit(prec):
+    """A fluid particle outside the box along a closed axis (the 3D duct's
+    walls): the bin clamps it into the edge cell and raises SPH_ERR_ESCAPE
+    (bit 16); the step completes."""
+    _print_case(f"escaped particle C5-small {prec}")
+    prm, s = I.config("C5", small=True)
+    closed = [d for d in range(1, prm["dim"]) if not prm["periodic"][d]]
+    assert closed, "the duct's transverse axes are closed"
+    d = closed[0]
+    s = I.snapshot_copy(s)
+    fl = np.flatnonzero(s["type"] == I.FLUID)
+    s["x"][fl[len(fl) // 2], d] = prm["hi"][d] + 0.5
+    sim = B().Simulation(prm, s, prec=prec)
+    sim.step(1)
+    assert sim.poll_error() & 16
