@@ -89,6 +89,9 @@ def lib():
         L.orc_quintic_gradw_factor.restype = C.c_double
         L.orc_quintic_gradw_factor.argtypes = [C.c_double, C.c_double, C.c_int]
         L.orc_num_threads.restype = C.c_int
+        L.orc_splitmix_uniform.restype = C.c_double
+        L.orc_splitmix_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_int]
+        L.orc_inlet_velocity.argtypes = [C.POINTER(OrcParams), C.c_int64, P, P]
         _lib = L
     return _lib
 
@@ -117,6 +120,20 @@ def quintic_w(r, h, dim):
 
 def quintic_gradw_factor(r, h, dim):
     return lib().orc_quintic_gradw_factor(r, h, dim)
+
+
+def splitmix_uniform(seed, pid, k):
+    """The k-th uniform in [0, 1) of particle pid under the seeded generator."""
+    return lib().orc_splitmix_uniform(int(seed), int(pid), int(k))
+
+
+def inlet_velocity(prm, pid, parent=(0.0, 0.0, 0.0)):
+    """Prescribed velocity of a re-spawned inlet particle with id pid."""
+    q = make_params(prm)
+    par = np.ascontiguousarray(parent, dtype=np.float64)
+    out = np.zeros(3)
+    lib().orc_inlet_velocity(C.byref(q), int(pid), _ptr(par), _ptr(out))
+    return out
 
 
 def num_threads():

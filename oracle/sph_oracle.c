@@ -1119,6 +1119,19 @@ int64_t orc_neighbors(void *h, int brute, int64_t *row_ptr, int32_t *col, int64_
     return nnz;
 }
 
+/* Test access to the seeded inlet noise: the k-th uniform of particle `id`
+ * (splitmix_uniform) and the prescribed velocity a re-spawned inlet particle
+ * with this id receives (inlet_velocity, parent velocity `parent`). */
+double orc_splitmix_uniform(uint64_t seed, int64_t id, int k)
+{
+    return splitmix_uniform(seed, id, k);
+}
+
+void orc_inlet_velocity(const orc_params *q, int64_t id, const double *parent, double *out)
+{
+    inlet_velocity(q, id, parent, out);
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
