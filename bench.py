@@ -3,19 +3,26 @@
 
 A step is one explicit-midpoint RK2 step of the whole path (bin + Morton
 sort, neighbour table, density, boundary values, force pass, stage updates,
-time-average/transfer/re-spawn bookkeeping, drag) on the 2D channel workload
-(4 x 1, dx = 0.01, 40,000 fluid particles, 5-layer inlet and hybrid outlet,
-Gaussian pressure pulse of amplitude 0.01 rho0 c0 U at x = 2, width 0.1).
+time-average/transfer/re-spawn bookkeeping) with the state resident in HBM.
+The default workload is the largest single-GPU configuration: the 3D duct
+4 x 1 x 1, dx = 0.01 (4.0M fluid particles, 5-layer inlet and hybrid outlet,
+3-layer no-slip walls, 1 % seeded inlet noise; 4.6M particles in all).
 
 Metric: pair-interactions/s = (fluid-neighbour pairs per right-hand side) x 2
-right-hand sides per step x steps / time, with the state resident in HBM.
-Prints one JSON line. The roofline object reports the force kernel (the
-dominant kernel) timed alone with HIP events on the library's stream; the
-cpu_baseline object times the FP64 CPU oracle on a bounded sample.
+right-hand sides per step x steps / time. The line's value is the FP64 path;
+the FP32 path (FP32 pair arithmetic on cell-relative offsets, compensated
+sums) and the adjoint (one reverse right-hand side) are reported beside it
+under "forms". The roofline object reports the force pass, timed alone with
+HIP events on the library's stream, against the algorithmic bytes per
+particle of the hot-path scope table (156 B in 3D FP64: x, u, ut, p, V, rho,
+type in, a, b, pdot out), with the implementation's own byte count beside it;
+cpu_baseline times the FP64 CPU oracle on a bounded sample of the workload,
+on one host thread and on all of them.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import hashlib
 import json
 import os
@@ -27,93 +34,146 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 METRIC = "pair-interactions/s of EDAC RHS (FP64 vs FP32 vs adjoint) + HBM roofline %"
 WORKLOADS = {
+    "C5": "3D duct 4x1x1 dx=0.01 (4.0M fluid + 5-layer inlet + 5-layer hybrid outlet + "
+          "3-layer no-slip walls = 4.6M particles), uniform inlet u=1 with seeded 1% noise, "
+          "Wendland C2 h=dx",
     "C2": "2D channel 4x1 dx=0.01, 40k fluid + 5-layer inlet + 5-layer hybrid outlet, "
           "Gaussian pulse A=0.01 rho0 c0 U at x=2 w=0.1, Wendland C2 h=dx",
     "C1": "2D periodic box 1x1, 40x40 Taylor-Green, Wendland C2 h=dx",
     "C3": "2D cylinder D=2 Re=200 in 60x32, dx=D/50, 3-layer slip walls",
     "C4": "2D channel 4x1 dx=0.01 with D=0.2 cylinder, Re=20",
-    "C5": "3D duct 4x1x1 dx=0.01, no-slip walls, inlet noise 1%",
     "C2Q": "2D channel 4x1 dx=0.01 with the C2 pulse, the paper's quintic spline "
            "(support 3h) at h=1.2 dx",
 }
+# Algorithmic bytes per particle per right-hand side (every array the pass
+# needs read once, every output written once; neighbour re-reads served by
+# LDS or cache not counted): pass D = neighbours + density, pass F = force.
+# FP32 3D splits its 112 B total the way the 2D rows split.
+SCOPE_BYTES = {(2, "fp64"): (36, 116), (3, "fp64"): (44, 156),
+               (2, "fp32"): (24, 64), (3, "fp32"): (28, 84)}
+# Algorithmic flops per ordered neighbour pair of the force pass (neighbour
+# average 6, pair terms 75, one square root and two divisions counted once).
+FORCE_FLOPS_PER_PAIR = 84
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def force_bytes(sim, counts, types, prec_bytes):
-    """Algorithmic HBM bytes of one force-pass launch: every array the kernel
-    needs read once and every output written once (neighbour gathers that hit
-    cache are not counted)."""
-    import numpy as np
-    D = sim.dim
-    n = len(types)
+def force_bytes(counts, types, prec_bytes, dim):
+    """The implementation's own byte count of one force launch: as the scope
+    figure plus the neighbour count and indices each fluid or body row reads
+    and the kind byte of every row."""
     fb = (types == 0) | (types == 5)
+    n = len(types)
     nfb = int(fb.sum())
     nnz = int(counts[fb].sum())
-    pos = 8 * D if prec_bytes == 8 else 4 * D + 4  # FP32: cell offsets + packed cell
-    rd = n * 1 + nfb * (pos + 2 * prec_bytes * D + 3 * prec_bytes + 4) + 4 * nnz
-    wr = n * (2 * prec_bytes * D + 2 * prec_bytes) + int((types == 5).sum()) * 8 * D
-    return rd + wr, dict(read=rd, write=wr, n=n, n_fluid_or_body=nfb, nnz=nnz)
+    pos = 8 * dim if prec_bytes == 8 else 4 * dim + 4  # FP32: cell offsets + packed cell
+    rd = n * 1 + nfb * (pos + 2 * prec_bytes * dim + 3 * prec_bytes + 4) + 4 * nnz
+    wr = n * (2 * prec_bytes * dim + 2 * prec_bytes) + int((types == 5).sum()) * 8 * dim
+    return rd + wr
 
 
 def source_hash():
     h = hashlib.sha256()
-    for f in ("pairs.hip", "sph_dev.h"):
-        with open(os.path.join(ROOT, "paper_1907_04034_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    csrc = os.path.join(ROOT, "paper_1907_04034_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(workload, prec):
-    """HBM bytes per force launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+def counters_summary(workload, prec):
+    """Traffic and limiter of the force pass from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", f"k_force_{workload}_{prec}_counters.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
-    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
     h = re.search(r"source_sha:\s*([0-9a-f]+)", txt)
-    if not m or not h or h.group(1) != source_hash():
+    if not h or h.group(1) != source_hash():
         return None
-    return float(m.group(1))
+    out = {}
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if m:
+        out["traffic"] = float(m.group(1))
+    m = re.search(r"limiter:\s*(hbm|alu)\b", txt)
+    if m:
+        out["bound"] = m.group(1)
+    return out
 
 
-def cpu_baseline(prm, s, budget_s):
-    """The FP64 oracle as it stands, on the host's cores, over the first steps
-    of the same workload until about budget_s seconds of stepping."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_sample(prm, s, xmax):
+    """The workload's particles with x < xmax (inlet, walls and fluid of the
+    first stretch of the tunnel): a bounded sample of the same structure."""
+    import numpy as np
+    keep = s["x"][:, 0] < xmax
+    t = {k: np.ascontiguousarray(v[keep]) for k, v in s.items()}
+    t["id"] = np.arange(int(keep.sum()), dtype=np.int64)
+    return t
+
+
+def cpu_baseline(prm, s, args):
+    """The FP64 oracle as it stands: one right-hand side (neighbour lists,
+    density, boundary values, force pass) on a sample of the workload, timed
+    on one host thread and on all of them; pair-interactions/s."""
     import numpy as np
     from oracle import oracle as O
     O.build(force=False)
-    o = O.Oracle(prm, s)
-    chunk = max(1, min(10, 400_000 // len(s["p"])))
-    steps, pairs, elapsed = 0, 0, 0.0
-    while elapsed < budget_s and steps < prm.get("steps", 2000):
-        row, _ = o.neighbors()
-        fl = o.state()["type"] == 0
-        p_rhs = int((np.diff(row)[fl] - 1).sum())
-        t1 = time.perf_counter()
-        o.step(chunk)
-        elapsed += time.perf_counter() - t1
-        steps += chunk
-        pairs += 2 * chunk * p_rhs
-    return dict(value=pairs / elapsed, unit="pair-interactions/s", cores=O.num_threads(),
-                kind="oracle",
-                sample=f"FP64 oracle, first {steps} RK2 steps ({2 * steps} RHS) of the same "
-                       f"workload, {elapsed:.1f} s of stepping")
+    if prm["dim"] == 3:
+        t = oracle_sample(prm, s, args.cpu_sample_x)
+        what = f"the first {args.cpu_sample_x:g} m of the duct ({len(t['p'])} particles)"
+    else:
+        t = s
+        what = f"the whole workload ({len(t['p'])} particles)"
+    o = O.Oracle(prm, t)
+    row, _ = o.neighbors()
+    fl = o.state()["type"] == 0
+    p_rhs = int((np.diff(row)[fl] - 1).sum())
+    out = {}
+    allt = os.cpu_count() or 1
+    for label, nt in (("all", allt), ("one", 1)):
+        O.set_threads(nt)
+        reps, elapsed = 0, 0.0
+        budget = args.cpu_budget if label == "all" else 2 * args.cpu_budget
+        while elapsed < budget / 2 and reps < 20:
+            t1 = time.perf_counter()
+            o.rhs()
+            elapsed += time.perf_counter() - t1
+            reps += 1
+        out[label] = (p_rhs * reps / elapsed, nt, reps, elapsed)
+    O.set_threads(allt)
+    v_all, n_all, r_all, e_all = out["all"]
+    v_one, _, r_one, e_one = out["one"]
+    return dict(value=v_all, unit="pair-interactions/s", cores=n_all, kind="oracle",
+                sample=f"FP64 oracle right-hand sides on {what}, {p_rhs} pairs each: "
+                       f"{r_all} on {n_all} threads in {e_all:.1f} s, {r_one} on 1 thread "
+                       f"in {e_one:.1f} s",
+                value_1thread=v_one, cpu_model=cpu_model(), host_cpus=allt)
 
 
-def adjoint_bytes(sim, counts, types, prec_bytes):
+def adjoint_bytes(counts, types, prec_bytes, dim):
     """Algorithmic HBM bytes of one reverse right-hand side (sph_rhs_adjoint):
     the forward state and stored derived fields read once per row, the weights
     and seeds read once, the neighbour indices read once per pass that walks
     them (pairs, neighbour average, boundary, density), every adjoint output
     written once. Re-reads of neighbour rows are served by cache and do not
     count."""
-    D = sim.dim
+    D = dim
     n = len(types)
     nnz = int(counts.sum())
     state = 8 * D + prec_bytes * (2 * D + 1) + 1 + 3 * prec_bytes  # x, u, ut, p, type, rho, V, pbar
@@ -124,6 +184,29 @@ def adjoint_bytes(sim, counts, types, prec_bytes):
     rd = n * (state + weights + bnd + internal // 2) + 4 * nnz * 4 + 4 * n * 4
     wr = n * (outputs + internal // 2)
     return rd + wr
+
+
+class Marker:
+    """roctx ranges around the timed regions, so that a rocprofv3 trace of this
+    command can be restricted to them (--marker-trace). No-op if the roctx
+    library is absent."""
+
+    def __init__(self, on):
+        self.lib = None
+        if on:
+            try:
+                self.lib = ctypes.CDLL("librocprofiler-sdk-roctx.so")
+                self.lib.roctxRangePushA.argtypes = [ctypes.c_char_p]
+            except OSError:
+                self.lib = None
+
+    def push(self, name):
+        if self.lib:
+            self.lib.roctxRangePushA(name.encode())
+
+    def pop(self):
+        if self.lib:
+            self.lib.roctxRangePop()
 
 
 def timed_launches(stream, reps, launch):
@@ -140,6 +223,124 @@ def timed_launches(stream, reps, launch):
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def run_steps(prm, s, prec, args, mark, label):
+    """W warm-up steps, then K timed steps between HIP events on the library's
+    stream (and the host clock); returns the simulation and its timings."""
+    import torch
+    from paper_1907_04034_amd import binding as B
+    sim = B.Simulation(prm, s, prec=prec)
+    stream = torch.cuda.current_stream()
+    sim.step(args.warmup)
+    bits = sim.poll_error()
+    if bits:
+        raise SystemExit(f"device error bits after warm-up ({prec}): {bits}")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    mark.push(f"timed steps {label}")
+    w0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    mark.pop()
+    gpu_ms = e0.elapsed_time(e1)
+    bits = sim.poll_error()
+    if bits:
+        raise SystemExit(f"device error bits in the timed region ({prec}): {bits}")
+    cnt, _ = sim.neighbor_table()
+    types = sim.state()["type"]
+    p_rhs = int((cnt[types == 0] - 1).sum())
+    t_step = max(gpu_ms, wall * 1e3) / args.steps
+    log(f"bench {label}: {args.steps} steps in {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms "
+        f"wall; {p_rhs} pairs per RHS")
+    return sim, dict(ms_per_step=t_step, pairs_per_rhs=p_rhs, value=2 * p_rhs / (t_step * 1e-3),
+                     n=int(len(types)))
+
+
+def kernel_timings(sim, prec, args, mark, label):
+    """The force pass (sph_force, one kernel launch) and the neighbour search
+    (sph_neighbors with density) alone, on a fresh bin of the current state."""
+    import torch
+    stream = torch.cuda.current_stream()
+    sim.bin()
+    sim.neighbors()
+    sim.rhs()
+    torch.cuda.synchronize()
+    reps = args.force_reps
+    mark.push(f"force launches {label}")
+    f_us = 1e3 * timed_launches(stream, reps, lambda: sim.force(reduce_drag=False))
+    mark.pop()
+    mark.push(f"search launches {label}")
+    s_us = 1e3 * timed_launches(stream, max(5, reps // 4), sim.neighbors)
+    mark.pop()
+    cnt, _ = sim.neighbor_table()
+    types = sim.state()["type"]
+    if sim.poll_error():
+        raise SystemExit(f"device error bits in the kernel timings ({prec})")
+    return f_us, s_us, cnt, types
+
+
+def roofline(prm, prec, f_us, cnt, types, counters):
+    import numpy as np
+    dim = prm["dim"]
+    n = len(types)
+    per = SCOPE_BYTES[(dim, prec)][1]
+    alg = per * n
+    hbm = alg / (f_us * 1e-6) / 1e9
+    own = force_bytes(cnt, types, 8 if prec == "fp64" else 4, dim)
+    pairs = int((cnt[types == 0] - 1).sum() + np.maximum(cnt[types == 5] - 1, 0).sum())
+    flops = FORCE_FLOPS_PER_PAIR * pairs
+    tflops = flops / (f_us * 1e-6) / 1e12
+    hbm_view = dict(bound="hbm", kernel="k_force", achieved=hbm, peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=hbm / HBM_PEAK_GBS,
+                    traffic=(counters or {}).get("traffic"),
+                    bytes_per_particle=per, particles=n, algorithmic_bytes_per_launch=alg,
+                    launch_us=f_us, own_bytes_per_launch=own,
+                    own_achieved_gbs=own / (f_us * 1e-6) / 1e9, source_sha=source_hash())
+    alu_view = dict(bound="alu", kernel="k_force", achieved=tflops,
+                    peak=VALU_PEAK_TFLOPS[prec], unit="TFLOP/s",
+                    frac=tflops / VALU_PEAK_TFLOPS[prec], flops_per_pair=FORCE_FLOPS_PER_PAIR,
+                    pairs_per_launch=pairs, launch_us=f_us)
+    bound = (counters or {}).get("bound")
+    if bound is None:
+        bound = "alu" if alu_view["frac"] > hbm_view["frac"] else "hbm"
+    main, other = (hbm_view, alu_view) if bound == "hbm" else (alu_view, hbm_view)
+    if bound == "alu":
+        main["traffic"] = hbm_view["traffic"]
+    return main, other
+
+
+def adjoint_rhs_rate(sim, prec, args, mark):
+    """One reverse right-hand side (sph_rhs_adjoint, four kernels) on the
+    current state: pair-interactions/s of reversed pairs and its bytes."""
+    import numpy as np
+    import torch
+    stream = torch.cuda.current_stream()
+    sim.bin()
+    sim.neighbors()
+    sim.rhs()
+    cnt, _ = sim.neighbor_table()
+    types = sim.state()["type"]
+    n = len(types)
+    rng = np.random.default_rng(0)
+    w = rng.standard_normal((n, 3))
+    sim.rhs_adjoint(abar=w, bbar=w, pdbar=w[:, 0], fbar=(1.0, 0.0, 0.0))
+    torch.cuda.synchronize()
+    st = sim._adj_struct((1.0, 0.0, 0.0))
+    mark.push("adjoint launches")
+    a_us = 1e3 * timed_launches(stream, max(5, args.force_reps // 4),
+                                lambda: sim.rhs_adjoint_launch(st))
+    mark.pop()
+    if sim.poll_error():
+        raise SystemExit("device error bits in the adjoint timing")
+    p_rhs = int((cnt[types == 0] - 1).sum())
+    ab = adjoint_bytes(cnt, types, 8 if prec == "fp64" else 4, sim.dim)
+    return dict(value=p_rhs / (a_us * 1e-6), unit="pair-interactions/s", precision=prec,
+                launch_us=a_us, pairs_per_rhs=p_rhs, algorithmic_bytes=ab,
+                hbm_frac=ab / (a_us * 1e-6) / 1e9 / HBM_PEAK_GBS)
 
 
 def adjoint_bench(args):
@@ -160,7 +361,6 @@ def adjoint_bench(args):
     stream = torch.cuda.current_stream()
     fbar = np.zeros((K, 3))
     fbar[:, 0] = 1.0 / K
-    # warm-up: a short forward + reverse on its own simulation
     wsim = B.Simulation(prm, s, prec=args.precision)
     w = A.DragAdjoint(wsim, max(2, min(args.warmup, 20)), segment=args.segment)
     w.forward()
@@ -187,7 +387,6 @@ def adjoint_bench(args):
     if sim.poll_error():
         raise SystemExit("device error in the timed region")
     J = float(hist[:, 0].mean().item())
-    # pairs per right-hand side at the start state (the reverse ends there)
     sim2 = B.Simulation(prm, s, prec=args.precision)
     sim2.bin()
     sim2.neighbors()
@@ -196,41 +395,23 @@ def adjoint_bench(args):
     types = sim2.state()["type"]
     p_rhs = int((cnt[types == 0] - 1).sum())
     value = 2 * p_rhs * K / (times["backward"] * 1e-3)
-    # one reverse right-hand side, timed alone
-    n = len(types)
-    rng = np.random.default_rng(0)
-    ab = rng.standard_normal((n, 3))
-    sim2.rhs_adjoint(abar=ab, bbar=ab, pdbar=ab[:, 0], fbar=(1.0, 0.0, 0.0))
-    torch.cuda.synchronize()
-    reps = args.force_reps
-    st_adj = sim2._adj_struct()
-    a_us = 1e3 * timed_launches(stream, reps, lambda: sim2.rhs_adjoint_launch(st_adj))
-    prec_bytes = 8 if args.precision == "fp64" else 4
-    abytes = adjoint_bytes(sim2, cnt, types, prec_bytes)
-    achieved = abytes / (a_us * 1e-6) / 1e9
+    one = adjoint_rhs_rate(sim2, args.precision, args, Marker(False))
     out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "pair-interactions/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": min(args.warmup, 20),
-        "ms_per_step": times["backward"] / K,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 pairs / f64 positions",
+        "metric": METRIC, "value": value, "unit": "pair-interactions/s", "n_gpus": 1,
+        "steps": K, "warmup": min(args.warmup, 20), "ms_per_step": times["backward"] / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config] + ", gradient of the time-averaged drag "
                    "w.r.t. the inlet profile", "config": args.config, "form": "adjoint",
                    "particles": int(len(s["p"])), "pairs_per_rhs": p_rhs, "rhs_per_step": 2,
                    "precision": args.precision, "segment": run.segment,
-                   "forward_ms": times["forward"], "backward_ms": times["backward"],
-                   "J": J},
+                   "forward_ms": times["forward"], "backward_ms": times["backward"], "J": J},
         "roofline": {"bound": "hbm", "kernel": "sph_rhs_adjoint (4 kernels)",
-                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": abytes, "launch_us": a_us},
+                     "achieved": one["algorithmic_bytes"] / (one["launch_us"] * 1e-6) / 1e9,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": one["hbm_frac"],
+                     "traffic": None, "algorithmic_bytes_per_launch": one["algorithmic_bytes"],
+                     "launch_us": one["launch_us"]},
     }
     print(json.dumps(out), flush=True)
 
@@ -238,15 +419,25 @@ def adjoint_bench(args):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=400)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--config", default="C2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--force-reps", type=int, default=100)
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--config", default="C5", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the line's value")
+    ap.add_argument("--forms", default="fp32,adjoint",
+                    help="forms timed beside the value (comma list of fp64, fp32, adjoint; "
+                         "'none' for none)")
+    ap.add_argument("--force-reps", type=int, default=40)
+    ap.add_argument("--cpu-budget", type=float, default=10.0,
+                    help="seconds of oracle work per thread count (about)")
+    ap.add_argument("--cpu-sample-x", type=float, default=0.3,
+                    help="3D workloads: the oracle times the particles with x below this")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (for counter scaling)")
+    ap.add_argument("--mark", action="store_true",
+                    help="roctx ranges around the timed regions (for rocprofv3 --marker-trace)")
+    ap.add_argument("--calibrate-mib", type=int, default=0,
+                    help="also run a read-only and a write-only pass over a buffer of this "
+                         "size (scales the HBM counters)")
     ap.add_argument("--form", default="forward", choices=["forward", "adjoint"],
                     help="adjoint: gradient of the time-averaged drag (default config C4)")
     ap.add_argument("--segment", type=int, default=50, help="adjoint checkpoint interval")
@@ -267,19 +458,18 @@ def main():
         if args.outlet != "hybrid" or args.mirror_inlet:
             raise SystemExit("the adjoint form covers the hybrid outlet and the "
                              "characteristic inlet only")
-        if args.config == "C2" and "--config" not in sys.argv:
+        if "--config" not in sys.argv:
             args.config = "C4"
         if "--steps" not in sys.argv:
             args.steps = 500
         adjoint_bench(args)
         return
 
-    import numpy as np
     import torch
-    from paper_1907_04034_amd import binding as B
     from paper_1907_04034_amd import inputs as I
 
     torch.cuda.set_device(0)
+    mark = Marker(args.mark)
     prm, s = I.config(args.config)
     prm["outlet"] = I.OUTLETS[args.outlet]
     if args.mirror_inlet:
@@ -288,90 +478,67 @@ def main():
         prm["flags"] |= I.FLAG_REUSE_BINS
     log(f"bench: {prm['name']} n={len(s['p'])} prec={args.precision} "
         f"reuse_bins={not args.sort_every_step} outlet={args.outlet}")
-    sim = B.Simulation(prm, s, prec=args.precision)
-    stream = torch.cuda.current_stream()
 
-    if args.copy_calibration_mib:
-        nb = args.copy_calibration_mib << 20
-        a = torch.empty(nb, dtype=torch.uint8, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
+    if args.calibrate_mib:
+        nb = args.calibrate_mib << 20
+        buf = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+        buf.fill_(1.0)  # write-only: nb bytes
         torch.cuda.synchronize()
-        log(f"bench: copy calibration {nb} bytes x3 done")
+        tot = buf.sum()  # read-only: nb bytes
+        torch.cuda.synchronize()
+        log(f"bench: calibration over {nb} bytes (fill, sum = {float(tot):.0f})")
+        del buf
 
-    sim.step(args.warmup)
-    bits = sim.poll_error()
-    if bits:
-        raise SystemExit(f"device error bits after warmup: {bits}")
-    torch.cuda.synchronize()
-
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    e0.record(stream)
-    sim.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_ms = e0.elapsed_time(e1)
-    bits = sim.poll_error()
-    if bits:
-        raise SystemExit(f"device error bits in timed region: {bits}")
-    log(f"bench: {args.steps} steps in {gpu_ms:.2f} ms (events), {wall * 1e3:.2f} ms wall")
-
-    # pairs per right-hand side, from the neighbour table of the last stage
-    cnt, _ = sim.neighbor_table()
-    st = sim.state()
-    types = st["type"]
-    fl = types == 0
-    p_rhs = int((cnt[fl] - 1).sum())
-    t_step = max(gpu_ms, wall * 1e3) / args.steps
-    value = 2 * p_rhs / (t_step * 1e-3)
-
-    # dominant kernel alone: fresh bin/neighbours/rhs, then force launches
-    sim.bin()
-    sim.neighbors()
-    sim.rhs()
-    cnt, _ = sim.neighbor_table()
-    types = sim.state()["type"]
-    torch.cuda.synchronize()
-    reps = args.force_reps
-    f_us = 1e3 * timed_launches(stream, reps, lambda: sim.force(reduce_drag=False))
-    prec_bytes = 8 if args.precision == "fp64" else 4
-    fbytes, fdetail = force_bytes(sim, cnt, types, prec_bytes)
-    achieved = fbytes / (f_us * 1e-6) / 1e9
-    traffic = traffic_from_profile(args.config, args.precision)
-    log(f"bench: k_force {f_us:.2f} us/launch, {fbytes / 1e6:.2f} MB algorithmic, "
-        f"{achieved:.1f} GB/s")
+    forms = [f for f in args.forms.split(",") if f and f != "none"]
+    sim, main_t = run_steps(prm, s, args.precision, args, mark, args.precision)
+    f_us, s_us, cnt, types = kernel_timings(sim, args.precision, args, mark, args.precision)
+    counters = counters_summary(args.config, args.precision)
+    roof, roof_other = roofline(prm, args.precision, f_us, cnt, types, counters)
+    log(f"bench: k_force {f_us:.1f} us/launch ({roof['bound']} {roof['frac']:.3f}), "
+        f"search {s_us:.1f} us/launch")
+    result_forms = {args.precision: dict(main_t, force_us=f_us, search_us=s_us,
+                                         unit="pair-interactions/s")}
+    if "adjoint" in forms:
+        result_forms["adjoint"] = adjoint_rhs_rate(sim, args.precision, args, mark)
+        log(f"bench: adjoint RHS {result_forms['adjoint']['launch_us']:.1f} us")
+    del sim
+    torch.cuda.empty_cache()
+    for prec in ("fp64", "fp32"):
+        if prec in forms and prec != args.precision:
+            sim2, t2 = run_steps(prm, s, prec, args, mark, prec)
+            f2, s2, c2, ty2 = kernel_timings(sim2, prec, args, mark, prec)
+            r2, _ = roofline(prm, prec, f2, c2, ty2, counters_summary(args.config, prec))
+            result_forms[prec] = dict(t2, force_us=f2, search_us=s2, unit="pair-interactions/s",
+                                      force_roofline=r2)
+            del sim2
+            torch.cuda.empty_cache()
 
     out = {
         "metric": METRIC,
-        "value": value,
+        "value": main_t["value"],
         "unit": "pair-interactions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": t_step,
+        "ms_per_step": main_t["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 pairs / f64 positions",
+        "dtype": "f64" if args.precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOADS[args.config], "config": args.config,
-                   "particles": int(len(s["p"])), "pairs_per_rhs": p_rhs,
+                   "particles": main_t["n"], "pairs_per_rhs": main_t["pairs_per_rhs"],
                    "rhs_per_step": 2, "precision": args.precision, "outlet": args.outlet,
                    "inlet": "mirror" if args.mirror_inlet else "characteristic",
                    "cell_order": "sorted every step" if args.sort_every_step
                    else "kept while the cell skin allows"},
-        "roofline": {"bound": "hbm", "kernel": "k_force", "achieved": achieved,
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": traffic, "algorithmic_bytes_per_launch": fbytes,
-                     "launch_us": f_us, "source_sha": source_hash()},
+        "roofline": roof,
+        "roofline_other_roof": roof_other,
+        "forms": result_forms,
     }
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle sample")
-        out["cpu_baseline"] = cpu_baseline(prm, s, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(prm, s, args)
     print(json.dumps(out), flush=True)
 
 

@@ -89,6 +89,7 @@ def lib():
         L.orc_quintic_gradw_factor.restype = C.c_double
         L.orc_quintic_gradw_factor.argtypes = [C.c_double, C.c_double, C.c_int]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_splitmix_uniform.restype = C.c_double
         L.orc_splitmix_uniform.argtypes = [C.c_uint64, C.c_int64, C.c_int]
         L.orc_inlet_velocity.argtypes = [C.POINTER(OrcParams), C.c_int64, P, P]
@@ -138,6 +139,11 @@ def inlet_velocity(prm, pid, parent=(0.0, 0.0, 0.0)):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_threads(n):
+    """OpenMP threads of later oracle calls (results do not depend on it)."""
+    lib().orc_set_threads(int(n))
 
 
 class Oracle:

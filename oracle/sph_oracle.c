@@ -1132,6 +1132,17 @@ void orc_inlet_velocity(const orc_params *q, int64_t id, const double *parent, d
     inlet_velocity(q, id, parent, out);
 }
 
+/* Threads of the OpenMP loops of later calls (benchmark timing of the oracle
+ * on one and on all host cores); results do not depend on it. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP
