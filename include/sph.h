@@ -277,6 +277,26 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
              sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
              size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): sph_step
+ * with the library's own scratch in place of the caller's workspace. The
+ * scratch is a static device array of SPH_STATIC_SCRATCH_BYTES (32 MiB) that
+ * every GPU the library runs on holds from the library's load until the
+ * process ends; this call allocates nothing. It clears the part it uses, runs
+ * the steps exactly as sph_step does with a freshly zeroed workspace (same
+ * kernels, same results bit for bit), and writes the call's device error bits
+ * (SPH_ERR_*) to *err_out (device memory, may be NULL) at the end of the call,
+ * on the stream. Returns SPH_ECAPACITY, before any launch, when the capacity
+ * and cell grid need a larger workspace than the scratch holds (sph_workspace
+ * _size > SPH_STATIC_SCRATCH_BYTES; about 65k particles in a 2D channel).
+ * Every call on one GPU shares that GPU's scratch: calls that overlap in time
+ * on one GPU (other streams or threads) race and must be serialised by the
+ * caller. */
+#define SPH_STATIC_SCRATCH_BYTES (32u << 20)
+int sph_step_static(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+                    sph_derived *out, int32_t nsteps, double *drag_hist, uint32_t *err_out,
+                    void *stream);
+
 /* Reverse pass (vector-Jacobian product) of one right-hand side, written by
  * hand from the forward formulas (no automatic differentiation): the
  * gradient of

@@ -24,7 +24,8 @@ EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
             "sph_rhs_adjoint", "sph_outlet_extrapolate_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
             "sph_step_adjoint", "sph_step_record_store", "sph_step_adjoint_stored",
-            "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count", "sph_last_error"]
+            "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count", "sph_last_error",
+            "sph_step_static"]
 EV_PUSH, EV_TO_OUTLET, EV_DELETE, EV_SPAWN = 1, 2, 4, 8
 FLAG_REUSE_BINS = 8
 
@@ -88,6 +89,10 @@ def lib():
     """Load libsph.so (raises if it is missing: there is no fallback path)."""
     global _lib
     if _lib is None:
+        # torch brings its own HIP runtime: it must be the process's runtime
+        # before libsph.so binds to one, or the library's launches and torch's
+        # device memory would belong to different runtimes
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libsph.so not built ({LIB_PATH}); run __graft_entry__.build()")
         L = C.CDLL(LIB_PATH)
@@ -104,6 +109,7 @@ def lib():
         L.sph_rhs.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_force.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_step.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, sz, _P]
+        L.sph_step_static.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, _P]
         L.sph_rhs_adjoint.argtypes = [SP, ST, NL, DE, C.POINTER(SphAdjoint), _P, sz, _P]
         L.sph_outlet_extrapolate_adjoint.argtypes = L.sph_rhs_adjoint.argtypes
         LA = C.POINTER(SphStateAdjoint)
@@ -328,6 +334,23 @@ class Simulation:
                               C.byref(self.nl), C.byref(self.out), int(nsteps), dh, ws, nb,
                               self.stream), "sph_step")
         self.binned = True
+
+    def step_static(self, nsteps, drag_hist=None):
+        """sph_step on the library's static scratch (no workspace argument); the
+        call's device error bits land in a device word read by static_error()."""
+        t = self.torch
+        if not hasattr(self, "static_err"):
+            self.static_err = t.zeros(1, dtype=t.int32, device=self.dev)
+        dh = drag_hist.data_ptr() if drag_hist is not None else None
+        _check(lib().sph_step_static(C.byref(self.q), C.byref(self.st), C.byref(self.alt),
+                                     C.byref(self.nl), C.byref(self.out), int(nsteps), dh,
+                                     self.static_err.data_ptr(), self.stream),
+               "sph_step_static")
+        self.binned = True
+
+    def static_error(self):
+        """Device error bits of the last step_static call (synchronises)."""
+        return int(self.static_err.item()) & 0xFFFFFFFF
 
     def poll_error(self):
         bits = C.c_uint32(0)

@@ -527,6 +527,29 @@ static int check_lam(const sph_state_adjoint *l, int64_t cap, const char *name)
     return SPH_OK;
 }
 
+// sph_step on a given workspace (also the static-scratch entry point's body)
+int step_on_workspace(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+                      sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
+                      size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
+    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
+    rc = check_state(alt, prm, "alt");
+    if (rc) return rc;
+    if (alt->cap != st->cap || alt->prec != st->prec)
+        return fail(SPH_EINVAL, "alt must match state in cap and precision");
+    if (nsteps < 0) return fail(SPH_EINVAL, "nsteps < 0");
+    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
+    for (int32_t s = 0; s < nsteps; ++s)
+        one_step(c, st, alt, nl, out, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr, nullptr,
+                 nullptr);
+    if (nsteps > 0) launch_finish_spawn(c.k, dev_state(st), at<int32_t>(ws, c.w.nspawn), c.s);
+    return check_hip("sph_step");
+}
+
+int api_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
 }  // namespace sph
 
 using namespace sph;
@@ -647,20 +670,7 @@ int sph_step(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl
              sph_derived *out, int32_t nsteps, double *drag_hist, void *ws, size_t ws_bytes,
              void *stream)
 {
-    Ctx c;
-    int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
-    if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
-    rc = check_state(alt, prm, "alt");
-    if (rc) return rc;
-    if (alt->cap != st->cap || alt->prec != st->prec)
-        return fail(SPH_EINVAL, "alt must match state in cap and precision");
-    if (nsteps < 0) return fail(SPH_EINVAL, "nsteps < 0");
-    launch_spread(c.k, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.rebin), c.s);
-    for (int32_t s = 0; s < nsteps; ++s)
-        one_step(c, st, alt, nl, out, drag_hist ? drag_hist + 3 * int64_t(s) : nullptr, nullptr,
-                 nullptr);
-    if (nsteps > 0) launch_finish_spawn(c.k, dev_state(st), at<int32_t>(ws, c.w.nspawn), c.s);
-    return check_hip("sph_step");
+    return step_on_workspace(prm, st, alt, nl, out, nsteps, drag_hist, ws, ws_bytes, stream);
 }
 
 int sph_step_record(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,

@@ -78,4 +78,10 @@ void launch_adj_finish(const Dev &k, const DevState &m, const DevState &pre,
 void launch_profile_grad(const Dev &k, const int64_t *n, const DevLam &L, const int32_t *index,
                          int32_t ntheta, double *grad, hipStream_t s);
 
+// entry-point internals shared by the C ABI's source files
+int step_on_workspace(const sph_params *prm, sph_state *st, sph_state *alt, sph_nlist *nl,
+                      sph_derived *out, int32_t nsteps, double *drag_hist, void *ws,
+                      size_t ws_bytes, void *stream);
+int api_error(int code, const char *msg);  // sets sph_last_error()'s message, returns code
+
 }  // namespace sph
