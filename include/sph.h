@@ -65,9 +65,17 @@ enum {
  * (the reverse passes use the kernel's own derivatives).
  * SPH_FLAG_MIRROR_INLET gives inlet particles the pressure mirrored from the
  * fluid (Sec. 3 with Sec. 3.2, as SPH_OUTLET_MIRROR describes, pressure
- * only) instead of the characteristic J3 (forward only). */
+ * only) instead of the characteristic J3 (forward only). SPH_FLAG_NO_TILES
+ * keeps the neighbour search and the force pass on their gather kernels
+ * (neighbours read from global memory row by row) where the library would
+ * otherwise stage each tile of cells and its halo in LDS; both produce the
+ * same neighbour table and the same values. The library stages tiles where a
+ * tile's halo is expected to fit its LDS capacity at lattice density;
+ * SPH_FLAG_TILES uses them whatever the expected fill (halo rows past the
+ * capacity are then read from global memory). */
 enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8,
-       SPH_FLAG_QUINTIC = 16, SPH_FLAG_MIRROR_INLET = 32 };
+       SPH_FLAG_QUINTIC = 16, SPH_FLAG_MIRROR_INLET = 32, SPH_FLAG_NO_TILES = 64,
+       SPH_FLAG_TILES = 128 };
 
 /* sph_params.outlet: how outlet particles get their values and move. Every
  * rule advects outlet particles along x only; u, p are those of the rule, ut = u.
@@ -196,6 +204,22 @@ typedef struct sph_derived {
  * list_cap (or the automatic count) entries per particle, the FP32 force
  * pass's packed neighbour records, error word); the same for both precisions. */
 int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
+
+/* Launch configuration the library derives from the parameters for a
+ * capacity and precision (no GPU needed): the cell grid; whether the
+ * neighbour search and the force pass stage each tile of cells and its halo
+ * in LDS (tiles = 1) or gather neighbours from global memory; the tile extent
+ * and halo size in cells; the lanes per target of the force pass and of the
+ * search; whether the step path keeps candidate lists between sorts. */
+typedef struct sph_launch_info {
+    int32_t cells[3];
+    int32_t tiles;
+    int32_t tile_cells[3];
+    int32_t halo_cells;
+    int32_t group_force, group_search;
+    int32_t lists;
+} sph_launch_info;
+int sph_launch_config(const sph_params *prm, int64_t cap, int32_t prec, sph_launch_info *out);
 
 /* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D; with
  * SPH_FLAG_QUINTIC 1.6 times the lattice count of the 3h ball plus 12, in

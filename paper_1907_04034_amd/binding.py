@@ -25,7 +25,7 @@ EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors
             "sph_rhs_adjoint", "sph_outlet_extrapolate_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
             "sph_step_adjoint", "sph_step_record_store", "sph_step_adjoint_stored",
             "sph_inlet_profile_grad", "sph_poll_error", "sph_live_count", "sph_last_error",
-            "sph_step_static"]
+            "sph_step_static", "sph_launch_config"]
 EV_PUSH, EV_TO_OUTLET, EV_DELETE, EV_SPAWN = 1, 2, 4, 8
 FLAG_REUSE_BINS = 8
 
@@ -46,6 +46,12 @@ class SphParams(C.Structure):
 
 
 _P = C.c_void_p
+
+
+class SphLaunchInfo(C.Structure):
+    _fields_ = [("cells", C.c_int32 * 3), ("tiles", C.c_int32), ("tile_cells", C.c_int32 * 3),
+                ("halo_cells", C.c_int32), ("group_force", C.c_int32),
+                ("group_search", C.c_int32), ("lists", C.c_int32)]
 
 
 class SphState(C.Structure):
@@ -110,6 +116,7 @@ def lib():
         L.sph_force.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_step.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, sz, _P]
         L.sph_step_static.argtypes = [SP, ST, ST, NL, DE, C.c_int32, _P, _P, _P]
+        L.sph_launch_config.argtypes = [SP, C.c_int64, C.c_int32, C.POINTER(SphLaunchInfo)]
         L.sph_rhs_adjoint.argtypes = [SP, ST, NL, DE, C.POINTER(SphAdjoint), _P, sz, _P]
         L.sph_outlet_extrapolate_adjoint.argtypes = L.sph_rhs_adjoint.argtypes
         LA = C.POINTER(SphStateAdjoint)
@@ -157,6 +164,17 @@ def make_params(prm):
     q.list_cap = int(prm.get("list_cap", 0))
     q.outlet = int(prm.get("outlet", 0))
     return q
+
+
+def launch_config(prm, cap, prec="fp64"):
+    """The launch configuration the library derives (dict; no GPU needed)."""
+    q = make_params(prm)
+    out = SphLaunchInfo()
+    _check(lib().sph_launch_config(C.byref(q), int(cap), FP64 if prec == "fp64" else FP32,
+                                   C.byref(out)), "sph_launch_config")
+    return dict(cells=tuple(out.cells), tiles=bool(out.tiles), tile_cells=tuple(out.tile_cells),
+                halo_cells=out.halo_cells, group_force=out.group_force,
+                group_search=out.group_search, lists=bool(out.lists))
 
 
 def workspace_size(prm, cap):

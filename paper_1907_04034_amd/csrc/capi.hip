@@ -161,6 +161,42 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         // (0.936 -> 0.942 ms)
         k->lists = (p->dim == 3 || cap < 300000 || prec == SPH_FP64) ? 1 : 0;
     }
+    {
+        // LDS tiles of the pair passes: the first tb key bits of the
+        // interleaving (2 x 2 x 2 cells in 3D, 4 x 4 in 2D), used where the
+        // halo of a tile is expected, at lattice density, to fit the LDS
+        // capacity of both pair passes
+        int tb = p->dim == 3 ? 3 : 4;
+        if (tb > total_bits) tb = total_bits;
+        int e[3] = {0, 0, 0};
+        int maxb = 0;
+        for (int a = 0; a < p->dim; ++a) maxb = k->bits[a] > maxb ? k->bits[a] : maxb;
+        int pos = 0;
+        for (int b = 0; b < maxb && pos < tb; ++b)
+            for (int a = 0; a < p->dim && pos < tb; ++a)
+                if (b < k->bits[a]) {
+                    ++e[a];
+                    ++pos;
+                }
+        k->tb = tb;
+        k->nhalo = 1;
+        double rows_per_cell = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            k->text[a] = a < p->dim ? (1 << e[a]) : 1;
+            k->hext[a] = a < p->dim ? k->text[a] + 2 : 1;
+            k->nhalo *= k->hext[a];
+            if (a < p->dim) rows_per_cell *= k->cs[a] / p->dx;
+        }
+        k->ntiles = int64_t(k->nkeys) >> tb;
+        const double expect = k->nhalo * rows_per_cell;
+        // (the smaller FP64 capacity for both precisions: the workspace
+        // layout, which the choice changes, does not depend on the precision)
+        const int cap_s = tile_cap_search(p->dim), cap_f = tile_cap_force(p->dim, SPH_FP64);
+        const int cap = cap_s < cap_f ? cap_s : cap_f;
+        k->tiles = !(p->flags & SPH_FLAG_NO_TILES) && k->nhalo <= kHaloCellsMax &&
+                   (expect <= 0.95 * cap || (p->flags & SPH_FLAG_TILES));
+        if (k->tiles) k->lists = 0;  // the tiled search walks the stencil from LDS
+    }
     k->x_inlet = p->x_inlet;
     k->x_outlet = p->x_outlet;
     k->x_outlet_end = p->x_outlet_end;
@@ -425,7 +461,8 @@ static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields 
 {
     const int want = drag || hist;
     launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), c.der(o), off ? off : c.off(),
-                 at<uint32_t>(c.ws, c.w.cpos_s), mode, want, c.dragpart(),
+                 at<uint32_t>(c.ws, c.w.cpos_s), at<uint32_t>(c.ws, c.w.spread),
+                 at<int32_t>(c.ws, c.w.cell_start), mode, want, c.dragpart(),
                  at<double>(c.ws, c.w.xbin), at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
     if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
 }
@@ -569,6 +606,24 @@ int32_t sph_default_maxnb(const sph_params *prm)
         return m < 32 ? 32 : (m > 1024 ? 1024 : m);
     }
     return prm && prm->dim == 3 ? 80 : 32;
+}
+
+int sph_launch_config(const sph_params *prm, int64_t cap, int32_t prec, sph_launch_info *out)
+{
+    if (!out) return fail(SPH_EINVAL, "out is NULL");
+    Dev k;
+    int rc = make_dev(prm, cap, prec, 1, &k);
+    if (rc) return rc;
+    for (int d = 0; d < 3; ++d) {
+        out->cells[d] = k.nc[d];
+        out->tile_cells[d] = k.text[d];
+    }
+    out->tiles = k.tiles;
+    out->halo_cells = k.nhalo;
+    out->group_force = force_group(k);
+    out->group_search = nbr_group(k);
+    out->lists = k.lists;
+    return SPH_OK;
 }
 
 int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes)

@@ -13,108 +13,10 @@
 // (the neighbours of one target are contiguous, one coalesced load per group)
 // and the block -> particle-range mapping is XCD-aware so that each of the 8
 // XCDs works on a contiguous slab and its L2 serves the neighbour re-reads.
+#include "pair_terms.h"
 #include "sph_launch.h"
 
 namespace sph {
-
-// ----------------------------------------------------------------- helpers
-template <int DIM>
-struct Grp {
-    static constexpr int G = DIM == 2 ? 16 : 32;   // lanes per target
-    static constexpr int NS = DIM == 2 ? 9 : 27;   // stencil cells
-    static constexpr int PER_BLOCK = kBlock / G;   // targets per block
-};
-
-// Lanes per target of the neighbour search and the force pass are template
-// parameters: many lanes per target keep small systems busy (every gather of
-// a target in flight at once), few lanes (down to one) spend no issue slots on
-// idle lanes and cross-lane reductions when the particle count alone fills
-// the chip. The host picks them from the capacity (override in sph_params).
-
-// Error-free addition (Knuth TwoSum): s + e == a + b exactly.
-__device__ inline void two_sum(float a, float b, float &s, float &e)
-{
-    s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
-// Per-lane accumulator and its group reduction: plain sums in FP64; in FP32
-// a value plus its running rounding error, carried through the reduction.
-template <typename T>
-struct Acc {
-    T s = T(0);
-    __device__ inline void add(T v) { s += v; }
-    template <int G>
-    __device__ inline T reduce() { return gsum<G>(s); }
-};
-
-template <>
-struct Acc<float> {
-    float s = 0.f, e = 0.f;
-    __device__ inline void add(float v)
-    {
-        float t;
-        two_sum(s, v, s, t);
-        e += t;
-    }
-    template <int G>
-    __device__ inline float reduce()
-    {
-#pragma unroll
-        for (int m = G / 2; m > 0; m >>= 1) {
-            float os = __shfl_xor(s, m, G), oe = __shfl_xor(e, m, G), t;
-            two_sum(s, os, s, t);
-            e = e + oe + t;
-        }
-        return s + e;
-    }
-};
-
-// Writes the neighbour record of row i (lanes of the group split the 16-byte
-// chunks): the stage's position (FP64) or cell offset (FP32, the same value
-// as the offset array), p, u, w = ut - u, rho, V, the kind and in FP32 the
-// packed cell.
-template <int DIM, typename T, int G>
-__device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &R, void *rec,
-                                 int64_t i, T S, const double xi[3], const int c[3],
-                                 uint32_t cposi, int lane)
-{
-    using L = Rec<DIM, T>;
-    const int64_t C = k.cap;
-    T v[L::NC * L::PER];
-#pragma unroll
-    for (int q = 0; q < L::NC * L::PER; ++q) v[q] = T(0);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        if constexpr (L::F32)
-            v[L::X + d] = T(float(xi[d] - (k.lo[d] + double(c[d]) * k.cs[d])));
-        else
-            v[L::X + d] = T(xi[d]);
-        const T u = ld<T>(R.u, d * C + i);
-        v[L::U + d] = u;
-        v[L::W + d] = ld<T>(R.ut, d * C + i) - u;
-    }
-    v[L::P] = ld<T>(R.p, i);
-    if constexpr (L::PACKED) {
-        v[L::VOL] = S;
-        v[L::AUX] = rec_word<T>(cposi | (kind_class(m.type[i]) << 30));
-    } else if constexpr (L::F32) {
-        v[L::RHO] = T(k.mass) * S;
-        v[L::VOL] = T(1) / S;
-        v[L::AUX] = rec_word<T>(cposi);
-        v[L::AUX + 1] = rec_word<T>(uint32_t(m.type[i]));
-    } else {
-        v[L::RHO] = T(k.mass) * S;
-        v[L::VOL] = T(1) / S;
-        v[L::AUX] = rec_word<T>(uint32_t(m.type[i]));
-    }
-    using V = typename Chunk<T>::V;
-    V *dst = reinterpret_cast<V *>(static_cast<T *>(rec) + i * L::N);
-#pragma unroll
-    for (int ch = 0; ch < L::NC; ++ch)
-        if ((ch & (G - 1)) == (lane & (G - 1))) dst[ch] = Chunk<T>::make(v + ch * L::PER);
-}
 
 // ---------------------------------------------- neighbour table + density
 // The 3^d stencil cells, taken in (dz, dy, dx) order and each in member
@@ -865,298 +767,6 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
     }
 }
 
-// ------------------------------------------------------------ stage updates
-// Cell skin along axis d. The neighbour search finds every pair within 2h as
-// long as each particle stays within disp_max of the position it had at the
-// last sort (cells are at least 2h + 2 disp_max wide). Half update (mode 1):
-// the stage-1 position xs and the half position v must stay inside, else an
-// error. Full update (mode 2, bin reuse only): ask the next bin to sort unless
-// the new position plus one more step's displacement (from the start value
-// x0) stays inside.
-__device__ inline void skin_check(const Dev &k, int d, int mode, double xs, double v, double x0,
-                                  double xb, int32_t *rebin, uint32_t *err)
-{
-#pragma clang fp contract(off)
-    if (mode == 1) {
-        const double ds = min_image(xs - xb, k.periodic[d], k.L[d], k.halfL[d]);
-        const double dh = min_image(v - xb, k.periodic[d], k.L[d], k.halfL[d]);
-        if (!(fabs(ds) <= k.disp_max && fabs(dh) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
-    } else if (k.reuse) {
-        const double db = min_image(v - xb, k.periodic[d], k.L[d], k.halfL[d]);
-        const double dn = min_image(v - x0, k.periodic[d], k.L[d], k.halfL[d]);
-        if (!(fabs(db) + fabs(dn) <= k.disp_max)) *rebin = 1;
-    }
-}
-
-
-// Explicit-midpoint RK2 (the integrator is the implementation's reading; the
-// paper defers time stepping to the EDAC paper) with eq:transport-vel applied
-// per stage and eq:advection for positions. Contraction is off so that the
-// update evaluates the formula as written. Every load comes before the first
-// store: the stores could alias the arrays read as far as the compiler knows,
-// and a load placed after a store waits for it.
-template <int DIM, typename T>
-__device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &W, int64_t i,
-                                   int mode, const T ui[3], T pi, const T a[3], const T b[3],
-                                   T pd, const double *xbin, int32_t *rebin, uint32_t *err)
-{
-#pragma clang fp contract(off)
-    const int64_t C = k.cap;
-    const double dt = mode == 2 ? k.dt : k.hdt;
-    // stage position xs, start position xw (full update), skin reference xb,
-    // start velocity u0 and, in the full update, the half-state advection
-    // velocity and start pressure
-    double xs[3] = {0, 0, 0}, xw[3] = {0, 0, 0}, xb[3] = {0, 0, 0}, u0[3] = {0, 0, 0},
-           uth[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        xs[d] = R.x[d * C + i];
-        xb[d] = xbin[d * C + i];
-        if (mode == 2) {
-            xw[d] = W.x[d * C + i];
-            u0[d] = double(ld<T>(W.u, d * C + i));
-            uth[d] = double(ld<T>(R.ut, d * C + i));
-        } else {
-            u0[d] = double(ui[d]);
-        }
-    }
-    const double p0 = mode == 2 ? double(ld<T>(W.p, i)) : double(pi);
-    bool fin = true;
-    double xn[3] = {0, 0, 0}, un[3] = {0, 0, 0}, utn[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const double x0 = mode == 2 ? xw[d] : xs[d];
-        un[d] = u0[d] + dt * double(a[d]);
-        utn[d] = un[d] + dt * double(b[d]);
-        const double adv = mode == 2 ? uth[d] : utn[d];
-        xn[d] = x0 + dt * adv;
-        fin = fin && isfinite(un[d]) && isfinite(utn[d]);
-    }
-    const double pn = p0 + dt * double(pd);
-    fin = fin && isfinite(pn);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double v = xn[d];
-        if (k.periodic[d]) {
-            const double hi = k.lo[d] + k.L[d];
-            if (v >= hi) v -= k.L[d];
-            else if (v < k.lo[d]) v += k.L[d];
-        }
-        skin_check(k, d, mode, xs[d], v, mode == 2 ? xw[d] : 0.0, xb[d], rebin, err);
-        fin = fin && isfinite(v);
-        W.x[d * C + i] = v;
-        st<T>(W.u, d * C + i, T(un[d]));
-        st<T>(W.ut, d * C + i, T(utn[d]));
-    }
-    st<T>(W.p, i, T(pn));
-    if (!fin) raise_error(err, SPH_ERR_NONFINITE);
-}
-
-// Inlet rows move with their prescribed velocity and outlet rows along x with
-// the speed of their rule (Sec. 3.4: no transverse motion); walls are fixed.
-// The full update also makes the half state's boundary values the step's.
-template <int DIM, typename T>
-__device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fields &R,
-                                      const Fields &W, int64_t i, int t, int mode,
-                                      const double *jcur, const double *xbin, int32_t *rebin,
-                                      uint32_t *err)
-{
-#pragma clang fp contract(off)
-    const int64_t C = k.cap;
-    const double dt = mode == 2 ? k.dt : k.hdt;
-    // outlet rules other than the hybrid and a mirrored inlet keep (part of)
-    // the start values: the half state carries them into stage 2
-    const bool keep = mode == 1 && ((t == SPH_OUTLET && k.outlet != SPH_OUTLET_HYBRID) ||
-                                    (t == SPH_INLET && (k.flags & SPH_FLAG_MIRROR_INLET)));
-    const bool copy = mode == 2 || keep;  // u, ut, p of R carried into W
-    const bool moves = t == SPH_INLET || t == SPH_OUTLET;
-    // every load before the first store (as in stage_fluid)
-    double x0[3] = {0, 0, 0};
-    T uc[3] = {T(0), T(0), T(0)}, utc[3] = {T(0), T(0), T(0)}, pc = T(0);
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        x0[d] = mode == 2 ? W.x[d * C + i] : R.x[d * C + i];
-        if (copy) {
-            uc[d] = ld<T>(R.u, d * C + i);
-            utc[d] = ld<T>(R.ut, d * C + i);
-        }
-    }
-    if (copy) pc = ld<T>(R.p, i);
-    double vx = 0.0, xs0 = 0.0, xb0 = 0.0;
-    if (moves) {
-        // outlet speed: its own x velocity, or the extrapolated fluid
-        // velocity of the modified do-nothing rule
-        vx = t == SPH_INLET ? m.uin[i]
-             : k.outlet == SPH_OUTLET_MOD_DO_NOTHING ? jcur[i]
-                                                     : double(ld<T>(R.u, i));
-        xs0 = R.x[i];
-        xb0 = xbin[i];
-    }
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        double v = x0[d];
-        if (d == 0 && moves) {
-            v = x0[0] + dt * vx;
-            skin_check(k, 0, mode, xs0, v, x0[0], xb0, rebin, err);
-            if (!isfinite(v)) raise_error(err, SPH_ERR_NONFINITE);
-        }
-        W.x[d * C + i] = v;
-        if (copy) {
-            st<T>(W.u, d * C + i, uc[d]);
-            st<T>(W.ut, d * C + i, utc[d]);
-        }
-    }
-    if (copy) st<T>(W.p, i, pc);
-}
-
-// One neighbour's data as a lane of the force pass needs it.
-template <int DIM, typename T>
-struct Nbr {
-    int32_t j;
-    int tj;
-    T r[3], r2, u[3], w[3], p, rho, vol;  // w = ut - u
-};
-
-// One neighbour's data: FP32 from its record (Rec) in a few 16-byte loads;
-// FP64 one load per field from the state and derived arrays (measured: the
-// 128- and 80-byte FP64 records made the force pass slower, 1.93 -> 2.11 ms
-// on the 4.6M-particle duct, while FP32 records cut it 1.67 -> 1.23 ms).
-// fetch_nbr only issues the loads and finish_nbr does the arithmetic on them,
-// so a lane that prefetches several neighbours issues every fetch before the
-// first finish and their gathers overlap (a separation computed right after
-// its loads makes the next neighbour's loads wait for them).
-template <int DIM, typename T>
-struct NbrRaw {
-    using L = Rec<DIM, T>;
-    T v[L::F32 ? L::NC * L::PER : 1];  // FP32: the record
-    double xj[3];                      // FP64: the fields
-    T u[3], ut[3], p, rho, vol;
-    int tj;
-    int32_t j;
-};
-
-template <int DIM, typename T>
-__device__ inline void fetch_nbr(const Dev &k, const DevState &m, const Fields &R,
-                                 const DevDerived &o, int32_t j, NbrRaw<DIM, T> &w)
-{
-    using L = Rec<DIM, T>;
-    w.j = j;
-    if constexpr (L::F32) {
-        using V = typename Chunk<T>::V;
-        const V *src =
-            reinterpret_cast<const V *>(static_cast<const T *>(o.rec) + int64_t(j) * L::N);
-#pragma unroll
-        for (int ch = 0; ch < L::NC; ++ch) Chunk<T>::get(src[ch], w.v + ch * L::PER);
-    } else {
-        const int64_t C = k.cap;
-        w.tj = m.type[j];
-        w.xj[2] = 0.0;
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            w.xj[d] = R.x[d * C + j];
-            w.u[d] = ld<T>(R.u, d * C + j);
-            w.ut[d] = ld<T>(R.ut, d * C + j);
-        }
-        w.p = ld<T>(R.p, j);
-        w.rho = ld<T>(o.rho, j);
-        w.vol = ld<T>(o.vol, j);
-    }
-}
-
-template <int DIM, typename T>
-__device__ inline void finish_nbr(const Dev &k, const Sep<DIM, T> &sep, const NbrRaw<DIM, T> &w,
-                                  Nbr<DIM, T> &nb)
-{
-    using L = Rec<DIM, T>;
-    nb.j = w.j;
-    if constexpr (L::F32) {
-        const T *v = w.v;
-        if constexpr (L::PACKED) {
-            const uint32_t word = rec_uint<T>(v[L::AUX]);
-            nb.tj = class_kind(word >> 30);
-            nb.r2 = sep.get_rec(k, v + L::X, word & kCellBits, nb.r);
-            const T S = v[L::VOL];
-            nb.rho = T(k.mass) * S;
-            nb.vol = T(1) / S;
-        } else {
-            nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
-            nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
-            nb.rho = v[L::RHO];
-            nb.vol = v[L::VOL];
-        }
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            nb.u[d] = v[L::U + d];
-            nb.w[d] = v[L::W + d];
-        }
-        nb.p = v[L::P];
-    } else {
-        nb.tj = w.tj;
-        nb.r2 = dist2_exact<DIM>(k, sep.xi, w.xj, nb.r);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            nb.u[d] = w.u[d];
-            nb.w[d] = w.ut[d] - w.u[d];
-        }
-        nb.p = w.p;
-        nb.rho = w.rho;
-        nb.vol = w.vol;
-    }
-}
-
-template <int DIM, typename T>
-__device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R,
-                                const DevDerived &o, const Sep<DIM, T> &sep, int32_t j,
-                                Nbr<DIM, T> &nb)
-{
-    NbrRaw<DIM, T> w;
-    fetch_nbr<DIM, T>(k, m, R, o, j, w);
-    finish_nbr<DIM, T>(k, sep, w, nb);
-}
-
-// Contribution of neighbour nb to target i (see the force-pass comment).
-template <int DIM, typename T>
-__device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3], T pi, T rhoi,
-                                T vi2, T pavg, const Nbr<DIM, T> &nb, Acc<T> acc[3],
-                                Acc<T> bacc[3], Acc<T> &pdot, double fb[3])
-{
-    const T F = kernel_f<T>(k, T(sqrt(nb.r2)) * T(k.inv_h), T(k.gnorm));
-    T gw[3] = {0, 0, 0};
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) gw[d] = F * nb.r[d];
-    const T vsq = vi2 + nb.vol * nb.vol;
-    const T inv_rs = T(1) / (rhoi + nb.rho);
-    const T ptil = (nb.rho * (pi - pavg) + rhoi * (nb.p - pavg)) * inv_rs;
-    const T hm = T(2) * rhoi * nb.rho * inv_rs;  // eta~ / nu
-    const T dfac = F * nb.r2 / (nb.r2 + T(k.eta_h2));
-    const T nu = T(k.nu);
-    if (t == SPH_FLUID) {
-        T si = T(0), sj = T(0);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) si += wi[d] * gw[d];
-        if (nb.tj == SPH_FLUID)
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) sj += nb.w[d] * gw[d];
-        const T visc = nb.tj == SPH_WALL_SLIP ? T(0) : hm * nu * dfac;
-        const T f = vsq * T(k.inv_mass);
-        const bool wall = is_wall(nb.tj);
-        T udiv = T(0);
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            const T aterm = T(0.5) * (rhoi * ui[d] * si + nb.rho * nb.u[d] * sj);
-            acc[d].add(f * (-ptil * gw[d] + aterm + visc * (ui[d] - nb.u[d])));
-            bacc[d].add(-T(k.pb) * T(k.inv_mass) * vsq * gw[d]);
-            udiv += (ui[d] - (wall ? T(0) : nb.u[d])) * gw[d];
-        }
-        pdot.add(T(k.mass) * rhoi / nb.rho * T(k.c2) * udiv +
-                 f * (hm * T(k.nu_damp)) * dfac * (pi - nb.p));
-    } else {
-#pragma unroll
-        for (int d = 0; d < DIM; ++d)
-            fb[d] += double(vsq * (-ptil * gw[d] + hm * nu * dfac * (ui[d] - nb.u[d])));
-    }
-}
-
 // ---------------------------------------------------------------- force pass
 // Fluid i: pbar_i (eq:pavg, self included), then over j != i the momentum
 // rate of eq:tvf-momentum with p~_ij of eq:tvf-p-ij-basa, the background term
@@ -1407,10 +1017,14 @@ static int pick(int override, int64_t cap, int small, int large)
 
 int force_group(const Dev &k) { return pick(k.g_force, k.cap, k.dim == 2 ? 4 : 8, 4); }
 int nbr_group(const Dev &k) { return pick(k.g_nbr, k.cap, 8, k.lists ? 8 : (k.dim == 2 ? 2 : 4)); }
-int force_grid(const Dev &k) { return grid_for(k, force_group(k)); }
+int force_grid(const Dev &k) { return k.tiles ? tile_grid(k) : grid_for(k, force_group(k)); }
 // the most blocks any variant launches (fewest targets per block): sizes the
 // per-block drag partials
-int force_grid_max(const Dev &k) { return grid_for(k, 32); }
+int force_grid_max(const Dev &k)
+{
+    const int g = grid_for(k, 32);
+    return k.tiles && tile_grid(k) > g ? tile_grid(k) : g;
+}
 
 // Lanes per boundary row and grid cap of the boundary pass (grid-stride over
 // the device-side count of boundary rows; blocks past the count exit at
@@ -1502,6 +1116,10 @@ void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevN
                     int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
                     hipStream_t s)
 {
+    if (k.tiles) {
+        launch_tsearch(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err, s);
+        return;
+    }
     if (k.dim == 2 && k.prec == SPH_FP64)
         nbrdens_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, v,
                               vmode, err, s);
@@ -1577,9 +1195,15 @@ static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fie
 
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
-                  const uint32_t *cpos, int mode, int want_drag, double *dragpart,
-                  const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s)
+                  const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
+                  int mode, int want_drag, double *dragpart, const double *xbin,
+                  int32_t *rebin, uint32_t *err, hipStream_t s)
 {
+    if (k.tiles) {
+        launch_tforce(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,
+                      dragpart, xbin, rebin, err, s);
+        return;
+    }
     if (k.dim == 2 && k.prec == SPH_FP64)
         force_dt<2, double>(k, m, R, W, nl, o, off, cpos, mode, want_drag, dragpart, xbin, rebin,
                             err, s);

@@ -35,10 +35,29 @@ struct Dev {
     double rv2;  // squared radius of the step path's candidate lists
     int vmax;    // candidate-list entries per particle
     int lists;   // the step path keeps candidate lists (else it searches the stencil)
+    // LDS tiles of the pair passes: a tile is an aligned block of 2^tb Morton
+    // keys, a box of text[a] cells per axis; its halo (the tile grown by one
+    // cell on every side) holds every neighbour of the tile's rows
+    int tiles;          // 1: the neighbour search and force pass use the tiled kernels
+    int tb;             // key bits per tile
+    int text[3];        // tile extent per axis (cells)
+    int hext[3];        // halo extent per axis (text + 2)
+    int nhalo;          // halo cells per tile (product of hext)
+    int64_t ntiles;     // nkeys >> tb
     double x_inlet, x_outlet, x_outlet_end, inlet_len, pgate, U, noise_amp;
     uint64_t noise_seed;
     float hf, inv_hf, sup2f, wnormf, gnormf, massf, c2f, nuf, nu_dampf, eta_h2f, pbf;
 };
+
+// LDS capacity of the tiled kernels, in halo rows (rows past it are read
+// from global memory): the search stages FP64 positions, the force pass the
+// FP32 neighbour record or the FP64 fields x, u, ut, p, rho, V and the kind.
+constexpr int kHaloCellsMax = 128;
+__host__ __device__ constexpr int tile_cap_search(int dim) { return dim == 3 ? 1024 : 512; }
+__host__ __device__ constexpr int tile_cap_force(int dim, int prec)
+{
+    return prec == SPH_FP32 ? (dim == 3 ? 1024 : 512) : (dim == 3 ? 768 : 384);
+}
 
 // Device pointers of one state (element type of the real fields depends on
 // the precision).

@@ -51,8 +51,23 @@ void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const Dev
                      hipStream_t s);
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
-                  const uint32_t *cpos, int mode, int want_drag, double *dragpart,
-                  const double *xbin, int32_t *rebin, uint32_t *err, hipStream_t s);
+                  const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
+                  int mode, int want_drag, double *dragpart, const double *xbin,
+                  int32_t *rebin, uint32_t *err, hipStream_t s);
+int nbr_group(const Dev &k);
+
+// LDS-tiled pair passes (Dev::tiles): same arguments and results as the
+// gather kernels launched by launch_nbrdens (stencil walk) and launch_force
+int tile_grid(const Dev &k);
+void launch_tsearch(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                    const DevDerived &o, int dens, const uint32_t *spread,
+                    const int32_t *cell_start, const uint32_t *cpos, float *off,
+                    int32_t *rebin_clear, uint32_t *err, hipStream_t s);
+void launch_tforce(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
+                   const DevNlist &nl, const DevDerived &o, const float *off,
+                   const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
+                   int mode, int want_drag, double *dragpart, const double *xbin,
+                   int32_t *rebin, uint32_t *err, hipStream_t s);
 void launch_drag_final(const Dev &k, const double *dragpart, double *drag, double *hist,
                        hipStream_t s);
 
