@@ -241,7 +241,8 @@ int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws,
  * in FP64 without fused multiply-add, minimum image on periodic axes. If out
  * is not NULL the summation density of sph_density is written from the same
  * pairs. Particles must not have moved more than the cell skin since the bin
- * (sph_step checks this on the device). */
+ * (sph_step checks this on the device). With LDS tiles the table holds at
+ * most sph_default_maxnb entries per row (a deeper nl is rejected). */
 int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph_derived *out,
                   void *ws, size_t ws_bytes, void *stream);
 
@@ -267,7 +268,10 @@ int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist
 /* One right-hand side: sph_density, sph_outlet_extrapolate, then the force
  * pass of Sec. 2 (eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum, eq:p-edac and
  * the background term of eq:transport-vel) for fluid particles and the body
- * force of Sec. 4.6 eq:tvf-momentum_solid, reduced into out->drag. */
+ * force of Sec. 4.6 eq:tvf-momentum_solid, reduced into out->drag. nl must be
+ * the table the last sph_neighbors on this workspace wrote, unchanged: with
+ * LDS tiles (sph_launch_config) the force pass reads the LDS slot of each of
+ * its entries, which that search keeps in the workspace. */
 int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_derived *out,
             void *ws, size_t ws_bytes, void *stream);
 
@@ -278,7 +282,8 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
  * change in between): eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
  * eq:p-edac and the background term of eq:transport-vel for fluid particles;
  * eq:tvf-momentum_solid for body particles, reduced into out->drag (skipped
- * when out->drag is NULL, so that the call is exactly one kernel launch). */
+ * when out->drag is NULL, so that the call is exactly one kernel launch).
+ * As for sph_rhs, nl must be the last sph_neighbors table of this workspace. */
 int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
               sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 

@@ -405,6 +405,9 @@ void launch_bin(const Dev &k, const DevState &a, const DevState &b, const BinBuf
         hipLaunchKernelGGL((k_gather<3, float>), gg, blk, 0, s, k, a, b, w.tmp, w.cell_start,
                            w.cpos, w.cpos_s, w.blist, w.bcount, w.nspawn, w.rebin, w.xbin,
                            w.vfresh);
+    // tile records of the LDS-tiled pair passes (only when this bin sorted)
+    if (k.tiles)
+        launch_tile_table(k, a.n, w.cell_start, w.spread, w.cpos_s, w.vfresh, w.ttab, err, s);
 }
 
 }  // namespace sph

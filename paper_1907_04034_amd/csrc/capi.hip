@@ -46,6 +46,20 @@ namespace sph {
 
 constexpr double pi_d = 3.14159265358979323846;
 
+// Default neighbour-table depth: 32 in 2D and 80 in 3D for Wendland C2; for
+// the quintic spline 1.6 times the lattice count of the 3h ball plus 12, in
+// multiples of 16 (80 in 2D and 336 in 3D at h = 1.2 dx).
+static int32_t default_maxnb(const sph_params *prm)
+{
+    if (prm && (prm->flags & SPH_FLAG_QUINTIC) && prm->h > 0 && prm->dx > 0) {
+        const double R = 3.0 * prm->h / prm->dx;
+        const double ball = prm->dim == 3 ? 4.0 / 3.0 * pi_d * R * R * R : pi_d * R * R;
+        const int m = int(std::ceil((1.6 * ball + 12.0) / 16.0)) * 16;
+        return m < 32 ? 32 : (m > 1024 ? 1024 : m);
+    }
+    return prm && prm->dim == 3 ? 80 : 32;
+}
+
 // Validates the parameter block and derives the kernel constants.
 static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *k)
 {
@@ -196,6 +210,7 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         k->tiles = !(p->flags & SPH_FLAG_NO_TILES) && k->nhalo <= kHaloCellsMax &&
                    (expect <= 0.95 * cap || (p->flags & SPH_FLAG_TILES));
         if (k->tiles) k->lists = 0;  // the tiled search walks the stencil from LDS
+        k->lmax = default_maxnb(p);
     }
     k->x_inlet = p->x_inlet;
     k->x_outlet = p->x_outlet;
@@ -260,6 +275,9 @@ static WsLayout layout(const Dev &k)
     // neighbour records of the FP32 force pass (sized whatever the precision:
     // the workspace size does not depend on it)
     w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, float>()) * C);
+    // LDS slots of the tiled search's table entries, read by the force pass
+    w.lslot = take(k.tiles ? sizeof(uint16_t) * size_t(k.lmax) * C : 0);
+    w.ttab = take(k.tiles ? sizeof(int32_t) * size_t(tile_table_ints(k)) : 0);
     w.total = off;
     return w;
 }
@@ -369,6 +387,7 @@ struct Ctx {
         b.rebin = at<int32_t>(ws, w.rebin);
         b.xbin = at<double>(ws, w.xbin);
         b.vfresh = at<int32_t>(ws, w.vfresh);
+        b.ttab = at<int32_t>(ws, w.ttab);
         return b;
     }
     Fields half() const
@@ -414,6 +433,11 @@ static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws
     if (!ws) return fail(SPH_EINVAL, "workspace is NULL");
     if (ws_bytes < c->w.total)
         return fail(SPH_ECAPACITY, "workspace has %zu bytes, needs %zu", ws_bytes, c->w.total);
+    if (c->k.tiles && maxnb > c->k.lmax)
+        return fail(SPH_EINVAL,
+                    "neighbour table depth %d exceeds %d (sph_default_maxnb), which the LDS-tiled "
+                    "pair passes hold per row; use a shallower table or SPH_FLAG_NO_TILES",
+                    maxnb, c->k.lmax);
     c->ws = ws;
     c->s = static_cast<hipStream_t>(stream);
     return SPH_OK;
@@ -443,6 +467,7 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
     launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? c.der(o) : DevDerived{},
                    dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
                    at<uint32_t>(c.ws, c.w.cpos_s), off ? off : c.off(),
+                   at<uint16_t>(c.ws, c.w.lslot), at<int32_t>(c.ws, c.w.ttab),
                    clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
 }
 
@@ -461,8 +486,8 @@ static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields 
 {
     const int want = drag || hist;
     launch_force(c.k, dev_state(st), R, W, dev_nlist(nl), c.der(o), off ? off : c.off(),
-                 at<uint32_t>(c.ws, c.w.cpos_s), at<uint32_t>(c.ws, c.w.spread),
-                 at<int32_t>(c.ws, c.w.cell_start), mode, want, c.dragpart(),
+                 at<uint32_t>(c.ws, c.w.cpos_s), at<int32_t>(c.ws, c.w.ttab),
+                 at<uint16_t>(c.ws, c.w.lslot), mode, want, c.dragpart(),
                  at<double>(c.ws, c.w.xbin), at<int32_t>(c.ws, c.w.rebin), c.err(), c.s);
     if (want) launch_drag_final(c.k, c.dragpart(), drag, hist, c.s);
 }
@@ -595,18 +620,7 @@ extern "C" {
 
 const char *sph_last_error(void) { return g_err.c_str(); }
 
-int32_t sph_default_maxnb(const sph_params *prm)
-{
-    if (prm && (prm->flags & SPH_FLAG_QUINTIC) && prm->h > 0 && prm->dx > 0) {
-        // 1.6 times the lattice count of the 3h ball plus 12, in multiples of
-        // 16 (80 in 2D and 336 in 3D at h = 1.2 dx)
-        const double R = 3.0 * prm->h / prm->dx;
-        const double ball = prm->dim == 3 ? 4.0 / 3.0 * pi_d * R * R * R : pi_d * R * R;
-        const int m = int(std::ceil((1.6 * ball + 12.0) / 16.0)) * 16;
-        return m < 32 ? 32 : (m > 1024 ? 1024 : m);
-    }
-    return prm && prm->dim == 3 ? 80 : 32;
-}
+int32_t sph_default_maxnb(const sph_params *prm) { return default_maxnb(prm); }
 
 int sph_launch_config(const sph_params *prm, int64_t cap, int32_t prec, sph_launch_info *out)
 {

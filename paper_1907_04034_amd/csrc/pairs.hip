@@ -1113,11 +1113,11 @@ static void nbrdens_dt(const Dev &k, const DevState &m, const Fields &R, const D
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const uint32_t *spread,
                     const int32_t *cell_start, const uint32_t *cpos, float *off,
-                    int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
-                    hipStream_t s)
+                    uint16_t *lslot, const int32_t *ttab, int32_t *rebin_clear, const VList &v,
+                    int vmode, uint32_t *err, hipStream_t s)
 {
     if (k.tiles) {
-        launch_tsearch(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err, s);
+        launch_tsearch(k, m, R, nl, o, dens, ttab, cpos, off, lslot, rebin_clear, err, s);
         return;
     }
     if (k.dim == 2 && k.prec == SPH_FP64)
@@ -1195,13 +1195,13 @@ static void force_dt(const Dev &k, const DevState &m, const Fields &R, const Fie
 
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
-                  const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
-                  int mode, int want_drag, double *dragpart, const double *xbin,
-                  int32_t *rebin, uint32_t *err, hipStream_t s)
+                  const uint32_t *cpos, const int32_t *ttab, const uint16_t *lslot, int mode,
+                  int want_drag, double *dragpart, const double *xbin, int32_t *rebin,
+                  uint32_t *err, hipStream_t s)
 {
     if (k.tiles) {
-        launch_tforce(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,
-                      dragpart, xbin, rebin, err, s);
+        launch_tforce(k, m, R, W, nl, o, off, cpos, ttab, lslot, mode, want_drag, dragpart, xbin,
+                      rebin, err, s);
         return;
     }
     if (k.dim == 2 && k.prec == SPH_FP64)

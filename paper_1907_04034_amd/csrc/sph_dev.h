@@ -44,6 +44,7 @@ struct Dev {
     int hext[3];        // halo extent per axis (text + 2)
     int nhalo;          // halo cells per tile (product of hext)
     int64_t ntiles;     // nkeys >> tb
+    int lmax;           // depth of the tiled search's LDS-slot table (the default table depth)
     double x_inlet, x_outlet, x_outlet_end, inlet_len, pgate, U, noise_amp;
     uint64_t noise_seed;
     float hf, inv_hf, sup2f, wnormf, gnormf, massf, c2f, nuf, nu_dampf, eta_h2f, pbf;
@@ -250,7 +251,7 @@ struct VList {
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, scat, tmp,
         cpos, cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
-        vnbr, rec, total;
+        vnbr, rec, lslot, ttab, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

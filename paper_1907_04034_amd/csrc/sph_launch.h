@@ -16,6 +16,7 @@ struct BinBufs {
     int32_t *rebin;  // 1: the next bin sorts; 0: it keeps the order (Dev::reuse)
     double *xbin;    // [3][cap] positions at the last sort, sorted order
     int32_t *vfresh; // set by the gather: 1 if it sorted
+    int32_t *ttab;   // tile records of the LDS-tiled pair passes (Dev::tiles)
 };
 
 int64_t scan_tiles(int64_t n);
@@ -38,11 +39,13 @@ void launch_copy_rows(const Dev &k, const DevState &a, const DevState &b, const 
 int force_group(const Dev &k);
 int force_grid(const Dev &k);
 int force_grid_max(const Dev &k);
+// lslot: the tiled search's table of LDS slots (workspace, [cap][lmax]);
+// ttab: the tile records (workspace)
 void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const uint32_t *spread,
                     const int32_t *cell_start, const uint32_t *cpos, float *off,
-                    int32_t *rebin_clear, const VList &v, int vmode, uint32_t *err,
-                    hipStream_t s);
+                    uint16_t *lslot, const int32_t *ttab, int32_t *rebin_clear, const VList &v,
+                    int vmode, uint32_t *err, hipStream_t s);
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, const uint32_t *cpos, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
@@ -51,25 +54,30 @@ void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const Dev
                      hipStream_t s);
 void launch_force(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                   const DevNlist &nl, const DevDerived &o, const float *off,
-                  const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
-                  int mode, int want_drag, double *dragpart, const double *xbin,
-                  int32_t *rebin, uint32_t *err, hipStream_t s);
+                  const uint32_t *cpos, const int32_t *ttab, const uint16_t *lslot, int mode,
+                  int want_drag, double *dragpart, const double *xbin, int32_t *rebin,
+                  uint32_t *err, hipStream_t s);
 int nbr_group(const Dev &k);
-
-// LDS-tiled pair passes (Dev::tiles): same arguments and results as the
-// gather kernels launched by launch_nbrdens (stencil walk) and launch_force
-int tile_grid(const Dev &k);
-void launch_tsearch(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
-                    const DevDerived &o, int dens, const uint32_t *spread,
-                    const int32_t *cell_start, const uint32_t *cpos, float *off,
-                    int32_t *rebin_clear, uint32_t *err, hipStream_t s);
-void launch_tforce(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
-                   const DevNlist &nl, const DevDerived &o, const float *off,
-                   const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
-                   int mode, int want_drag, double *dragpart, const double *xbin,
-                   int32_t *rebin, uint32_t *err, hipStream_t s);
 void launch_drag_final(const Dev &k, const double *dragpart, double *drag, double *hist,
                        hipStream_t s);
+
+// LDS-tiled pair passes (Dev::tiles): same arguments and results as the
+// gather kernels launched by launch_nbrdens (stencil walk) and launch_force;
+// table: the tile records k_tile_table writes after every sort
+int tile_grid(const Dev &k);
+int64_t tile_table_ints(const Dev &k);
+void launch_tile_table(const Dev &k, const int64_t *nrows, const int32_t *cell_start,
+                       const uint32_t *spread, const uint32_t *cpos, const int32_t *sorted,
+                       int32_t *table, uint32_t *err, hipStream_t s);
+void launch_tsearch(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
+                    const DevDerived &o, int dens, const int32_t *table, const uint32_t *cpos,
+                    float *off, uint16_t *lslot, int32_t *rebin_clear, uint32_t *err,
+                    hipStream_t s);
+void launch_tforce(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
+                   const DevNlist &nl, const DevDerived &o, const float *off,
+                   const uint32_t *cpos, const int32_t *table, const uint16_t *lslot, int mode,
+                   int want_drag, double *dragpart, const double *xbin, int32_t *rebin,
+                   uint32_t *err, hipStream_t s);
 
 // reverse pass of one right-hand side
 void launch_rhs_adjoint(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

@@ -1,73 +1,91 @@
 // tiles.hip -- LDS-tiled neighbour search and force pass of libsph (gfx950).
 //
-// A block owns one tile: an aligned block of 2^tb Morton keys, i.e. a box of
-// cells (2 x 2 x 2 in 3D, 4 x 4 in 2D) whose rows are contiguous in the
-// sorted state. It reads the row ranges of the tile's halo (the box grown by
-// one cell on every side, which holds every neighbour of every row of the
-// tile), scans their lengths into LDS offsets with one wave, and copies the
-// halo's rows into LDS with coalesced loads: FP64 positions for the search;
-// the packed neighbour record (FP32) or the FP64 fields for the force pass.
-// Groups of G lanes then take the tile's rows in turn and read every
-// neighbour from LDS instead of gathering it row by row from global memory
-// (rows past the LDS capacity are read from global memory).
+// A tile is an aligned block of 2^tb Morton keys, i.e. a box of cells
+// (2 x 2 x 2 in 3D, 4 x 4 in 2D) whose rows are contiguous in the sorted
+// state; its halo (the box grown by one cell on every side) holds every
+// neighbour of every row of the tile. After each sort k_tile_table writes one
+// record per tile: the tile's rows, its first cell, and for every halo cell
+// the first row and the LDS slot of its first row (an exclusive scan of the
+// cell lengths, in halo-index order, x fastest). A block of the pair passes
+// owns one tile: it reads the tile's record in one coalesced load, copies the
+// halo's rows into LDS (a few threads per halo cell, coalesced along the
+// cell's rows): FP64 positions for the search; the packed neighbour record
+// (FP32) or the FP64 fields for the force pass. Groups of G lanes then take
+// the tile's rows in turn and read every neighbour from LDS instead of
+// gathering it row by row from global memory (rows past the LDS capacity are
+// read from global memory).
 //
-// Search: a row's candidates are the members of its 3^d stencil cells in
-// stencil order, walked as one sequence with the FMA-free FP64 predicate and
-// compacted by ballot, so its table row is the gather kernel's row, entry for
-// entry; the density is summed in table order (lane l adds entries l, l + G,
-// ...), as there. Force: a lane's table entries visit the row's stencil cells
-// in order (the table is stencil-then-cell ordered), so a cursor over those
-// cells maps each entry to its LDS slot; the pair terms, their order and the
-// reductions are those of the gather kernel.
+// The three cells of a row's stencil along x are consecutive halo indices and
+// so consecutive LDS slots: the stencil is 9 runs of contiguous slots in 3D
+// (3 in 2D), and walking them in order visits the candidates in
+// stencil-then-cell order.
+//
+// Search: lanes test the candidates of each run in chunks of G with the
+// FMA-free FP64 predicate, and a ballot compacts the hits, so a row's table
+// entries are the gather kernel's, in the same order; the density is summed
+// in table order (lane l adds entries l, l + G, ...), as there. Besides the
+// global row of every entry the search writes its LDS slot (a 16-bit table in
+// the workspace), from which the force pass of the same bin reads each
+// neighbour without looking its row up again; the pair terms, their order
+// and the reductions are those of the gather kernel.
 #include "pair_terms.h"
 #include "sph_launch.h"
 
 namespace sph {
 
-// Halo of one tile, in LDS.
-struct TileHalo {
-    int32_t gbeg[kHaloCellsMax];  // first row of each halo cell (global)
-    int32_t len[kHaloCellsMax];   // rows in it
-    int32_t off[kHaloCellsMax];   // its first LDS slot (exclusive scan of len)
-    int32_t total;                // rows in the halo
-    int32_t r0, r1;               // the tile's own rows
-    int32_t org[3];               // the tile's first cell
-    int32_t ok;                   // 0: empty tile
-};
+// Tile record (int32): [0] first row, [1] end row, [2] packed first cell,
+// [3] halo rows, [4 + c] first row of halo cell c, [4 + nhalo + c] its first
+// LDS slot for c <= nhalo (the last entry is the halo's row count).
+__host__ __device__ constexpr int tile_rec_ints(int nhalo) { return (5 + 2 * nhalo + 3) & ~3; }
+int64_t tile_table_ints(const Dev &k) { return k.ntiles * tile_rec_ints(k.nhalo); }
 
-// Row ranges and LDS offsets of the halo of `tile` (every thread of the block
-// calls it). Returns false, for the whole block, for an empty tile.
+// ------------------------------------------------------------- tile table
+// One wave per tile (two halo cells per lane). Runs after every bin and
+// returns at once when the bin kept the order (the table stays valid).
 template <int DIM>
-__device__ inline bool tile_setup(const Dev &k, int64_t tile, int64_t n,
-                                  const int32_t *cell_start, const uint32_t *spread,
-                                  const uint32_t *cpos, TileHalo &H, uint32_t *err)
+__global__ void __launch_bounds__(kBlock) k_tile_table(Dev k, const int64_t *nrows,
+                                                       const int32_t *cell_start,
+                                                       const uint32_t *spread,
+                                                       const uint32_t *cpos,
+                                                       const int32_t *sorted, int32_t *table,
+                                                       uint32_t *err)
 {
-    const int t = threadIdx.x;
-    if (t == 0) {
-        const int64_t key0 = tile << k.tb;
-        const int32_t a = cell_start[key0], b = cell_start[key0 + (int64_t(1) << k.tb)];
-        const bool sane = a >= 0 && a <= b && int64_t(b) <= n;
-        if (!sane) raise_error(err, SPH_ERR_CELL_RANGE);
-        H.ok = sane && a < b;
-        H.r0 = a;
-        H.r1 = b;
-        if (H.ok) {
-            int c[3] = {0, 0, 0};
-            unpack_cell<DIM>(cpos[a], c);
-#pragma unroll
-            for (int d = 0; d < 3; ++d) H.org[d] = c[d] & ~(k.text[d] - 1);
-        }
+    if (*sorted == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t tile = int64_t(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
+    if (tile >= k.ntiles) return;
+    const int64_t n = *nrows;
+    const int RI = tile_rec_ints(k.nhalo);
+    int32_t *rec = table + tile * RI;
+    const int64_t key0 = tile << k.tb;
+    int32_t a = cell_start[key0], b = cell_start[key0 + (int64_t(1) << k.tb)];
+    if (!(a >= 0 && a <= b && int64_t(b) <= n)) {
+        if (lane == 0) raise_error(err, SPH_ERR_CELL_RANGE);
+        a = b = 0;
     }
-    __syncthreads();
-    if (!H.ok) return false;
-    if (t < k.nhalo) {
+    if (a == b) {  // empty tile: its record says so
+        if (lane == 0) {
+            rec[0] = a;
+            rec[1] = b;
+        }
+        return;
+    }
+    int org[3] = {0, 0, 0};
+    unpack_cell<DIM>(cpos[a], org);
+#pragma unroll
+    for (int d = 0; d < 3; ++d) org[d] &= ~(k.text[d] - 1);
+    int32_t gb[2] = {0, 0}, ln[2] = {0, 0};
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int t = 2 * lane + u;
+        if (t >= k.nhalo) continue;
         const int hx = k.hext[0], hy = k.hext[1];
         const int tt[3] = {t % hx, (t / hx) % hy, t / (hx * hy)};
         int cc[3] = {0, 0, 0};
         bool valid = true;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
-            int v = H.org[d] - 1 + tt[d];
+            int v = org[d] - 1 + tt[d];
             if (v < 0 || v >= k.nc[d]) {
                 // the cell beyond either end wraps on a periodic axis; cells of
                 // the padded key space past it hold no rows
@@ -76,49 +94,111 @@ __device__ inline bool tile_setup(const Dev &k, int64_t tile, int64_t n,
             }
             cc[d] = v;
         }
-        int32_t b = 0, e = 0;
         if (valid) {
             const uint32_t key = morton_key<DIM>(spread, cc);
-            b = cell_start[key];
-            e = cell_start[key + 1];
-            if (b < 0 || b > e || int64_t(e) > n) {
+            const int32_t cb = cell_start[key], ce = cell_start[key + 1];
+            if (cb < 0 || cb > ce || int64_t(ce) > n) {
                 raise_error(err, SPH_ERR_CELL_RANGE);
-                b = e = 0;
+            } else {
+                gb[u] = cb;
+                ln[u] = ce - cb;
             }
         }
-        H.gbeg[t] = b;
-        H.len[t] = e - b;
     }
-    __syncthreads();
-    // exclusive scan of the lengths: one wave, two cells per lane
-    if (t < 64) {
-        const int i0 = 2 * t, i1 = 2 * t + 1;
-        const int v0 = i0 < k.nhalo ? H.len[i0] : 0, v1 = i1 < k.nhalo ? H.len[i1] : 0;
-        int incl = v0 + v1;
+    // exclusive scan of the lengths over the wave
+    const int v0 = ln[0], v1 = ln[1];
+    int incl = v0 + v1;
 #pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const int y = __shfl_up(incl, o);
-            if (t >= o) incl += y;
-        }
-        const int excl = incl - v0 - v1;
-        if (i0 < k.nhalo) H.off[i0] = excl;
-        if (i1 < k.nhalo) H.off[i1] = excl + v0;
-        if (t == 63) H.total = incl;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += y;
     }
+    const int excl = incl - v0 - v1;
+    const int total = __shfl(incl, 63, 64);
+    const int i0 = 2 * lane, i1 = 2 * lane + 1;
+    if (i0 < k.nhalo) {
+        rec[4 + i0] = gb[0];
+        rec[4 + k.nhalo + i0] = excl;
+    }
+    if (i1 < k.nhalo) {
+        rec[4 + i1] = gb[1];
+        rec[4 + k.nhalo + i1] = excl + v0;
+    }
+    if (lane == 0) {
+        rec[0] = a;
+        rec[1] = b;
+        rec[2] = int32_t(pack_cell<DIM>(org));
+        rec[3] = total;
+        rec[4 + 2 * k.nhalo] = total;
+    }
+}
+
+// Tile of hardware block blockIdx.x. The 8 XCDs receive consecutive hardware
+// blocks round-robin; they take chunks of kTileChunk consecutive tiles in turn
+// (XCD x the chunks x, x + 8, ...), so that the tiles of a chunk, which share
+// most of their halos, meet in one L2, and every XCD gets a share of the
+// occupied tiles (a contiguous eighth of the tile index range per XCD would
+// leave some XCDs only the empty padding of the Morton key space). -1 past
+// the last tile.
+constexpr int kTileChunk = 16;
+__device__ inline int64_t tile_of_block(int64_t ntiles)
+{
+    const int64_t b = blockIdx.x, x = b % 8, w = b / 8;
+    const int64_t t = ((w / kTileChunk) * 8 + x) * kTileChunk + w % kTileChunk;
+    return t < ntiles ? t : -1;
+}
+
+// The record of one tile in LDS, with its accessors.
+struct TileHalo {
+    int32_t rec[(5 + 2 * kHaloCellsMax + 3) & ~3];
+    int nh;
+    __device__ inline int r0() const { return rec[0]; }
+    __device__ inline int r1() const { return rec[1]; }
+    __device__ inline int total() const { return rec[3]; }
+    __device__ inline int gbeg(int c) const { return rec[4 + c]; }
+    __device__ inline int off(int c) const { return rec[4 + nh + c]; }  // c <= nh
+    __device__ inline int len(int c) const { return off(c + 1) - off(c); }
+};
+
+// Loads the tile's record (every thread of the block calls it); false, for
+// the whole block, for an empty tile.
+template <int DIM>
+__device__ inline bool tile_load(const Dev &k, int64_t tile, const int32_t *table, TileHalo &H,
+                                 int org[3])
+{
+    const int RI = tile_rec_ints(k.nhalo);
+    const int32_t *src = table + tile * RI;
+    for (int t = threadIdx.x; t < RI; t += kBlock) H.rec[t] = src[t];
+    H.nh = k.nhalo;
     __syncthreads();
+    if (H.r0() >= H.r1()) return false;
+    unpack_cell<DIM>(uint32_t(H.rec[2]), org);
     return true;
 }
 
-// Halo cell holding LDS slot f (the last cell whose offset is <= f).
-__device__ inline int halo_cell_of(const TileHalo &H, int nhalo, int f)
+// Copies the halo's rows into LDS slots below cap: threads in groups per
+// halo cell, each group walking its cell's rows. put(f, j): slot f, row j.
+template <typename Put>
+__device__ inline void tile_stage(const TileHalo &H, int cap, Put put)
 {
-    int lo = 0, hi = nhalo;
+    const int per = kBlock / H.nh;  // threads per halo cell
+    const int t = threadIdx.x;
+    const int c = t / per;
+    if (c >= H.nh) return;
+    const int o = H.off(c), l = H.len(c), g = H.gbeg(c);
+    for (int q = t - c * per; q < l && o + q < cap; q += per) put(o + q, int64_t(g) + q);
+}
+
+// Global row of LDS slot f (any slot below the halo's row count).
+__device__ inline int32_t halo_row(const TileHalo &H, int f)
+{
+    int lo = 0, hi = H.nh;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (H.off[mid] <= f) lo = mid;
+        if (H.off(mid) <= f) lo = mid;
         else hi = mid;
     }
-    return lo;
+    return H.gbeg(lo) + (f - H.off(lo));
 }
 
 // Halo index of stencil cell sc ((dz, dy, dx) order, dx fastest) of a row in
@@ -130,83 +210,50 @@ __device__ inline int halo_index(const Dev &k, const int lc[3], int sc)
     return ((lc[2] + sc / 9) * k.hext[1] + lc[1] + (sc / 3) % 3) * k.hext[0] + lc[0] + sc % 3;
 }
 
-// ---------------------------------------------------------------- search
-// Candidates of one lane, NB at a time: global row and LDS slot of entries
-// lane, lane + G, ... of the row's stencil sequence.
-template <int DIM, int NB, int G>
-struct TileWalk {
-    const Dev &k;
-    const TileHalo &H;
-    int lc[3];
-    int sc, mo, h;
-    static constexpr int NS = DIM == 2 ? 9 : 27;
-    __device__ inline TileWalk(const Dev &kk, const TileHalo &HH, const int l[3], int lane)
-        : k(kk), H(HH)
-    {
-        lc[0] = l[0];
-        lc[1] = l[1];
-        lc[2] = l[2];
-        sc = 0;
-        mo = lane;
-        h = halo_index<DIM>(k, lc, 0);
-        advance();
-    }
-    __device__ inline void advance()
-    {
-        while (sc < NS && mo >= H.len[h]) {
-            mo -= H.len[h];
-            if (++sc < NS) h = halo_index<DIM>(k, lc, sc);
-        }
-    }
-    __device__ inline void next(int32_t jj[NB], int32_t ss[NB], bool hv[NB])
-    {
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            hv[b] = sc < NS;
-            jj[b] = hv[b] ? H.gbeg[h] + mo : 0;  // row 0 as a harmless dummy
-            ss[b] = hv[b] ? H.off[h] + mo : 0;
-            mo += G;
-            advance();
-        }
-    }
-};
+// First halo cell of run r (the cells dx = -1, 0, 1 of stencil row (dy, dz),
+// r = 3 (dz + 1) + dy + 1 in 3D, dy + 1 in 2D) of a row in tile-local cell lc.
+template <int DIM>
+__device__ inline int run_cell(const Dev &k, const int lc[3], int r)
+{
+    if (DIM == 2) return (lc[1] + r) * k.hext[0] + lc[0];
+    return ((lc[2] + r / 3) * k.hext[1] + lc[1] + r % 3) * k.hext[0] + lc[0];
+}
 
+// ---------------------------------------------------------------- search
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R, DevNlist nl,
                                                     DevDerived o, int dens,
-                                                    const uint32_t *spread,
-                                                    const int32_t *cell_start,
-                                                    const uint32_t *cpos, float *off,
+                                                    const int32_t *table, const uint32_t *cpos,
+                                                    float *off, uint16_t *lslot,
                                                     int32_t *rebin_clear, uint32_t *err)
 {
     // the step's bin has run: later updates of this step may request the next
     if (rebin_clear && blockIdx.x == 0 && threadIdx.x == 0) *rebin_clear = 0;
     constexpr int CAP = tile_cap_search(DIM);
-    constexpr int NS = DIM == 2 ? 9 : 27;
+    constexpr int NR = DIM == 2 ? 3 : 9;  // runs of three cells along x
     constexpr int PB = kBlock / G;
-    constexpr int NB = 4;
+    constexpr int NB = 2;                 // chunks of G candidates per round
     __shared__ TileHalo H;
     __shared__ double s_x[DIM][CAP];
     __shared__ T s_w[PB][G];
-    const int64_t tile = xcd_block(k.ntiles);
+    const int64_t tile = tile_of_block(k.ntiles);
     if (tile < 0) return;
-    const int64_t n = *m.n;
     const int64_t C = k.cap;
-    if (!tile_setup<DIM>(k, tile, n, cell_start, spread, cpos, H, err)) return;
-    const int nst = H.total < CAP ? H.total : CAP;
-    for (int f = threadIdx.x; f < nst; f += kBlock) {
-        const int c = halo_cell_of(H, k.nhalo, f);
-        const int64_t j = H.gbeg[c] + (f - H.off[c]);
+    int org[3] = {0, 0, 0};
+    if (!tile_load<DIM>(k, tile, table, H, org)) return;
+    const int nst = H.total() < CAP ? H.total() : CAP;  // >= 1: the tile has rows
+    tile_stage(H, CAP, [&](int f, int64_t j) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) s_x[d][f] = R.x[d * C + j];
-    }
+    });
     __syncthreads();
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int gshift = (threadIdx.x & 63) & ~(G - 1);
     const uint64_t gmask = G == 64 ? ~0ull : ((1ull << (G & 63)) - 1);
     const uint64_t below = (1ull << lane) - 1;
-    for (int64_t i = H.r0 + grp; i < H.r1; i += PB) {
+    const int lmax = nl.maxnb < k.lmax ? nl.maxnb : k.lmax;
+    for (int64_t i = H.r0() + grp; i < H.r1(); i += PB) {
         double xi[3] = {0, 0, 0};
         int c[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
         const uint32_t cposi = cpos[i];
@@ -214,60 +261,81 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
         for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
         unpack_cell<DIM>(cposi, c);
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) lc[d] = c[d] - H.org[d];
-        int total = 0;
-        for (int sc = lane; sc < NS; sc += G) total += H.len[halo_index<DIM>(k, lc, sc)];
-        total = gsum<G>(total);
+        for (int d = 0; d < DIM; ++d) lc[d] = c[d] - org[d];
         int32_t *row = nl.nbr + i * nl.maxnb;
+        uint16_t *lrow = lslot + i * k.lmax;
         Acc<T> sw;
         int cnt = 0;
-        TileWalk<DIM, NB, G> w(k, H, lc, lane);
-        for (int base = 0; base < total; base += NB * G) {
-            int32_t jj[NB], ss[NB];
-            bool hv[NB];
-            w.next(jj, ss, hv);
-            double xj[NB][3];
+        for (int r = 0; r < NR; ++r) {
+            // the run's three cells are consecutive halo indices and slots
+            const int h0 = run_cell<DIM>(k, lc, r);
+            const int o0 = H.off(h0), o1 = H.off(h0 + 1), o2 = H.off(h0 + 2);
+            const int32_t g0 = H.gbeg(h0), g1 = H.gbeg(h0 + 1), g2 = H.gbeg(h0 + 2);
+            const int rl = H.off(h0 + 3) - o0;
+            for (int base = 0; base < rl; base += NB * G) {
+                int32_t jj[NB];
+                int ss[NB];
+                bool hv[NB];
+                double xj[NB][3];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                const bool lds = ss[b] < nst;
+                for (int b = 0; b < NB; ++b) {
+                    const int q = base + b * G + lane;
+                    hv[b] = q < rl;
+                    const int f = o0 + q;
+                    ss[b] = f;
+                    jj[b] = f + (f < o1 ? g0 - o0 : (f < o2 ? g1 - o1 : g2 - o2));
+                    // positions from LDS (an absent candidate reads slot 0);
+                    // a row past the LDS capacity from global memory, under
+                    // a branch (two unconditional loads would be merged into
+                    // one generic load through a selected pointer)
+                    const int fs = hv[b] && f < nst ? f : 0;
+                    xj[b][2] = 0.0;
 #pragma unroll
-                for (int d = 0; d < 3; ++d)
-                    xj[b][d] = d < DIM ? (lds ? s_x[d][ss[b]] : R.x[d * C + jj[b]]) : 0.0;
-            }
+                    for (int d = 0; d < DIM; ++d) xj[b][d] = s_x[d][fs];
+                    if (hv[b] && f >= nst) {
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                double r[3];
-                const double r2 = dist2_exact<DIM>(k, xi, xj[b], r);
-                const bool hit = hv[b] && r2 < k.sup2;
-                int pos = cnt, nhit = hit ? 1 : 0;
-                if (G > 1) {
-                    const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
-                    pos = cnt + __popcll(bal & below);
-                    nhit = __popcll(bal);
-                }
-                if (hit && pos < nl.maxnb) row[pos] = jj[b];
-                if (dens && nhit > 0) {
-                    const T wv = hit ? kernel_w<T>(k, T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
-                    if (G == 1) {
-                        sw.add(wv);
-                    } else {
-                        // route each kernel value to the lane of its table
-                        // position, so that lane l sums entries l, l + G, ...
-                        if (hit) s_w[grp][pos & (G - 1)] = wv;
-                        __builtin_amdgcn_wave_barrier();
-                        const T got = s_w[grp][lane];
-                        __builtin_amdgcn_wave_barrier();
-                        if (((lane - cnt) & (G - 1)) < nhit) sw.add(got);
+                        for (int d = 0; d < DIM; ++d) xj[b][d] = R.x[d * C + jj[b]];
                     }
                 }
-                cnt += nhit;
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    double rr[3];
+                    const double r2 = dist2_exact<DIM>(k, xi, xj[b], rr);
+                    const bool hit = hv[b] && r2 < k.sup2;
+                    int pos = cnt, nhit = hit ? 1 : 0;
+                    if (G > 1) {
+                        const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
+                        pos = cnt + __popcll(bal & below);
+                        nhit = __popcll(bal);
+                    }
+                    if (hit && pos < lmax) {
+                        row[pos] = jj[b];
+                        lrow[pos] = uint16_t(ss[b]);
+                    }
+                    if (dens && nhit > 0) {
+                        const T wv =
+                            hit ? kernel_w<T>(k, T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
+                        if (G == 1) {
+                            sw.add(wv);
+                        } else {
+                            // route each kernel value to the lane of its table
+                            // position, so that lane l sums entries l, l + G, ...
+                            if (hit) s_w[grp][pos & (G - 1)] = wv;
+                            __builtin_amdgcn_wave_barrier();
+                            const T got = s_w[grp][lane];
+                            __builtin_amdgcn_wave_barrier();
+                            if (((lane - cnt) & (G - 1)) < nhit) sw.add(got);
+                        }
+                    }
+                    cnt += nhit;
+                }
             }
         }
         const T S = sw.template reduce<G>();
         if (lane == 0) {
-            if (cnt > nl.maxnb) {
+            if (cnt > lmax) {
                 raise_error(err, SPH_ERR_NBR_OVERFLOW);
-                cnt = nl.maxnb;
+                cnt = lmax;
             }
             nl.count[i] = cnt;
             if (dens) {
@@ -363,88 +431,55 @@ struct ForceStage<DIM, double> {
     __device__ inline double pres(int f) const { return f64[P][f]; }
 };
 
-// Maps a lane's table entries, which visit the row's stencil cells in order,
-// to LDS slots (or -1 for a row past the LDS capacity); entries outside the
-// row's stencil (a table of another bin) are reported and skipped.
-template <int DIM>
-struct Cursor {
-    const Dev &k;
-    const TileHalo &H;
-    int lc[3];
-    int sc;
-    int32_t gb, ln, so;
-    static constexpr int NS = DIM == 2 ? 9 : 27;
-    __device__ inline Cursor(const Dev &kk, const TileHalo &HH, const int l[3]) : k(kk), H(HH)
-    {
-        lc[0] = l[0];
-        lc[1] = l[1];
-        lc[2] = l[2];
-        reset();
-    }
-    __device__ inline void reset()
-    {
-        sc = 0;
-        const int h = halo_index<DIM>(k, lc, 0);
-        gb = H.gbeg[h];
-        ln = H.len[h];
-        so = H.off[h];
-    }
-    // returns false if j lies in none of the remaining stencil cells
-    __device__ inline bool find(int32_t j, int nst, int &slot)
-    {
-        while (!(j >= gb && j - gb < ln)) {
-            if (++sc >= NS) return false;
-            const int h = halo_index<DIM>(k, lc, sc);
-            gb = H.gbeg[h];
-            ln = H.len[h];
-            so = H.off[h];
-        }
-        const int f = so + (j - gb);
-        slot = f < nst ? f : -1;
-        return true;
-    }
-};
-
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, Fields W,
                                                    DevNlist nl, DevDerived o, const float *off,
-                                                   const uint32_t *cpos, const uint32_t *spread,
-                                                   const int32_t *cell_start, int mode,
+                                                   const uint32_t *cpos, const int32_t *table,
+                                                   const uint16_t *lslot, int mode,
                                                    int want_drag, double *dragpart,
                                                    const double *xbin, int32_t *rebin,
                                                    uint32_t *err)
 {
     using FS = ForceStage<DIM, T>;
     constexpr int PB = kBlock / G;
-    constexpr int NB = 4;
+    constexpr int CENTRE = DIM == 2 ? 4 : 13;  // the row's own cell in its stencil
+    constexpr int NQ = 8;                      // slots read per lane at a time
     __shared__ TileHalo H;
     __shared__ FS S;
     __shared__ double red_lds[3][PB];
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
-    const int64_t tile = xcd_block(k.ntiles);
+    const int64_t tile = tile_of_block(k.ntiles);
     const int64_t n = *m.n;
     const int64_t C = k.cap;
+    int org[3] = {0, 0, 0};
     bool have = tile >= 0;
-    if (have) have = tile_setup<DIM>(k, tile, n, cell_start, spread, cpos, H, err);
+    if (have) have = tile_load<DIM>(k, tile, table, H, org);
     double fbg[3] = {0, 0, 0};  // this group's body force over its rows
     if (have) {
-        const int nst = H.total < FS::CAP ? H.total : FS::CAP;
-        for (int f = threadIdx.x; f < nst; f += kBlock) {
-            const int c = halo_cell_of(H, k.nhalo, f);
-            S.put(k, m, R, o, f, int64_t(H.gbeg[c]) + (f - H.off[c]));
-        }
+        const int total = H.total();
+        const int nst = total < FS::CAP ? total : FS::CAP;
+        tile_stage(H, FS::CAP, [&](int f, int64_t j) { S.put(k, m, R, o, f, j); });
         __syncthreads();
-        for (int64_t i = H.r0 + grp; i < H.r1; i += PB) {
+        for (int64_t i = H.r0() + grp; i < H.r1(); i += PB) {
             const int t = m.type[i];
             if (t == SPH_FLUID || t == SPH_BODY) {
                 const int cnt = nl.count[i];
+                // LDS slots of the row's neighbours, written by the search of
+                // this bin: the first batch of the lane's entries (lane,
+                // lane + G, ...) is read with the count, whatever the count
+                // (the row holds lmax entries; those past the count are unused)
+                const uint16_t *lrow = lslot + i * k.lmax;
+                int fq0[NQ];
+#pragma unroll
+                for (int b = 0; b < NQ; ++b)
+                    fq0[b] = lane + b * G < k.lmax ? int(lrow[lane + b * G]) : 0;
                 Sep<DIM, T> sep;
                 sep.load_i(k, R, off, cpos, i);
                 int c[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
                 unpack_cell<DIM>(cpos[i], c);
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) lc[d] = c[d] - H.org[d];
+                for (int d = 0; d < DIM; ++d) lc[d] = c[d] - org[d];
                 T ui[3] = {0, 0, 0}, wi[3] = {0, 0, 0};
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
@@ -455,64 +490,69 @@ __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, 
                 const T rhoi = ld<T>(o.rho, i);
                 const T vi = ld<T>(o.vol, i);
                 const T vi2 = vi * vi;
-                const int32_t *row = nl.nbr + i * nl.maxnb;
+                // the row's own slot, in its stencil's centre cell
+                const int hc = halo_index<DIM>(k, lc, CENTRE);
+                const int self = H.off(hc) + int(i - H.gbeg(hc));
+                bool bad = false;
                 // the neighbour average of eq:pavg enters the fluid's momentum;
                 // the body force takes p~ about zero
                 T pavg = T(0);
                 if (t == SPH_FLUID && !(k.flags & SPH_FLAG_NO_PAVG)) {
                     Acc<T> sp;
-                    Cursor<DIM> cur(k, H, lc);
-                    bool bad = false;
-                    for (int q0 = lane; q0 < cnt; q0 += NB * G) {
-                        int32_t jb[NB];
+                    for (int q0 = lane; q0 < cnt; q0 += NQ * G) {
+                        int fq[NQ];
 #pragma unroll
-                        for (int f = 0; f < NB; ++f)
-                            jb[f] = q0 + f * G < cnt ? row[q0 + f * G] : -1;
+                        for (int b = 0; b < NQ; ++b)
+                            fq[b] = q0 == lane ? fq0[b]
+                                               : (q0 + b * G < cnt ? int(lrow[q0 + b * G]) : 0);
 #pragma unroll
-                        for (int f = 0; f < NB; ++f) {
-                            if (q0 + f * G >= cnt) continue;
-                            int slot;
-                            if (bad_index(jb[f], n) || !cur.find(jb[f], nst, slot)) {
+                        for (int b = 0; b < NQ; ++b) {
+                            if (q0 + b * G >= cnt) continue;
+                            const int f = fq[b];
+                            if (f >= total) {
                                 bad = true;
                                 continue;
                             }
-                            sp.add(slot >= 0 ? S.pres(slot) : ld<T>(R.p, jb[f]));
+                            T pj = S.pres(f < nst ? f : 0);
+                            if (f >= nst) pj = ld<T>(R.p, halo_row(H, f));
+                            sp.add(pj);
                         }
                     }
-                    if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
                     pavg = sp.template reduce<G>() / T(cnt);
                 }
                 Acc<T> acc[3], bacc[3], pdot;
                 double fb[3] = {0, 0, 0};
-                {
-                    Cursor<DIM> cur(k, H, lc);
-                    bool bad = false;
-                    for (int q0 = lane; q0 < cnt; q0 += NB * G) {
-                        int32_t jb[NB];
+                for (int q0 = lane; q0 < cnt; q0 += NQ * G) {
+                    int fq[NQ];
 #pragma unroll
-                        for (int f = 0; f < NB; ++f)
-                            jb[f] = q0 + f * G < cnt ? row[q0 + f * G] : -1;
+                    for (int b = 0; b < NQ; ++b)
+                        fq[b] = q0 == lane ? fq0[b]
+                                           : (q0 + b * G < cnt ? int(lrow[q0 + b * G]) : 0);
+                    const int left = (cnt - q0 + G - 1) / G;  // the lane's entries left
+                    const int nq = left < NQ ? left : NQ;
+                    // one neighbour at a time (the batch is shifted down), so
+                    // that the pair terms are not replicated per slot
+#pragma unroll 1
+                    for (int b = 0; b < nq; ++b) {
+                        const int f = fq[0];
 #pragma unroll
-                        for (int f = 0; f < NB; ++f) {
-                            if (q0 + f * G >= cnt) continue;
-                            int slot;
-                            if (bad_index(jb[f], n) || !cur.find(jb[f], nst, slot)) {
-                                bad = true;
-                                continue;
-                            }
-                            if (jb[f] == i) continue;
-                            NbrRaw<DIM, T> raw;
-                            if (slot >= 0) S.get(slot, jb[f], raw);
-                            else fetch_nbr<DIM, T>(k, m, R, o, jb[f], raw);
-                            Nbr<DIM, T> nb;
-                            finish_nbr<DIM, T>(k, sep, raw, nb);
-                            if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
-                            pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc,
-                                             pdot, fb);
+                        for (int x = 0; x + 1 < NQ; ++x) fq[x] = fq[x + 1];
+                        if (f >= total) {
+                            bad = true;
+                            continue;
                         }
+                        if (f == self) continue;
+                        NbrRaw<DIM, T> raw;
+                        if (f < nst) S.get(f, 0, raw);
+                        else fetch_nbr<DIM, T>(k, m, R, o, halo_row(H, f), raw);
+                        Nbr<DIM, T> nb;
+                        finish_nbr<DIM, T>(k, sep, raw, nb);
+                        if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
+                        pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot,
+                                         fb);
                     }
-                    if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
                 }
+                if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
                 T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) {
@@ -566,26 +606,34 @@ __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, 
 }
 
 // ------------------------------------------------------------------ launchers
-int tile_grid(const Dev &k) { return xcd_grid(k.ntiles); }
-
-template <int DIM, typename T, int G>
-static void tsearch_g(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
-                      const DevDerived &o, int dens, const uint32_t *spread,
-                      const int32_t *cell_start, const uint32_t *cpos, float *off,
-                      int32_t *rebin_clear, uint32_t *err, hipStream_t s)
+int tile_grid(const Dev &k)
 {
-    hipLaunchKernelGGL((k_tsearch<DIM, T, G>), dim3(tile_grid(k)), dim3(kBlock), 0, s, k, m, R,
-                       nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err);
+    const int64_t per = int64_t(8) * kTileChunk;
+    return int((k.ntiles + per - 1) / per * per);
+}
+
+void launch_tile_table(const Dev &k, const int64_t *nrows, const int32_t *cell_start,
+                       const uint32_t *spread, const uint32_t *cpos, const int32_t *sorted,
+                       int32_t *table, uint32_t *err, hipStream_t s)
+{
+    const dim3 g(unsigned((k.ntiles + kBlock / 64 - 1) / (kBlock / 64))), b(kBlock);
+    if (k.dim == 2)
+        hipLaunchKernelGGL(k_tile_table<2>, g, b, 0, s, k, nrows, cell_start, spread, cpos, sorted,
+                           table, err);
+    else
+        hipLaunchKernelGGL(k_tile_table<3>, g, b, 0, s, k, nrows, cell_start, spread, cpos, sorted,
+                           table, err);
 }
 
 template <int DIM, typename T>
 static void tsearch_dt(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
-                       const DevDerived &o, int dens, const uint32_t *spread,
-                       const int32_t *cell_start, const uint32_t *cpos, float *off,
-                       int32_t *rebin_clear, uint32_t *err, hipStream_t s)
+                       const DevDerived &o, int dens, const int32_t *table, const uint32_t *cpos,
+                       float *off, uint16_t *lslot, int32_t *rebin_clear, uint32_t *err,
+                       hipStream_t s)
 {
-#define SPH_TS_G(G) \
-    tsearch_g<DIM, T, G>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear, err, s)
+#define SPH_TS_G(G)                                                                        \
+    hipLaunchKernelGGL((k_tsearch<DIM, T, G>), dim3(tile_grid(k)), dim3(kBlock), 0, s, k, m, R, \
+                       nl, o, dens, table, cpos, off, lslot, rebin_clear, err)
     switch (nbr_group(k)) {
     case 1: SPH_TS_G(1); break;
     case 2: SPH_TS_G(2); break;
@@ -598,46 +646,31 @@ static void tsearch_dt(const Dev &k, const DevState &m, const Fields &R, const D
 }
 
 void launch_tsearch(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
-                    const DevDerived &o, int dens, const uint32_t *spread,
-                    const int32_t *cell_start, const uint32_t *cpos, float *off,
-                    int32_t *rebin_clear, uint32_t *err, hipStream_t s)
+                    const DevDerived &o, int dens, const int32_t *table, const uint32_t *cpos,
+                    float *off, uint16_t *lslot, int32_t *rebin_clear, uint32_t *err,
+                    hipStream_t s)
 {
     if (k.dim == 2 && k.prec == SPH_FP64)
-        tsearch_dt<2, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                              err, s);
+        tsearch_dt<2, double>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
     else if (k.dim == 3 && k.prec == SPH_FP64)
-        tsearch_dt<3, double>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                              err, s);
+        tsearch_dt<3, double>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
     else if (k.dim == 2)
-        tsearch_dt<2, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                             err, s);
+        tsearch_dt<2, float>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
     else
-        tsearch_dt<3, float>(k, m, R, nl, o, dens, spread, cell_start, cpos, off, rebin_clear,
-                             err, s);
-}
-
-template <int DIM, typename T, int G>
-static void tforce_g(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
-                     const DevNlist &nl, const DevDerived &o, const float *off,
-                     const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
-                     int mode, int want_drag, double *dragpart, const double *xbin,
-                     int32_t *rebin, uint32_t *err, hipStream_t s)
-{
-    hipLaunchKernelGGL((k_tforce<DIM, T, G>), dim3(tile_grid(k)), dim3(kBlock), 0, s, k, m, R, W,
-                       nl, o, off, cpos, spread, cell_start, mode, want_drag, dragpart, xbin,
-                       rebin, err);
+        tsearch_dt<3, float>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
 }
 
 template <int DIM, typename T>
 static void tforce_dt(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                       const DevNlist &nl, const DevDerived &o, const float *off,
-                      const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
+                      const uint32_t *cpos, const int32_t *table, const uint16_t *lslot,
                       int mode, int want_drag, double *dragpart, const double *xbin,
                       int32_t *rebin, uint32_t *err, hipStream_t s)
 {
-#define SPH_TF_G(G)                                                                             \
-    tforce_g<DIM, T, G>(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,   \
-                        dragpart, xbin, rebin, err, s)
+#define SPH_TF_G(G)                                                                        \
+    hipLaunchKernelGGL((k_tforce<DIM, T, G>), dim3(tile_grid(k)), dim3(kBlock), 0, s, k, m, R, \
+                       W, nl, o, off, cpos, table, lslot, mode, want_drag, dragpart, xbin,     \
+                       rebin, err)
     switch (force_group(k)) {
     case 1: SPH_TF_G(1); break;
     case 2: SPH_TF_G(2); break;
@@ -651,22 +684,18 @@ static void tforce_dt(const Dev &k, const DevState &m, const Fields &R, const Fi
 
 void launch_tforce(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                    const DevNlist &nl, const DevDerived &o, const float *off,
-                   const uint32_t *cpos, const uint32_t *spread, const int32_t *cell_start,
-                   int mode, int want_drag, double *dragpart, const double *xbin,
-                   int32_t *rebin, uint32_t *err, hipStream_t s)
+                   const uint32_t *cpos, const int32_t *table, const uint16_t *lslot, int mode,
+                   int want_drag, double *dragpart, const double *xbin, int32_t *rebin,
+                   uint32_t *err, hipStream_t s)
 {
-    if (k.dim == 2 && k.prec == SPH_FP64)
-        tforce_dt<2, double>(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,
-                             dragpart, xbin, rebin, err, s);
-    else if (k.dim == 3 && k.prec == SPH_FP64)
-        tforce_dt<3, double>(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,
-                             dragpart, xbin, rebin, err, s);
-    else if (k.dim == 2)
-        tforce_dt<2, float>(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,
-                            dragpart, xbin, rebin, err, s);
-    else
-        tforce_dt<3, float>(k, m, R, W, nl, o, off, cpos, spread, cell_start, mode, want_drag,
-                            dragpart, xbin, rebin, err, s);
+#define SPH_TF(D, TT)                                                                    \
+    tforce_dt<D, TT>(k, m, R, W, nl, o, off, cpos, table, lslot, mode, want_drag, dragpart, \
+                     xbin, rebin, err, s)
+    if (k.dim == 2 && k.prec == SPH_FP64) SPH_TF(2, double);
+    else if (k.dim == 3 && k.prec == SPH_FP64) SPH_TF(3, double);
+    else if (k.dim == 2) SPH_TF(2, float);
+    else SPH_TF(3, float);
+#undef SPH_TF
 }
 
 }  // namespace sph
