@@ -446,9 +446,9 @@ def main():
                     help="outlet rule (forward form only)")
     ap.add_argument("--mirror-inlet", action="store_true",
                     help="inlet pressure mirrored from the fluid (forward form only)")
-    ap.add_argument("--no-tiles", action="store_true",
-                    help="gather kernels for the neighbour search and force pass instead of "
-                         "the LDS-tiled ones")
+    ap.add_argument("--tiles", action="store_true",
+                    help="the LDS-tiled neighbour search and force pass instead of the gather "
+                         "kernels")
     ap.add_argument("--sort-every-step", action="store_true",
                     help="sort by cell at every step instead of keeping the cell order "
                          "while the skin allows")
@@ -479,8 +479,8 @@ def main():
         prm["flags"] |= I.FLAG_MIRROR_INLET
     if not args.sort_every_step:
         prm["flags"] |= I.FLAG_REUSE_BINS
-    if args.no_tiles:
-        prm["flags"] |= I.FLAG_NO_TILES
+    if args.tiles:
+        prm["flags"] |= I.FLAG_TILES
     log(f"bench: {prm['name']} n={len(s['p'])} prec={args.precision} "
         f"reuse_bins={not args.sort_every_step} outlet={args.outlet}")
 
@@ -537,7 +537,7 @@ def main():
                    "inlet": "mirror" if args.mirror_inlet else "characteristic",
                    "cell_order": "sorted every step" if args.sort_every_step
                    else "kept while the cell skin allows",
-                   "pair_kernels": "gather" if args.no_tiles else "LDS tiles"},
+                   "pair_kernels": "LDS tiles" if args.tiles else "gather"},
         "roofline": roof,
         "roofline_other_roof": roof_other,
         "forms": result_forms,

@@ -65,17 +65,15 @@ enum {
  * (the reverse passes use the kernel's own derivatives).
  * SPH_FLAG_MIRROR_INLET gives inlet particles the pressure mirrored from the
  * fluid (Sec. 3 with Sec. 3.2, as SPH_OUTLET_MIRROR describes, pressure
- * only) instead of the characteristic J3 (forward only). SPH_FLAG_NO_TILES
- * keeps the neighbour search and the force pass on their gather kernels
- * (neighbours read from global memory row by row) where the library would
- * otherwise stage each tile of cells and its halo in LDS; both produce the
- * same neighbour table and the same values. The library stages tiles where a
- * tile's halo is expected to fit its LDS capacity at lattice density;
- * SPH_FLAG_TILES uses them whatever the expected fill (halo rows past the
- * capacity are then read from global memory). */
+ * only) instead of the characteristic J3 (forward only). SPH_FLAG_TILES runs
+ * the neighbour search and the force pass on their LDS-tiled kernels (each
+ * tile of cells and its halo staged in LDS, halo rows past the capacity read
+ * from global memory) instead of the gather kernels (neighbours read from
+ * global memory row by row, through the caches); both produce the same
+ * neighbour table and densities and the same forces to rounding. The gather
+ * kernels are the default: on the workloads measured they are the faster. */
 enum { SPH_FLAG_NO_PAVG = 1, SPH_FLAG_DAMP_NU = 2, SPH_FLAG_NOISE = 4, SPH_FLAG_REUSE_BINS = 8,
-       SPH_FLAG_QUINTIC = 16, SPH_FLAG_MIRROR_INLET = 32, SPH_FLAG_NO_TILES = 64,
-       SPH_FLAG_TILES = 128 };
+       SPH_FLAG_QUINTIC = 16, SPH_FLAG_MIRROR_INLET = 32, SPH_FLAG_TILES = 128 };
 
 /* sph_params.outlet: how outlet particles get their values and move. Every
  * rule advects outlet particles along x only; u, p are those of the rule, ut = u.
@@ -114,7 +112,8 @@ enum {
     SPH_ERR_NONFINITE = 4u,     /* a non-finite value after a stage update */
     SPH_ERR_SKIN = 8u,          /* a particle moved more than the cell skin in a step */
     SPH_ERR_ESCAPE = 16u,       /* a particle left the box along a closed axis */
-    SPH_ERR_CELL_RANGE = 32u    /* corrupt cell/neighbour index found (input misuse) */
+    SPH_ERR_CELL_RANGE = 32u,   /* corrupt cell/neighbour index found (input misuse) */
+    SPH_ERR_NNZ_CAPACITY = 64u  /* sph_neighbors: more entries than csr->cap_nnz */
 };
 
 /* per-row events of one step, recorded by sph_step_record for the reverse */
@@ -184,6 +183,18 @@ typedef struct sph_nlist {
     int32_t *nbr;         /* [cap][maxnb] */
 } sph_nlist;
 
+/* Neighbour relation in compressed rows (sph_neighbors): the neighbours of
+ * particle i (itself included) are col[row_ptr[i] .. row_ptr[i+1]) for
+ * i < *st->n, in the same order as the rows of sph_neighbor_table. row_ptr
+ * has room for cap + 1 entries, col for cap_nnz; *nnz_out receives
+ * row_ptr[n] (device memory). */
+typedef struct sph_csr {
+    int64_t *row_ptr;     /* [cap + 1] */
+    int32_t *col;         /* [cap_nnz] (may be NULL when cap_nnz is 0) */
+    int64_t cap_nnz;      /* entries col can hold */
+    int64_t *nnz_out;     /* [1] total entries */
+} sph_csr;
+
 /* Results of one right-hand-side evaluation. rho, vol, pavg, a, b, pdot have
  * the state's element type. a, b, pdot are written for fluid particles (zero
  * elsewhere); force only for body particles (other rows are left as they
@@ -204,6 +215,9 @@ typedef struct sph_derived {
  * list_cap (or the automatic count) entries per particle, the FP32 force
  * pass's packed neighbour records, error word); the same for both precisions. */
 int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes);
+/* The same figure as a return value; 0 when the parameters are invalid
+ * (sph_last_error() says why). */
+size_t sph_workspace_bytes(const sph_params *prm, int64_t cap);
 
 /* Launch configuration the library derives from the parameters for a
  * capacity and precision (no GPU needed): the cell grid; whether the
@@ -236,15 +250,27 @@ int32_t sph_default_maxnb(const sph_params *prm);
 int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws,
             size_t ws_bytes, void *stream);
 
-/* Neighbour table at the current positions from the cells of the last
- * sph_bin on this workspace: j is a neighbour of i iff |r_i - r_j|^2 < (2h)^2
- * in FP64 without fused multiply-add, minimum image on periodic axes. If out
- * is not NULL the summation density of sph_density is written from the same
- * pairs. Particles must not have moved more than the cell skin since the bin
- * (sph_step checks this on the device). With LDS tiles the table holds at
- * most sph_default_maxnb entries per row (a deeper nl is rejected). */
-int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph_derived *out,
-                  void *ws, size_t ws_bytes, void *stream);
+/* Neighbour relation at the current positions from the cells of the last
+ * sph_bin on this workspace (the neighbour structure is the implementation's;
+ * the relation is the support of the kernel, Sec. 2 eq:summation-density): j
+ * is a neighbour of i iff |r_i - r_j|^2 < (2h)^2 ((3h)^2 with
+ * SPH_FLAG_QUINTIC) in FP64 without fused multiply-add, minimum image on
+ * periodic axes, i itself included. Written in compressed rows: a count
+ * pass, the row offsets (a scan of the counts) and a fill pass. row_ptr and
+ * *nnz_out are always written; when the total exceeds csr->cap_nnz nothing is
+ * written to col and SPH_ERR_NNZ_CAPACITY is set (call again with room for
+ * *nnz_out entries; no row is truncated). Particles must not have moved more
+ * than the cell skin since the bin. */
+int sph_neighbors(const sph_params *prm, const sph_state *st, sph_csr *csr, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* The same relation as a padded table of nl->maxnb entries per row, the
+ * layout the right-hand-side passes read (entries past maxnb are dropped and
+ * SPH_ERR_NBR_OVERFLOW is set). If out is not NULL the summation density of
+ * sph_density is written from the same pairs. With LDS tiles the table holds
+ * at most sph_default_maxnb entries per row (a deeper nl is rejected). */
+int sph_neighbor_table(const sph_params *prm, const sph_state *st, sph_nlist *nl,
+                       sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
 /* Summation density, Sec. 2 eq:summation-density, and the number-density
  * volume V_i = 1 / sum_j W_ij, for every particle, from the neighbour table. */

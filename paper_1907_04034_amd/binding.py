@@ -18,9 +18,10 @@ LIB_PATH = os.path.join(HERE, "libsph.so")
 FP64, FP32 = 0, 1
 FLUID, INLET, OUTLET, WALL_SLIP, WALL_NOSLIP, BODY, DEAD = 0, 1, 2, 3, 4, 5, 255
 ERR_BITS = {1: "NBR_OVERFLOW", 2: "CAPACITY", 4: "NONFINITE", 8: "SKIN", 16: "ESCAPE",
-            32: "CELL_RANGE"}
+            32: "CELL_RANGE", 64: "NNZ_CAPACITY"}
 
-EXPORTED = ["sph_workspace_size", "sph_default_maxnb", "sph_bin", "sph_neighbors",
+EXPORTED = ["sph_workspace_size", "sph_workspace_bytes", "sph_default_maxnb", "sph_bin",
+            "sph_neighbors", "sph_neighbor_table",
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
             "sph_rhs_adjoint", "sph_outlet_extrapolate_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
             "sph_step_adjoint", "sph_step_record_store", "sph_step_adjoint_stored",
@@ -63,6 +64,10 @@ class SphState(C.Structure):
 
 class SphNlist(C.Structure):
     _fields_ = [("maxnb", C.c_int32), ("count", _P), ("nbr", _P)]
+
+
+class SphCsr(C.Structure):
+    _fields_ = [("row_ptr", _P), ("col", _P), ("cap_nnz", C.c_int64), ("nnz_out", _P)]
 
 
 class SphAdjoint(C.Structure):
@@ -109,7 +114,10 @@ def lib():
         L.sph_default_maxnb.argtypes = [SP]
         L.sph_default_maxnb.restype = C.c_int32
         L.sph_bin.argtypes = [SP, ST, ST, _P, sz, _P]
-        L.sph_neighbors.argtypes = [SP, ST, NL, DE, _P, sz, _P]
+        L.sph_workspace_bytes.argtypes = [SP, C.c_int64]
+        L.sph_workspace_bytes.restype = C.c_size_t
+        L.sph_neighbors.argtypes = [SP, ST, C.POINTER(SphCsr), _P, sz, _P]
+        L.sph_neighbor_table.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_density.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_outlet_extrapolate.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_rhs.argtypes = [SP, ST, NL, DE, _P, sz, _P]
@@ -316,8 +324,33 @@ class Simulation:
         if not self.binned:
             self.bin()
         ws, nb = self._ws()
-        _check(lib().sph_neighbors(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
-                                   C.byref(self.out), ws, nb, self.stream), "sph_neighbors")
+        _check(lib().sph_neighbor_table(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
+                                        C.byref(self.out), ws, nb, self.stream),
+               "sph_neighbor_table")
+
+    def neighbors_csr(self, cap_nnz=None):
+        """sph_neighbors on the cells of the last bin: row_ptr [n+1] (int64)
+        and the first min(nnz, cap_nnz) entries of col (int32) as host arrays,
+        the total nnz and the device error bits of the call.
+        cap_nnz defaults to the padded table's capacity (cap x maxnb)."""
+        if not self.binned:
+            self.bin()
+        t = self.torch
+        if cap_nnz is None:
+            cap_nnz = self.cap * self.maxnb
+        row_ptr = t.full((self.cap + 1,), -1, dtype=t.int64, device=self.dev)
+        col = t.full((max(cap_nnz, 1),), -1, dtype=t.int32, device=self.dev)
+        nnz = t.full((1,), -1, dtype=t.int64, device=self.dev)
+        csr = SphCsr(row_ptr.data_ptr(), col.data_ptr() if cap_nnz > 0 else None, cap_nnz,
+                     nnz.data_ptr())
+        ws, nb = self._ws()
+        _check(lib().sph_neighbors(C.byref(self.q), C.byref(self.st), C.byref(csr), ws, nb,
+                                   self.stream), "sph_neighbors")
+        bits = self.poll_error()
+        n = self.live_count()
+        rp = row_ptr[:n + 1].cpu().numpy()
+        total = int(nnz.item())
+        return rp, col[:min(total, cap_nnz)].cpu().numpy(), total, bits
 
     def density(self):
         ws, nb = self._ws()

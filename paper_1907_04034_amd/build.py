@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsph.so")
-SOURCES = ["bin.hip", "pairs.hip", "tiles.hip", "adjoint.hip", "step_adjoint.hip", "update.hip", "capi.hip", "noalloc.hip"]
+SOURCES = ["bin.hip", "pairs.hip", "tiles.hip", "csr.hip", "adjoint.hip", "step_adjoint.hip", "update.hip", "capi.hip", "noalloc.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",

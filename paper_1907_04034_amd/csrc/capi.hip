@@ -176,10 +176,8 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
         k->lists = (p->dim == 3 || cap < 300000 || prec == SPH_FP64) ? 1 : 0;
     }
     {
-        // LDS tiles of the pair passes: the first tb key bits of the
-        // interleaving (2 x 2 x 2 cells in 3D, 4 x 4 in 2D), used where the
-        // halo of a tile is expected, at lattice density, to fit the LDS
-        // capacity of both pair passes
+        // LDS tiles of the pair passes (on request): the first tb key bits
+        // of the interleaving, 2 x 2 x 2 cells in 3D, 4 x 4 in 2D
         int tb = p->dim == 3 ? 3 : 4;
         if (tb > total_bits) tb = total_bits;
         int e[3] = {0, 0, 0};
@@ -194,22 +192,13 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
                 }
         k->tb = tb;
         k->nhalo = 1;
-        double rows_per_cell = 1.0;
         for (int a = 0; a < 3; ++a) {
             k->text[a] = a < p->dim ? (1 << e[a]) : 1;
             k->hext[a] = a < p->dim ? k->text[a] + 2 : 1;
             k->nhalo *= k->hext[a];
-            if (a < p->dim) rows_per_cell *= k->cs[a] / p->dx;
         }
         k->ntiles = int64_t(k->nkeys) >> tb;
-        const double expect = k->nhalo * rows_per_cell;
-        // (the smaller FP64 capacity for both precisions: the workspace
-        // layout, which the choice changes, does not depend on the precision)
-        const int cap_s = tile_cap_search(p->dim), cap_f = tile_cap_force(p->dim, SPH_FP64);
-        const int cap = cap_s < cap_f ? cap_s : cap_f;
-        k->tiles = !(p->flags & SPH_FLAG_NO_TILES) && k->nhalo <= kHaloCellsMax &&
-                   (expect <= 0.95 * cap || (p->flags & SPH_FLAG_TILES));
-        if (k->tiles) k->lists = 0;  // the tiled search walks the stencil from LDS
+        k->tiles = (p->flags & SPH_FLAG_TILES) && k->nhalo <= kHaloCellsMax;
         k->lmax = default_maxnb(p);
     }
     k->x_inlet = p->x_inlet;
@@ -271,13 +260,17 @@ static WsLayout layout(const Dev &k)
     w.xbin = take(sizeof(double) * 3 * C);
     w.vfresh = take(sizeof(int32_t));
     w.vcount = take(sizeof(int32_t) * C);
-    w.vnbr = take(k.lists ? sizeof(int32_t) * size_t(k.vmax) * C : 0);
+    // candidate lists: rows (gather kernels) or 16-bit LDS slots (tiled search)
+    w.vnbr = take(k.lists ? (k.tiles ? sizeof(uint16_t) : sizeof(int32_t)) * size_t(k.vmax) * C
+                          : 0);
     // neighbour records of the FP32 force pass (sized whatever the precision:
     // the workspace size does not depend on it)
     w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, float>()) * C);
     // LDS slots of the tiled search's table entries, read by the force pass
     w.lslot = take(k.tiles ? sizeof(uint16_t) * size_t(k.lmax) * C : 0);
     w.ttab = take(k.tiles ? sizeof(int32_t) * size_t(tile_table_ints(k)) : 0);
+    // span totals of the CSR row-offset scan
+    w.csum = take(sizeof(int64_t) * size_t(csr_spans(k.cap) + 1));
     w.total = off;
     return w;
 }
@@ -436,7 +429,7 @@ static int prepare(const sph_params *p, const sph_state *st, int maxnb, void *ws
     if (c->k.tiles && maxnb > c->k.lmax)
         return fail(SPH_EINVAL,
                     "neighbour table depth %d exceeds %d (sph_default_maxnb), which the LDS-tiled "
-                    "pair passes hold per row; use a shallower table or SPH_FLAG_NO_TILES",
+                    "pair passes hold per row; use a shallower table or leave SPH_FLAG_TILES off",
                     maxnb, c->k.lmax);
     c->ws = ws;
     c->s = static_cast<hipStream_t>(stream);
@@ -464,6 +457,7 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
     v.fresh = at<int32_t>(c.ws, c.w.vfresh);
     v.count = at<int32_t>(c.ws, c.w.vcount);
     v.nbr = at<int32_t>(c.ws, c.w.vnbr);
+    v.slot = at<uint16_t>(c.ws, c.w.vnbr);
     launch_nbrdens(c.k, dev_state(st), R, dev_nlist(nl), dens ? c.der(o) : DevDerived{},
                    dens, at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start),
                    at<uint32_t>(c.ws, c.w.cpos_s), off ? off : c.off(),
@@ -650,6 +644,12 @@ int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes)
     return SPH_OK;
 }
 
+size_t sph_workspace_bytes(const sph_params *prm, int64_t cap)
+{
+    size_t b = 0;
+    return sph_workspace_size(prm, cap, &b) == SPH_OK ? b : 0;
+}
+
 int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws, size_t ws_bytes,
             void *stream)
 {
@@ -666,14 +666,30 @@ int sph_bin(const sph_params *prm, sph_state *st, sph_state *alt, void *ws, size
     return check_hip("sph_bin");
 }
 
-int sph_neighbors(const sph_params *prm, const sph_state *st, sph_nlist *nl, sph_derived *out,
-                  void *ws, size_t ws_bytes, void *stream)
+int sph_neighbor_table(const sph_params *prm, const sph_state *st, sph_nlist *nl,
+                       sph_derived *out, void *ws, size_t ws_bytes, void *stream)
 {
     Ctx c;
     int rc = prepare(prm, st, nl ? nl->maxnb : 0, ws, ws_bytes, stream, &c);
     if (rc || (rc = check_nlist(nl))) return rc;
     if (out && (rc = check_derived(out, false))) return rc;
     do_nbrdens(c, st, fields_of(st), nl, out, out != nullptr, 0);
+    return check_hip("sph_neighbor_table");
+}
+
+int sph_neighbors(const sph_params *prm, const sph_state *st, sph_csr *csr, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, 0, ws, ws_bytes, stream, &c);
+    if (rc) return rc;
+    if (!csr || !csr->row_ptr || !csr->nnz_out)
+        return fail(SPH_EINVAL, "csr, csr->row_ptr and csr->nnz_out must not be NULL");
+    if (csr->cap_nnz < 0) return fail(SPH_EINVAL, "csr->cap_nnz is negative");
+    if (csr->cap_nnz > 0 && !csr->col) return fail(SPH_EINVAL, "csr->col is NULL");
+    launch_csr(c.k, dev_state(st), at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.cell_start),
+               at<uint32_t>(ws, c.w.cpos_s), csr->row_ptr, csr->col, csr->cap_nnz, csr->nnz_out,
+               at<int64_t>(ws, c.w.csum), c.err(), c.s);
     return check_hip("sph_neighbors");
 }
 

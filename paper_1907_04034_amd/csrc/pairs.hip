@@ -1117,7 +1117,8 @@ void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevN
                     int vmode, uint32_t *err, hipStream_t s)
 {
     if (k.tiles) {
-        launch_tsearch(k, m, R, nl, o, dens, ttab, cpos, off, lslot, rebin_clear, err, s);
+        launch_tsearch(k, m, R, nl, o, dens, ttab, cpos, off, lslot, rebin_clear, v, vmode, err,
+                       s);
         return;
     }
     if (k.dim == 2 && k.prec == SPH_FP64)

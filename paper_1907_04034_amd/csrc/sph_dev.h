@@ -244,14 +244,15 @@ struct DevNlist {
 struct VList {
     const int32_t *fresh;  // 1: the step's bin sorted (rebuild the lists)
     int32_t *count;        // entries per particle; -1: overflowed, search the stencil
-    int32_t *nbr;          // [cap][vmax]
+    int32_t *nbr;          // [cap][vmax] rows (gather kernels)
+    uint16_t *slot;        // [cap][vmax] LDS slots of the tile halos (tiled search)
 };
 
 // Workspace carving (byte offsets from the workspace base).
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, scat, tmp,
         cpos, cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
-        vnbr, rec, lslot, ttab, total;
+        vnbr, rec, lslot, ttab, csum, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

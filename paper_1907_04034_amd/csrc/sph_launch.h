@@ -69,10 +69,17 @@ int64_t tile_table_ints(const Dev &k);
 void launch_tile_table(const Dev &k, const int64_t *nrows, const int32_t *cell_start,
                        const uint32_t *spread, const uint32_t *cpos, const int32_t *sorted,
                        int32_t *table, uint32_t *err, hipStream_t s);
+// CSR neighbour relation (count, scan, fill); span_sum holds
+// csr_spans(cap) + 1 entries
+int csr_spans(int64_t cap);
+void launch_csr(const Dev &k, const DevState &m, const uint32_t *spread,
+                const int32_t *cell_start, const uint32_t *cpos, int64_t *row_ptr, int32_t *col,
+                int64_t cap_nnz, int64_t *nnz_out, int64_t *span_sum, uint32_t *err,
+                hipStream_t s);
 void launch_tsearch(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const int32_t *table, const uint32_t *cpos,
-                    float *off, uint16_t *lslot, int32_t *rebin_clear, uint32_t *err,
-                    hipStream_t s);
+                    float *off, uint16_t *lslot, int32_t *rebin_clear, const VList &v, int vmode,
+                    uint32_t *err, hipStream_t s);
 void launch_tforce(const Dev &k, const DevState &m, const Fields &R, const Fields &W,
                    const DevNlist &nl, const DevDerived &o, const float *off,
                    const uint32_t *cpos, const int32_t *table, const uint16_t *lslot, int mode,

@@ -115,6 +115,15 @@ __global__ void __launch_bounds__(kBlock) k_tile_table(Dev k, const int64_t *nro
     }
     const int excl = incl - v0 - v1;
     const int total = __shfl(incl, 63, 64);
+    if (total > 65535) {
+        // slots are 16-bit: a halo this crowded (a thousand rows per cell)
+        // is flagged and its tile skipped
+        if (lane == 0) {
+            raise_error(err, SPH_ERR_NBR_OVERFLOW);
+            rec[0] = rec[1] = a;
+        }
+        return;
+    }
     const int i0 = 2 * lane, i1 = 2 * lane + 1;
     if (i0 < k.nhalo) {
         rec[4 + i0] = gb[0];
@@ -220,12 +229,21 @@ __device__ inline int run_cell(const Dev &k, const int lc[3], int r)
 }
 
 // ---------------------------------------------------------------- search
+// Step path (vmode 1, 2): per-row candidate lists of LDS slots, recorded by
+// the first search after a sort (vmode 1 with *v.fresh: the stencil walk,
+// which also keeps every candidate within Dev::rv2 of the row) and walked by
+// every later search until the next sort. A list is a subsequence of the
+// stencil sequence that holds every hit (rows stay within the cell skin of
+// their binned positions, checked by the stage updates), and the tile layout
+// does not change between sorts, so its slots stay valid and the walk gives
+// the same table in the same order. vmode 0 walks the stencil only.
 template <int DIM, typename T, int G>
 __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R, DevNlist nl,
                                                     DevDerived o, int dens,
                                                     const int32_t *table, const uint32_t *cpos,
                                                     float *off, uint16_t *lslot,
-                                                    int32_t *rebin_clear, uint32_t *err)
+                                                    int32_t *rebin_clear, VList v, int vmode,
+                                                    uint32_t *err)
 {
     // the step's bin has run: later updates of this step may request the next
     if (rebin_clear && blockIdx.x == 0 && threadIdx.x == 0) *rebin_clear = 0;
@@ -235,18 +253,22 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
     constexpr int NB = 2;                 // chunks of G candidates per round
     __shared__ TileHalo H;
     __shared__ double s_x[DIM][CAP];
+    __shared__ int32_t s_row[CAP];
     __shared__ T s_w[PB][G];
     const int64_t tile = tile_of_block(k.ntiles);
     if (tile < 0) return;
     const int64_t C = k.cap;
     int org[3] = {0, 0, 0};
     if (!tile_load<DIM>(k, tile, table, H, org)) return;
-    const int nst = H.total() < CAP ? H.total() : CAP;  // >= 1: the tile has rows
+    const int total = H.total();
+    const int nst = total < CAP ? total : CAP;  // >= 1: the tile has rows
     tile_stage(H, CAP, [&](int f, int64_t j) {
 #pragma unroll
         for (int d = 0; d < DIM; ++d) s_x[d][f] = R.x[d * C + j];
+        s_row[f] = int32_t(j);
     });
     __syncthreads();
+    const bool build = vmode == 1 && *v.fresh != 0;
     const int lane = threadIdx.x & (G - 1);
     const int grp = threadIdx.x / G;
     const int gshift = (threadIdx.x & 63) & ~(G - 1);
@@ -254,6 +276,8 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
     const uint64_t below = (1ull << lane) - 1;
     const int lmax = nl.maxnb < k.lmax ? nl.maxnb : k.lmax;
     for (int64_t i = H.r0() + grp; i < H.r1(); i += PB) {
+        // the walk of this row: its stored list (vc >= 0) or the stencil
+        const int vc = (vmode != 0 && !build) ? v.count[i] : -1;
         double xi[3] = {0, 0, 0};
         int c[3] = {0, 0, 0}, lc[3] = {0, 0, 0};
         const uint32_t cposi = cpos[i];
@@ -264,15 +288,87 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
         for (int d = 0; d < DIM; ++d) lc[d] = c[d] - org[d];
         int32_t *row = nl.nbr + i * nl.maxnb;
         uint16_t *lrow = lslot + i * k.lmax;
+        uint16_t *vrow = v.slot + i * int64_t(k.vmax);
         Acc<T> sw;
-        int cnt = 0;
-        for (int r = 0; r < NR; ++r) {
-            // the run's three cells are consecutive halo indices and slots
-            const int h0 = run_cell<DIM>(k, lc, r);
-            const int o0 = H.off(h0), o1 = H.off(h0 + 1), o2 = H.off(h0 + 2);
-            const int32_t g0 = H.gbeg(h0), g1 = H.gbeg(h0 + 1), g2 = H.gbeg(h0 + 2);
-            const int rl = H.off(h0 + 3) - o0;
-            for (int base = 0; base < rl; base += NB * G) {
+        int cnt = 0, vcnt = 0;
+        // tests NB chunks of G candidates (global rows jj, LDS slots ss,
+        // positions xj) in sequence order: table entries by ballot and, when
+        // recording, list entries within rv
+        auto test = [&](const int32_t *jj, const int *ss, const bool *hv, double (*xj)[3],
+                        bool rec) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                double rr[3];
+                const double r2 = dist2_exact<DIM>(k, xi, xj[b], rr);
+                const bool hit = hv[b] && r2 < k.sup2;
+                int pos = cnt, nhit = hit ? 1 : 0;
+                if (G > 1) {
+                    const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
+                    pos = cnt + __popcll(bal & below);
+                    nhit = __popcll(bal);
+                }
+                if (hit && pos < lmax) {
+                    row[pos] = jj[b];
+                    lrow[pos] = uint16_t(ss[b]);
+                }
+                if (dens && nhit > 0) {
+                    const T wv = hit ? kernel_w<T>(k, T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
+                    if (G == 1) {
+                        sw.add(wv);
+                    } else {
+                        // route each kernel value to the lane of its table
+                        // position, so that lane l sums entries l, l + G, ...
+                        if (hit) s_w[grp][pos & (G - 1)] = wv;
+                        __builtin_amdgcn_wave_barrier();
+                        const T got = s_w[grp][lane];
+                        __builtin_amdgcn_wave_barrier();
+                        if (((lane - cnt) & (G - 1)) < nhit) sw.add(got);
+                    }
+                }
+                cnt += nhit;
+                if (rec) {
+                    const bool vhit = hv[b] && r2 < k.rv2;
+                    int vpos = vcnt, nv = vhit ? 1 : 0;
+                    if (G > 1) {
+                        const uint64_t bal = (uint64_t(__ballot(vhit)) >> gshift) & gmask;
+                        vpos = vcnt + __popcll(bal & below);
+                        nv = __popcll(bal);
+                    }
+                    if (vhit && vpos < k.vmax) vrow[vpos] = uint16_t(ss[b]);
+                    vcnt += nv;
+                }
+            }
+        };
+        // positions of slot f (LDS; past the capacity from global memory,
+        // under a branch: two unconditional loads would be merged into one
+        // generic load through a selected pointer)
+        auto position = [&](bool h, int f, int32_t j, double *x) {
+            const int fs = h && f < nst ? f : 0;
+            x[2] = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) x[d] = s_x[d][fs];
+            if (h && f >= nst) {
+#pragma unroll
+                for (int d = 0; d < DIM; ++d) x[d] = R.x[d * C + j];
+            }
+        };
+        if (vc >= 0) {
+            // the stored list; the next round's entries are read while this
+            // round is tested (entries past the list are not used)
+            bool bad = false;
+            int fc[NB];
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int q = b * G + lane;
+                fc[b] = q < vc ? int(vrow[q]) : 0;
+            }
+            for (int base = 0; base < vc; base += NB * G) {
+                int fn[NB];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) {
+                    const int q = base + NB * G + b * G + lane;
+                    fn[b] = q < vc ? int(vrow[q]) : 0;
+                }
                 int32_t jj[NB];
                 int ss[NB];
                 bool hv[NB];
@@ -280,54 +376,41 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
 #pragma unroll
                 for (int b = 0; b < NB; ++b) {
                     const int q = base + b * G + lane;
-                    hv[b] = q < rl;
-                    const int f = o0 + q;
+                    const int f = fc[b];
+                    const bool ok = f < total;
+                    bad = bad || (q < vc && !ok);
+                    hv[b] = q < vc && ok;
                     ss[b] = f;
-                    jj[b] = f + (f < o1 ? g0 - o0 : (f < o2 ? g1 - o1 : g2 - o2));
-                    // positions from LDS (an absent candidate reads slot 0);
-                    // a row past the LDS capacity from global memory, under
-                    // a branch (two unconditional loads would be merged into
-                    // one generic load through a selected pointer)
-                    const int fs = hv[b] && f < nst ? f : 0;
-                    xj[b][2] = 0.0;
-#pragma unroll
-                    for (int d = 0; d < DIM; ++d) xj[b][d] = s_x[d][fs];
-                    if (hv[b] && f >= nst) {
-#pragma unroll
-                        for (int d = 0; d < DIM; ++d) xj[b][d] = R.x[d * C + jj[b]];
-                    }
+                    jj[b] = !hv[b] ? 0 : (f < nst ? s_row[f] : halo_row(H, f));
+                    position(hv[b], f, jj[b], xj[b]);
                 }
+                test(jj, ss, hv, xj, false);
 #pragma unroll
-                for (int b = 0; b < NB; ++b) {
-                    double rr[3];
-                    const double r2 = dist2_exact<DIM>(k, xi, xj[b], rr);
-                    const bool hit = hv[b] && r2 < k.sup2;
-                    int pos = cnt, nhit = hit ? 1 : 0;
-                    if (G > 1) {
-                        const uint64_t bal = (uint64_t(__ballot(hit)) >> gshift) & gmask;
-                        pos = cnt + __popcll(bal & below);
-                        nhit = __popcll(bal);
+                for (int b = 0; b < NB; ++b) fc[b] = fn[b];
+            }
+            if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
+        } else {
+            for (int r = 0; r < NR; ++r) {
+                // the run's three cells are consecutive halo indices and slots
+                const int h0 = run_cell<DIM>(k, lc, r);
+                const int o0 = H.off(h0), o1 = H.off(h0 + 1), o2 = H.off(h0 + 2);
+                const int32_t g0 = H.gbeg(h0), g1 = H.gbeg(h0 + 1), g2 = H.gbeg(h0 + 2);
+                const int rl = H.off(h0 + 3) - o0;
+                for (int base = 0; base < rl; base += NB * G) {
+                    int32_t jj[NB];
+                    int ss[NB];
+                    bool hv[NB];
+                    double xj[NB][3];
+#pragma unroll
+                    for (int b = 0; b < NB; ++b) {
+                        const int q = base + b * G + lane;
+                        hv[b] = q < rl;
+                        const int f = o0 + q;
+                        ss[b] = f;
+                        jj[b] = f + (f < o1 ? g0 - o0 : (f < o2 ? g1 - o1 : g2 - o2));
+                        position(hv[b], f, jj[b], xj[b]);
                     }
-                    if (hit && pos < lmax) {
-                        row[pos] = jj[b];
-                        lrow[pos] = uint16_t(ss[b]);
-                    }
-                    if (dens && nhit > 0) {
-                        const T wv =
-                            hit ? kernel_w<T>(k, T(sqrt(r2) * k.inv_h), T(k.wnorm)) : T(0);
-                        if (G == 1) {
-                            sw.add(wv);
-                        } else {
-                            // route each kernel value to the lane of its table
-                            // position, so that lane l sums entries l, l + G, ...
-                            if (hit) s_w[grp][pos & (G - 1)] = wv;
-                            __builtin_amdgcn_wave_barrier();
-                            const T got = s_w[grp][lane];
-                            __builtin_amdgcn_wave_barrier();
-                            if (((lane - cnt) & (G - 1)) < nhit) sw.add(got);
-                        }
-                    }
-                    cnt += nhit;
+                    test(jj, ss, hv, xj, build);
                 }
             }
         }
@@ -338,6 +421,7 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
                 cnt = lmax;
             }
             nl.count[i] = cnt;
+            if (build) v.count[i] = vcnt <= k.vmax ? vcnt : -1;
             if (dens) {
                 st<T>(o.rho, i, T(k.mass) * S);
                 st<T>(o.vol, i, T(1) / S);
@@ -628,12 +712,12 @@ void launch_tile_table(const Dev &k, const int64_t *nrows, const int32_t *cell_s
 template <int DIM, typename T>
 static void tsearch_dt(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                        const DevDerived &o, int dens, const int32_t *table, const uint32_t *cpos,
-                       float *off, uint16_t *lslot, int32_t *rebin_clear, uint32_t *err,
-                       hipStream_t s)
+                       float *off, uint16_t *lslot, int32_t *rebin_clear, const VList &v,
+                       int vmode, uint32_t *err, hipStream_t s)
 {
 #define SPH_TS_G(G)                                                                        \
     hipLaunchKernelGGL((k_tsearch<DIM, T, G>), dim3(tile_grid(k)), dim3(kBlock), 0, s, k, m, R, \
-                       nl, o, dens, table, cpos, off, lslot, rebin_clear, err)
+                       nl, o, dens, table, cpos, off, lslot, rebin_clear, v, vmode, err)
     switch (nbr_group(k)) {
     case 1: SPH_TS_G(1); break;
     case 2: SPH_TS_G(2); break;
@@ -647,17 +731,16 @@ static void tsearch_dt(const Dev &k, const DevState &m, const Fields &R, const D
 
 void launch_tsearch(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, int dens, const int32_t *table, const uint32_t *cpos,
-                    float *off, uint16_t *lslot, int32_t *rebin_clear, uint32_t *err,
-                    hipStream_t s)
+                    float *off, uint16_t *lslot, int32_t *rebin_clear, const VList &v, int vmode,
+                    uint32_t *err, hipStream_t s)
 {
-    if (k.dim == 2 && k.prec == SPH_FP64)
-        tsearch_dt<2, double>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
-    else if (k.dim == 3 && k.prec == SPH_FP64)
-        tsearch_dt<3, double>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
-    else if (k.dim == 2)
-        tsearch_dt<2, float>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
-    else
-        tsearch_dt<3, float>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, err, s);
+#define SPH_TS(D, TT) \
+    tsearch_dt<D, TT>(k, m, R, nl, o, dens, table, cpos, off, lslot, rebin_clear, v, vmode, err, s)
+    if (k.dim == 2 && k.prec == SPH_FP64) SPH_TS(2, double);
+    else if (k.dim == 3 && k.prec == SPH_FP64) SPH_TS(3, double);
+    else if (k.dim == 2) SPH_TS(2, float);
+    else SPH_TS(3, float);
+#undef SPH_TS
 }
 
 template <int DIM, typename T>

@@ -42,8 +42,7 @@ FLAG_REUSE_BINS = 8  # GPU stepping option: keep the cell order while the skin a
                      # (same neighbour sets; the oracle ignores it)
 FLAG_QUINTIC = 16  # the paper's quintic spline (support 3h) instead of Wendland C2 (2h)
 FLAG_MIRROR_INLET = 32  # inlet pressure mirrored from the fluid instead of the characteristic J3
-FLAG_NO_TILES = 64  # GPU option: gather kernels instead of the LDS-tiled pair passes (same results)
-FLAG_TILES = 128    # GPU option: the LDS-tiled pair passes even where halos may overflow LDS
+FLAG_TILES = 128  # GPU option: the LDS-tiled pair passes instead of the gather kernels (same results)
 
 ID_GENERATION = 1 << 40   # a spawned inlet particle's id is its parent's + this
 

@@ -31,6 +31,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(B.SphParams) == 4 * 6 + 8 * 10 + 8 * 6 + 8 * 5 + 8 + 4 * 4
     assert C.sizeof(B.SphState) == 8 + 4 + 4 + 8 * 13
     assert C.sizeof(B.SphNlist) == 8 + 8 * 2
+    assert C.sizeof(B.SphCsr) == 8 * 4
     assert C.sizeof(B.SphDerived) == 8 * 11
     assert C.sizeof(B.SphAdjoint) == 8 * 6 + 8 * 3 + 8 * 8
     assert C.sizeof(B.SphStateAdjoint) == 8 + 8 * 8
@@ -166,3 +167,52 @@ def test_mirror_rule_validation():
     assert B.lib().sph_rhs_adjoint(C.byref(q), C.byref(st), C.byref(nl), C.byref(de),
                                    C.byref(adj), None, 0, None) == -6
     assert b"inlet" in B.lib().sph_last_error()
+
+
+def test_workspace_bytes_matches_workspace_size():
+    for cfg in ("C1", "C2", "C5"):
+        prm, s = I.config(cfg, small=True)
+        cap = len(s["p"]) * 2
+        q = B.make_params(prm)
+        out = C.c_size_t(0)
+        assert B.lib().sph_workspace_size(C.byref(q), cap, C.byref(out)) == 0
+        assert out.value > 0
+        assert B.lib().sph_workspace_bytes(C.byref(q), cap) == out.value
+    q = B.make_params(dict(prm, dim=4))
+    assert B.lib().sph_workspace_bytes(C.byref(q), 100) == 0
+    assert B.lib().sph_last_error()
+
+
+def _placeholder_state(prm, cap):
+    """A state whose arrays are placeholder addresses: calls that reject their
+    arguments on the host never reach them."""
+    st = B.SphState()
+    st.cap, st.dim, st.prec = cap, prm["dim"], 0
+    for name, typ in B.SphState._fields_:
+        if name not in ("cap", "dim", "prec"):
+            setattr(st, name, 4096)
+    return st
+
+
+def test_csr_arguments_rejected_before_launch():
+    prm, _ = I.config("C1")
+    q = B.make_params(prm)
+    cap = 2000
+    st = _placeholder_state(prm, cap)
+    ws_bytes = B.lib().sph_workspace_bytes(C.byref(q), cap)
+    ws = C.c_void_p(4096)
+    L = B.lib()
+    assert L.sph_neighbors(C.byref(q), C.byref(st), None, ws, ws_bytes, None) == -1
+    csr = B.SphCsr(None, 4096, 10, 4096)
+    assert L.sph_neighbors(C.byref(q), C.byref(st), C.byref(csr), ws, ws_bytes, None) == -1
+    assert b"row_ptr" in L.sph_last_error()
+    csr = B.SphCsr(4096, 4096, -1, 4096)
+    assert L.sph_neighbors(C.byref(q), C.byref(st), C.byref(csr), ws, ws_bytes, None) == -1
+    csr = B.SphCsr(4096, None, 10, 4096)
+    assert L.sph_neighbors(C.byref(q), C.byref(st), C.byref(csr), ws, ws_bytes, None) == -1
+    assert b"col" in L.sph_last_error()
+    csr = B.SphCsr(4096, 4096, 10, None)
+    assert L.sph_neighbors(C.byref(q), C.byref(st), C.byref(csr), ws, ws_bytes, None) == -1
+    # a workspace below sph_workspace_bytes is refused
+    csr = B.SphCsr(4096, 4096, 10, 4096)
+    assert L.sph_neighbors(C.byref(q), C.byref(st), C.byref(csr), ws, ws_bytes - 1, None) == -2

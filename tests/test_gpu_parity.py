@@ -292,19 +292,22 @@ def test_bin_reuse_matches_sorting_every_step():
     assert all(v < 1e-9 for v in err.values()), err
 
 
+@pytest.mark.parametrize("tiles", [False, True])
 @pytest.mark.parametrize("name,caps", [("C4", (1, 14)), ("C5", (1, 52))])
-def test_candidate_lists_match_stencil_search(name, caps):
+def test_candidate_lists_match_stencil_search(name, caps, tiles):
     """The step path's searches through stored candidate lists give the same
     neighbour tables, in the same order, as walking the cell stencil: the
     trajectory with the lists (automatic capacity) is bit-identical to one
     where every particle overflows its list (capacity 1: every search walks
-    the stencil) and to one where only some do."""
-    _print_case(f"candidate lists {name}")
+    the stencil) and to one where only some do. Both for the gather search
+    (lists of rows) and the LDS-tiled one (lists of halo slots)."""
+    _print_case(f"candidate lists {name} tiles={tiles}")
     prm, s = I.config(name, small=True)
     s = I.jitter(prm, s, 0.05, 3, types=(I.FLUID, I.INLET, I.OUTLET))
+    flags = prm["flags"] | I.FLAG_REUSE_BINS | (I.FLAG_TILES if tiles else 0)
     out = []
     for cap in (0,) + tuple(caps):
-        q = dict(prm, flags=prm["flags"] | I.FLAG_REUSE_BINS, list_cap=cap)
+        q = dict(prm, flags=flags, list_cap=cap)
         sim = B().Simulation(q, s)
         drag = torch.zeros((80, 3), dtype=torch.float64, device="cuda")
         sim.step(80, drag_hist=drag)
@@ -328,6 +331,8 @@ def test_empty_state(name, prec):
     sim = B().Simulation(prm, s0, prec=prec)
     sim.bin()
     sim.neighbors()
+    rp, _, nnz, bits = sim.neighbors_csr()
+    assert bits == 0 and nnz == 0 and rp.tolist() == [0]
     sim.rhs()
     drag = torch.zeros((5, 3), dtype=torch.float64, device="cuda")
     sim.step(5, drag_hist=drag)

@@ -1,4 +1,5 @@
-"""The LDS-tiled neighbour search and force pass against the gather kernels.
+"""The LDS-tiled neighbour search and force pass (SPH_FLAG_TILES) against the
+gather kernels (the default).
 
 With the same lanes per target, the tiled kernels reproduce the gather
 kernels' neighbour table bit for bit (same entries in the same order) and
@@ -10,8 +11,8 @@ size of a pair term); so do trajectories over 30 steps. The body-force total
 is summed over a different block decomposition. Cases
 cover 2D and 3D, both precisions, periodic axes with three cells (a tile's
 halo then holds one cell twice), inlet/outlet/wall/body rows, and the small
-3D duct with tiles forced, whose halos overflow the LDS capacity in places
-(those rows are read from global memory).
+3D duct, whose halos overflow the LDS capacity in places (those rows are
+read from global memory).
 """
 import numpy as np
 import pytest
@@ -31,9 +32,8 @@ def _case(name):
         prm, s = I.periodic_lattice(n_side=11, dim=3, dx=0.1)
     elif name == "C1":
         prm, s = I.config("C1")
-    elif name == "C5-forced":
+    elif name == "C5-small":
         prm, s = I.config("C5", small=True)
-        prm["flags"] |= I.FLAG_TILES
     else:
         prm, s = I.config(name, small=True)
     s = I.random_fields(prm, I.jitter(prm, s, 0.2, 7), 8, p_range=(-0.2, 0.2),
@@ -42,23 +42,24 @@ def _case(name):
     return prm, s
 
 
-CASES = ["lattice2d-nc3", "lattice3d", "C1", "C2", "C3", "C4", "C5-forced"]
+CASES = ["lattice2d-nc3", "lattice3d", "C1", "C2", "C3", "C4", "C5-small"]
 
 
 @pytest.mark.parametrize("name", CASES)
 def test_tiles_are_used(name):
-    """The library takes the tiled path for these inputs (host query, no GPU)."""
+    """The library takes the tiled path on request only (host query, no GPU)."""
     prm, s = _case(name)
     cap = int(len(s["p"]) * 1.25) + 256
     for prec in ("fp64", "fp32"):
-        assert B().launch_config(prm, cap, prec)["tiles"]
-        off = dict(prm, flags=prm["flags"] | I.FLAG_NO_TILES)
-        assert not B().launch_config(off, cap, prec)["tiles"]
+        assert not B().launch_config(prm, cap, prec)["tiles"]
+        on = dict(prm, flags=prm["flags"] | I.FLAG_TILES)
+        assert B().launch_config(on, cap, prec)["tiles"]
 
 
-def test_tiles_cover_the_workloads():
+def test_tile_shapes_of_the_workloads():
     for name in ("C1", "C2", "C3", "C4", "C5"):
         prm, s = I.config(name)
+        prm["flags"] |= I.FLAG_TILES
         cap = int(len(s["p"]) * 1.25) + 256
         cfg = B().launch_config(prm, cap)
         assert cfg["tiles"], name
@@ -68,8 +69,8 @@ def test_tiles_cover_the_workloads():
 
 def _rhs(prm, s, prec, tiles):
     p = dict(prm)
-    if not tiles:
-        p["flags"] = (p["flags"] | I.FLAG_NO_TILES) & ~I.FLAG_TILES
+    if tiles:
+        p["flags"] |= I.FLAG_TILES
     st, dv, sim = B().rhs_once(p, s, prec=prec)
     cnt, nbr = sim.neighbor_table()
     assert sim.poll_error() == 0
@@ -102,7 +103,7 @@ def test_tiled_rhs_equals_gather_kernels(name, prec):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("name", ["C2", "C4", "C5-forced", "lattice3d"])
+@pytest.mark.parametrize("name", ["C2", "C4", "C5-small", "lattice3d"])
 def test_tiled_steps_equal_gather_kernels(name, prec):
     """Whole steps (bin with the cell order kept while the skin allows,
     both stages, bookkeeping): the tiled run follows the gather run to rounding."""
@@ -113,8 +114,8 @@ def test_tiled_steps_equal_gather_kernels(name, prec):
     out = []
     for tiles in (False, True):
         p = dict(prm)
-        if not tiles:
-            p["flags"] = (p["flags"] | I.FLAG_NO_TILES) & ~I.FLAG_TILES
+        if tiles:
+            p["flags"] |= I.FLAG_TILES
         print(f"tiles steps: {name} {prec} tiles={tiles}", flush=True)
         sim = B().Simulation(p, s, prec=prec)
         dh = torch.zeros((steps, 3), dtype=torch.float64, device="cuda")
