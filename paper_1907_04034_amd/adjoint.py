@@ -304,20 +304,30 @@ class InletProfileDrag:
     def theta0(self):
         return I.inlet_profile(self.prm, self.base, self.rows)
 
-    def value(self, theta, keep=True):
+    def forward(self, theta):
+        """One forward run at theta: (J, drag history, tape), where the tape
+        (the run's Simulation and DragAdjoint) is what gradient() reverses."""
         s = I.set_inlet_profile(self.prm, self.base, self.rows, theta)
         sim = Bd.Simulation(self.prm, s, prec=self.prec, cap=self.cap)
         run = DragAdjoint(sim, self.nsteps, self.segment)
         hist = run.forward()
         if sim.poll_error():
             raise Bd.SphError("device error during the forward run")
-        if keep:
-            self.sim, self.run = sim, run
-        return float(hist[:, 0].mean().item()), hist
+        return float(hist[:, 0].mean().item()), hist, (sim, run)
 
-    def gradient(self, gJ=1.0):
-        """dJ/dtheta (device FP64 tensor [ntheta]) for the last value() call."""
-        t, sim, run = self.sim.torch, self.sim, self.run
+    def value(self, theta, keep=True):
+        """J(theta) and the drag history; keep=True makes this run the one
+        gradient() reverses by default."""
+        J, hist, tape = self.forward(theta)
+        if keep:
+            self.sim, self.run = tape
+        return J, hist
+
+    def gradient(self, gJ=1.0, tape=None):
+        """gJ dJ/dtheta (device FP64 tensor [ntheta]) for the run of `tape`
+        (default: the last value() call that kept its run)."""
+        sim, run = tape if tape is not None else (self.sim, self.run)
+        t = sim.torch
         fbar = np.zeros((self.nsteps, 3))
         fbar[:, 0] = float(gJ) / self.nsteps
         lam = run.backward(fbar)
@@ -338,15 +348,21 @@ def inlet_drag_objective():
     import torch
 
     class InletDragObjective(torch.autograd.Function):
+        # each application keeps its own forward run (Simulation and tape) in
+        # ctx, so several evaluations may precede their backward passes; the
+        # run is released after its backward
         @staticmethod
         def forward(ctx, theta, problem):
-            J, _ = problem.value(theta.detach().cpu().numpy())
-            ctx.problem = problem
+            J, _, tape = problem.forward(theta.detach().cpu().numpy())
+            ctx.problem, ctx.tape = problem, tape
             return theta.new_tensor(J)
 
         @staticmethod
         def backward(ctx, gJ):
-            g = ctx.problem.gradient(float(gJ))
+            if ctx.tape is None:
+                raise RuntimeError("InletDragObjective: backward called twice for one forward")
+            g = ctx.problem.gradient(float(gJ), tape=ctx.tape)
+            ctx.tape = None
             return g.to(gJ.device, gJ.dtype), None
 
     return InletDragObjective
