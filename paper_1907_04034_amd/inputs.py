@@ -283,6 +283,43 @@ def ramp_tunnel(dx=0.1, L=2.0, W=2.0, T=3.0, probe=1.7, long=False, U=1.0):
     return prm, s
 
 
+def pulse2d_tunnel(dx=0.1, L=2.0, W=2.0, T=3.0, probe=1.7, long=False, U=1.0, alpha=0.5):
+    """The paper's 2D pulse (Sec. 4.2): the ramp problem's tunnel (L x W fluid,
+    slip walls, 6 layers of inlet, outlet and wall particles, inviscid, the
+    paper's kernel at h = 1.2 dx) in uniform flow U; the inlet velocity then
+    follows pulse2d_inlet_velocity. alpha is the EDAC damping coefficient
+    (the paper's tables use 0.5 and sweep 0.1 to 1.0). long=True: the
+    reference domain of length probe + c T."""
+    c = 10.0 * U
+    Lx = probe + c * T if long else L
+    prm, s = channel(Lx=Lx, Ly=W, dx=dx, layers=6, U=U, nu=0.0, side_walls="slip",
+                     wall_layers=6, quintic=True, name=f"2D pulse tunnel {Lx:g}x{W:g} dx={dx:g}")
+    prm["alpha"] = alpha
+    prm["probe"] = [probe, 0.5 * W, 0.0]
+    return prm, s
+
+
+def pulse2d_inlet_velocity(y, t, W=2.0, U=1.0, delta=1e-3):
+    """Inlet x velocity of the 2D pulse (Sec. 4.2 eq:velfunc2, as read here):
+    U + 0.5 U cos(pi y' / 12) exp(-(t - 1)^2 / delta) for 1 < t < 1.1 s, else U,
+    with y' = y - W/2 measured from the channel's centre line. The printed
+    exponent has no minus sign and delta is not given; delta = 1e-3 makes the
+    pulse a half-Gaussian of about 0.03 s that has decayed to 5e-5 of its
+    height where the printed window closes. Works on numpy arrays and torch
+    tensors alike (y), t a float."""
+    if not (1.0 < t < 1.1):
+        return y * 0.0 + U
+    g = 0.5 * U * float(np.exp(-(t - 1.0) ** 2 / delta))
+    yc = y - 0.5 * W
+    try:
+        import torch
+        if isinstance(yc, torch.Tensor):
+            return U + g * torch.cos(np.pi * yc / 12.0)
+    except ImportError:
+        pass
+    return U + g * np.cos(np.pi * yc / 12.0)
+
+
 def ramp_inlet_velocity(t, U=1.0):
     """Inlet x velocity of the ramp problem: U t for t < 1 s, then U."""
     return U * min(max(t, 0.0), 1.0)

@@ -9,6 +9,7 @@ self-convergence of the integrator.
 """
 import itertools
 import math
+import os
 
 import mpmath as mp
 import numpy as np
@@ -822,3 +823,34 @@ def test_taylor_green_decay_sanity():
     ratio = np.abs(st["u"][:, :2]).max() / np.abs(s["u"][:, :2]).max()
     expect = math.exp(-8 * math.pi ** 2 * prm["nu"] * 100 * prm["dt"])
     assert 0.25 * (1 - expect) < 1 - ratio < 2 * (1 - expect)
+
+
+def test_pulse_tables_agree_with_each_other():
+    """The printed 2D-pulse tables (Sec. 4.2) hold the same run twice: the
+    errors of Table table:pulse2d_l2 are the alpha = 0.5 column of Table
+    table:pulse2d_edac_p, which pins the transcription of both files."""
+    import json
+    g = os.path.join(os.path.dirname(__file__), "golden")
+    l2 = json.load(open(os.path.join(g, "pulse2d_l2.json")))
+    sweep = json.load(open(os.path.join(g, "pulse2d_edac_p.json")))
+    col = sweep["alpha"].index(0.5)
+    for rule in ("hybrid", "moc", "do-nothing", "mod-do-nothing", "mirror"):
+        assert l2[rule]["p"] == sweep[rule][col], rule
+
+
+def test_pulse_inlet_velocity_reading():
+    """The 2D pulse's inlet velocity as read from Sec. 4.2 eq:velfunc2: U
+    outside 1 < t < 1.1 s, 1.5 U on the centre line just after t = 1 s, the
+    cos(pi y'/12) profile across the 2 m channel, and a Gaussian in t - 1 of
+    width delta (exp(-1) at (t - 1)^2 = delta)."""
+    y = np.array([0.0, 1.0, 2.0])
+    assert np.all(I.pulse2d_inlet_velocity(y, 0.5) == 1.0)
+    assert np.all(I.pulse2d_inlet_velocity(y, 1.2) == 1.0)
+    assert np.all(I.pulse2d_inlet_velocity(y, 1.0) == 1.0)  # the window is open
+    v = I.pulse2d_inlet_velocity(y, 1.0 + 1e-9)
+    assert abs(v[1] - 1.5) < 1e-12
+    assert abs(v[0] - (1.0 + 0.5 * np.cos(np.pi / 12))) < 1e-9
+    assert v[0] == v[2]
+    t = 1.0 + np.sqrt(4e-3)
+    w = I.pulse2d_inlet_velocity(y, t, delta=4e-3)
+    assert abs(w[1] - (1.0 + 0.5 * np.exp(-1.0))) < 1e-12
