@@ -158,10 +158,11 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     k->disp_max = 0.999 * 0.5 * min_slack;
     {
         // candidate lists: a pair closer than sup at positions within disp_max
-        // (per axis) of the binned ones is closer than sup + 2 sqrt(d) disp_max
-        // at the binned positions (a small relative margin covers rounding);
-        // capacity twice the lattice count of that ball, plus slack
-        const double rv = (sup + 2.0 * std::sqrt(double(p->dim)) * k->disp_max) * (1.0 + 1e-9);
+        // (Euclidean, the skin check of the stage updates) of the binned ones
+        // is closer than sup + 2 disp_max at the binned positions (a small
+        // relative margin covers rounding); capacity twice the lattice count
+        // of that ball, plus slack
+        const double rv = (sup + 2.0 * k->disp_max) * (1.0 + 1e-9);
         k->rv2 = rv * rv;
         const double q = rv / p->dx;
         const double ball = p->dim == 2 ? pi_d * q * q : 4.0 / 3.0 * pi_d * q * q * q;

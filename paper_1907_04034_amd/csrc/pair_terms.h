@@ -110,24 +110,52 @@ __device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &
 }
 
 // ------------------------------------------------------------ stage updates
-// Cell skin along axis d. The neighbour search finds every pair within 2h as
-// long as each particle stays within disp_max of the position it had at the
-// last sort (cells are at least 2h + 2 disp_max wide). Half update (mode 1):
-// the stage-1 position xs and the half position v must stay inside, else an
-// error. Full update (mode 2, bin reuse only): ask the next bin to sort unless
-// the new position plus one more step's displacement (from the start value
-// x0) stays inside.
-__device__ inline void skin_check(const Dev &k, int d, int mode, double xs, double v, double x0,
-                                  double xb, int32_t *rebin, uint32_t *err)
+// Cell skin. The neighbour search finds every pair within 2h as long as each
+// particle stays within disp_max (Euclidean) of the position it had at the
+// last sort: cells are at least 2h + 2 disp_max wide, and the step path's
+// candidate lists hold every pair within 2h + 2 disp_max at the binned
+// positions. Half update (mode 1): the stage-1 position xs and the half
+// position v must stay inside, else an error. Full update (mode 2, bin reuse
+// only): ask the next bin to sort unless the new position plus one more
+// step's displacement (from the start value x0) stays inside.
+template <int DIM>
+__device__ inline void skin_check(const Dev &k, int mode, const double xs[3], const double v[3],
+                                  const double x0[3], const double xb[3], int32_t *rebin,
+                                  uint32_t *err)
+{
+#pragma clang fp contract(off)
+    double a2 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double r = mode == 1 ? xs[d] : v[d];
+        const double s = mode == 1 ? v[d] : x0[d];
+        const double da = min_image(r - xb[d], k.periodic[d], k.L[d], k.halfL[d]);
+        const double db = min_image(v[d] - (mode == 1 ? xb[d] : s), k.periodic[d], k.L[d],
+                                    k.halfL[d]);
+        a2 = a2 + da * da;
+        b2 = b2 + db * db;
+    }
+    if (mode == 1) {
+        const double lim2 = k.disp_max * k.disp_max;
+        if (!(a2 <= lim2 && b2 <= lim2)) raise_error(err, SPH_ERR_SKIN);
+    } else if (k.reuse) {
+        if (!(sqrt(a2) + sqrt(b2) <= k.disp_max)) *rebin = 1;
+    }
+}
+
+// The same for rows that move along x only (inlet and outlet): their
+// displacement is the x offset.
+__device__ inline void skin_check_x(const Dev &k, int mode, double xs, double v, double x0,
+                                    double xb, int32_t *rebin, uint32_t *err)
 {
 #pragma clang fp contract(off)
     if (mode == 1) {
-        const double ds = min_image(xs - xb, k.periodic[d], k.L[d], k.halfL[d]);
-        const double dh = min_image(v - xb, k.periodic[d], k.L[d], k.halfL[d]);
+        const double ds = min_image(xs - xb, k.periodic[0], k.L[0], k.halfL[0]);
+        const double dh = min_image(v - xb, k.periodic[0], k.L[0], k.halfL[0]);
         if (!(fabs(ds) <= k.disp_max && fabs(dh) <= k.disp_max)) raise_error(err, SPH_ERR_SKIN);
     } else if (k.reuse) {
-        const double db = min_image(v - xb, k.periodic[d], k.L[d], k.halfL[d]);
-        const double dn = min_image(v - x0, k.periodic[d], k.L[d], k.halfL[d]);
+        const double db = min_image(v - xb, k.periodic[0], k.L[0], k.halfL[0]);
+        const double dn = min_image(v - x0, k.periodic[0], k.L[0], k.halfL[0]);
         if (!(fabs(db) + fabs(dn) <= k.disp_max)) *rebin = 1;
     }
 }
@@ -178,6 +206,7 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
     }
     const double pn = p0 + dt * double(pd);
     fin = fin && isfinite(pn);
+    double xv[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         double v = xn[d];
@@ -186,12 +215,13 @@ __device__ inline void stage_fluid(const Dev &k, const Fields &R, const Fields &
             if (v >= hi) v -= k.L[d];
             else if (v < k.lo[d]) v += k.L[d];
         }
-        skin_check(k, d, mode, xs[d], v, mode == 2 ? xw[d] : 0.0, xb[d], rebin, err);
+        xv[d] = v;
         fin = fin && isfinite(v);
         W.x[d * C + i] = v;
         st<T>(W.u, d * C + i, T(un[d]));
         st<T>(W.ut, d * C + i, T(utn[d]));
     }
+    skin_check<DIM>(k, mode, xs, xv, xw, xb, rebin, err);
     st<T>(W.p, i, T(pn));
     if (!fin) raise_error(err, SPH_ERR_NONFINITE);
 }
@@ -241,7 +271,7 @@ __device__ inline void stage_boundary(const Dev &k, const DevState &m, const Fie
         double v = x0[d];
         if (d == 0 && moves) {
             v = x0[0] + dt * vx;
-            skin_check(k, 0, mode, xs0, v, x0[0], xb0, rebin, err);
+            skin_check_x(k, mode, xs0, v, x0[0], xb0, rebin, err);
             if (!isfinite(v)) raise_error(err, SPH_ERR_NONFINITE);
         }
         W.x[d * C + i] = v;
