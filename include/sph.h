@@ -241,8 +241,8 @@ int sph_launch_config(const sph_params *prm, int64_t cap, int32_t prec, sph_laun
 int32_t sph_default_maxnb(const sph_params *prm);
 
 /* Cell-linked list (no paper passage; the neighbour structure is the
- * implementation's): cell = floor((x - lo) / cs) with cells at least 2.6h
- * wide in 2D and 2.2h in 3D, Morton key, counting sort with ties ordered by
+ * implementation's): cell = floor((x - lo) / cs) with cells at least 1.3 (2D)
+ * or 1.2 (3D) times the kernel's support wide, Morton key, counting sort with ties ordered by
  * id; every state array
  * is gathered into *alt's buffers (scratch of the same capacity and
  * precision) and the sorted rows are copied back, so *st is sorted in place

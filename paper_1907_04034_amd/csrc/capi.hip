@@ -95,9 +95,11 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     const double sup = (k->quintic ? 3.0 : 2.0) * p->h;
     // cells are at least sup (1 + skin) wide. A wider skin sorts less often
     // but widens the candidate search; measured per step: in 2D a skin of
-    // 0.3 beats 0.1, 0.2 and 0.5 (41k and 1.2M particles), in 3D 0.1 beats
-    // 0.2, 0.3 and 0.5 (4.6M), where the candidate ball grows as its cube
-    const double skin = p->dim == 2 ? 0.3 : 0.1;
+    // 0.3 beats 0.1 and 0.2, with 0.4 and 0.5 within 1.5 % (41k and 1.2M
+    // particles); in 3D (4.6M, FP64) 0.2 gives 8.04 ms against 8.44, 8.09,
+    // 8.57 and 8.48 ms at 0.1, 0.15, 0.25 and 0.3, where the candidate ball
+    // grows as its cube and the integer cell counts make the curve uneven
+    const double skin = p->dim == 2 ? 0.3 : 0.2;
     const double cell_min = sup * (1.0 + skin);
     int total_bits = 0;
     double min_slack = 1e300;
