@@ -261,8 +261,9 @@ def run_steps(prm, s, prec, args, mark, label):
 
 
 def kernel_timings(sim, prec, args, mark, label):
-    """The force pass (sph_force, one kernel launch) and the neighbour search
-    (sph_neighbors with density) alone, on a fresh bin of the current state."""
+    """The force pass (sph_force, one kernel launch) and the API's neighbour
+    search (sph_neighbor_table with density: the stencil walk, without the
+    step path's candidate lists) alone, on a fresh bin of the current state."""
     import torch
     stream = torch.cuda.current_stream()
     sim.bin()
@@ -500,8 +501,8 @@ def main():
     counters = counters_summary(args.config, args.precision)
     roof, roof_other = roofline(prm, args.precision, f_us, cnt, types, counters)
     log(f"bench: k_force {f_us:.1f} us/launch ({roof['bound']} {roof['frac']:.3f}), "
-        f"search {s_us:.1f} us/launch")
-    result_forms = {args.precision: dict(main_t, force_us=f_us, search_us=s_us,
+        f"stencil search {s_us:.1f} us/launch")
+    result_forms = {args.precision: dict(main_t, force_us=f_us, stencil_search_us=s_us,
                                          unit="pair-interactions/s")}
     if "adjoint" in forms:
         result_forms["adjoint"] = adjoint_rhs_rate(sim, args.precision, args, mark)
@@ -513,7 +514,7 @@ def main():
             sim2, t2 = run_steps(prm, s, prec, args, mark, prec)
             f2, s2, c2, ty2 = kernel_timings(sim2, prec, args, mark, prec)
             r2, _ = roofline(prm, prec, f2, c2, ty2, counters_summary(args.config, prec))
-            result_forms[prec] = dict(t2, force_us=f2, search_us=s2, unit="pair-interactions/s",
+            result_forms[prec] = dict(t2, force_us=f2, stencil_search_us=s2, unit="pair-interactions/s",
                                       force_roofline=r2)
             del sim2
             torch.cuda.empty_cache()
