@@ -283,6 +283,34 @@ def ramp_tunnel(dx=0.1, L=2.0, W=2.0, T=3.0, probe=1.7, long=False, U=1.0):
     return prm, s
 
 
+def bump_tunnel(dx=0.005, L=1.0, W=0.1, T=0.2, long=False, U=1.0, alpha=0.1, rho0=1000.0):
+    """The paper's 1D pressure bump (Sec. 4.1, eq:pressurebump, after
+    Lastiwka et al.): fluid of density rho0 moving at U through an L long
+    tunnel, 6 layers of inlet and outlet particles, periodic across (a 1D
+    problem in a 2D domain, W wide), inviscid, the paper's kernel at
+    h = 1.2 dx, EDAC alpha = 0.1. Pressure p(x) = 1 - 0.2 exp(-(x - 0.5)^2 /
+    0.001) in the fluid and 1 at inlet and outlet, here shifted by -1 Pa (the
+    scheme sees pressure only through differences, apart from the acoustic
+    gate at rho0 U^2 / 2 = 500 Pa, which this bump never reaches; the
+    characteristics outlet's p_ref = 1 Pa of the paper is then its 0). The
+    spacing is not given for this case (the paper's default 0.1 m cannot
+    resolve a bump of width 0.03 m); 0.005 m puts 6 particles in its width.
+    long=True: a tunnel of length L + (c + U) T, which the right-going wave
+    does not leave within T."""
+    c = 10.0 * U
+    Lx = L + (c + U) * T if long else L
+    prm, s = channel(Lx=Lx, Ly=W, dx=dx, layers=6, U=U, nu=0.0, side_walls=None,
+                     quintic=True, name=f"1D bump tunnel {Lx:g}x{W:g} dx={dx:g}")
+    prm.update(alpha=alpha, rho0=rho0)
+    prm["pb"] = rho0 * prm["c"] ** 2
+    fl = s["type"] == FLUID
+    s["p"][:] = 0.0
+    s["p"][fl] = -0.2 * np.exp(-((s["x"][fl, 0] - 0.5) ** 2) / 0.001)
+    s["ring"][:, :, 3] = s["p"][:, None]
+    s["avg"][:, 3] = s["p"]
+    return prm, s
+
+
 def pulse2d_tunnel(dx=0.1, L=2.0, W=2.0, T=3.0, probe=1.7, long=False, U=1.0, alpha=0.5):
     """The paper's 2D pulse (Sec. 4.2): the ramp problem's tunnel (L x W fluid,
     slip walls, 6 layers of inlet, outlet and wall particles, inviscid, the
