@@ -102,7 +102,11 @@ TRAJ_KEYS = (("x", True), ("u", True), ("p", False), ("avg", False), ("jprev", F
 
 
 def _by_id(st):
-    idx = np.argsort(st["id"])
+    """Live rows sorted by id. Rows a step's end deleted stay in the device
+    state, of kind DEAD, until the next bin drops them; they are not
+    particles."""
+    live = np.flatnonzero(st["type"] != I.DEAD)
+    idx = live[np.argsort(st["id"][live])]
     return {k: v[idx] for k, v in st.items()}
 
 
@@ -122,13 +126,11 @@ def _oracle_state(prm, s, steps):
 
 
 # The mirror outlet in the small 3D duct: near the corner of a no-slip wall
-# and the outlet the fit drives a spike (the oracle reaches p = 28 and
-# u_x = 30 after 44 steps), so particles outrun the 3D cell skin and the HIP
-# path reports SPH_ERR_SKIN; the rule is compared there for one RHS only.
-TRAJ_CASES = [pytest.param(rule, name, steps, marks=pytest.mark.skip(
-                  reason="mirror outlet diverges at the wall corner of the small 3D duct "
-                         "(oracle and HIP path alike); one-RHS parity covers it"))
-              if (rule == "mirror" and name == "C5-small") else (rule, name, steps)
+# and the outlet the fit drives a spike (in the oracle max |u| is 1.09 after
+# 24 steps, 1.26 after 41 and 30 after 44, when particles outrun the 3D cell
+# skin), so that case is compared over the 24 steps before the spike, which
+# already hold re-spawns.
+TRAJ_CASES = [(rule, name, 24 if (rule == "mirror" and name == "C5-small") else steps)
               for rule in RULES for name, steps in [("C2-small", 300), ("C5-small", 60)]]
 
 

@@ -121,7 +121,11 @@ TRAJ_KEYS = (("x", True), ("u", True), ("p", False), ("avg", False), ("jprev", F
 
 
 def _by_id(st):
-    idx = np.argsort(st["id"])
+    """Live rows sorted by id. Rows a step's end deleted stay in the device
+    state, of kind DEAD, until the next bin drops them; they are not
+    particles."""
+    live = np.flatnonzero(st["type"] != I.DEAD)
+    idx = live[np.argsort(st["id"][live])]
     return {k: v[idx] for k, v in st.items()}
 
 
