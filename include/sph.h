@@ -277,7 +277,7 @@ int sph_neighbor_table(const sph_params *prm, const sph_state *st, sph_nlist *nl
 int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
                 sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
-/* Boundary values from the fluid (needs sph_bin, sph_neighbors and
+/* Boundary values from the fluid (needs sph_bin, sph_neighbor_table and
  * sph_density first, in the same workspace: the rows and cells of the last
  * bin are used): wall ghost pressure/velocity by Shepard averaging; outlet
  * particles by the rule in prm->outlet, by default the hybrid rule of
@@ -295,13 +295,13 @@ int sph_outlet_extrapolate(const sph_params *prm, sph_state *st, const sph_nlist
  * pass of Sec. 2 (eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum, eq:p-edac and
  * the background term of eq:transport-vel) for fluid particles and the body
  * force of Sec. 4.6 eq:tvf-momentum_solid, reduced into out->drag. nl must be
- * the table the last sph_neighbors on this workspace wrote, unchanged: with
+ * the table the last sph_neighbor_table on this workspace wrote, unchanged: with
  * LDS tiles (sph_launch_config) the force pass reads the LDS slot of each of
  * its entries, which that search keeps in the workspace. */
 int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_derived *out,
             void *ws, size_t ws_bytes, void *stream);
 
-/* The force pass alone (needs sph_density, or sph_neighbors with out, and
+/* The force pass alone (needs sph_density, or sph_neighbor_table with out, and
  * sph_outlet_extrapolate on the same neighbour table, state and workspace
  * first; for FP32 states those passes leave packed copies of each particle's
  * values in the workspace, which this pass gathers, so the state must not
@@ -309,7 +309,7 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
  * eq:p-edac and the background term of eq:transport-vel for fluid particles;
  * eq:tvf-momentum_solid for body particles, reduced into out->drag (skipped
  * when out->drag is NULL, so that the call is exactly one kernel launch).
- * As for sph_rhs, nl must be the last sph_neighbors table of this workspace. */
+ * As for sph_rhs, nl must be the last sph_neighbor_table of this workspace. */
 int sph_force(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
               sph_derived *out, void *ws, size_t ws_bytes, void *stream);
 
@@ -360,7 +360,7 @@ int sph_step_static(const sph_params *prm, sph_state *st, sph_state *alt, sph_nl
  * and the outlet rows' time averages, through the force pass, the neighbour
  * average pressure (eq:pavg), the boundary values (walls, hybrid outlet
  * eq:characteristic-vars / eq:shepard / eq:acou, inlet J3) and the summation
- * density. Preconditions: sph_neighbors and sph_rhs have run on the same
+ * density. Preconditions: sph_neighbor_table and sph_rhs have run on the same
  * state, table, derived buffers and workspace (the reverse reads the stored
  * rho, V, pbar, boundary values, J and Shepard sums). Optional seeds add
  *     + sum over non-fluid rows (pseed p + useed . u) + sum over inlet/outlet
@@ -499,7 +499,7 @@ int sph_inlet_profile_grad(const sph_params *prm, const sph_state *st,
  *         rows jseed . J
  * with respect to the fluid's x, u, p, the inlet velocities, the averages and
  * the previous-step J. Arguments as sph_rhs_adjoint; abar, bbar, pdbar and
- * fbar are ignored. Preconditions: sph_neighbors (with density) and
+ * fbar are ignored. Preconditions: sph_neighbor_table (with density) and
  * sph_outlet_extrapolate have run on the same state, table and buffers. */
 int sph_outlet_extrapolate_adjoint(const sph_params *prm, const sph_state *st,
                                    const sph_nlist *nl, const sph_derived *fwd,

@@ -423,7 +423,7 @@ class Simulation:
                     useed=None, jseed=None, boundary_only=False):
         """Gradient of L = sum_fluid(abar.a + bbar.b + pdbar*pdot) + fbar.drag
         + sum_nonfluid(pseed*p + useed.u) + sum_inlet/outlet(jseed.J) for the current
-        stage (sph_neighbors and sph_rhs must have run). Weights are host arrays in
+        stage (sph_neighbor_table and sph_rhs must have run). Weights are host arrays in
         the current device row order ((n, 3) or (n,)); returns host gradients in the
         same order (xbar, ubar, utbar, uinbar, jprevbar: (n, 3); pbar: (n,); avgbar:
         (n, 4) with the pressure in the last column)."""
