@@ -235,6 +235,30 @@ typedef struct sph_launch_info {
 } sph_launch_info;
 int sph_launch_config(const sph_params *prm, int64_t cap, int32_t prec, sph_launch_info *out);
 
+/* The cell structure of the last bin on this workspace (sph_bin, or the bin
+ * that opens each sph_step; the neighbour structure is the implementation's,
+ * no paper passage). Cells are cs[d] = (hi - lo)[d] / ncell[d] wide, at least
+ * 1.3 (2D) or 1.2 (3D) times the kernel's support; a row's cell is
+ * floor((x - lo) / cs) at the position it had when the rows were last sorted.
+ * Cells are numbered by the Morton key of sph_cell_key, and the rows of key k
+ * are [cell_start[k], cell_start[k + 1]) of the sorted state (valid while the
+ * cell order is kept, i.e. until the next sorting bin). */
+typedef struct sph_cells {
+    int32_t ncell[3];     /* out: cells per axis (1 past dim) */
+    double cs[3];         /* out: cell widths */
+    int64_t nkeys;        /* out: keys are 0 .. nkeys - 1 (a power of two) */
+    int32_t *cell_start;  /* device, [nkeys + 1], caller-owned; NULL: not copied */
+    uint32_t *key;        /* device, [cap]: the key of each live row; NULL: not written */
+} sph_cells;
+int sph_get_cells(const sph_params *prm, const sph_state *st, sph_cells *out, void *ws,
+                  size_t ws_bytes, void *stream);
+
+/* Morton key of cell (cx, cy, cz) (cz = 0 in 2D) for these parameters and
+ * capacity: bit b of every axis comes before bit b + 1 of any axis, in axis
+ * order, an axis contributing only its ceil(log2(ncell)) bits. Returns -1 for
+ * invalid parameters or a cell outside the grid. Host only. */
+int64_t sph_cell_key(const sph_params *prm, int64_t cap, int32_t cx, int32_t cy, int32_t cz);
+
 /* Default neighbour-table depth for the parameters (32 in 2D, 80 in 3D; with
  * SPH_FLAG_QUINTIC 1.6 times the lattice count of the 3h ball plus 12, in
  * multiples of 16: 80 in 2D and 336 in 3D at h = 1.2 dx). */

@@ -21,7 +21,7 @@ ERR_BITS = {1: "NBR_OVERFLOW", 2: "CAPACITY", 4: "NONFINITE", 8: "SKIN", 16: "ES
             32: "CELL_RANGE", 64: "NNZ_CAPACITY"}
 
 EXPORTED = ["sph_workspace_size", "sph_workspace_bytes", "sph_default_maxnb", "sph_bin",
-            "sph_neighbors", "sph_neighbor_table",
+            "sph_neighbors", "sph_neighbor_table", "sph_get_cells", "sph_cell_key",
             "sph_density", "sph_outlet_extrapolate", "sph_rhs", "sph_force", "sph_step",
             "sph_rhs_adjoint", "sph_outlet_extrapolate_adjoint", "sph_step_record", "sph_step_adjoint_scratch_size",
             "sph_step_adjoint", "sph_step_record_store", "sph_step_adjoint_stored",
@@ -68,6 +68,11 @@ class SphNlist(C.Structure):
 
 class SphCsr(C.Structure):
     _fields_ = [("row_ptr", _P), ("col", _P), ("cap_nnz", C.c_int64), ("nnz_out", _P)]
+
+
+class SphCells(C.Structure):
+    _fields_ = [("ncell", C.c_int32 * 3), ("cs", C.c_double * 3), ("nkeys", C.c_int64),
+                ("cell_start", _P), ("key", _P)]
 
 
 class SphAdjoint(C.Structure):
@@ -118,6 +123,9 @@ def lib():
         L.sph_workspace_bytes.restype = C.c_size_t
         L.sph_neighbors.argtypes = [SP, ST, C.POINTER(SphCsr), _P, sz, _P]
         L.sph_neighbor_table.argtypes = [SP, ST, NL, DE, _P, sz, _P]
+        L.sph_get_cells.argtypes = [SP, ST, C.POINTER(SphCells), _P, sz, _P]
+        L.sph_cell_key.argtypes = [SP, C.c_int64, C.c_int32, C.c_int32, C.c_int32]
+        L.sph_cell_key.restype = C.c_int64
         L.sph_density.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_outlet_extrapolate.argtypes = [SP, ST, NL, DE, _P, sz, _P]
         L.sph_rhs.argtypes = [SP, ST, NL, DE, _P, sz, _P]
@@ -327,6 +335,24 @@ class Simulation:
         _check(lib().sph_neighbor_table(C.byref(self.q), C.byref(self.st), C.byref(self.nl),
                                         C.byref(self.out), ws, nb, self.stream),
                "sph_neighbor_table")
+
+    def cells(self):
+        """The cell structure of the last bin (sph_get_cells) as host arrays:
+        ncell, cs, nkeys, cell_start [nkeys + 1] and the key of every live
+        row."""
+        t = self.torch
+        out = SphCells()
+        ws, nb = self._ws()
+        _check(lib().sph_get_cells(C.byref(self.q), C.byref(self.st), C.byref(out), ws, nb,
+                                   self.stream), "sph_get_cells")
+        cs = t.full((out.nkeys + 1,), -1, dtype=t.int32, device=self.dev)
+        key = t.zeros((self.cap,), dtype=t.int32, device=self.dev)
+        out.cell_start, out.key = cs.data_ptr(), key.data_ptr()
+        _check(lib().sph_get_cells(C.byref(self.q), C.byref(self.st), C.byref(out), ws, nb,
+                                   self.stream), "sph_get_cells")
+        n = self.live_count()
+        return dict(ncell=tuple(out.ncell), cs=tuple(out.cs), nkeys=int(out.nkeys),
+                    cell_start=cs.cpu().numpy(), key=key[:n].cpu().numpy().view(np.uint32))
 
     def neighbors_csr(self, cap_nnz=None):
         """sph_neighbors on the cells of the last bin: row_ptr [n+1] (int64)

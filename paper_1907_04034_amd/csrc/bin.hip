@@ -285,6 +285,37 @@ __global__ void k_gather(Dev k, DevState a, DevState b, const int32_t *tmp,
     }
 }
 
+// The cell structure for the API: cell_start copied, each live row's key from
+// its packed cell.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_cells_out(Dev k, const int64_t *nptr,
+                                                      const uint32_t *spread,
+                                                      const int32_t *cell_start,
+                                                      const uint32_t *cpos, int32_t *cs_out,
+                                                      uint32_t *key_out)
+{
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (cs_out && t <= int64_t(k.nkeys)) cs_out[t] = cell_start[t];
+    if (key_out && t < *nptr) {
+        int c[3] = {0, 0, 0};
+        unpack_cell<DIM>(cpos[t], c);
+        key_out[t] = morton_key<DIM>(spread, c);
+    }
+}
+
+void launch_cells_out(const Dev &k, const int64_t *n, const uint32_t *spread,
+                      const int32_t *cell_start, const uint32_t *cpos, int32_t *cs_out,
+                      uint32_t *key_out, hipStream_t s)
+{
+    const int64_t m = (int64_t(k.nkeys) + 1) > k.cap ? (int64_t(k.nkeys) + 1) : k.cap;
+    if (k.dim == 2)
+        hipLaunchKernelGGL(k_cells_out<2>, dim3(nblocks(m)), dim3(kBlock), 0, s, k, n, spread,
+                           cell_start, cpos, cs_out, key_out);
+    else
+        hipLaunchKernelGGL(k_cells_out<3>, dim3(nblocks(m)), dim3(kBlock), 0, s, k, n, spread,
+                           cell_start, cpos, cs_out, key_out);
+}
+
 // ------------------------------------------------------------------ launchers
 void launch_spread(const Dev &k, uint32_t *spread, int32_t *rebin, hipStream_t s)
 {

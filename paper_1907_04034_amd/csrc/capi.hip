@@ -647,6 +647,46 @@ int sph_workspace_size(const sph_params *prm, int64_t cap, size_t *bytes)
     return SPH_OK;
 }
 
+int sph_get_cells(const sph_params *prm, const sph_state *st, sph_cells *out, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    Ctx c;
+    int rc = prepare(prm, st, 0, ws, ws_bytes, stream, &c);
+    if (rc) return rc;
+    if (!out) return fail(SPH_EINVAL, "out is NULL");
+    for (int d = 0; d < 3; ++d) {
+        out->ncell[d] = c.k.nc[d];
+        out->cs[d] = c.k.cs[d];
+    }
+    out->nkeys = int64_t(c.k.nkeys);
+    if (!out->cell_start && !out->key) return SPH_OK;  // sizes only: nothing to launch
+    launch_cells_out(c.k, st->n, at<uint32_t>(ws, c.w.spread), at<int32_t>(ws, c.w.cell_start),
+                     at<uint32_t>(ws, c.w.cpos_s), out->cell_start, out->key, c.s);
+    return check_hip("sph_get_cells");
+}
+
+int64_t sph_cell_key(const sph_params *prm, int64_t cap, int32_t cx, int32_t cy, int32_t cz)
+{
+    Dev k;
+    if (make_dev(prm, cap, SPH_FP64, 1, &k)) return -1;
+    const int32_t c[3] = {cx, cy, cz};
+    int maxb = 0;
+    for (int a = 0; a < k.dim; ++a) {
+        if (c[a] < 0 || c[a] >= k.nc[a]) return -1;
+        maxb = k.bits[a] > maxb ? k.bits[a] : maxb;
+    }
+    if (k.dim == 2 && cz != 0) return -1;
+    int64_t key = 0;
+    int pos = 0;
+    for (int b = 0; b < maxb; ++b)
+        for (int a = 0; a < k.dim; ++a)
+            if (b < k.bits[a]) {
+                if ((c[a] >> b) & 1) key |= int64_t(1) << pos;
+                ++pos;
+            }
+    return key;
+}
+
 size_t sph_workspace_bytes(const sph_params *prm, int64_t cap)
 {
     size_t b = 0;

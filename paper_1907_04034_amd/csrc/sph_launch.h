@@ -69,6 +69,10 @@ int64_t tile_table_ints(const Dev &k);
 void launch_tile_table(const Dev &k, const int64_t *nrows, const int32_t *cell_start,
                        const uint32_t *spread, const uint32_t *cpos, const int32_t *sorted,
                        int32_t *table, uint32_t *err, hipStream_t s);
+// the cell structure of the last bin (API copy)
+void launch_cells_out(const Dev &k, const int64_t *n, const uint32_t *spread,
+                      const int32_t *cell_start, const uint32_t *cpos, int32_t *cs_out,
+                      uint32_t *key_out, hipStream_t s);
 // CSR neighbour relation (count, scan, fill); span_sum holds
 // csr_spans(cap) + 1 entries
 int csr_spans(int64_t cap);

@@ -2,9 +2,11 @@
 every entry point declared in include/sph.h, and rejects bad arguments on the
 host before any launch."""
 import ctypes as C
+import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 from paper_1907_04034_amd import binding as B
@@ -32,6 +34,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(B.SphState) == 8 + 4 + 4 + 8 * 13
     assert C.sizeof(B.SphNlist) == 8 + 8 * 2
     assert C.sizeof(B.SphCsr) == 8 * 4
+    assert C.sizeof(B.SphCells) == 4 * 3 + 4 + 8 * 3 + 8 * 3
     assert C.sizeof(B.SphDerived) == 8 * 11
     assert C.sizeof(B.SphAdjoint) == 8 * 6 + 8 * 3 + 8 * 8
     assert C.sizeof(B.SphStateAdjoint) == 8 + 8 * 8
@@ -216,3 +219,51 @@ def test_csr_arguments_rejected_before_launch():
     # a workspace below sph_workspace_bytes is refused
     csr = B.SphCsr(4096, 4096, 10, 4096)
     assert L.sph_neighbors(C.byref(q), C.byref(st), C.byref(csr), ws, ws_bytes - 1, None) == -2
+
+
+def _interleave(c, bits):
+    """Morton key as documented for sph_cell_key: bit b of every axis before
+    bit b + 1 of any axis, in axis order, an axis giving only its own bits."""
+    key, pos = 0, 0
+    for b in range(max(bits)):
+        for a in range(len(bits)):
+            if b < bits[a]:
+                key |= ((c[a] >> b) & 1) << pos
+                pos += 1
+    return key
+
+
+@pytest.mark.parametrize("cfg", ["C2", "C5", "C2Q"])
+def test_cell_key_is_the_documented_interleave(cfg):
+    prm, s = I.config(cfg, small=True)
+    cap = len(s["p"]) * 2
+    q = B.make_params(prm)
+    info = B.launch_config(prm, cap)
+    D = prm["dim"]
+    nc = list(info["cells"][:D])
+    bits = [int(math.ceil(math.log2(n))) if n > 1 else 0 for n in nc]
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        c = [int(rng.integers(0, n)) for n in nc] + [0] * (3 - D)
+        assert B.lib().sph_cell_key(C.byref(q), cap, *c) == _interleave(c[:D], bits)
+    assert B.lib().sph_cell_key(C.byref(q), cap, nc[0], 0, 0) == -1
+    assert B.lib().sph_cell_key(C.byref(q), cap, -1, 0, 0) == -1
+    if D == 2:
+        assert B.lib().sph_cell_key(C.byref(q), cap, 0, 0, 1) == -1
+
+
+def test_get_cells_rejects_null_output():
+    prm, _ = I.config("C1")
+    q = B.make_params(prm)
+    cap = 2000
+    st = _placeholder_state(prm, cap)
+    ws_bytes = B.lib().sph_workspace_bytes(C.byref(q), cap)
+    assert B.lib().sph_get_cells(C.byref(q), C.byref(st), None, C.c_void_p(4096), ws_bytes,
+                                 None) == -1
+    # sizes only (no device array requested): no launch, host fields filled
+    out = B.SphCells()
+    assert B.lib().sph_get_cells(C.byref(q), C.byref(st), C.byref(out), C.c_void_p(4096),
+                                 ws_bytes, None) == 0
+    info = B.launch_config(prm, cap)
+    assert tuple(out.ncell) == tuple(info["cells"])
+    assert out.nkeys >= out.ncell[0] * out.ncell[1]
