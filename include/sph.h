@@ -41,6 +41,9 @@ typedef enum {
     SPH_OK = 0,
     SPH_EINVAL = -1,       /* bad argument, detected on the host */
     SPH_ECAPACITY = -2,    /* a size exceeds a capacity, detected on the host */
+    SPH_ENONFINITE = -3,   /* a parameter is NaN or infinite (values that become
+                              non-finite on the device set SPH_ERR_NONFINITE) */
+    SPH_ECFL = -4,         /* dt above the acoustic bound 0.5 h / (c + U) */
     SPH_EHIP = -5,         /* a HIP runtime call failed */
     SPH_EUNSUPPORTED = -6  /* valid but not provided (e.g. dim 1) */
 } sph_status;

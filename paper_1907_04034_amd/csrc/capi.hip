@@ -67,11 +67,23 @@ static int make_dev(const sph_params *p, int64_t cap, int prec, int maxnb, Dev *
     if (p->dim == 1) return fail(SPH_EUNSUPPORTED, "dim 1 is not provided");
     if (p->dim != 2 && p->dim != 3) return fail(SPH_EINVAL, "dim must be 2 or 3 (got %d)", p->dim);
     if (p->n_avg != kNavg) return fail(SPH_EINVAL, "n_avg must be %d (got %d)", kNavg, p->n_avg);
+    {
+        const double vals[] = {p->h, p->dx, p->rho0, p->c, p->U, p->nu, p->alpha, p->eta, p->dt,
+                               p->pb, p->lo[0], p->lo[1], p->lo[2], p->hi[0], p->hi[1], p->hi[2],
+                               p->x_inlet, p->x_outlet, p->x_outlet_end, p->inlet_len,
+                               p->noise_amp};
+        const char *names[] = {"h", "dx", "rho0", "c", "U", "nu", "alpha", "eta", "dt", "pb",
+                               "lo[0]", "lo[1]", "lo[2]", "hi[0]", "hi[1]", "hi[2]", "x_inlet",
+                               "x_outlet", "x_outlet_end", "inlet_len", "noise_amp"};
+        for (size_t q = 0; q < sizeof vals / sizeof vals[0]; ++q)
+            if (!std::isfinite(vals[q]))
+                return fail(SPH_ENONFINITE, "parameter %s is not finite", names[q]);
+    }
     if (!(p->h > 0) || !(p->dx > 0) || !(p->rho0 > 0) || !(p->c > 0) || !(p->dt > 0) ||
         !(p->eta > 0) || !(p->nu >= 0) || !(p->pb >= 0) || !(p->alpha >= 0) || !(p->U >= 0))
         return fail(SPH_EINVAL, "h, dx, rho0, c, dt, eta must be > 0 and nu, pb, alpha, U >= 0");
     if (p->dt * (p->c + p->U) > 0.5 * p->h)
-        return fail(SPH_EINVAL, "dt = %g exceeds the acoustic bound 0.5 h / (c + U) = %g", p->dt,
+        return fail(SPH_ECFL, "dt = %g exceeds the acoustic bound 0.5 h / (c + U) = %g", p->dt,
                     0.5 * p->h / (p->c + p->U));
     if (cap < 1 || cap > INT32_MAX) return fail(SPH_EINVAL, "cap must be in [1, 2^31)");
     if (p->list_cap < 0 || p->list_cap > 2048)

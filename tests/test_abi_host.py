@@ -98,6 +98,16 @@ def test_host_validation_rejects_bad_parameters():
     q = B.make_params(dict(prm, dim=1))
     out = C.c_size_t(0)
     assert B.lib().sph_workspace_size(C.byref(q), 10, C.byref(out)) == -6
+    # dt above the acoustic bound: SPH_ECFL; a non-finite parameter: SPH_ENONFINITE
+    q = B.make_params(dict(prm, dt=1.0))
+    assert B.lib().sph_workspace_size(C.byref(q), 10, C.byref(out)) == -4
+    assert b"acoustic bound" in B.lib().sph_last_error()
+    for key in ("h", "dt", "x_outlet"):
+        q = B.make_params(dict(prm, **{key: float("nan")}))
+        assert B.lib().sph_workspace_size(C.byref(q), 10, C.byref(out)) == -3, key
+        assert key.encode() in B.lib().sph_last_error()
+    q = B.make_params(dict(prm, hi=[float("inf"), 1.0, 0.0]))
+    assert B.lib().sph_workspace_size(C.byref(q), 10, C.byref(out)) == -3
 
 
 def test_null_state_rejected_before_launch():
