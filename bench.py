@@ -10,7 +10,7 @@ The default workload is the largest single-GPU configuration: the 3D duct
 
 Metric: pair-interactions/s = (fluid-neighbour pairs per right-hand side) x 2
 right-hand sides per step x steps / time. The line's value is the FP64 path;
-the FP32 path (FP32 pair arithmetic on cell-relative offsets, compensated
+the FP32 path (FP32 pair arithmetic on cell-relative offsets, FP64
 sums) and the adjoint (one reverse right-hand side) are reported beside it
 under "forms". The roofline object reports the force pass, timed alone with
 HIP events on the library's stream, against the algorithmic bytes per

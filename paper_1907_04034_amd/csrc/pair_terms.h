@@ -1,6 +1,6 @@
 // pair_terms.h -- device pieces shared by the pair kernels of libsph (the
 // gather kernels of pairs.hip and the LDS-tiled kernels of tiles.hip):
-// compensated accumulation, the FP32 neighbour record, one neighbour's data,
+// per-lane accumulation, the FP32 neighbour record, one neighbour's data,
 // the pair terms of the force pass and the fused RK2 stage updates. Both
 // kernel families evaluate every formula through these functions, so their
 // arithmetic is the same operation for operation.
@@ -24,16 +24,11 @@ struct Grp {
 // idle lanes and cross-lane reductions when the particle count alone fills
 // the chip. The host picks them from the capacity (override in sph_params).
 
-// Error-free addition (Knuth TwoSum): s + e == a + b exactly.
-__device__ inline void two_sum(float a, float b, float &s, float &e)
-{
-    s = a + b;
-    float bb = s - a;
-    e = (a - (s - bb)) + (b - bb);
-}
-
 // Per-lane accumulator and its group reduction: plain sums in FP64; in FP32
-// a value plus its running rounding error, carried through the reduction.
+// the FP32 terms are summed in an FP64 accumulator (one conversion and one
+// FP64 addition per term, which costs fewer VALU issue slots than carrying a
+// compensated FP32 pair through TwoSum, and keeps more bits), rounded to FP32
+// once after the group reduction.
 template <typename T>
 struct Acc {
     T s = T(0);
@@ -44,24 +39,10 @@ struct Acc {
 
 template <>
 struct Acc<float> {
-    float s = 0.f, e = 0.f;
-    __device__ inline void add(float v)
-    {
-        float t;
-        two_sum(s, v, s, t);
-        e += t;
-    }
+    double s = 0.0;
+    __device__ inline void add(float v) { s += double(v); }
     template <int G>
-    __device__ inline float reduce()
-    {
-#pragma unroll
-        for (int m = G / 2; m > 0; m >>= 1) {
-            float os = __shfl_xor(s, m, G), oe = __shfl_xor(e, m, G), t;
-            two_sum(s, os, s, t);
-            e = e + oe + t;
-        }
-        return s + e;
-    }
+    __device__ inline float reduce() { return float(gsum<G>(s)); }
 };
 
 // Writes the neighbour record of row i (lanes of the group split the 16-byte

@@ -7,9 +7,8 @@
 // from the particle count) owns one target particle and each lane a subset of
 // its neighbours, so several neighbour gathers of a target are in flight at
 // once and small particle counts still put thousands of waves on the 256 CUs. Per-target sums are
-// reduced across the group with lane shuffles; in FP32 the reduction carries
-// the rounding error of every addition (TwoSum), i.e. compensated FP32
-// accumulation. Particles are Morton-sorted, the neighbour table is row-major
+// reduced across the group with lane shuffles; in FP32 the terms are summed
+// in FP64 per lane and across the group, then rounded once. Particles are Morton-sorted, the neighbour table is row-major
 // (the neighbours of one target are contiguous, one coalesced load per group)
 // and the block -> particle-range mapping is XCD-aware so that each of the 8
 // XCDs works on a contiguous slab and its L2 serves the neighbour re-reads.

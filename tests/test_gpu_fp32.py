@@ -1,5 +1,5 @@
-"""FP32 form (FP32 pair arithmetic on cell-relative coordinates with
-compensated FP32 accumulation; FP64 positions, neighbour predicate and
+"""FP32 form (FP32 pair arithmetic on cell-relative coordinates with FP64
+accumulation of the terms; FP64 positions, neighbour predicate and
 outlet characteristic extrapolation) against the FP64 oracle.
 
 Gate for pair sums (a, b, pdot): max_i |f32_i - f64_i| <= 1e-5 max_i sum_j |t_ij|
