@@ -369,21 +369,30 @@ __device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R
     finish_nbr<DIM, T>(k, sep, w, nb);
 }
 
+// Division and square root of the pair terms: exact in FP64; in FP32 the
+// hardware reciprocal and square root (v_rcp_f32, v_sqrt_f32, within about one
+// ulp) instead of the correctly rounded sequences, which cost several times the
+// issue slots in this arithmetic-bound pass.
+__device__ inline double pdiv(double a, double b) { return a / b; }
+__device__ inline float pdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double psqrt(double x) { return sqrt(x); }
+__device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // Contribution of neighbour nb to target i (see the force-pass comment).
 template <int DIM, typename T>
 __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3], T pi, T rhoi,
                                 T vi2, T pavg, const Nbr<DIM, T> &nb, Acc<T> acc[3],
                                 Acc<T> bacc[3], Acc<T> &pdot, double fb[3])
 {
-    const T F = kernel_f<T>(k, T(sqrt(nb.r2)) * T(k.inv_h), T(k.gnorm));
+    const T F = kernel_f<T>(k, psqrt(nb.r2) * T(k.inv_h), T(k.gnorm));
     T gw[3] = {0, 0, 0};
 #pragma unroll
     for (int d = 0; d < DIM; ++d) gw[d] = F * nb.r[d];
     const T vsq = vi2 + nb.vol * nb.vol;
-    const T inv_rs = T(1) / (rhoi + nb.rho);
+    const T inv_rs = pdiv(T(1), rhoi + nb.rho);
     const T ptil = (nb.rho * (pi - pavg) + rhoi * (nb.p - pavg)) * inv_rs;
     const T hm = T(2) * rhoi * nb.rho * inv_rs;  // eta~ / nu
-    const T dfac = F * nb.r2 / (nb.r2 + T(k.eta_h2));
+    const T dfac = pdiv(F * nb.r2, nb.r2 + T(k.eta_h2));
     const T nu = T(k.nu);
     if (t == SPH_FLUID) {
         T si = T(0), sj = T(0);
@@ -403,7 +412,7 @@ __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3
             bacc[d].add(-T(k.pb) * T(k.inv_mass) * vsq * gw[d]);
             udiv += (ui[d] - (wall ? T(0) : nb.u[d])) * gw[d];
         }
-        pdot.add(T(k.mass) * rhoi / nb.rho * T(k.c2) * udiv +
+        pdot.add(pdiv(T(k.mass) * rhoi, nb.rho) * T(k.c2) * udiv +
                  f * (hm * T(k.nu_damp)) * dfac * (pi - nb.p));
     } else {
 #pragma unroll
