@@ -62,7 +62,7 @@ __device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
         if constexpr (L::F32)
-            v[L::X + d] = T(float(xi[d] - (k.lo[d] + double(c[d]) * k.cs[d])));
+            v[L::X + d] = T(cell_offset(k, d, xi[d], c[d]));
         else
             v[L::X + d] = T(xi[d]);
         const T u = ld<T>(R.u, d * C + i);

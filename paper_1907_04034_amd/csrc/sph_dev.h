@@ -430,6 +430,21 @@ __device__ inline void st(void *p, int64_t i, T v)
 
 __device__ inline bool bad_index(int32_t j, int64_t n) { return uint64_t(j) >= uint64_t(n); }
 
+// FP32 offset of position x from the corner of cell c along axis d (c is the
+// row's cell at the last sort). On a periodic axis the position is taken at
+// its image nearest that cell: a row that crossed the face since the sort was
+// wrapped into the box by its stage update while its cell stayed on the far
+// side, and the plain difference would be off by the box length.
+__device__ inline float cell_offset(const Dev &k, int d, double x, int c)
+{
+    double o = x - (k.lo[d] + double(c) * k.cs[d]);
+    if (k.periodic[d]) {
+        if (o > k.halfL[d]) o -= k.L[d];
+        else if (o < -k.halfL[d]) o += k.L[d];
+    }
+    return float(o);
+}
+
 // Pair separation r_i - r_j in the arithmetic type. FP64: minimum image of
 // the absolute positions. FP32: cell-relative offsets plus the (wrapped)
 // cell difference times the cell size, so no large coordinate is rounded to

@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
         if (sizeof(T) == 4) {
             // offsets from the bin cell's corner, for the FP32 pair arithmetic
             for (int d = lane; d < DIM; d += G)
-                off[d * C + i] = float(xi[d] - (k.lo[d] + double(c[d]) * k.cs[d]));
+                off[d * C + i] = cell_offset(k, d, xi[d], c[d]);
         }
     }
 }

@@ -145,6 +145,78 @@ def test_fp32_trajectory_drift_bounded(name, steps):
     assert dx < 1e-3 and du < 1e-3
 
 
+def _vortex_box_3d(n_side=10, U=1.0):
+    """Unit periodic cube with the divergence-free field u = U (-cos kx sin ky
+    cos kz, sin kx cos ky cos kz, 0), k = 2 pi, and p = -rho0 U^2 / 16 (cos 2kx
+    + cos 2ky)(cos 2kz + 2): the rows next to the faces move across them."""
+    prm, s = I.periodic_lattice(n_side=n_side, dim=3, dx=1.0 / n_side, U=U)
+    k = 2.0 * np.pi
+    x, y, z = s["x"][:, 0], s["x"][:, 1], s["x"][:, 2]
+    s["u"][:, 0] = -U * np.cos(k * x) * np.sin(k * y) * np.cos(k * z)
+    s["u"][:, 1] = U * np.sin(k * x) * np.cos(k * y) * np.cos(k * z)
+    s["u"][:, 2] = 0.0
+    s["ut"][:] = s["u"]
+    s["p"][:] = (-prm["rho0"] * U * U / 16.0 * (np.cos(2 * k * x) + np.cos(2 * k * y))
+                 * (np.cos(2 * k * z) + 2.0))
+    init = np.concatenate([s["u"], s["p"][:, None]], axis=1)
+    s["ring"][:] = init[:, None, :]
+    s["avg"][:] = init
+    return prm, s
+
+
+@pytest.mark.parametrize("reuse", [False, True])
+@pytest.mark.parametrize("name", ["tgv2d", "vortex3d"])
+def test_fp32_periodic_face_crossing(name, reuse):
+    """Particles that cross a periodic face between two sorts keep their pair
+    terms in FP32: the cell offsets of such a row are taken at the image
+    nearest its binned cell (the stage update wraps the position into the
+    box, the binned cell stays on the far side until the next sort). Taylor-
+    Green boxes, 100 FP32 steps against the FP64 oracle, with and without the
+    cell order kept between sorts; the run must see crossings. The flows
+    amplify rounding-sized differences, so the bar is relative: positions and
+    velocities within 20 times the oracle's own response to an FP32-sized
+    change (a factor 1 + 2^-24) of the initial positions (measured: 0.6 to 4
+    times; offsets taken without the image were 2.6e3 to 8.7e5 times)."""
+    steps = 100
+    if name == "tgv2d":
+        prm, s = I.taylor_green_box(n_side=20)
+    else:
+        prm, s = _vortex_box_3d()
+    if reuse:
+        prm = dict(prm, flags=prm["flags"] | I.FLAG_REUSE_BINS)
+    print(f"fp32 periodic crossing {name} steps={steps} reuse={reuse}", flush=True)
+    D = prm["dim"]
+    L = np.array(prm["hi"][:D]) - np.array(prm["lo"][:D])
+    o = O.Oracle(prm, s)
+    o.step(steps)
+    ref = o.state()
+
+    def errors(st):
+        assert np.array_equal(np.sort(st["id"]), np.sort(ref["id"]))
+        perm = _match(st, ref)
+        d = st["x"][:, :D] - ref["x"][perm][:, :D]
+        d -= L * np.round(d / L)
+        return (np.abs(d).max() / prm["dx"],
+                np.abs(st["u"][:, :D] - ref["u"][perm][:, :D]).max() / prm["U"])
+
+    s2 = I.snapshot_copy(s)
+    s2["x"][:, :D] *= 1.0 + 2.0 ** -24
+    o2 = O.Oracle(prm, s2)
+    o2.step(steps)
+    sx, su = errors(o2.state())
+    start = {int(v): k for k, v in enumerate(s["id"])}
+    moved = ref["x"][:, :D] - s["x"][[start[int(v)] for v in ref["id"]]][:, :D]
+    crossed = int((np.abs(moved) > 0.5 * L).any(axis=1).sum())
+    sim = B().Simulation(prm, s, prec="fp32")
+    sim.step(steps)
+    assert sim.poll_error() == 0
+    ex, eu = errors(sim.state())
+    print(f"  {crossed} particles crossed a face; |dx|/dx={ex:.2e} |du|/U={eu:.2e}; "
+          f"oracle FP32-size sensitivity {sx:.2e} {su:.2e}", flush=True)
+    assert crossed > 0
+    assert ex <= 20 * sx and eu <= 20 * su
+
+
 def _round_stored(snap):
     """The snapshot with the fields the FP32 form stores in FP32 (u, ut, p)
     rounded to FP32, as the FP32 state holds them."""
