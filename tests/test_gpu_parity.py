@@ -296,23 +296,25 @@ def test_bin_reuse_matches_sorting_every_step():
     assert all(v < 1e-9 for v in err.values()), err
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("tiles", [False, True])
 @pytest.mark.parametrize("name,caps", [("C4", (1, 14)), ("C5", (1, 52))])
-def test_candidate_lists_match_stencil_search(name, caps, tiles):
+def test_candidate_lists_match_stencil_search(name, caps, tiles, prec):
     """The step path's searches through stored candidate lists give the same
     neighbour tables, in the same order, as walking the cell stencil: the
     trajectory with the lists (automatic capacity) is bit-identical to one
     where every particle overflows its list (capacity 1: every search walks
     the stencil) and to one where only some do. Both for the gather search
-    (lists of rows) and the LDS-tiled one (lists of halo slots)."""
-    _print_case(f"candidate lists {name} tiles={tiles}")
+    (lists of rows) and the LDS-tiled one (lists of halo slots), in FP64 and
+    FP32."""
+    _print_case(f"candidate lists {name} tiles={tiles} {prec}")
     prm, s = I.config(name, small=True)
     s = I.jitter(prm, s, 0.05, 3, types=(I.FLUID, I.INLET, I.OUTLET))
     flags = prm["flags"] | I.FLAG_REUSE_BINS | (I.FLAG_TILES if tiles else 0)
     out = []
     for cap in (0,) + tuple(caps):
         q = dict(prm, flags=flags, list_cap=cap)
-        sim = B().Simulation(q, s)
+        sim = B().Simulation(q, s, prec=prec)
         drag = torch.zeros((80, 3), dtype=torch.float64, device="cuda")
         sim.step(80, drag_hist=drag)
         assert sim.poll_error() == 0
