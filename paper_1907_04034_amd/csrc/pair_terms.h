@@ -378,11 +378,19 @@ __device__ inline float pdiv(float a, float b) { return a * __builtin_amdgcn_rcp
 __device__ inline double psqrt(double x) { return sqrt(x); }
 __device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// Contribution of neighbour nb to target i (see the force-pass comment).
+// Contribution of neighbour nb to target i. The pressure of eq:tvf-p-ij-basa
+// is split as p~_ij = (p_i - pbar_i) + rho_i (p_j - p_i) / (rho_i + rho_j)
+// (the same value: the density weights sum to one), so a fluid target sums
+// only the pair-dependent part here and g = sum_j (V_i^2 + V_j^2)/m_i grad W_ij;
+// the caller adds -(p_i - pbar_i) g to the momentum rate once pbar_i, summed
+// over the same pairs, is known, and forms b = -p_b g (the background term of
+// eq:tvf-momentum). One sweep over the neighbours thus gives every sum, and
+// each rounding error stays proportional to a pressure difference, as in the
+// unsplit form. A body target takes p~ about zero (pbar = 0, the unsplit form).
 template <int DIM, typename T>
 __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3], T pi, T rhoi,
-                                T vi2, T pavg, const Nbr<DIM, T> &nb, Acc<T> acc[3],
-                                Acc<T> bacc[3], Acc<T> &pdot, double fb[3])
+                                T vi2, const Nbr<DIM, T> &nb, Acc<T> acc[3], Acc<T> gacc[3],
+                                Acc<T> &pdot, double fb[3])
 {
     const T F = kernel_f<T>(k, psqrt(nb.r2) * T(k.inv_h), T(k.gnorm));
     T gw[3] = {0, 0, 0};
@@ -390,11 +398,11 @@ __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3
     for (int d = 0; d < DIM; ++d) gw[d] = F * nb.r[d];
     const T vsq = vi2 + nb.vol * nb.vol;
     const T inv_rs = pdiv(T(1), rhoi + nb.rho);
-    const T ptil = (nb.rho * (pi - pavg) + rhoi * (nb.p - pavg)) * inv_rs;
     const T hm = T(2) * rhoi * nb.rho * inv_rs;  // eta~ / nu
     const T dfac = pdiv(F * nb.r2, nb.r2 + T(k.eta_h2));
     const T nu = T(k.nu);
     if (t == SPH_FLUID) {
+        const T pdif = rhoi * (nb.p - pi) * inv_rs;
         T si = T(0), sj = T(0);
 #pragma unroll
         for (int d = 0; d < DIM; ++d) si += wi[d] * gw[d];
@@ -408,16 +416,32 @@ __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3
 #pragma unroll
         for (int d = 0; d < DIM; ++d) {
             const T aterm = T(0.5) * (rhoi * ui[d] * si + nb.rho * nb.u[d] * sj);
-            acc[d].add(f * (-ptil * gw[d] + aterm + visc * (ui[d] - nb.u[d])));
-            bacc[d].add(-T(k.pb) * T(k.inv_mass) * vsq * gw[d]);
+            acc[d].add(f * (-pdif * gw[d] + aterm + visc * (ui[d] - nb.u[d])));
+            gacc[d].add(f * gw[d]);
             udiv += (ui[d] - (wall ? T(0) : nb.u[d])) * gw[d];
         }
         pdot.add(pdiv(T(k.mass) * rhoi, nb.rho) * T(k.c2) * udiv +
                  f * (hm * T(k.nu_damp)) * dfac * (pi - nb.p));
     } else {
+        const T ptil = (nb.rho * pi + rhoi * nb.p) * inv_rs;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
             fb[d] += double(vsq * (-ptil * gw[d] + hm * nu * dfac * (ui[d] - nb.u[d])));
+    }
+}
+
+// The momentum and background rates of a fluid target from the group's sums:
+// a = sum_j(...) - (p_i - pbar_i) g and b = -p_b g, formed in FP64 and
+// rounded once to the field type.
+template <int DIM, typename T, int G>
+__device__ inline void finish_rates(const Dev &k, Acc<T> acc[3], Acc<T> gacc[3], double dp,
+                                    T a[3], T b[3])
+{
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double g = gsum<G>(gacc[d].s);
+        a[d] = T(gsum<G>(acc[d].s) - dp * g);
+        b[d] = T(-k.pb * g);
     }
 }
 

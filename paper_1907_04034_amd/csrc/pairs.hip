@@ -767,9 +767,10 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
 }
 
 // ---------------------------------------------------------------- force pass
-// Fluid i: pbar_i (eq:pavg, self included), then over j != i the momentum
-// rate of eq:tvf-momentum with p~_ij of eq:tvf-p-ij-basa, the background term
-// of eq:transport-vel and the pressure rate of eq:p-edac. A = rho u (ut - u)
+// Fluid i, in one sweep over its neighbours: pbar_i (eq:pavg, self included)
+// and over j != i the momentum rate of eq:tvf-momentum with p~_ij of
+// eq:tvf-p-ij-basa (its pbar_i part applied after the sweep, see pair_acc),
+// the background term of eq:transport-vel and the pressure rate of eq:p-edac. A = rho u (ut - u)
 // for fluid, 0 otherwise; slip walls take no viscous part; walls enter the
 // divergence with zero wall velocity and the viscous term with u_g.
 // Body i: force of eq:tvf-momentum_solid from fluid neighbours.
@@ -816,11 +817,10 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
             const T rhoi = ld<T>(o.rho, i);
             const T vi = ld<T>(o.vol, i);
             const T vi2 = vi * vi;
-            // the lane's first PF neighbours are loaded before the pbar
-            // reduction (all indices first, then all rows), so that with at
-            // most PF*G neighbours all gathers form two round trips; the
-            // indices are read whatever the count (within the row's maxnb
-            // entries; entries past the count are not used)
+            // one sweep over the neighbours gives every sum (pair_acc): the
+            // lane's first PF neighbours are fetched at once, all indices
+            // first (read whatever the count, within the row's maxnb entries;
+            // entries past the count are not used), then all rows
             const int32_t *row = nl.nbr + i * nl.maxnb;
             int32_t jp[PF];
             bool okp[PF];
@@ -841,50 +841,21 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
 #pragma unroll
             for (int f = 0; f < PF; ++f)
                 fetch_nbr<DIM, T>(k, m, R, o, okp[f] ? jp[f] : int32_t(i), raw[f]);
-            Nbr<DIM, T> nbp[PF];
+            // psum: the pressures of eq:pavg (every neighbour, self included)
+            Acc<T> acc[3], gacc[3], pdot, psum;
 #pragma unroll
-            for (int f = 0; f < PF; ++f) finish_nbr<DIM, T>(k, sep, raw[f], nbp[f]);
-            // the neighbour average of eq:pavg enters the fluid's momentum;
-            // the body force takes p~ about zero (the average of a surface
-            // particle's neighbours would cancel the pressure on the body)
-            T pavg = T(0);
-            if (t == SPH_FLUID && !(k.flags & SPH_FLAG_NO_PAVG)) {
-                Acc<T> sp;
-#pragma unroll
-                for (int f = 0; f < PF; ++f)
-                    if (okp[f]) sp.add(nbp[f].p);
-                // the rest: in batches of PF slots (indices, then pressures)
-                // where the tail is long (3D) or the rows are records (FP32);
-                // in 2D FP64 the batch's registers cost more than it saves
-                // (1.2M particles: 4 -> 3 waves per SIMD, 188 -> 207 us)
-                if constexpr (!kBatchTail)
-                    for (int q = lane + PF * G; q < cnt; q += G) {
-                        const int32_t j = row[q];
-                        if (!bad_index(j, n)) sp.add(ld<T>(R.p, j));
-                    }
-                else
-                for (int q0 = lane + PF * G; q0 < cnt; q0 += PF * G) {
-                    int32_t jb[PF];
-                    T pb[PF];
-#pragma unroll
-                    for (int f = 0; f < PF; ++f) jb[f] = q0 + f * G < cnt ? row[q0 + f * G] : -1;
-#pragma unroll
-                    for (int f = 0; f < PF; ++f)
-                        pb[f] = ld<T>(R.p, bad_index(jb[f], n) ? int32_t(i) : jb[f]);
-#pragma unroll
-                    for (int f = 0; f < PF; ++f)
-                        if (q0 + f * G < cnt && !bad_index(jb[f], n)) sp.add(pb[f]);
-                }
-                pavg = sp.template reduce<G>() / T(cnt);
+            for (int f = 0; f < PF; ++f) {
+                if (!okp[f]) continue;
+                Nbr<DIM, T> nb;
+                finish_nbr<DIM, T>(k, sep, raw[f], nb);
+                psum.add(nb.p);
+                if (jp[f] != i && !(t == SPH_BODY && nb.tj != SPH_FLUID))
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
             }
-            Acc<T> acc[3], bacc[3], pdot;
-#pragma unroll
-            for (int f = 0; f < PF; ++f)
-                if (okp[f] && jp[f] != i && !(t == SPH_BODY && nbp[f].tj != SPH_FLUID))
-                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nbp[f], acc, bacc, pdot,
-                                     fb);
-            // the rest, batched as for pbar: each batch fetched like the first
-            // slots (indices, then every row, then the arithmetic in slot order)
+            // the rest: in batches of PF slots (indices, then every row, then
+            // the arithmetic in slot order) where the tail is long (3D) or the
+            // rows are records (FP32); in 2D FP64 the batch's registers cost
+            // more than it saves (1.2M particles: 4 -> 3 waves per SIMD)
             if constexpr (!kBatchTail)
                 for (int q = lane + PF * G; q < cnt; q += G) {
                     const int32_t j = row[q];
@@ -892,11 +863,11 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                         raise_error(err, SPH_ERR_CELL_RANGE);
                         continue;
                     }
-                    if (j == i) continue;
                     Nbr<DIM, T> nb;
                     load_nbr<DIM, T>(k, m, R, o, sep, j, nb);
-                    if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
-                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
+                    psum.add(nb.p);
+                    if (j == i || (t == SPH_BODY && nb.tj != SPH_FLUID)) continue;
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
                 }
             else
             for (int q0 = lane + PF * G; q0 < cnt; q0 += PF * G) {
@@ -918,20 +889,25 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                     fetch_nbr<DIM, T>(k, m, R, o, okb[f] ? jb[f] : int32_t(i), rb[f]);
 #pragma unroll
                 for (int f = 0; f < PF; ++f) {
-                    if (!okb[f] || jb[f] == i) continue;
+                    if (!okb[f]) continue;
                     Nbr<DIM, T> nb;
                     finish_nbr<DIM, T>(k, sep, rb[f], nb);
-                    if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
-                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot, fb);
+                    psum.add(nb.p);
+                    if (jb[f] == i || (t == SPH_BODY && nb.tj != SPH_FLUID)) continue;
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
                 }
             }
+            // the neighbour average of eq:pavg enters the fluid's momentum;
+            // the body force takes p~ about zero (the average of a surface
+            // particle's neighbours would cancel the pressure on the body)
+            double pbar = 0.0;
+            const double ps = gsum<G>(psum.s);
+            if (t == SPH_FLUID && !(k.flags & SPH_FLAG_NO_PAVG)) pbar = ps / double(cnt);
+            const T pavg = T(pbar);
             T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+            finish_rates<DIM, T, G>(k, acc, gacc, double(pi) - pbar, a, b);
 #pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                a[d] = acc[d].template reduce<G>();
-                b[d] = bacc[d].template reduce<G>();
-                fb[d] = gsum<G>(fb[d]);
-            }
+            for (int d = 0; d < DIM; ++d) fb[d] = gsum<G>(fb[d]);
             const T pd = pdot.template reduce<G>();
             if (lane == 0) {
                 if (mode == 0) {

@@ -580,7 +580,7 @@ __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, 
                 bool bad = false;
                 // the neighbour average of eq:pavg enters the fluid's momentum;
                 // the body force takes p~ about zero
-                T pavg = T(0);
+                double pbar = 0.0;
                 if (t == SPH_FLUID && !(k.flags & SPH_FLAG_NO_PAVG)) {
                     Acc<T> sp;
                     for (int q0 = lane; q0 < cnt; q0 += NQ * G) {
@@ -602,9 +602,10 @@ __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, 
                             sp.add(pj);
                         }
                     }
-                    pavg = sp.template reduce<G>() / T(cnt);
+                    pbar = gsum<G>(sp.s) / double(cnt);
                 }
-                Acc<T> acc[3], bacc[3], pdot;
+                const T pavg = T(pbar);
+                Acc<T> acc[3], gacc[3], pdot;
                 double fb[3] = {0, 0, 0};
                 for (int q0 = lane; q0 < cnt; q0 += NQ * G) {
                     int fq[NQ];
@@ -632,18 +633,14 @@ __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, 
                         Nbr<DIM, T> nb;
                         finish_nbr<DIM, T>(k, sep, raw, nb);
                         if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
-                        pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, pavg, nb, acc, bacc, pdot,
-                                         fb);
+                        pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
                     }
                 }
                 if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
                 T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
+                finish_rates<DIM, T, G>(k, acc, gacc, double(pi) - pbar, a, b);
 #pragma unroll
-                for (int d = 0; d < DIM; ++d) {
-                    a[d] = acc[d].template reduce<G>();
-                    b[d] = bacc[d].template reduce<G>();
-                    fb[d] = gsum<G>(fb[d]);
-                }
+                for (int d = 0; d < DIM; ++d) fb[d] = gsum<G>(fb[d]);
                 const T pd = pdot.template reduce<G>();
                 if (lane == 0) {
                     if (mode == 0) {
