@@ -278,8 +278,9 @@ static WsLayout layout(const Dev &k)
     // candidate lists: rows (gather kernels) or 16-bit LDS slots (tiled search)
     w.vnbr = take(k.lists ? (k.tiles ? sizeof(uint16_t) : sizeof(int32_t)) * size_t(k.vmax) * C
                           : 0);
-    // neighbour records of the FP32 force pass (sized whatever the precision:
-    // the workspace size does not depend on it)
+    // neighbour records of the FP32 force pass, or the FP64 Shepard sums
+    // (sized for the records whatever the precision: the workspace size does
+    // not depend on it)
     w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, float>()) * C);
     // LDS slots of the tiled search's table entries, read by the force pass
     w.lslot = take(k.tiles ? sizeof(uint16_t) * size_t(k.lmax) * C : 0);
@@ -358,6 +359,7 @@ static DevDerived dev_derived(const sph_derived *o)
     d.sfl = o->sfl;
     d.red = o->red;
     d.rec = nullptr;
+    d.shep = nullptr;
     return d;
 }
 
@@ -413,6 +415,7 @@ struct Ctx {
     {
         DevDerived d = dev_derived(o);
         d.rec = k.prec == SPH_FP32 ? at<void>(ws, w.rec) : nullptr;
+        d.shep = k.prec == SPH_FP64 ? at<void>(ws, w.rec) : nullptr;
         return d;
     }
     double *dragpart() const { return at<double>(ws, w.dragpart); }

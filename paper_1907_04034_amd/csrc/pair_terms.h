@@ -273,7 +273,7 @@ struct Nbr {
 };
 
 // One neighbour's data: FP32 from its record (Rec) in a few 16-byte loads;
-// FP64 one load per field from the state and derived arrays (measured: the
+// FP64 one load per field from the state arrays and the Shepard sum (measured: the
 // 128- and 80-byte FP64 records made the force pass slower, 1.93 -> 2.11 ms
 // on the 4.6M-particle duct, while FP32 records cut it 1.67 -> 1.23 ms).
 // fetch_nbr only issues the loads and finish_nbr does the arithmetic on them,
@@ -285,7 +285,7 @@ struct NbrRaw {
     using L = Rec<DIM, T>;
     T v[L::F32 ? L::NC * L::PER : 1];  // FP32: the record
     double xj[3];                      // FP64: the fields
-    T u[3], ut[3], p, rho, vol;
+    T u[3], ut[3], p, s;  // FP64: s is the Shepard sum
     int tj;
     int32_t j;
 };
@@ -313,8 +313,7 @@ __device__ inline void fetch_nbr(const Dev &k, const DevState &m, const Fields &
             w.ut[d] = ld<T>(R.ut, d * C + j);
         }
         w.p = ld<T>(R.p, j);
-        w.rho = ld<T>(o.rho, j);
-        w.vol = ld<T>(o.vol, j);
+        w.s = ld<T>(o.shep, j);
     }
 }
 
@@ -354,8 +353,8 @@ __device__ inline void finish_nbr(const Dev &k, const Sep<DIM, T> &sep, const Nb
             nb.w[d] = w.ut[d] - w.u[d];
         }
         nb.p = w.p;
-        nb.rho = w.rho;
-        nb.vol = w.vol;
+        nb.rho = T(k.mass) * w.s;  // as the density pass forms the stored fields
+        nb.vol = T(1) / w.s;
     }
 }
 

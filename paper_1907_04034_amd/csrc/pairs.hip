@@ -281,6 +281,7 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
         if (dens) {
             st<T>(o.rho, i, T(k.mass) * S);
             st<T>(o.vol, i, T(1) / S);
+            if (o.shep) st<T>(o.shep, i, S);
         }
     }
     if (dens && o.rec)
@@ -328,6 +329,7 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
     if (lane == 0) {
         st<T>(o.rho, i, T(k.mass) * S);
         st<T>(o.vol, i, T(1) / S);
+        if (o.shep) st<T>(o.shep, i, S);
     }
     if (o.rec) {
         int c[3] = {0, 0, 0};

@@ -84,6 +84,10 @@ struct DevDerived {
     double *jcur, *force, *drag, *sfl;
     uint8_t *red;
     void *rec;  // neighbour records of the force pass (Rec), [cap][Rec::N]
+    // FP64: the Shepard sums S of the density pass, from which the force pass
+    // forms a neighbour's rho = m S and V = 1/S (one gather instead of two,
+    // the same operations as the stored fields, so the same values)
+    void *shep;
 };
 
 // Neighbour record: what the force pass gathers of a neighbour j, packed so

@@ -425,6 +425,7 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
             if (dens) {
                 st<T>(o.rho, i, T(k.mass) * S);
                 st<T>(o.vol, i, T(1) / S);
+                if (o.shep) st<T>(o.shep, i, S);
             }
         }
         if (dens && o.rec) write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cposi, lane);
@@ -438,7 +439,7 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
 
 // ----------------------------------------------------------------- force
 // Halo rows of the force pass in LDS: the packed record (FP32) or the FP64
-// fields a neighbour contributes (x, u, ut, p, rho, V, kind).
+// fields a neighbour contributes (x, u, ut, p, the Shepard sum, kind).
 template <int DIM, typename T>
 struct ForceStage;
 
@@ -474,8 +475,8 @@ struct ForceStage<DIM, float> {
 template <int DIM>
 struct ForceStage<DIM, double> {
     static constexpr int CAP = tile_cap_force(DIM, SPH_FP64);
-    static constexpr int X = 0, U = DIM, UT = 2 * DIM, P = 3 * DIM, RHO = 3 * DIM + 1,
-                         VOL = 3 * DIM + 2, NF = 3 * DIM + 3;
+    static constexpr int X = 0, U = DIM, UT = 2 * DIM, P = 3 * DIM, SH = 3 * DIM + 1,
+                         NF = 3 * DIM + 2;
     double f64[NF][CAP];
     uint8_t kind[CAP];
     __device__ inline void put(const Dev &k, const DevState &m, const Fields &R,
@@ -490,8 +491,7 @@ struct ForceStage<DIM, double> {
             v[UT + d] = ld<double>(R.ut, d * C + j);
         }
         v[P] = ld<double>(R.p, j);
-        v[RHO] = ld<double>(o.rho, j);
-        v[VOL] = ld<double>(o.vol, j);
+        v[SH] = ld<double>(o.shep, j);
         const uint8_t t = m.type[j];
 #pragma unroll
         for (int q = 0; q < NF; ++q) f64[q][f] = v[q];
@@ -509,8 +509,7 @@ struct ForceStage<DIM, double> {
             w.ut[d] = f64[UT + d][f];
         }
         w.p = f64[P][f];
-        w.rho = f64[RHO][f];
-        w.vol = f64[VOL][f];
+        w.s = f64[SH][f];
     }
     __device__ inline double pres(int f) const { return f64[P][f]; }
 };
