@@ -272,6 +272,15 @@ struct Nbr {
     T r[3], r2, u[3], w[3], p, rho, vol;  // w = ut - u
 };
 
+// Division and square root of the pair terms: exact in FP64; in FP32 the
+// hardware reciprocal and square root (v_rcp_f32, v_sqrt_f32, within about one
+// ulp) instead of the correctly rounded sequences, which cost several times the
+// issue slots in this arithmetic-bound pass.
+__device__ inline double pdiv(double a, double b) { return a / b; }
+__device__ inline float pdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double psqrt(double x) { return sqrt(x); }
+__device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // One neighbour's data: FP32 from its record (Rec) in a few 16-byte loads;
 // FP64 one load per field from the state arrays and the Shepard sum (measured: the
 // 128- and 80-byte FP64 records made the force pass slower, 1.93 -> 2.11 ms
@@ -331,7 +340,7 @@ __device__ inline void finish_nbr(const Dev &k, const Sep<DIM, T> &sep, const Nb
             nb.r2 = sep.get_rec(k, v + L::X, word & kCellBits, nb.r);
             const T S = v[L::VOL];
             nb.rho = T(k.mass) * S;
-            nb.vol = T(1) / S;
+            nb.vol = pdiv(T(1), S);
         } else {
             nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
             nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
@@ -368,14 +377,6 @@ __device__ inline void load_nbr(const Dev &k, const DevState &m, const Fields &R
     finish_nbr<DIM, T>(k, sep, w, nb);
 }
 
-// Division and square root of the pair terms: exact in FP64; in FP32 the
-// hardware reciprocal and square root (v_rcp_f32, v_sqrt_f32, within about one
-// ulp) instead of the correctly rounded sequences, which cost several times the
-// issue slots in this arithmetic-bound pass.
-__device__ inline double pdiv(double a, double b) { return a / b; }
-__device__ inline float pdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
-__device__ inline double psqrt(double x) { return sqrt(x); }
-__device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
 // Contribution of neighbour nb to target i. The pressure of eq:tvf-p-ij-basa
 // is split as p~_ij = (p_i - pbar_i) + rho_i (p_j - p_i) / (rho_i + rho_j)
@@ -385,11 +386,13 @@ __device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 // over the same pairs, is known, and forms b = -p_b g (the background term of
 // eq:tvf-momentum). One sweep over the neighbours thus gives every sum, and
 // each rounding error stays proportional to a pressure difference, as in the
-// unsplit form. A body target takes p~ about zero (pbar = 0, the unsplit form).
+// unsplit form. A body target takes p~ about zero (pbar = 0, the unsplit form)
+// and sums the force of eq:tvf-momentum_solid in acc, which it does not use
+// otherwise.
 template <int DIM, typename T>
 __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3], T pi, T rhoi,
                                 T vi2, const Nbr<DIM, T> &nb, Acc<T> acc[3], Acc<T> gacc[3],
-                                Acc<T> &pdot, double fb[3])
+                                Acc<T> &pdot)
 {
     const T F = kernel_f<T>(k, psqrt(nb.r2) * T(k.inv_h), T(k.gnorm));
     T gw[3] = {0, 0, 0};
@@ -419,28 +422,33 @@ __device__ inline void pair_acc(const Dev &k, int t, const T ui[3], const T wi[3
             gacc[d].add(f * gw[d]);
             udiv += (ui[d] - (wall ? T(0) : nb.u[d])) * gw[d];
         }
-        pdot.add(pdiv(T(k.mass) * rhoi, nb.rho) * T(k.c2) * udiv +
-                 f * (hm * T(k.nu_damp)) * dfac * (pi - nb.p));
+        // m_j rho_i / rho_j of eq:p-edac is rho_i V_j: every particle has
+        // mass m and V = 1/S = m/rho
+        pdot.add(rhoi * nb.vol * T(k.c2) * udiv + f * (hm * T(k.nu_damp)) * dfac * (pi - nb.p));
     } else {
         const T ptil = (nb.rho * pi + rhoi * nb.p) * inv_rs;
 #pragma unroll
         for (int d = 0; d < DIM; ++d)
-            fb[d] += double(vsq * (-ptil * gw[d] + hm * nu * dfac * (ui[d] - nb.u[d])));
+            acc[d].add(vsq * (-ptil * gw[d] + hm * nu * dfac * (ui[d] - nb.u[d])));
     }
 }
 
-// The momentum and background rates of a fluid target from the group's sums:
+// The group's sums: for a fluid target the momentum and background rates
 // a = sum_j(...) - (p_i - pbar_i) g and b = -p_b g, formed in FP64 and
-// rounded once to the field type.
+// rounded once to the field type; for a body target the body force fb (a and
+// b zero).
 template <int DIM, typename T, int G>
-__device__ inline void finish_rates(const Dev &k, Acc<T> acc[3], Acc<T> gacc[3], double dp,
-                                    T a[3], T b[3])
+__device__ inline void finish_rates(const Dev &k, int t, Acc<T> acc[3], Acc<T> gacc[3],
+                                    double dp, T a[3], T b[3], double fb[3])
 {
+    const bool body = t == SPH_BODY;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
+        const double s = gsum<G>(acc[d].s);
         const double g = gsum<G>(gacc[d].s);
-        a[d] = T(gsum<G>(acc[d].s) - dp * g);
-        b[d] = T(-k.pb * g);
+        fb[d] = body ? s : 0.0;
+        a[d] = body ? T(0) : T(s - dp * g);
+        b[d] = body ? T(0) : T(-k.pb * g);
     }
 }
 

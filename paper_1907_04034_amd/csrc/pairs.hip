@@ -852,7 +852,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                 finish_nbr<DIM, T>(k, sep, raw[f], nb);
                 psum.add(nb.p);
                 if (jp[f] != i && !(t == SPH_BODY && nb.tj != SPH_FLUID))
-                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot);
             }
             // the rest: in batches of PF slots (indices, then every row, then
             // the arithmetic in slot order) where the tail is long (3D) or the
@@ -869,7 +869,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                     load_nbr<DIM, T>(k, m, R, o, sep, j, nb);
                     psum.add(nb.p);
                     if (j == i || (t == SPH_BODY && nb.tj != SPH_FLUID)) continue;
-                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot);
                 }
             else
             for (int q0 = lane + PF * G; q0 < cnt; q0 += PF * G) {
@@ -896,7 +896,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
                     finish_nbr<DIM, T>(k, sep, rb[f], nb);
                     psum.add(nb.p);
                     if (jb[f] == i || (t == SPH_BODY && nb.tj != SPH_FLUID)) continue;
-                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
+                    pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot);
                 }
             }
             // the neighbour average of eq:pavg enters the fluid's momentum;
@@ -907,9 +907,7 @@ __global__ void __launch_bounds__(kBlock) k_force(Dev k, DevState m, Fields R, F
             if (t == SPH_FLUID && !(k.flags & SPH_FLAG_NO_PAVG)) pbar = ps / double(cnt);
             const T pavg = T(pbar);
             T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
-            finish_rates<DIM, T, G>(k, acc, gacc, double(pi) - pbar, a, b);
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) fb[d] = gsum<G>(fb[d]);
+            finish_rates<DIM, T, G>(k, t, acc, gacc, double(pi) - pbar, a, b, fb);
             const T pd = pdot.template reduce<G>();
             if (lane == 0) {
                 if (mode == 0) {

@@ -632,14 +632,12 @@ __global__ void __launch_bounds__(kBlock) k_tforce(Dev k, DevState m, Fields R, 
                         Nbr<DIM, T> nb;
                         finish_nbr<DIM, T>(k, sep, raw, nb);
                         if (t == SPH_BODY && nb.tj != SPH_FLUID) continue;
-                        pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot, fb);
+                        pair_acc<DIM, T>(k, t, ui, wi, pi, rhoi, vi2, nb, acc, gacc, pdot);
                     }
                 }
                 if (bad) raise_error(err, SPH_ERR_CELL_RANGE);
                 T a[3] = {0, 0, 0}, b[3] = {0, 0, 0};
-                finish_rates<DIM, T, G>(k, acc, gacc, double(pi) - pbar, a, b);
-#pragma unroll
-                for (int d = 0; d < DIM; ++d) fb[d] = gsum<G>(fb[d]);
+                finish_rates<DIM, T, G>(k, t, acc, gacc, double(pi) - pbar, a, b, fb);
                 const T pd = pdot.template reduce<G>();
                 if (lane == 0) {
                     if (mode == 0) {
