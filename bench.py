@@ -450,6 +450,11 @@ def main():
     ap.add_argument("--tiles", action="store_true",
                     help="the LDS-tiled neighbour search and force pass instead of the gather "
                          "kernels")
+    ap.add_argument("--group-force", type=int, default=0,
+                    help="lanes per target of the force pass (1..32; 0: the library's choice)")
+    ap.add_argument("--group-nbr", type=int, default=0,
+                    help="lanes per target of the neighbour search (1..32; 0: the library's "
+                         "choice)")
     ap.add_argument("--sort-every-step", action="store_true",
                     help="sort by cell at every step instead of keeping the cell order "
                          "while the skin allows")
@@ -476,6 +481,8 @@ def main():
     mark = Marker(args.mark)
     prm, s = I.config(args.config)
     prm["outlet"] = I.OUTLETS[args.outlet]
+    prm["group_force"] = args.group_force
+    prm["group_nbr"] = args.group_nbr
     if args.mirror_inlet:
         prm["flags"] |= I.FLAG_MIRROR_INLET
     if not args.sort_every_step:

@@ -278,10 +278,12 @@ static WsLayout layout(const Dev &k)
     // candidate lists: rows (gather kernels) or 16-bit LDS slots (tiled search)
     w.vnbr = take(k.lists ? (k.tiles ? sizeof(uint16_t) : sizeof(int32_t)) * size_t(k.vmax) * C
                           : 0);
-    // neighbour records of the FP32 force pass, or the FP64 Shepard sums
-    // (sized for the records whatever the precision: the workspace size does
-    // not depend on it)
-    w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, float>()) * C);
+    // neighbour records of the force pass: FP32, or FP64 in 3D (sized for the
+    // larger whatever the precision: the workspace size does not depend on it)
+    w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, double>()) * C);
+    // the FP64 Shepard sums, from which k_pack_rec forms the records and
+    // which the LDS-tiled force pass stages
+    w.shep = take(sizeof(double) * C);
     // LDS slots of the tiled search's table entries, read by the force pass
     w.lslot = take(k.tiles ? sizeof(uint16_t) * size_t(k.lmax) * C : 0);
     w.ttab = take(k.tiles ? sizeof(int32_t) * size_t(tile_table_ints(k)) : 0);
@@ -414,8 +416,9 @@ struct Ctx {
     DevDerived der(const sph_derived *o) const
     {
         DevDerived d = dev_derived(o);
-        d.rec = k.prec == SPH_FP32 ? at<void>(ws, w.rec) : nullptr;
-        d.shep = k.prec == SPH_FP64 ? at<void>(ws, w.rec) : nullptr;
+        // records where the force pass gathers them (Rec::USE): FP32, 3D FP64
+        d.rec = k.prec == SPH_FP32 || k.dim == 3 ? at<void>(ws, w.rec) : nullptr;
+        d.shep = k.prec == SPH_FP64 ? at<void>(ws, w.shep) : nullptr;
         return d;
     }
     double *dragpart() const { return at<double>(ws, w.dragpart); }
@@ -481,6 +484,7 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
                    at<uint32_t>(c.ws, c.w.cpos_s), off ? off : c.off(),
                    at<uint16_t>(c.ws, c.w.lslot), at<int32_t>(c.ws, c.w.ttab),
                    clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
+    if (dens) launch_pack_rec(c.k, dev_state(st), R, c.der(o), c.s);
 }
 
 static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
@@ -759,6 +763,7 @@ int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
     launch_density(c.k, dev_state(st), fields_of(st), dev_nlist(nl), c.der(out),
                    at<uint32_t>(ws, c.w.cpos_s), c.err(), c.s);
+    launch_pack_rec(c.k, dev_state(st), fields_of(st), c.der(out), c.s);
     return check_hip("sph_density");
 }
 
@@ -781,6 +786,7 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
     const Fields F = fields_of(st);
     launch_density(c.k, dev_state(st), F, dev_nlist(nl), c.der(out), at<uint32_t>(ws, c.w.cpos_s),
                    c.err(), c.s);
+    launch_pack_rec(c.k, dev_state(st), F, c.der(out), c.s);
     do_boundary(c, st, F, nl, out);
     do_force(c, st, F, F, nl, out, 0, out->drag, nullptr);
     return check_hip("sph_rhs");

@@ -45,26 +45,24 @@ struct Acc<float> {
     __device__ inline float reduce() { return float(gsum<G>(s)); }
 };
 
-// Writes the neighbour record of row i (lanes of the group split the 16-byte
-// chunks): the stage's position (FP64) or cell offset (FP32, the same value
-// as the offset array), p, u, w = ut - u, rho, V, the kind and in FP32 the
-// packed cell.
+// Writes the FP32 neighbour record of row i (lanes of the group split the
+// 16-byte chunks): the cell offset (the same value as the offset array), p,
+// u, w = ut - u, rho and V or S, the kind and the packed cell. (FP64 records
+// are written by k_pack_rec.)
 template <int DIM, typename T, int G>
 __device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &R, void *rec,
                                  int64_t i, T S, const double xi[3], const int c[3],
                                  uint32_t cposi, int lane)
 {
     using L = Rec<DIM, T>;
+    static_assert(L::F32, "FP64 records are written by k_pack_rec");
     const int64_t C = k.cap;
     T v[L::NC * L::PER];
 #pragma unroll
     for (int q = 0; q < L::NC * L::PER; ++q) v[q] = T(0);
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        if constexpr (L::F32)
-            v[L::X + d] = T(cell_offset(k, d, xi[d], c[d]));
-        else
-            v[L::X + d] = T(xi[d]);
+        v[L::X + d] = T(cell_offset(k, d, xi[d], c[d]));
         const T u = ld<T>(R.u, d * C + i);
         v[L::U + d] = u;
         v[L::W + d] = ld<T>(R.ut, d * C + i) - u;
@@ -73,21 +71,16 @@ __device__ inline void write_rec(const Dev &k, const DevState &m, const Fields &
     if constexpr (L::PACKED) {
         v[L::VOL] = S;
         v[L::AUX] = rec_word<T>(cposi | (kind_class(m.type[i]) << 30));
-    } else if constexpr (L::F32) {
+    } else {
         v[L::RHO] = T(k.mass) * S;
         v[L::VOL] = T(1) / S;
         v[L::AUX] = rec_word<T>(cposi);
         v[L::AUX + 1] = rec_word<T>(uint32_t(m.type[i]));
-    } else {
-        v[L::RHO] = T(k.mass) * S;
-        v[L::VOL] = T(1) / S;
-        v[L::AUX] = rec_word<T>(uint32_t(m.type[i]));
     }
-    using V = typename Chunk<T>::V;
-    V *dst = reinterpret_cast<V *>(static_cast<T *>(rec) + i * L::N);
 #pragma unroll
     for (int ch = 0; ch < L::NC; ++ch)
-        if ((ch & (G - 1)) == (lane & (G - 1))) dst[ch] = Chunk<T>::make(v + ch * L::PER);
+        if ((ch & (G - 1)) == (lane & (G - 1)))
+            *rec_chunk<DIM, T>(rec, C, i, ch) = Chunk<T>::make(v + ch * L::PER);
 }
 
 // ------------------------------------------------------------ stage updates
@@ -281,10 +274,10 @@ __device__ inline float pdiv(float a, float b) { return a * __builtin_amdgcn_rcp
 __device__ inline double psqrt(double x) { return sqrt(x); }
 __device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-// One neighbour's data: FP32 from its record (Rec) in a few 16-byte loads;
-// FP64 one load per field from the state arrays and the Shepard sum (measured: the
-// 128- and 80-byte FP64 records made the force pass slower, 1.93 -> 2.11 ms
-// on the 4.6M-particle duct, while FP32 records cut it 1.67 -> 1.23 ms).
+// One neighbour's data from its record (Rec) in a few 16-byte loads (measured
+// on the 4.6M-particle duct: FP32 records cut the force pass 1.67 -> 1.23 ms;
+// row-major FP64 records of 128 and 80 bytes made it slower, 1.93 -> 2.11 ms,
+// where the chunk-major ones of rec_chunk do not).
 // fetch_nbr only issues the loads and finish_nbr does the arithmetic on them,
 // so a lane that prefetches several neighbours issues every fetch before the
 // first finish and their gathers overlap (a separation computed right after
@@ -292,9 +285,9 @@ __device__ inline float psqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 template <int DIM, typename T>
 struct NbrRaw {
     using L = Rec<DIM, T>;
-    T v[L::F32 ? L::NC * L::PER : 1];  // FP32: the record
-    double xj[3];                      // FP64: the fields
-    T u[3], ut[3], p, s;  // FP64: s is the Shepard sum
+    T v[L::USE ? L::NC * L::PER : 1];  // the record
+    double xj[L::USE ? 1 : 3];         // 2D FP64: the fields and the Shepard sum
+    T u[L::USE ? 1 : 3], ut[L::USE ? 1 : 3], p, s;
     int tj;
     int32_t j;
 };
@@ -305,12 +298,10 @@ __device__ inline void fetch_nbr(const Dev &k, const DevState &m, const Fields &
 {
     using L = Rec<DIM, T>;
     w.j = j;
-    if constexpr (L::F32) {
-        using V = typename Chunk<T>::V;
-        const V *src =
-            reinterpret_cast<const V *>(static_cast<const T *>(o.rec) + int64_t(j) * L::N);
+    if constexpr (L::USE) {
 #pragma unroll
-        for (int ch = 0; ch < L::NC; ++ch) Chunk<T>::get(src[ch], w.v + ch * L::PER);
+        for (int ch = 0; ch < L::NC; ++ch)
+            Chunk<T>::get(*rec_chunk<DIM, T>(o.rec, k.cap, j, ch), w.v + ch * L::PER);
     } else {
         const int64_t C = k.cap;
         w.tj = m.type[j];
@@ -331,28 +322,26 @@ __device__ inline void finish_nbr(const Dev &k, const Sep<DIM, T> &sep, const Nb
                                   Nbr<DIM, T> &nb)
 {
     using L = Rec<DIM, T>;
+    const T *v = w.v;
     nb.j = w.j;
-    if constexpr (L::F32) {
-        const T *v = w.v;
-        if constexpr (L::PACKED) {
-            const uint32_t word = rec_uint<T>(v[L::AUX]);
-            nb.tj = class_kind(word >> 30);
-            nb.r2 = sep.get_rec(k, v + L::X, word & kCellBits, nb.r);
-            const T S = v[L::VOL];
-            nb.rho = T(k.mass) * S;
-            nb.vol = pdiv(T(1), S);
-        } else {
-            nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
-            nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
-            nb.rho = v[L::RHO];
-            nb.vol = v[L::VOL];
-        }
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            nb.u[d] = v[L::U + d];
-            nb.w[d] = v[L::W + d];
-        }
-        nb.p = v[L::P];
+    if constexpr (L::PACKED) {
+        const uint32_t word = rec_uint<T>(v[L::AUX]);
+        nb.tj = class_kind(word >> 30);
+        nb.r2 = sep.get_rec(k, v + L::X, word & kCellBits, nb.r);
+        const T S = v[L::VOL];
+        nb.rho = T(k.mass) * S;
+        nb.vol = pdiv(T(1), S);
+    } else if constexpr (L::F32) {
+        nb.tj = int(rec_uint<T>(v[L::AUX + 1]));
+        nb.r2 = sep.get_rec(k, v + L::X, rec_uint<T>(v[L::AUX]), nb.r);
+        nb.rho = v[L::RHO];
+        nb.vol = v[L::VOL];
+    } else if constexpr (L::USE) {
+        nb.tj = int(rec_uint<T>(v[L::AUX]));
+        nb.r2 = sep.get_rec(k, v + L::X, nb.r);
+        const T S = v[L::VOL];
+        nb.rho = T(k.mass) * S;  // as the density pass forms the stored fields
+        nb.vol = T(1) / S;
     } else {
         nb.tj = w.tj;
         nb.r2 = dist2_exact<DIM>(k, sep.xi, w.xj, nb.r);
@@ -362,9 +351,16 @@ __device__ inline void finish_nbr(const Dev &k, const Sep<DIM, T> &sep, const Nb
             nb.w[d] = w.ut[d] - w.u[d];
         }
         nb.p = w.p;
-        nb.rho = T(k.mass) * w.s;  // as the density pass forms the stored fields
+        nb.rho = T(k.mass) * w.s;
         nb.vol = T(1) / w.s;
+        return;
     }
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        nb.u[d] = v[L::U + d];
+        nb.w[d] = v[L::W + d];
+    }
+    nb.p = v[L::P];
 }
 
 template <int DIM, typename T>

@@ -284,8 +284,8 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
             if (o.shep) st<T>(o.shep, i, S);
         }
     }
-    if (dens && o.rec)
-        write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cpos[i], lane);
+    if constexpr (sizeof(T) == 4)
+        if (dens && o.rec) write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cpos[i], lane);
     if (sizeof(T) == 4) {
         // offsets from the bin cell's corner, for the FP32 pair arithmetic
         for (int d = lane; d < DIM; d += G)
@@ -331,26 +331,63 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
         st<T>(o.vol, i, T(1) / S);
         if (o.shep) st<T>(o.shep, i, S);
     }
-    if (o.rec) {
-        int c[3] = {0, 0, 0};
-        const uint32_t cp = cpos[i];
-        unpack_cell<DIM>(cp, c);
-        write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cp, lane);
+    if constexpr (sizeof(T) == 4) {
+        if (o.rec) {
+            int c[3] = {0, 0, 0};
+            const uint32_t cp = cpos[i];
+            unpack_cell<DIM>(cp, c);
+            write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cp, lane);
+        }
     }
+}
+
+// FP64 neighbour records (chunk-major, rec_chunk) of every live row from the
+// stage's fields and the Shepard sums of the density pass just run: one
+// thread per row, so that each field load and each chunk store is coalesced
+// across the wave (written inside the neighbour search, whose gathers already
+// saturate the vector memory path, the same records cost about twice as
+// long). Every load is issued before the first store.
+template <int DIM>
+__global__ void __launch_bounds__(kBlock) k_pack_rec(Dev k, DevState m, Fields R, DevDerived o)
+{
+    using L = Rec<DIM, double>;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= *m.n) return;
+    const int64_t C = k.cap;
+    double v[L::NC * L::PER];
+#pragma unroll
+    for (int q = 0; q < L::NC * L::PER; ++q) v[q] = 0.0;
+    double ut[DIM];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        v[L::X + d] = R.x[d * C + i];
+        v[L::U + d] = ld<double>(R.u, d * C + i);
+        ut[d] = ld<double>(R.ut, d * C + i);
+    }
+    v[L::P] = ld<double>(R.p, i);
+    v[L::VOL] = ld<double>(o.shep, i);
+    const uint32_t t = m.type[i];
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) v[L::W + d] = ut[d] - v[L::U + d];
+    v[L::AUX] = rec_word<double>(t);
+#pragma unroll
+    for (int ch = 0; ch < L::NC; ++ch)
+        *rec_chunk<DIM, double>(o.rec, C, i, ch) = Chunk<double>::make(v + ch * L::PER);
 }
 
 // Record slots of the boundary values of row i (p, u, ut - u), from the very
 // values the state receives, so that record and state agree bit for bit.
 template <int DIM, typename T>
-__device__ inline void rec_put_pu(void *rec, int64_t i, T p, const T u[3], const T ut[3])
+__device__ inline void rec_put_pu(void *rec, int64_t cap, int64_t i, T p, const T u[3],
+                                  const T ut[3])
 {
     using L = Rec<DIM, T>;
-    T *r = static_cast<T *>(rec) + i * L::N;
-    r[L::P] = p;
+    static_assert(L::USE, "no records in this form");
+    *rec_slot<DIM, T>(rec, cap, i, L::P) = p;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-        r[L::U + d] = u[d];
-        r[L::W + d] = ut[d] - u[d];
+        *rec_slot<DIM, T>(rec, cap, i, L::U + d) = u[d];
+        *rec_slot<DIM, T>(rec, cap, i, L::W + d) = ut[d] - u[d];
     }
 }
 
@@ -675,7 +712,9 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 st<T>(R.p, i, T(pw));
 #pragma unroll
                 for (int d = 0; d < DIM; ++d) st<T>(R.u, d * C + i, uw[d]);
-                if (o.rec) rec_put_pu<DIM, T>(o.rec, i, T(pw), uw, ut_old);
+                if constexpr (Rec<DIM, T>::USE) {
+                    if (o.rec) rec_put_pu<DIM, T>(o.rec, C, i, T(pw), uw, ut_old);
+                }
             }
             continue;
         }
@@ -763,7 +802,9 @@ __global__ void __launch_bounds__(kBlock) k_boundary(Dev k, DevState m, Fields R
                 st<T>(R.u, d * C + i, uv[d]);
                 st<T>(R.ut, d * C + i, utv[d]);
             }
-            if (o.rec) rec_put_pu<DIM, T>(o.rec, i, pv, uv, utv);
+            if constexpr (Rec<DIM, T>::USE) {
+                if (o.rec) rec_put_pu<DIM, T>(o.rec, C, i, pv, uv, utv);
+            }
         }
     }
 }
@@ -1115,6 +1156,14 @@ void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevN
 {
     SPH_PREC_DIM(k_density, (k.dim == 2 ? grid_for(k, Grp<2>::G) : grid_for(k, Grp<3>::G)), k, m,
                  R, nl, o, cpos, err);
+}
+
+void launch_pack_rec(const Dev &k, const DevState &m, const Fields &R, const DevDerived &o,
+                     hipStream_t s)
+{
+    // 2D FP64 gathers the fields instead (Rec::USE)
+    if (k.prec != SPH_FP64 || k.dim != 3 || !o.rec || !o.shep) return;
+    hipLaunchKernelGGL(k_pack_rec<3>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, m, R, o);
 }
 
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

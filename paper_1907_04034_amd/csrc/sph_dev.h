@@ -83,19 +83,21 @@ struct DevDerived {
     void *rho, *vol, *pavg, *a, *b, *pdot;
     double *jcur, *force, *drag, *sfl;
     uint8_t *red;
-    void *rec;  // neighbour records of the force pass (Rec), [cap][Rec::N]
-    // FP64: the Shepard sums S of the density pass, from which the force pass
-    // forms a neighbour's rho = m S and V = 1/S (one gather instead of two,
-    // the same operations as the stored fields, so the same values)
+    void *rec;  // neighbour records of the force pass (Rec, rec_chunk)
+    // FP64 with LDS tiles: the Shepard sums S of the density pass, which the
+    // tiled force pass stages for a neighbour's rho = m S and V = 1/S
     void *shep;
 };
 
 // Neighbour record: what the force pass gathers of a neighbour j, packed so
 // that it arrives in a few 16-byte loads instead of one load per field
-// (positions or FP32 cell offsets, p, u, w = ut - u, rho, V, kind and, in FP32,
-// the packed cell). Written by the density pass (every row) and the boundary
-// pass (the values it sets), in the state's element type; slots in T units.
-// The library keeps records for FP32 states only. In 3D FP32 the record is
+// (positions or FP32 cell offsets, p, u, w = ut - u, rho and V or the Shepard
+// sum S, kind and, in FP32, the packed cell). Written by the density pass
+// (every row) and the boundary pass (the values it sets), in the state's
+// element type; slots in T units. FP64 records hold S, from which a
+// neighbour's rho = m S and V = 1/S are formed per pair by the operations
+// that give the stored fields, so the values are the same: 96 bytes in 3D, 80
+// in 2D. In 3D FP32 the record is
 // packed into 48 bytes: the Shepard sum S stands for rho = m S (formed per
 // pair as the density pass forms the stored field) and V = 1/S (per pair by
 // the hardware reciprocal, within about an ulp of the stored field, like the
@@ -106,16 +108,25 @@ template <int DIM, typename T>
 struct Rec {
     static constexpr bool F32 = sizeof(T) == 4;
     static constexpr bool PACKED = F32 && DIM == 3;
-    static constexpr int X = 0, P = DIM, U = 4, RHO = PACKED ? -1 : (DIM == 3 ? 7 : 3),
-                         W = PACKED ? 7 : (DIM == 3 ? 8 : 6),
-                         VOL = PACKED ? 10 : (DIM == 3 ? 11 : 8),  // PACKED: S
-                         AUX = PACKED ? 11 : (DIM == 3 ? 12 : 9);
+    // the Shepard sum S in place of rho and V (FP64 and 3D FP32)
+    static constexpr bool SREC = PACKED || !F32;
+    // chunk-major (FP64) or row-major (FP32) storage, see rec_chunk
+    static constexpr bool CM = !F32;
+    // the force pass gathers records (FP32, 3D FP64) or, in 2D FP64, the
+    // state's fields and the Shepard sum (measured: 2D FP64 records left the
+    // 1.2M-particle cylinder's force pass at 168 us and the pass that writes
+    // them cost more than they saved, 0.850 -> 0.873 ms per step)
+    static constexpr bool USE = F32 || DIM == 3;
+    static constexpr int X = 0, P = DIM, U = 4, RHO = SREC ? -1 : 3, W = DIM == 3 ? 7 : 6,
+                         VOL = DIM == 3 ? 10 : (F32 ? 8 : 3),  // SREC: S
+                         AUX = DIM == 3 ? 11 : (F32 ? 9 : 8);
     // FP32: cell bits and kind bits (one word when PACKED); FP64: kind
-    static constexpr int USED = PACKED ? 12 : AUX + (F32 ? 2 : 1);
+    static constexpr int USED = F32 && !PACKED ? AUX + 2 : AUX + 1;
     static constexpr int PER = 16 / int(sizeof(T));    // T per 16-byte chunk
     static constexpr int NC = (USED + PER - 1) / PER;  // chunks that carry data
-    static constexpr int N = PACKED ? 12 : (DIM == 3 ? 16 : (F32 ? 12 : 10));  // stride in T
+    static constexpr int N = NC * PER;                 // row stride in T (row-major)
 };
+
 
 // What the force pass distinguishes of a neighbour's kind: fluid, inlet or
 // outlet (and rows already marked dead), slip wall, no-slip wall or body.
@@ -146,6 +157,28 @@ struct Chunk<double> {
     __device__ static inline void get(const V &c, double *v) { v[0] = c.x; v[1] = c.y; }
     __device__ static inline V make(const double *v) { return V{v[0], v[1]}; }
 };
+
+// Chunk ch (16 bytes) of row j's record. FP32 records are row-major (a row's
+// chunks together); FP64 records are chunk-major (chunk ch of every row
+// together, at ch * cap + j), so that the chunks of neighbouring rows share
+// cache lines: a wave's gather of neighbour chunks then touches about 30
+// 64-byte lines per instruction against 46 for a row-major record and 23 per
+// field for the state's own arrays, 6 chunk loads against 13 field loads per
+// neighbour in 3D. (FP32 records measured the same either way: that pass is
+// bound by its arithmetic.)
+template <int DIM, typename T>
+__device__ inline typename Chunk<T>::V *rec_chunk(void *rec, int64_t cap, int64_t j, int ch)
+{
+    using L = Rec<DIM, T>;
+    auto *b = reinterpret_cast<typename Chunk<T>::V *>(rec);
+    return L::CM ? b + (int64_t(ch) * cap + j) : b + (j * L::NC + ch);
+}
+template <int DIM, typename T>
+__device__ inline T *rec_slot(void *rec, int64_t cap, int64_t j, int slot)
+{
+    using L = Rec<DIM, T>;
+    return reinterpret_cast<T *>(rec_chunk<DIM, T>(rec, cap, j, slot / L::PER)) + slot % L::PER;
+}
 
 // kind and packed cell stored in record slots (bit copies in FP32)
 template <typename T>
@@ -257,7 +290,7 @@ struct VList {
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, scat, tmp,
         cpos, cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
-        vnbr, rec, lslot, ttab, csum, total;
+        vnbr, rec, shep, lslot, ttab, csum, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)

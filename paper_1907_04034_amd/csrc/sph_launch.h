@@ -46,6 +46,8 @@ void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevN
                     const int32_t *cell_start, const uint32_t *cpos, float *off,
                     uint16_t *lslot, const int32_t *ttab, int32_t *rebin_clear, const VList &v,
                     int vmode, uint32_t *err, hipStream_t s);
+void launch_pack_rec(const Dev &k, const DevState &m, const Fields &R, const DevDerived &o,
+                     hipStream_t s);
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, const uint32_t *cpos, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

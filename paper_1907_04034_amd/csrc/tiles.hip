@@ -428,7 +428,8 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
                 if (o.shep) st<T>(o.shep, i, S);
             }
         }
-        if (dens && o.rec) write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cposi, lane);
+        if constexpr (sizeof(T) == 4)
+            if (dens && o.rec) write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cposi, lane);
         if (sizeof(T) == 4) {
             // offsets from the bin cell's corner, for the FP32 pair arithmetic
             for (int d = lane; d < DIM; d += G)
@@ -448,14 +449,12 @@ struct ForceStage<DIM, float> {
     using L = Rec<DIM, float>;
     static constexpr int CAP = tile_cap_force(DIM, SPH_FP32);
     float4 rec[CAP][L::NC];
-    __device__ inline void put(const Dev &, const DevState &, const Fields &,
+    __device__ inline void put(const Dev &k, const DevState &, const Fields &,
                                const DevDerived &o, int f, int64_t j)
     {
-        const float4 *src = reinterpret_cast<const float4 *>(static_cast<const float *>(o.rec) +
-                                                              j * L::N);
         float4 v[L::NC];
 #pragma unroll
-        for (int ch = 0; ch < L::NC; ++ch) v[ch] = src[ch];
+        for (int ch = 0; ch < L::NC; ++ch) v[ch] = *rec_chunk<DIM, float>(o.rec, k.cap, j, ch);
 #pragma unroll
         for (int ch = 0; ch < L::NC; ++ch) rec[f][ch] = v[ch];
     }
@@ -497,19 +496,37 @@ struct ForceStage<DIM, double> {
         for (int q = 0; q < NF; ++q) f64[q][f] = v[q];
         kind[f] = t;
     }
+    // the staged fields in the record's layout (w = ut - u formed as the
+    // record writer forms it)
     __device__ inline void get(int f, int32_t j, NbrRaw<DIM, double> &w) const
     {
+        using L = Rec<DIM, double>;
         w.j = j;
-        w.tj = kind[f];
-        w.xj[2] = 0.0;
+        if constexpr (L::USE) {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            w.xj[d] = f64[X + d][f];
-            w.u[d] = f64[U + d][f];
-            w.ut[d] = f64[UT + d][f];
+            for (int q = 0; q < L::NC * L::PER; ++q) w.v[q] = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                w.v[L::X + d] = f64[X + d][f];
+                const double u = f64[U + d][f];
+                w.v[L::U + d] = u;
+                w.v[L::W + d] = f64[UT + d][f] - u;
+            }
+            w.v[L::P] = f64[P][f];
+            w.v[L::VOL] = f64[SH][f];
+            w.v[L::AUX] = rec_word<double>(uint32_t(kind[f]));
+        } else {
+            w.tj = kind[f];
+            w.xj[2] = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+                w.xj[d] = f64[X + d][f];
+                w.u[d] = f64[U + d][f];
+                w.ut[d] = f64[UT + d][f];
+            }
+            w.p = f64[P][f];
+            w.s = f64[SH][f];
         }
-        w.p = f64[P][f];
-        w.s = f64[SH][f];
     }
     __device__ inline double pres(int f) const { return f64[P][f]; }
 };
