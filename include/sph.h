@@ -331,8 +331,9 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
 /* The force pass alone (needs sph_density, or sph_neighbor_table with out, and
  * sph_outlet_extrapolate on the same neighbour table, state and workspace
  * first; those passes leave in the workspace what this pass gathers of a
- * neighbour, packed copies of each particle's values for FP32 states and the
- * Shepard sums for FP64 states, so the state must not change in between): eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
+ * neighbour, packed copies of each particle's values (FP32 states, and 3D FP64
+ * states, whose copies sph_outlet_extrapolate writes) or the Shepard sums (2D
+ * FP64 states), so the state must not change in between): eq:pavg, eq:tvf-p-ij-basa, eq:tvf-momentum,
  * eq:p-edac and the background term of eq:transport-vel for fluid particles;
  * eq:tvf-momentum_solid for body particles, reduced into out->drag (skipped
  * when out->drag is NULL, so that the call is exactly one kernel launch).

@@ -484,16 +484,20 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
                    at<uint32_t>(c.ws, c.w.cpos_s), off ? off : c.off(),
                    at<uint16_t>(c.ws, c.w.lslot), at<int32_t>(c.ws, c.w.ttab),
                    clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
-    if (dens) launch_pack_rec(c.k, dev_state(st), R, c.der(o), c.s);
 }
 
+// Boundary values, then (3D FP64) the neighbour records of the stage, which
+// take the boundary rows' new values from the state (FP32 records are
+// written by the density pass and their boundary slots by this pass).
 static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
                         const sph_derived *o)
 {
-    launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), c.der(o),
-                    at<int32_t>(c.ws, c.w.blist), at<int32_t>(c.ws, c.w.bcount),
-                    at<uint32_t>(c.ws, c.w.spread), at<int32_t>(c.ws, c.w.cell_start), c.err(),
-                    c.s);
+    DevDerived d = c.der(o);
+    if (c.k.prec == SPH_FP64) d.rec = nullptr;
+    launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), d, at<int32_t>(c.ws, c.w.blist),
+                    at<int32_t>(c.ws, c.w.bcount), at<uint32_t>(c.ws, c.w.spread),
+                    at<int32_t>(c.ws, c.w.cell_start), c.err(), c.s);
+    launch_pack_rec(c.k, dev_state(st), R, c.der(o), c.s);
 }
 
 static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields &W,
@@ -763,7 +767,6 @@ int sph_density(const sph_params *prm, const sph_state *st, const sph_nlist *nl,
     if (rc || (rc = check_nlist(nl)) || (rc = check_derived(out, false))) return rc;
     launch_density(c.k, dev_state(st), fields_of(st), dev_nlist(nl), c.der(out),
                    at<uint32_t>(ws, c.w.cpos_s), c.err(), c.s);
-    launch_pack_rec(c.k, dev_state(st), fields_of(st), c.der(out), c.s);
     return check_hip("sph_density");
 }
 
@@ -786,7 +789,6 @@ int sph_rhs(const sph_params *prm, sph_state *st, const sph_nlist *nl, sph_deriv
     const Fields F = fields_of(st);
     launch_density(c.k, dev_state(st), F, dev_nlist(nl), c.der(out), at<uint32_t>(ws, c.w.cpos_s),
                    c.err(), c.s);
-    launch_pack_rec(c.k, dev_state(st), F, c.der(out), c.s);
     do_boundary(c, st, F, nl, out);
     do_force(c, st, F, F, nl, out, 0, out->drag, nullptr);
     return check_hip("sph_rhs");

@@ -342,11 +342,12 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
 }
 
 // FP64 neighbour records (chunk-major, rec_chunk) of every live row from the
-// stage's fields and the Shepard sums of the density pass just run: one
-// thread per row, so that each field load and each chunk store is coalesced
-// across the wave (written inside the neighbour search, whose gathers already
-// saturate the vector memory path, the same records cost about twice as
-// long). Every load is issued before the first store.
+// stage's fields, after the boundary pass has set its rows' values, and the
+// Shepard sums of the density pass: one thread per row, so that each field
+// load and each chunk store is coalesced across the wave (written inside the
+// neighbour search, whose gathers already saturate the vector memory path,
+// the same records cost about twice as long; and the boundary pass would
+// have to patch its rows' slots). Every load is issued before the first store.
 template <int DIM>
 __global__ void __launch_bounds__(kBlock) k_pack_rec(Dev k, DevState m, Fields R, DevDerived o)
 {
