@@ -281,8 +281,8 @@ static WsLayout layout(const Dev &k)
     // neighbour records of the force pass: FP32, or FP64 in 3D (sized for the
     // larger whatever the precision: the workspace size does not depend on it)
     w.rec = take((k.dim == 2 ? rec_bytes<2, float>() : rec_bytes<3, double>()) * C);
-    // the FP64 Shepard sums, from which k_pack_rec forms the records and
-    // which the LDS-tiled force pass stages
+    // the Shepard sums (FP64, 3D FP32), from which k_pack_rec forms the
+    // records and which the 2D FP64 and LDS-tiled force passes gather
     w.shep = take(sizeof(double) * C);
     // LDS slots of the tiled search's table entries, read by the force pass
     w.lslot = take(k.tiles ? sizeof(uint16_t) * size_t(k.lmax) * C : 0);
@@ -418,7 +418,7 @@ struct Ctx {
         DevDerived d = dev_derived(o);
         // records where the force pass gathers them (Rec::USE): FP32, 3D FP64
         d.rec = k.prec == SPH_FP32 || k.dim == 3 ? at<void>(ws, w.rec) : nullptr;
-        d.shep = k.prec == SPH_FP64 ? at<void>(ws, w.shep) : nullptr;
+        d.shep = k.prec == SPH_FP64 || k.dim == 3 ? at<void>(ws, w.shep) : nullptr;
         return d;
     }
     double *dragpart() const { return at<double>(ws, w.dragpart); }
@@ -486,18 +486,18 @@ static void do_nbrdens(Ctx &c, const sph_state *st, const Fields &R, const sph_n
                    clear_rebin ? at<int32_t>(c.ws, c.w.rebin) : nullptr, v, vmode, c.err(), c.s);
 }
 
-// Boundary values, then (3D FP64) the neighbour records of the stage, which
-// take the boundary rows' new values from the state (FP32 records are
-// written by the density pass and their boundary slots by this pass).
+// Boundary values, then (3D) the neighbour records of the stage, which take
+// the boundary rows' new values from the state (2D FP32 records are written
+// by the density pass and their boundary slots by the boundary pass).
 static void do_boundary(Ctx &c, const sph_state *st, const Fields &R, const sph_nlist *nl,
                         const sph_derived *o)
 {
     DevDerived d = c.der(o);
-    if (c.k.prec == SPH_FP64) d.rec = nullptr;
+    if (c.k.dim == 3) d.rec = nullptr;  // packed below
     launch_boundary(c.k, dev_state(st), R, dev_nlist(nl), d, at<int32_t>(c.ws, c.w.blist),
                     at<int32_t>(c.ws, c.w.bcount), at<uint32_t>(c.ws, c.w.spread),
                     at<int32_t>(c.ws, c.w.cell_start), c.err(), c.s);
-    launch_pack_rec(c.k, dev_state(st), R, c.der(o), c.s);
+    launch_pack_rec(c.k, dev_state(st), R, c.der(o), at<uint32_t>(c.ws, c.w.cpos_s), c.s);
 }
 
 static void do_force(Ctx &c, const sph_state *st, const Fields &R, const Fields &W,

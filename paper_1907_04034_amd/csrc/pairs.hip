@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(kBlock) k_nbrdens(Dev k, DevState m, Fields R,
             if (o.shep) st<T>(o.shep, i, S);
         }
     }
-    if constexpr (sizeof(T) == 4)
+    if constexpr (sizeof(T) == 4 && DIM == 2)
         if (dens && o.rec) write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cpos[i], lane);
     if (sizeof(T) == 4) {
         // offsets from the bin cell's corner, for the FP32 pair arithmetic
@@ -331,7 +331,7 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
         st<T>(o.vol, i, T(1) / S);
         if (o.shep) st<T>(o.shep, i, S);
     }
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && DIM == 2) {
         if (o.rec) {
             int c[3] = {0, 0, 0};
             const uint32_t cp = cpos[i];
@@ -341,39 +341,55 @@ __global__ void __launch_bounds__(kBlock) k_density(Dev k, DevState m, Fields R,
     }
 }
 
-// FP64 neighbour records (chunk-major, rec_chunk) of every live row from the
-// stage's fields, after the boundary pass has set its rows' values, and the
-// Shepard sums of the density pass: one thread per row, so that each field
-// load and each chunk store is coalesced across the wave (written inside the
-// neighbour search, whose gathers already saturate the vector memory path,
-// the same records cost about twice as long; and the boundary pass would
-// have to patch its rows' slots). Every load is issued before the first store.
-template <int DIM>
-__global__ void __launch_bounds__(kBlock) k_pack_rec(Dev k, DevState m, Fields R, DevDerived o)
+// 3D neighbour records of every live row from the stage's fields, after the
+// boundary pass has set its rows' values, and the Shepard sums of the density
+// pass: FP64 chunk-major (x, p, u, w, S, kind), FP32 row-major (cell offsets
+// as the offset array holds them, p, u, w, S, kind class and packed cell).
+// One thread per row, so that each field load and each chunk store is
+// coalesced across the wave: written inside the neighbour search, whose
+// gathers already saturate the vector memory path, the same records cost
+// about twice as long, and the boundary pass would have to patch its rows'
+// slots. Every load is issued before the first store.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_pack_rec(Dev k, DevState m, Fields R, DevDerived o,
+                                                     const uint32_t *cpos)
 {
-    using L = Rec<DIM, double>;
+    using L = Rec<3, T>;
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= *m.n) return;
     const int64_t C = k.cap;
-    double v[L::NC * L::PER];
+    T v[L::NC * L::PER];
 #pragma unroll
-    for (int q = 0; q < L::NC * L::PER; ++q) v[q] = 0.0;
-    double ut[DIM];
+    for (int q = 0; q < L::NC * L::PER; ++q) v[q] = T(0);
+    double x[3];
+    T ut[3];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        v[L::X + d] = R.x[d * C + i];
-        v[L::U + d] = ld<double>(R.u, d * C + i);
-        ut[d] = ld<double>(R.ut, d * C + i);
+    for (int d = 0; d < 3; ++d) {
+        x[d] = R.x[d * C + i];
+        v[L::U + d] = ld<T>(R.u, d * C + i);
+        ut[d] = ld<T>(R.ut, d * C + i);
     }
-    v[L::P] = ld<double>(R.p, i);
-    v[L::VOL] = ld<double>(o.shep, i);
+    v[L::P] = ld<T>(R.p, i);
+    v[L::VOL] = ld<T>(o.shep, i);
     const uint32_t t = m.type[i];
+    uint32_t cp = 0;
+    if constexpr (L::F32) cp = cpos[i];
 #pragma unroll
-    for (int d = 0; d < DIM; ++d) v[L::W + d] = ut[d] - v[L::U + d];
-    v[L::AUX] = rec_word<double>(t);
+    for (int d = 0; d < 3; ++d) v[L::W + d] = ut[d] - v[L::U + d];
+    if constexpr (L::F32) {
+        int c[3] = {0, 0, 0};
+        unpack_cell<3>(cp, c);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[L::X + d] = cell_offset(k, d, x[d], c[d]);
+        v[L::AUX] = rec_word<T>(cp | (kind_class(int(t)) << 30));
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) v[L::X + d] = x[d];
+        v[L::AUX] = rec_word<T>(t);
+    }
 #pragma unroll
     for (int ch = 0; ch < L::NC; ++ch)
-        *rec_chunk<DIM, double>(o.rec, C, i, ch) = Chunk<double>::make(v + ch * L::PER);
+        *rec_chunk<3, T>(o.rec, C, i, ch) = Chunk<T>::make(v + ch * L::PER);
 }
 
 // Record slots of the boundary values of row i (p, u, ut - u), from the very
@@ -1160,11 +1176,18 @@ void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevN
 }
 
 void launch_pack_rec(const Dev &k, const DevState &m, const Fields &R, const DevDerived &o,
-                     hipStream_t s)
+                     const uint32_t *cpos, hipStream_t s)
 {
-    // 2D FP64 gathers the fields instead (Rec::USE)
-    if (k.prec != SPH_FP64 || k.dim != 3 || !o.rec || !o.shep) return;
-    hipLaunchKernelGGL(k_pack_rec<3>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, m, R, o);
+    // 3D only: 2D FP64 gathers the fields (Rec::USE), 2D FP32 records are
+    // written by the density pass (a dispatch of their own cost the small 2D
+    // systems more than it saved)
+    if (k.dim != 3 || !o.rec || !o.shep) return;
+    if (k.prec == SPH_FP64)
+        hipLaunchKernelGGL(k_pack_rec<double>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, m, R,
+                           o, cpos);
+    else
+        hipLaunchKernelGGL(k_pack_rec<float>, dim3(nblocks(k.cap)), dim3(kBlock), 0, s, k, m, R,
+                           o, cpos);
 }
 
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

@@ -47,7 +47,7 @@ void launch_nbrdens(const Dev &k, const DevState &m, const Fields &R, const DevN
                     uint16_t *lslot, const int32_t *ttab, int32_t *rebin_clear, const VList &v,
                     int vmode, uint32_t *err, hipStream_t s);
 void launch_pack_rec(const Dev &k, const DevState &m, const Fields &R, const DevDerived &o,
-                     hipStream_t s);
+                     const uint32_t *cpos, hipStream_t s);
 void launch_density(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,
                     const DevDerived &o, const uint32_t *cpos, uint32_t *err, hipStream_t s);
 void launch_boundary(const Dev &k, const DevState &m, const Fields &R, const DevNlist &nl,

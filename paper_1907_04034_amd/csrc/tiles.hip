@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(kBlock) k_tsearch(Dev k, DevState m, Fields R,
                 if (o.shep) st<T>(o.shep, i, S);
             }
         }
-        if constexpr (sizeof(T) == 4)
+        if constexpr (sizeof(T) == 4 && DIM == 2)
             if (dens && o.rec) write_rec<DIM, T, G>(k, m, R, o.rec, i, S, xi, c, cposi, lane);
         if (sizeof(T) == 4) {
             // offsets from the bin cell's corner, for the FP32 pair arithmetic
