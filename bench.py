@@ -64,15 +64,23 @@ def log(msg):
 
 
 def force_bytes(counts, types, prec_bytes, dim):
-    """The implementation's own byte count of one force launch: as the scope
-    figure plus the neighbour count and indices each fluid or body row reads
-    and the kind byte of every row."""
+    """The implementation's own byte count of one force launch: each fluid or
+    body row's own fields (position or cell offsets, u, ut, p, rho, V), count
+    and table entries; every row's neighbour data read once (its record, 96
+    bytes in 3D FP64 and 48 in FP32, or in 2D FP64 its position, u, ut, p,
+    Shepard sum and kind) and its kind byte; the writes of a, b, pdot and
+    pbar and of the body force."""
     fb = (types == 0) | (types == 5)
     n = len(types)
     nfb = int(fb.sum())
     nnz = int(counts[fb].sum())
     pos = 8 * dim if prec_bytes == 8 else 4 * dim + 4  # FP32: cell offsets + packed cell
-    rd = n * 1 + nfb * (pos + 2 * prec_bytes * dim + 3 * prec_bytes + 4) + 4 * nnz
+    own = pos + 2 * prec_bytes * dim + 3 * prec_bytes + 4
+    if prec_bytes == 4 or dim == 3:
+        nbr = 96 if prec_bytes == 8 else 48
+    else:
+        nbr = 8 * dim + 2 * prec_bytes * dim + 2 * prec_bytes + 1
+    rd = n * (1 + nbr) + nfb * own + 4 * nnz
     wr = n * (2 * prec_bytes * dim + 2 * prec_bytes) + int((types == 5).sum()) * 8 * dim
     return rd + wr
 
