@@ -85,13 +85,40 @@ def force_bytes(counts, types, prec_bytes, dim):
     return rd + wr
 
 
+def code_text(src):
+    """C++/HIP source without its comments and whitespace (string and
+    character literals kept as written): what the compiled kernels depend on."""
+    out, i, n = [], 0, len(src)
+    while i < n:
+        c = src[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and src[j] != c:
+                j += 2 if src[j] == "\\" else 1
+            out.append(src[i:j + 1])
+            i = j + 1
+        elif src.startswith("//", i):
+            i = src.find("\n", i)
+            i = n if i < 0 else i
+        elif src.startswith("/*", i):
+            i = src.find("*/", i + 2)
+            i = n if i < 0 else i + 2
+        else:
+            if not c.isspace():
+                out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def source_hash():
+    """Hash of the kernel sources' code (comments and whitespace left out), so
+    that a counter summary stays valid across edits of comments only."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1907_04034_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith((".hip", ".h")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+                h.update(code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -84,20 +84,22 @@ struct DevDerived {
     double *jcur, *force, *drag, *sfl;
     uint8_t *red;
     void *rec;  // neighbour records of the force pass (Rec, rec_chunk)
-    // FP64 with LDS tiles: the Shepard sums S of the density pass, which the
-    // tiled force pass stages for a neighbour's rho = m S and V = 1/S
+    // the Shepard sums S of the density pass (FP64 and 3D FP32), from which
+    // the 3D records are packed and the 2D FP64 and LDS-tiled force passes
+    // form a neighbour's rho = m S and V = 1/S
     void *shep;
 };
 
 // Neighbour record: what the force pass gathers of a neighbour j, packed so
 // that it arrives in a few 16-byte loads instead of one load per field
 // (positions or FP32 cell offsets, p, u, w = ut - u, rho and V or the Shepard
-// sum S, kind and, in FP32, the packed cell). Written by the density pass
-// (every row) and the boundary pass (the values it sets), in the state's
-// element type; slots in T units. FP64 records hold S, from which a
-// neighbour's rho = m S and V = 1/S are formed per pair by the operations
-// that give the stored fields, so the values are the same: 96 bytes in 3D, 80
-// in 2D. In 3D FP32 the record is
+// sum S, kind and, in FP32, the packed cell), in the state's element type;
+// slots in T units. 3D records are written after the boundary pass by
+// k_pack_rec, 2D FP32 ones by the density pass with the boundary pass
+// updating the slots of the values it sets; 2D FP64 has none (Rec::USE). FP64
+// records (96 bytes) hold S, from which a neighbour's rho = m S and V = 1/S
+// are formed per pair by the operations that give the stored fields, so the
+// values are the same. In 3D FP32 the record is
 // packed into 48 bytes: the Shepard sum S stands for rho = m S (formed per
 // pair as the density pass forms the stored field) and V = 1/S (per pair by
 // the hardware reciprocal, within about an ulp of the stored field, like the
@@ -111,7 +113,7 @@ struct Rec {
     // the Shepard sum S in place of rho and V (FP64 and 3D FP32)
     static constexpr bool SREC = PACKED || !F32;
     // chunk-major (FP64) or row-major (FP32) storage, see rec_chunk
-    static constexpr bool CM = !F32;
+    static constexpr bool CM = !F32;  // (3D FP32 measured the same either way)
     // the force pass gathers records (FP32, 3D FP64) or, in 2D FP64, the
     // state's fields and the Shepard sum (measured: 2D FP64 records left the
     // 1.2M-particle cylinder's force pass at 168 us and the pass that writes
