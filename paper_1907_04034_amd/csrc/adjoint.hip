@@ -290,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
     const bool weighted = A.abar || A.bbar || A.pdbar || A.fbar[0] != 0.0 || A.fbar[1] != 0.0 ||
                           A.fbar[2] != 0.0;
     const int cnt = weighted ? nl.count[i] : 0;
+    bool nonfluid = false;  // a neighbour that is not fluid (bflag)
     for (int q = lane; q < cnt; q += G) {
         const int32_t j = nl.nbr[i * nl.maxnb + q];
         if (bad_index(j, n)) {
@@ -299,6 +300,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
         if (j == i) continue;
         Ep<T> J;
         load_ep<DIM, T>(k, m, R, o, j, J);
+        nonfluid = nonfluid || J.t != SPH_FLUID;
         T r[3], rn[3];
         const T r2 = sep.get(k, R, off, cpos, j, r);
 #pragma unroll
@@ -345,7 +347,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_pairs(Dev k, DevState m, Fields 
     Kb.rho = gsum<G>(Kb.rho);
     Kb.vol = gsum<G>(Kb.vol);
     Pb = gsum<G>(Pb);
+    const double nf = gsum<G>(nonfluid ? 1.0 : 0.0);
     if (lane != 0) return;
+    // without the walk (no weights) the neighbours are unknown: flag the row
+    if (A.bflag) A.bflag[i] = (!weighted || nf > 0.0) ? 1 : 0;
     // boundary values may carry adjoints from outside this right-hand side
     // (a stage update that reads them)
     const bool seeded = K.t != SPH_FLUID;
@@ -506,6 +511,9 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
     for (int d = 0; d < DIM; ++d) xi[d] = R.x[d * C + i];
     const bool red = o.sfl[i] > 0.0;
     const bool blue_io = !red && (t == SPH_INLET || t == SPH_OUTLET) && A.jprevbar;
+    // a fluid row without a non-fluid neighbour (bflag 0, from the pair
+    // reverse) has no boundary row to gather from: its sums stay zero
+    const int fcnt = (!A.bflag || A.bflag[i]) ? cnt : 0;
     if (t == SPH_FLUID) {
         const double pf = double(ld<T>(R.p, i)), rhof = double(ld<T>(o.rho, i));
         double uf[3] = {0, 0, 0}, avgf[4] = {0, 0, 0, 0};
@@ -513,7 +521,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_bnd(Dev k, DevState m, Fields R,
         for (int d = 0; d < DIM; ++d) uf[d] = double(ld<T>(R.u, d * C + i));
 #pragma unroll
         for (int c = 0; c <= DIM; ++c) avgf[c] = m.avg[c * C + i];
-        for (int q0 = lane; q0 < cnt; q0 += kAdjBatch * G) {
+        for (int q0 = lane; q0 < fcnt; q0 += kAdjBatch * G) {
             int32_t jj[kAdjBatch], js[kAdjBatch];
             bool ok[kAdjBatch];
             adj_slots<G>(nl, i, cnt, q0, n, err, jj, ok, js);

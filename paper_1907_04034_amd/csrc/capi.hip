@@ -284,6 +284,8 @@ static WsLayout layout(const Dev &k)
     // the Shepard sums (FP64, 3D FP32), from which k_pack_rec forms the
     // records and which the 2D FP64 and LDS-tiled force passes gather
     w.shep = take(sizeof(double) * C);
+    // per-row flags of the reverse passes (a non-fluid neighbour)
+    w.bflag = take(C);
     // LDS slots of the tiled search's table entries, read by the force pass
     w.lslot = take(k.tiles ? sizeof(uint16_t) * size_t(k.lmax) * C : 0);
     w.ttab = take(k.tiles ? sizeof(int32_t) * size_t(tile_table_ints(k)) : 0);
@@ -932,6 +934,7 @@ static void reverse_step(Ctx &c, const sph_state *st, const DevState &m, const F
     A.Pbar = P(L.Pbar);
     A.Sbar = P(L.Sbar);
     A.jg = P(L.jg);
+    A.bflag = at<uint8_t>(c.ws, c.w.bflag);
 
     launch_adj_end(c.k, m, S, A, c.s);
     launch_rhs_adjoint(c.k, m, H, dev_nlist(nl2), dev_derived(d2), A, off2, cell, c.err(), c.s);
@@ -1156,6 +1159,7 @@ static int rhs_adjoint_impl(const sph_params *prm, const sph_state *st, const sp
     A.Pbar = adj->scratch + 5 * C;
     A.Sbar = adj->scratch + 6 * C;
     A.jg = adj->scratch + 7 * C;       // [3][cap]
+    A.bflag = at<uint8_t>(c.ws, c.w.bflag);
     launch_rhs_adjoint(c.k, dev_state(st), fields_of(st), dev_nlist(nl), dev_derived(fwd), A,
                        c.off(), at<uint32_t>(c.ws, c.w.cpos_s), c.err(), c.s);
     return check_hip(what);

@@ -206,6 +206,10 @@ struct DevAdj {
     double fbar[3];
     double *xbar, *ubar, *utbar, *pbar, *uinbar, *avgbar, *jprevbar;
     double *wbar, *rhobar, *volbar, *Pbar, *Sbar, *jg;
+    // per row: 1 if a neighbour is not fluid (or unknown), written by the pair
+    // reverse; a fluid row with 0 has no boundary neighbour to gather from in
+    // the boundary reverse (null: every row walks its neighbours)
+    uint8_t *bflag = nullptr;
 };
 
 // Logical block for hardware block blockIdx.x when nb_logical blocks are
@@ -292,7 +296,7 @@ struct VList {
 struct WsLayout {
     size_t err, nspawn, bcount, spread, counts, cell_start, cursor, tilesum, keys, scat, tmp,
         cpos, cpos_s, blist, hx, hu, hut, hp, off, dragpart, sflag, stile, rebin, xbin, vfresh, vcount,
-        vnbr, rec, shep, lslot, ttab, csum, total;
+        vnbr, rec, shep, bflag, lslot, ttab, csum, total;
 };
 
 __host__ __device__ inline bool is_wall(int t)
